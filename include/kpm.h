@@ -1,0 +1,183 @@
+/*
+ * kpm.h -- C ABI of libkpm: the data-parallel hot path of the kernel
+ * polynomial (Chebyshev) spectral method of KITE (arXiv:1910.05194) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int status: KPM_OK (0) or a negative KPM_E_*
+ *   code.  On failure kpm_last_error() returns a thread-local message.  No
+ *   C++ exception crosses the ABI and the library never aborts the process.
+ * - Arguments are validated before any device work is enqueued.
+ * - The caller owns every input and output buffer.  "Host" pointers are
+ *   ordinary CPU memory; "device" pointers are HIP device allocations (for
+ *   example torch tensors' data_ptr()).  The library owns its workspace,
+ *   which lives inside a plan (kpm_plan_*) or, for the one-shot calls, is
+ *   released before the call returns.
+ * - hip_stream is a hipStream_t (NULL = the default stream).  Device work is
+ *   enqueued on it.  Host outputs are complete when the call returns; device
+ *   outputs are complete once the stream has been synchronised.
+ * - Energies are in eV, lengths in nm.  Moments are always FP64.
+ *
+ * Model (paper Sec. 3(a) pattern rules, Sec. 3(d) lattice listing, eq. HQAHE,
+ * Sec. 4 magnetic field):
+ * - KPM_HONEYCOMB: 2 orbitals per cell (sublattices A, B), a1 = (a, 0),
+ *   a2 = (a/2, a sqrt(3)/2), a = 0.24595 nm, A at (0, -a_cc/2), B at
+ *   (0, +a_cc/2), a_cc = 0.142 nm; bonds A(n) - B(n + d), d in {(0,0),
+ *   (1,-1), (0,-1)} with matrix element t.
+ * - KPM_HONEYCOMB_SPIN: the same with two spins per site (4 orbitals per
+ *   cell) and the Rashba term (2i/3) lambda_R (s x d_ij)_z, d_ij the unit
+ *   bond vector from site j to site i.
+ * - KPM_SQUARE: 1 orbital per cell, bonds to the four nearest cells.
+ * - Periodic boundaries in both directions.  Peierls phases for a uniform
+ *   flux (flux per cell in units of h/e, flux * L1 an integer) use the Landau
+ *   gauge A = flux * (0, s1) in fractional coordinates: a hop from site j to
+ *   site i gets exp(2 pi i flux (s1_i + s1_j)/2 (s2_i - s2_j)), evaluated with
+ *   the unwrapped image of the neighbour.
+ * - Anderson disorder V_site = W (u - 1/2), identical for both spins; a site
+ *   is vacant iff u' < vacancy_p (its orbitals and bonds are removed).
+ * - Orbital index o = ((n2*L1 + n1)*n_sub + s)*n_spin + sigma.
+ * - Random numbers: counter-based SplitMix64 (Steele, Lea & Flood 2014),
+ *   key(purpose, seed, a, b) = mix(mix(mix(seed + purpose*G) + a*G) + b*G),
+ *   x_i = mix(key + (i+1)*G), u_i = (x_i >> 11) 2^-53, G = 0x9E3779B97F4A7C15.
+ *   Purposes: 1 = random phase (a = lattice index in the batch, b = vector r,
+ *   counter = orbital), 2 = Anderson (counter = site), 3 = vacancy.
+ */
+#ifndef KPM_H
+#define KPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KPM_OK 0
+#define KPM_E_INVALID (-1)      /* bad argument, detected before any launch */
+#define KPM_E_NOMEM (-2)        /* device allocation failed */
+#define KPM_E_DEVICE (-3)       /* HIP runtime error */
+#define KPM_E_SPECTRUM (-4)     /* |mu_n| > 1 + 1e-6 or non-finite: the bounds do not enclose the spectrum */
+#define KPM_E_UNSUPPORTED (-5)  /* valid request outside what this build implements */
+
+#define KPM_HONEYCOMB 0
+#define KPM_HONEYCOMB_SPIN 1
+#define KPM_SQUARE 2
+
+#define KPM_FP32 0
+#define KPM_FP64 1
+
+#define KPM_START_RANDOM_PHASE 0
+#define KPM_START_SITES 1
+
+#define KPM_GAMMA_FP64 0
+#define KPM_GAMMA_FP32 1
+#define KPM_GAMMA_SPLIT_BF16 2
+
+/* One lattice (a KITE configuration + disorder + modification). */
+typedef struct kpm_lattice_t {
+  int32_t kind;            /* KPM_HONEYCOMB | KPM_HONEYCOMB_SPIN | KPM_SQUARE */
+  int32_t L1, L2;          /* unit cells along a1, a2; each >= 2 */
+  double t;                /* nearest-neighbour hopping matrix element, eV */
+  double rashba;           /* lambda_R, eV (KPM_HONEYCOMB_SPIN only, else 0) */
+  double flux;             /* flux per cell in h/e; flux*L1 integer; not for KPM_SQUARE */
+  double anderson_w;       /* W >= 0, eV */
+  double vacancy_p;        /* 0 <= p < 1 */
+  uint64_t disorder_seed;
+  double e_min, e_max;     /* spectrum bounds used for the rescaling, eV, e_min < e_max */
+} kpm_lattice_t;
+
+/* DOS / LDOS moment request (KITE Calculation.dos / ldos). */
+typedef struct kpm_dos_params_t {
+  int32_t num_moments;     /* M >= 2 */
+  int32_t num_random;      /* R >= 1 random vectors per lattice (ignored for KPM_START_SITES) */
+  uint64_t vector_seed;
+  int32_t precision;       /* KPM_FP32 | KPM_FP64: vector storage and recursion arithmetic */
+  int32_t start;           /* KPM_START_RANDOM_PHASE | KPM_START_SITES */
+  const int64_t* sites;    /* host array of orbital indices (KPM_START_SITES); R := num_sites */
+  int32_t num_sites;
+} kpm_dos_params_t;
+
+/* Optional launch shape of the Chebyshev step kernel (0 = library choice / autotune cache). */
+typedef struct kpm_tune_t {
+  int32_t block;           /* threads per workgroup (64..1024, multiple of 64) */
+  int32_t rows;            /* lattice rows (along a2) per tile */
+  int32_t grid;            /* persistent workgroups (multiple of 8); 0 = one per tile */
+  int32_t use_graph;       /* 1 = replay the step loop as a captured hipGraph (default), 0 = eager */
+} kpm_tune_t;
+
+typedef struct kpm_plan_info_t {
+  int32_t n_steps;               /* step-kernel launches per run (ceil(M/2)) */
+  int32_t n_tiles;               /* tiles in the work list */
+  int32_t grid, block, rows, tile_cells_x;
+  int32_t r_padded;              /* vectors per orbital as stored (R rounded up) */
+  int64_t n_orbitals;            /* orbitals in the batch, vacancies included */
+  double bytes_per_step;         /* algorithmic HBM bytes of one step launch */
+  double last_loop_ms;           /* step loop of the last run (hipEvents on the run's stream) */
+  double last_run_ms;            /* whole last run (hipEvents) */
+  int64_t n_active_total;        /* active orbitals summed over lattices (after the last run) */
+} kpm_plan_info_t;
+
+typedef struct kpm_plan kpm_plan_t;
+
+int kpm_version(void);
+const char* kpm_last_error(void);
+
+/*
+ * DOS / LDOS Chebyshev moments (paper eqs. e6, e8; Sec. 2(c) stochastic trace;
+ * eq. PcomplexityFactor: R vectors, S = n_lat realisations per call).
+ *
+ * For every lattice l and start vector r:
+ *   mu^(l,r)_n = <r|T_n(H~_l)|r> / norm_l,   n = 0..M-1,
+ *   H~ = (H - de+)/de-, de+- = (e_max +- e_min)/2 (eqs. rescalingH/E),
+ * with |r> = sum_o exp(2 pi i u_{r,o}) |o> over active orbitals and norm_l =
+ * number of active orbitals (random phase), or |r> = |sites[r]> and norm = 1
+ * (LDOS, Sec. 4 LDOS example).  All lattices of a batch share M, R, precision
+ * and start kind and run in one persistent kernel per Chebyshev step.
+ *
+ * Outputs (either may be NULL):
+ *   mu_per_vector  [n_lat][R][M] FP64
+ *   mu_mean        [n_lat][M]    FP64, the mean over r
+ * out_on_device: 0 = host pointers, 1 = device pointers.
+ * Errors: KPM_E_INVALID (L < 2, M < 2, R < 1, e_min >= e_max, flux*L1 not an
+ * integer, flux on a square lattice, Rashba on a spinless lattice, lattices of
+ * different kinds in one batch, an LDOS site out of range or vacant);
+ * KPM_E_SPECTRUM if a moment is non-finite or exceeds 1 + 1e-6 in magnitude,
+ * i.e. the bounds do not enclose the spectrum (the paper warns that estimated
+ * bounds need checking; outputs are still written); KPM_E_NOMEM, KPM_E_DEVICE.
+ */
+int kpm_moments_dos(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
+                    double* mu_per_vector, double* mu_mean, int32_t out_on_device, void* hip_stream);
+
+/* Reusable form of kpm_moments_dos: create allocates the device workspace
+ * (two vector buffers of n_orbitals * R_padded complex values, per-site disorder
+ * arrays, the tile work list, moment partials); run builds the disorder, the
+ * start vectors and runs the whole recursion (replayed as a hipGraph after the
+ * first run when tune->use_graph != 0); destroy frees everything.  A plan may
+ * be run on different streams but not concurrently with itself. */
+int kpm_plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
+                    const kpm_tune_t* tune, kpm_plan_t** plan);
+int kpm_plan_run(kpm_plan_t* plan, double* mu_per_vector, double* mu_mean, int32_t out_on_device,
+                 void* hip_stream);
+int kpm_plan_info(kpm_plan_t* plan, kpm_plan_info_t* info);
+int kpm_plan_destroy(kpm_plan_t* plan);
+
+/*
+ * Jackson-damped DOS reconstruction (eqs. e7, delta_function_cheb_expansion;
+ * Jackson kernel of Weisse et al., Rev. Mod. Phys. 78, 275 (2006), which the
+ * paper cites):
+ *   rho(E_k) = [g_0 mu_0 + 2 sum_{n=1}^{M-1} g_n mu_n T_n(eps_k)] / (pi sqrt(1-eps_k^2) de-),
+ *   g_n = [(M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1))]/(M+1),
+ * eps_k = (E_k - de+)/de-; energies outside (e_min, e_max) give 0.  The
+ * printed factor of eqs. sss/e8 is read as 2/(1+delta_n0) (see eqs. e4, e7).
+ * mu [M], energies_ev [K], rho [K] (per eV per orbital), all FP64; host
+ * pointers (on_device = 0) or device pointers (on_device = 1).  M may be any
+ * prefix length of a longer moment table (post-processing with fewer moments).
+ */
+int kpm_reconstruct_jackson(const double* mu, int32_t M, const double* energies_ev, int32_t K,
+                            double e_min, double e_max, double* rho, int32_t on_device,
+                            void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPM_H */

@@ -1,0 +1,1132 @@
+// DOS / LDOS Chebyshev moments on gfx950.
+//
+// Paper passages: eq. e6 (matrix Chebyshev recursion), eq. e8 and Sec. 2(c)
+// (stochastic trace, random vectors), Sec. 3(a) (matrix-free pattern-rule
+// Hamiltonian with disorder fused into the multiplication), Sec. 3(b) (tiles
+// of the lattice processed as a unit), eq. PcomplexityFactor (R vectors, S
+// realisations).
+//
+// Data layout in HBM: one batch buffer per Chebyshev vector, lattice after
+// lattice; inside a lattice [n2][n1][sublattice][spin][r] complex, r fastest,
+// R padded to a multiple of the 16-byte pack (2 complex64 or 1 complex128).
+// Each thread owns one (site, 16-byte chunk of r) column of a tile and walks
+// the tile's rows along a2, so the neighbour rows it reads were loaded by the
+// same workgroup one row earlier (L1/L2 hits) and every vector element crosses
+// HBM once per step: read v_n, read v_{n-1}, write v_{n+1} in place of v_{n-1}.
+//
+// Moments use the product identities T_{2n} = 2 T_n^2 - T_0 and
+// T_{2n+1} = 2 T_{n+1} T_n - T_1 (from T_m T_n = (T_{m+n} + T_{|m-n|})/2), so
+// one step yields two moments from <v_n|v_n> and <v_{n+1}|v_n>, accumulated in
+// FP64 in registers (products of FP32 values are exact in FP64), reduced per
+// workgroup in LDS and across workgroups by a fixed-order tree: results are
+// bitwise reproducible.
+
+#include "kpm_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+namespace kpm {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+
+// ---------------------------------------------------------------------------
+// Geometry (paper Sec. 3(d) listing): honeycomb a = 0.24595 nm, a_cc = 0.142 nm.
+// ---------------------------------------------------------------------------
+constexpr double kAHc = 0.24595, kAccHc = 0.142;
+// Honeycomb bond classes: A(n) - B(n + d_k).
+constexpr int kBondD1[3] = {0, 1, 0};
+constexpr int kBondD2[3] = {0, -1, -1};
+
+struct Geometry {
+  double a1[2], a2[2], tauA[2], tauB[2];
+  double fA[2], fB[2];   // fractional coordinates of the sublattice positions
+};
+
+static Geometry honeycomb_geometry() {
+  Geometry g;
+  g.a1[0] = kAHc; g.a1[1] = 0.0;
+  g.a2[0] = kAHc / 2.0; g.a2[1] = kAHc * std::sqrt(3.0) / 2.0;
+  g.tauA[0] = 0.0; g.tauA[1] = -kAccHc / 2.0;
+  g.tauB[0] = 0.0; g.tauB[1] = kAccHc / 2.0;
+  auto frac = [&](const double* r, double* f) {
+    // Solve r = f0 a1 + f1 a2 (a1 has no y component).
+    f[1] = r[1] / g.a2[1];
+    f[0] = (r[0] - f[1] * g.a2[0]) / g.a1[0];
+  };
+  frac(g.tauA, g.fA);
+  frac(g.tauB, g.fB);
+  return g;
+}
+
+// Per-lattice constants seen by the kernels.
+template <typename T>
+struct LatDev {
+  int32_t L1, L2;
+  int64_t site_off;     // first site of the lattice in the batch per-site arrays
+  int64_t vec_off;      // first T element of the lattice's block in a vector buffer
+  int64_t phase_off;    // first complex entry of its [L1][3] Peierls table
+  T onsite_const;       // -de+/de- (used when there is no per-site array)
+  T hop;                // t/de-
+  T blk[3][8];          // spin lattice: H_{A,B'} / de- for bond class k (2x2 complex, row-major), no phase
+};
+
+template <typename T>
+struct StepArgs {
+  const LatDev<T>* lats;
+  const int4* tiles;      // (lattice, r-group, x0, y0)
+  const int* slot_of;     // moment slot of each tile
+  int n_tiles;
+  const T* __restrict__ v;
+  T* __restrict__ w;
+  const T* onsite;
+  const uint8_t* mask;
+  const T* phase;         // complex interleaved
+  double* part;           // [n_slots][Rw][2] for this step
+  T a, b;                 // v_{n+1} = a H~ v_n - b v_{n-1}
+  int read_w;
+  int Tx, Ty, E, Ew, Rp;
+};
+
+template <int KIND>
+struct KindTraits;
+template <>
+struct KindTraits<KPM_HONEYCOMB> { static constexpr int NSUB = 2, NSPIN = 1, NNB = 3; };
+template <>
+struct KindTraits<KPM_HONEYCOMB_SPIN> { static constexpr int NSUB = 2, NSPIN = 2, NNB = 3; };
+template <>
+struct KindTraits<KPM_SQUARE> { static constexpr int NSUB = 1, NSPIN = 1, NNB = 4; };
+
+template <typename T>
+__device__ inline void cmul_acc(T& ore, T& oim, T are, T aim, T bre, T bim) {
+  ore += are * bre - aim * bim;
+  oim += are * bim + aim * bre;
+}
+
+// ---------------------------------------------------------------------------
+// The Chebyshev step: one launch = one grid-wide step of eq. e6 over every
+// tile of every lattice in the batch, with the two doubling dot products.
+// ---------------------------------------------------------------------------
+template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE>
+__global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
+  using P = Pack<T>;
+  constexpr int NC = P::NC;
+  constexpr int NSUB = KindTraits<KIND>::NSUB;
+  constexpr int NSPIN = KindTraits<KIND>::NSPIN;
+  constexpr int NNB = KindTraits<KIND>::NNB;
+  extern __shared__ double lds[];
+
+  const int tid = threadIdx.x;
+  const int Ew = A.Ew;
+  const int cl = tid % Ew;
+  const int grp = tid / Ew;               // index of this thread among those sharing cl
+  const int n_grp = blockDim.x / Ew;
+  const int s = grp % NSUB;
+  const int xl = grp / NSUB;
+  const int Rp = A.Rp;
+
+  // XCD-aware static schedule: workgroup b runs on XCD b % 8; XCD x owns the
+  // contiguous tile range [x*T/8, (x+1)*T/8) so that neighbouring tiles share
+  // an L2.
+  const int xcd = blockIdx.x & 7;
+  const int jx = blockIdx.x >> 3;
+  const int gx = gridDim.x >> 3;
+  const int t_begin = (int)(((int64_t)xcd * A.n_tiles) >> 3);
+  const int t_end = (int)(((int64_t)(xcd + 1) * A.n_tiles) >> 3);
+
+  double vv[NC], wv[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) vv[j] = wv[j] = 0.0;
+
+  for (int ti = t_begin + jx; ti < t_end; ti += gx) {
+    const int4 tl = A.tiles[ti];
+    const LatDev<T>& Lg = A.lats[tl.x];
+    // Lattice constants into registers (the stores below cannot alias them).
+    struct {
+      int64_t site_off, vec_off, phase_off;
+      T onsite_const, hop;
+      T blk[3][8];
+    } L;
+    L.site_off = Lg.site_off;
+    L.vec_off = Lg.vec_off;
+    L.phase_off = Lg.phase_off;
+    L.onsite_const = Lg.onsite_const;
+    L.hop = Lg.hop;
+    if constexpr (KIND == KPM_HONEYCOMB_SPIN) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) L.blk[k][q] = Lg.blk[k][q];
+    }
+    const int L1 = Lg.L1, L2 = Lg.L2;
+    const int n1 = tl.z + xl;
+    const int c = tl.y * Ew + cl;
+    const bool act = (grp < n_grp) && (xl < A.Tx) && (n1 < L1) && (c < A.E) && (tid < n_grp * Ew);
+    if (act) {
+      const T* __restrict__ vb = A.v + L.vec_off;
+      T* __restrict__ wb = A.w + L.vec_off;
+      const int n1p = (n1 + 1 == L1) ? 0 : n1 + 1;
+      const int n1m = (n1 == 0) ? L1 - 1 : n1 - 1;
+      // Hopping coefficients of this column (Peierls phases depend on n1 only).
+      T hre[NNB], him[NNB];
+#pragma unroll
+      for (int k = 0; k < NNB; ++k) { hre[k] = L.hop; him[k] = (T)0; }
+      if constexpr (PHASE) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          // Table index = the A site's cell n1 (the B' image is unwrapped).
+          const int na = (s == 0) ? n1 : ((k == 1) ? n1m : n1);
+          const T pre = A.phase[2 * (L.phase_off + (int64_t)na * 3 + k)];
+          const T pim = A.phase[2 * (L.phase_off + (int64_t)na * 3 + k) + 1];
+          hre[k] = pre;
+          him[k] = (s == 0) ? pim : -pim;   // B side: conjugate
+          if constexpr (KIND != KPM_HONEYCOMB_SPIN) {
+            hre[k] *= L.hop;
+            him[k] *= L.hop;
+          }
+        }
+      }
+      const int yend = min(tl.w + A.Ty, L2);
+      for (int y = tl.w; y < yend; ++y) {
+        const int ym = (y == 0) ? L2 - 1 : y - 1;
+        const int yp = (y + 1 == L2) ? 0 : y + 1;
+        const int64_t site = ((int64_t)y * L1 + n1) * NSUB + s;
+        int64_t nb[NNB];
+        if constexpr (KIND == KPM_SQUARE) {
+          nb[0] = (int64_t)y * L1 + n1p;
+          nb[1] = (int64_t)y * L1 + n1m;
+          nb[2] = (int64_t)yp * L1 + n1;
+          nb[3] = (int64_t)ym * L1 + n1;
+        } else {
+          if (s == 0) {   // A(n) <- B(n), B(n + (1,-1)), B(n + (0,-1))
+            nb[0] = ((int64_t)y * L1 + n1) * 2 + 1;
+            nb[1] = ((int64_t)ym * L1 + n1p) * 2 + 1;
+            nb[2] = ((int64_t)ym * L1 + n1) * 2 + 1;
+          } else {        // B(n) <- A(n), A(n - (1,-1)), A(n - (0,-1))
+            nb[0] = ((int64_t)y * L1 + n1) * 2;
+            nb[1] = ((int64_t)yp * L1 + n1m) * 2;
+            nb[2] = ((int64_t)yp * L1 + n1) * 2;
+          }
+        }
+        const int64_t coff = (int64_t)c * NC * 2;
+        P vo[NSPIN], wo[NSPIN], vn[NNB][NSPIN];
+#pragma unroll
+        for (int sp = 0; sp < NSPIN; ++sp) {
+          vo[sp] = *reinterpret_cast<const P*>(vb + (site * NSPIN + sp) * Rp * 2 + coff);
+          if (A.read_w) wo[sp] = *reinterpret_cast<const P*>(wb + (site * NSPIN + sp) * Rp * 2 + coff);
+#pragma unroll
+          for (int k = 0; k < NNB; ++k)
+            vn[k][sp] = *reinterpret_cast<const P*>(vb + (nb[k] * NSPIN + sp) * Rp * 2 + coff);
+        }
+        T ons = L.onsite_const;
+        if constexpr (ONSITE) ons = A.onsite[L.site_off + site];
+        bool alive = true;
+        if constexpr (MASK) alive = A.mask[L.site_off + site] != 0;
+
+        P out[NSPIN];
+#pragma unroll
+        for (int sp = 0; sp < NSPIN; ++sp) {
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            T hr = ons * vo[sp].v[2 * j], hi = ons * vo[sp].v[2 * j + 1];
+            if constexpr (KIND == KPM_HONEYCOMB_SPIN) {
+              // out_sigma = sum_k phase_k * sum_s' B_k[sigma][s'] v_k,s'  (A side)
+              //           = sum_k conj(phase_k) * sum_s' conj(B_k[s'][sigma]) v_k,s'  (B side)
+#pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                T br = 0, bi = 0;
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                  T er, ei;
+                  if (s == 0) {
+                    er = L.blk[k][2 * (sp * 2 + s2)];
+                    ei = L.blk[k][2 * (sp * 2 + s2) + 1];
+                  } else {
+                    er = L.blk[k][2 * (s2 * 2 + sp)];
+                    ei = -L.blk[k][2 * (s2 * 2 + sp) + 1];
+                  }
+                  cmul_acc(br, bi, er, ei, vn[k][s2].v[2 * j], vn[k][s2].v[2 * j + 1]);
+                }
+                if constexpr (PHASE) {
+                  cmul_acc(hr, hi, hre[k], him[k], br, bi);
+                } else {
+                  hr += br;
+                  hi += bi;
+                }
+              }
+            } else {
+              if constexpr (PHASE) {
+#pragma unroll
+                for (int k = 0; k < NNB; ++k)
+                  cmul_acc(hr, hi, hre[k], him[k], vn[k][0].v[2 * j], vn[k][0].v[2 * j + 1]);
+              } else {
+                T sr = 0, si = 0;
+#pragma unroll
+                for (int k = 0; k < NNB; ++k) {
+                  sr += vn[k][0].v[2 * j];
+                  si += vn[k][0].v[2 * j + 1];
+                }
+                hr += L.hop * sr;
+                hi += L.hop * si;
+              }
+            }
+            T orr = A.a * hr, oi = A.a * hi;
+            if (A.read_w) {
+              orr -= A.b * wo[sp].v[2 * j];
+              oi -= A.b * wo[sp].v[2 * j + 1];
+            }
+            if (!alive) { orr = 0; oi = 0; }
+            out[sp].v[2 * j] = orr;
+            out[sp].v[2 * j + 1] = oi;
+            const double xr = (double)vo[sp].v[2 * j], xi = (double)vo[sp].v[2 * j + 1];
+            vv[j] += xr * xr + xi * xi;
+            wv[j] += (double)orr * xr + (double)oi * xi;
+          }
+          *reinterpret_cast<P*>(wb + (site * NSPIN + sp) * Rp * 2 + coff) = out[sp];
+        }
+      }
+    }
+    // Flush the accumulators when the next tile of this workgroup belongs to
+    // another moment slot (another lattice / r-group) or this was the last.
+    const int tn = ti + gx;
+    const int slot = A.slot_of[ti];
+    if (tn >= t_end || A.slot_of[tn] != slot) {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        lds[tid * 2 * NC + 2 * j] = vv[j];
+        lds[tid * 2 * NC + 2 * j + 1] = wv[j];
+        vv[j] = wv[j] = 0.0;
+      }
+      __syncthreads();
+      int p2 = 1;
+      while (p2 < n_grp) p2 <<= 1;
+      for (int st = p2 >> 1; st > 0; st >>= 1) {
+        if (grp < st && grp + st < n_grp) {
+#pragma unroll
+          for (int q = 0; q < 2 * NC; ++q) lds[tid * 2 * NC + q] += lds[(tid + st * Ew) * 2 * NC + q];
+        }
+        __syncthreads();
+      }
+      if (tid < Ew) {
+        double* dst = A.part + ((int64_t)slot * Ew * NC + tid * NC) * 2;
+#pragma unroll
+        for (int q = 0; q < 2 * NC; ++q) dst[q] = lds[tid * 2 * NC + q];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Model build: Anderson potential, vacancy mask, active-orbital count.
+// ---------------------------------------------------------------------------
+struct ModelLat {
+  int64_t site_off, n_sites;
+  double W, p, de_p, de_m;
+  uint64_t key_anderson, key_vacancy;
+  int n_spin;
+};
+
+template <typename T>
+__global__ void model_kernel(const ModelLat* ml, int lat, T* onsite, uint8_t* mask,
+                             unsigned long long* active) {
+  const ModelLat m = ml[lat];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool alive = true;
+  if (i < m.n_sites) {
+    double V = 0.0;
+    if (m.W != 0.0) V = m.W * (sm_uniform(m.key_anderson, (uint64_t)i) - 0.5);
+    if (m.p > 0.0) alive = !(sm_uniform(m.key_vacancy, (uint64_t)i) < m.p);
+    if (onsite) onsite[m.site_off + i] = (T)((V - m.de_p) / m.de_m);
+    if (mask) mask[m.site_off + i] = alive ? 1 : 0;
+  }
+  // Count active orbitals: wave-level ballot, one atomic per wave.
+  const bool contrib = (i < m.n_sites) && alive;
+  const unsigned long long bal = __ballot(contrib);
+  if ((threadIdx.x & 63) == 0 && bal) atomicAdd(active + lat, (unsigned long long)__popcll(bal) * m.n_spin);
+}
+
+__global__ void zero_u64(unsigned long long* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+// Peierls table: theta_k(n1) = 2 pi flux (s1_A + s1_B')/2 (s2_A - s2_B') for the
+// hop B' -> A with B' = A + d_k unwrapped (fractional coordinates).
+struct PhaseLat {
+  int64_t off;
+  int L1;
+  double flux;
+  double fA0, fA1, fB0, fB1;
+};
+
+template <typename T>
+__global__ void phase_kernel(const PhaseLat* pl, int lat, T* phase) {
+  const PhaseLat q = pl[lat];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= q.L1 * 3) return;
+  const int n1 = i / 3, k = i % 3;
+  const int d1 = (k == 1) ? 1 : 0;
+  const int d2 = (k == 0) ? 0 : -1;
+  const double s1a = n1 + q.fA0, s2a = q.fA1;
+  const double s1b = n1 + d1 + q.fB0, s2b = d2 + q.fB1;
+  const double th = 2.0 * M_PI * q.flux * 0.5 * (s1a + s1b) * (s2a - s2b);
+  phase[2 * (q.off + i)] = (T)cos(th);
+  phase[2 * (q.off + i) + 1] = (T)sin(th);
+}
+
+// Start vectors: random phases exp(2 pi i u) (FP64, rounded once), zero on
+// vacant sites and on padded vectors.
+template <typename T>
+__global__ void start_phase_kernel(T* x, int64_t vec_off, int64_t n_orb, int n_spin, int R, int Rp,
+                                   const uint64_t* keys, const uint8_t* mask, int64_t site_off) {
+  using P = Pack<T>;
+  constexpr int NC = P::NC;
+  const int E = Rp / NC;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_orb * E) return;
+  const int64_t o = idx / E;
+  const int c = (int)(idx % E);
+  const bool alive = mask ? (mask[site_off + o / n_spin] != 0) : true;
+  P p;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int r = c * NC + j;
+    double cr = 0.0, ci = 0.0;
+    if (alive && r < R) {
+      const double u = sm_uniform(keys[r], (uint64_t)o);
+      sincospi(2.0 * u, &ci, &cr);
+    }
+    p.v[2 * j] = (T)cr;
+    p.v[2 * j + 1] = (T)ci;
+  }
+  *reinterpret_cast<P*>(x + vec_off + (o * Rp + (int64_t)c * NC) * 2) = p;
+}
+
+template <typename T>
+__global__ void fill_zero_kernel(T* x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = (T)0;
+}
+
+template <typename T>
+__global__ void start_sites_kernel(T* x, int64_t vec_off, const int64_t* sites, int R, int Rp) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  x[vec_off + (sites[r] * Rp + r) * 2] = (T)1;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reduction of moment slots: dots[lat][r][step][2].
+// grid = (steps in chunk, lattice*r-groups, ceil(2*Rw/64)), block = 1024:
+// lane -> output, 16 waves -> contiguous slot sub-ranges, fixed-order sums.
+// ---------------------------------------------------------------------------
+__global__ void reduce_slots_kernel(const double* part, int64_t part_step_stride, int Rw, const int2* ranges,
+                                    int n_rg, int Rp, int n_steps, int step0, double* dots) {
+  __shared__ double red[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sc = blockIdx.x;                 // step within the chunk
+  const int lr = blockIdx.y;
+  const int o = blockIdx.z * 64 + lane;      // output index within (r_local, q)
+  const int2 rg = ranges[lr];
+  const double* pb = part + (int64_t)sc * part_step_stride;
+  double acc = 0.0;
+  if (o < 2 * Rw) {
+    const int per = (rg.y + 15) / 16;
+    const int b = rg.x + wave * per;
+    const int e = min(rg.x + rg.y, b + per);
+    for (int sl = b; sl < e; ++sl) acc += pb[(int64_t)sl * 2 * Rw + o];
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && o < 2 * Rw) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += red[k][lane];
+    const int lat = lr / n_rg, g = lr % n_rg;
+    const int r = g * Rw + o / 2, q = o & 1;
+    if (r < Rp) dots[(((int64_t)lat * Rp + r) * n_steps + step0 + sc) * 2 + q] = s;
+  }
+}
+
+// mu_0 = <v0|v0>/norm, mu_1 = <v1|v0>/norm, mu_2k = 2<vk|vk>/norm - mu_0,
+// mu_2k+1 = 2<vk+1|vk>/norm - mu_1.
+__global__ void finish_kernel(const double* dots, int n_lat, int R, int Rp, int n_steps, int M,
+                              const unsigned long long* active, int ldos, double* mu, int* flag) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_lat * R * M) return;
+  const int n = (int)(idx % M);
+  const int64_t lr = idx / M;
+  const int r = (int)(lr % R);
+  const int lat = (int)(lr / R);
+  const double norm = ldos ? 1.0 : (double)active[lat];
+  const double* d = dots + ((int64_t)lat * Rp + r) * n_steps * 2;
+  const double mu0 = d[0] / norm, mu1 = d[1] / norm;
+  double val;
+  const int k = n >> 1;
+  if (n == 0) val = mu0;
+  else if (n == 1) val = mu1;
+  else if ((n & 1) == 0) val = 2.0 * d[2 * k] / norm - mu0;
+  else val = 2.0 * d[2 * k + 1] / norm - mu1;
+  mu[idx] = val;
+  if (!(fabs(val) <= 1.0 + 1e-6)) atomicMax(flag, n + 1);
+}
+
+__global__ void mean_kernel(const double* mu, int n_lat, int R, int M, double* mean) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_lat * M) return;
+  const int n = (int)(idx % M);
+  const int lat = (int)(idx / M);
+  double s = 0.0;
+  for (int r = 0; r < R; ++r) s += mu[((int64_t)lat * R + r) * M + n];
+  mean[idx] = s / R;
+}
+
+__global__ void zero_int(int* p) { *p = 0; }
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+static void* pick_step(bool onsite, bool mask, bool phase) {
+  const int k = (onsite ? 4 : 0) | (mask ? 2 : 0) | (phase ? 1 : 0);
+  switch (k) {
+    case 0: return (void*)step_kernel<T, KIND, false, false, false>;
+    case 1: return (void*)step_kernel<T, KIND, false, false, true>;
+    case 2: return (void*)step_kernel<T, KIND, false, true, false>;
+    case 3: return (void*)step_kernel<T, KIND, false, true, true>;
+    case 4: return (void*)step_kernel<T, KIND, true, false, false>;
+    case 5: return (void*)step_kernel<T, KIND, true, false, true>;
+    case 6: return (void*)step_kernel<T, KIND, true, true, false>;
+    default: return (void*)step_kernel<T, KIND, true, true, true>;
+  }
+}
+
+template <typename T>
+static void* pick_step_kind(int kind, bool onsite, bool mask, bool phase) {
+  if (kind == KPM_HONEYCOMB) return pick_step<T, KPM_HONEYCOMB>(onsite, mask, phase);
+  if (kind == KPM_HONEYCOMB_SPIN) return pick_step<T, KPM_HONEYCOMB_SPIN>(onsite, mask, phase);
+  return pick_step<T, KPM_SQUARE>(onsite, mask, false);
+}
+
+}  // namespace kpm
+
+struct kpm_plan {
+  std::vector<kpm_lattice_t> lats;
+  kpm_dos_params_t p;
+  std::vector<int64_t> sites;
+  int n_lat = 0, kind = 0, prec = 0, n_sub = 0, n_spin = 0;
+  int M = 0, R = 0, Rp = 0, NC = 0, E = 0, Ew = 0, n_rg = 0, Tx = 0, Ty = 0, block = 0, grid = 0;
+  int n_steps = 0, n_tiles = 0, n_slots = 0, steps_per_chunk = 0;
+  bool has_onsite = false, has_mask = false, has_phase = false, use_graph = true;
+  int64_t n_orb = 0, n_sites = 0, n_phase = 0;
+  std::vector<int64_t> site_off, vec_off, phase_off;
+  size_t tsize = 0;
+  // device memory
+  void* X = nullptr;
+  void* Y = nullptr;
+  void* onsite = nullptr;
+  uint8_t* mask = nullptr;
+  void* phase = nullptr;
+  void* latdev = nullptr;
+  int4* tiles = nullptr;
+  int* slot_of = nullptr;
+  int2* ranges = nullptr;
+  double* part = nullptr;
+  double* dots = nullptr;
+  uint64_t* keys = nullptr;
+  int64_t* d_sites = nullptr;
+  unsigned long long* active = nullptr;
+  kpm::ModelLat* mlat = nullptr;
+  kpm::PhaseLat* plat = nullptr;
+  int* flag = nullptr;
+  double* mu_dev = nullptr;
+  double* mean_dev = nullptr;
+  void* step_fn = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_loop = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
+  double bytes_per_step = 0.0;
+  int64_t n_active_total = 0;
+};
+
+namespace kpm {
+
+static int validate_lattice(const kpm_lattice_t& L, int idx) {
+  KPM_CHECK_ARG(L.kind == KPM_HONEYCOMB || L.kind == KPM_HONEYCOMB_SPIN || L.kind == KPM_SQUARE,
+                "lattice %d: unknown kind %d", idx, L.kind);
+  KPM_CHECK_ARG(L.L1 >= 2 && L.L2 >= 2, "lattice %d: L1, L2 must be >= 2 (got %d, %d)", idx, L.L1, L.L2);
+  KPM_CHECK_ARG(std::isfinite(L.e_min) && std::isfinite(L.e_max) && L.e_min < L.e_max,
+                "lattice %d: need e_min < e_max", idx);
+  KPM_CHECK_ARG(std::isfinite(L.t), "lattice %d: t must be finite", idx);
+  KPM_CHECK_ARG(L.anderson_w >= 0.0 && std::isfinite(L.anderson_w), "lattice %d: anderson_w must be >= 0", idx);
+  KPM_CHECK_ARG(L.vacancy_p >= 0.0 && L.vacancy_p < 1.0, "lattice %d: vacancy_p must be in [0, 1)", idx);
+  KPM_CHECK_ARG(L.rashba == 0.0 || L.kind == KPM_HONEYCOMB_SPIN,
+                "lattice %d: Rashba coupling needs KPM_HONEYCOMB_SPIN", idx);
+  if (L.flux != 0.0) {
+    KPM_CHECK_ARG(L.kind != KPM_SQUARE, "lattice %d: flux on the square lattice is not supported", idx);
+    const double q = L.flux * L.L1;
+    KPM_CHECK_ARG(std::fabs(q - std::round(q)) < 1e-9, "lattice %d: flux*L1 must be an integer (got %.12g)", idx, q);
+  }
+  // Bounds that are too tight are detected from the moments themselves
+  // (|mu_n| <= 1 must hold when the rescaled spectrum lies in [-1, 1]).
+  return KPM_OK;
+}
+
+template <typename T>
+static void fill_latdev(kpm_plan* P, std::vector<LatDev<T>>& out) {
+  const Geometry g = honeycomb_geometry();
+  out.resize(P->n_lat);
+  for (int l = 0; l < P->n_lat; ++l) {
+    const kpm_lattice_t& L = P->lats[l];
+    const double de_p = 0.5 * (L.e_max + L.e_min), de_m = 0.5 * (L.e_max - L.e_min);
+    LatDev<T>& d = out[l];
+    std::memset(&d, 0, sizeof(d));
+    d.L1 = L.L1;
+    d.L2 = L.L2;
+    d.site_off = P->site_off[l];
+    d.vec_off = P->vec_off[l];
+    d.phase_off = P->phase_off[l];
+    d.onsite_const = (T)(-de_p / de_m);
+    d.hop = (T)(L.t / de_m);
+    if (L.kind == KPM_HONEYCOMB_SPIN) {
+      typedef std::complex<double> cd;
+      const cd I(0.0, 1.0);
+      const cd sx[2][2] = {{0.0, 1.0}, {1.0, 0.0}};
+      const cd sy[2][2] = {{0.0, -I}, {I, 0.0}};
+      for (int k = 0; k < 3; ++k) {
+        // Bond vector from B' = B(n + d_k) to A(n) (the hop j -> i with i = A).
+        double dv[2];
+        for (int ax = 0; ax < 2; ++ax)
+          dv[ax] = g.tauA[ax] - (kBondD1[k] * g.a1[ax] + kBondD2[k] * g.a2[ax] + g.tauB[ax]);
+        const double nrm = std::sqrt(dv[0] * dv[0] + dv[1] * dv[1]);
+        const double dx = dv[0] / nrm, dy = dv[1] / nrm;
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b) {
+            cd e = (a == b ? cd(L.t, 0.0) : cd(0.0, 0.0)) +
+                   (2.0 * I / 3.0) * L.rashba * (sx[a][b] * dy - sy[a][b] * dx);
+            e /= de_m;
+            d.blk[k][2 * (a * 2 + b)] = (T)e.real();
+            d.blk[k][2 * (a * 2 + b) + 1] = (T)e.imag();
+          }
+      }
+    }
+  }
+}
+
+static int plan_alloc(kpm_plan* P, void** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? KPM_E_NOMEM : KPM_E_DEVICE;
+  }
+  return KPM_OK;
+}
+
+static void plan_free(kpm_plan* P) {
+  void* bufs[] = {P->X, P->Y, P->onsite, P->mask, P->phase, P->latdev, P->tiles, P->slot_of, P->ranges,
+                  P->part, P->dots, P->keys, P->d_sites, P->active, P->mlat, P->plat, P->flag,
+                  P->mu_dev, P->mean_dev};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (P->graph_loop) (void)hipGraphExecDestroy(P->graph_loop);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  for (auto& e : P->ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+static int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
+                       const kpm_tune_t* tune, kpm_plan** out) {
+  KPM_CHECK_ARG(out != nullptr, "plan output pointer is NULL");
+  *out = nullptr;
+  KPM_CHECK_ARG(lat != nullptr && n_lat >= 1, "need at least one lattice");
+  KPM_CHECK_ARG(p != nullptr, "params is NULL");
+  KPM_CHECK_ARG(p->num_moments >= 2, "num_moments must be >= 2");
+  KPM_CHECK_ARG(p->precision == KPM_FP32 || p->precision == KPM_FP64, "precision must be KPM_FP32 or KPM_FP64");
+  KPM_CHECK_ARG(p->start == KPM_START_RANDOM_PHASE || p->start == KPM_START_SITES, "unknown start kind");
+  for (int l = 0; l < n_lat; ++l) KPM_TRY(validate_lattice(lat[l], l));
+  for (int l = 1; l < n_lat; ++l)
+    KPM_CHECK_ARG(lat[l].kind == lat[0].kind, "all lattices of a batch must have the same kind");
+  int R;
+  if (p->start == KPM_START_SITES) {
+    KPM_CHECK_ARG(p->sites != nullptr && p->num_sites >= 1, "KPM_START_SITES needs sites");
+    R = p->num_sites;
+  } else {
+    KPM_CHECK_ARG(p->num_random >= 1, "num_random must be >= 1");
+    R = p->num_random;
+  }
+  kpm_plan* P = new kpm_plan();
+  P->lats.assign(lat, lat + n_lat);
+  P->p = *p;
+  if (p->start == KPM_START_SITES) P->sites.assign(p->sites, p->sites + p->num_sites);
+  P->p.sites = nullptr;
+  P->n_lat = n_lat;
+  P->kind = lat[0].kind;
+  P->prec = p->precision;
+  P->n_sub = (P->kind == KPM_SQUARE) ? 1 : 2;
+  P->n_spin = (P->kind == KPM_HONEYCOMB_SPIN) ? 2 : 1;
+  P->M = p->num_moments;
+  P->R = R;
+  P->tsize = (P->prec == KPM_FP32) ? 4 : 8;
+  P->NC = (P->prec == KPM_FP32) ? 2 : 1;
+  P->Rp = (int)ceil_div(R, P->NC) * P->NC;
+  P->E = P->Rp / P->NC;
+  P->n_steps = (P->M + 1) / 2;
+
+  // Per-lattice offsets and which optional arrays are needed.
+  int64_t so = 0, po = 0;
+  for (int l = 0; l < n_lat; ++l) {
+    const kpm_lattice_t& L = lat[l];
+    const int64_t ns = (int64_t)L.L1 * L.L2 * P->n_sub;
+    P->site_off.push_back(so);
+    P->vec_off.push_back(so * P->n_spin * P->Rp * 2);
+    P->phase_off.push_back(L.flux != 0.0 ? po : 0);
+    if (L.flux != 0.0) po += (int64_t)L.L1 * 3;
+    so += ns;
+    if (L.anderson_w != 0.0) P->has_onsite = true;
+    if (L.vacancy_p > 0.0) P->has_mask = true;
+    if (L.flux != 0.0) P->has_phase = true;
+  }
+  P->n_sites = so;
+  P->n_orb = so * P->n_spin;
+  P->n_phase = po;
+  // A lattice without its own table in a batch that needs one gets a table of
+  // flux 0 (all phases 1).
+  if (P->has_phase) {
+    for (int l = 0; l < n_lat; ++l)
+      if (lat[l].flux == 0.0) {
+        P->phase_off[l] = P->n_phase;
+        P->n_phase += (int64_t)lat[l].L1 * 3;
+      }
+  }
+
+  // LDOS sites: range and vacancy checks on the host with the same generator.
+  if (p->start == KPM_START_SITES) {
+    for (int l = 0; l < n_lat; ++l) {
+      const int64_t norb = (int64_t)lat[l].L1 * lat[l].L2 * P->n_sub * P->n_spin;
+      const uint64_t kv = sm_key(kPurposeVacancy, lat[l].disorder_seed, 0, 0);
+      for (int r = 0; r < R; ++r) {
+        const int64_t o = P->sites[r];
+        if (o < 0 || o >= norb) {
+          set_error("LDOS site %lld out of range [0, %lld) for lattice %d", (long long)o, (long long)norb, l);
+          delete P;
+          return KPM_E_INVALID;
+        }
+        if (lat[l].vacancy_p > 0.0 && sm_uniform(kv, (uint64_t)(o / P->n_spin)) < lat[l].vacancy_p) {
+          set_error("LDOS site %lld of lattice %d is vacant", (long long)o, l);
+          delete P;
+          return KPM_E_INVALID;
+        }
+      }
+    }
+  }
+
+  // Launch shape.
+  P->block = (tune && tune->block > 0) ? tune->block : 256;
+  P->Ty = (tune && tune->rows > 0) ? tune->rows : 64;
+  P->use_graph = tune ? (tune->use_graph != 0) : true;
+  if (P->block < 64 || P->block > 1024 || (P->block % 64) != 0) {
+    set_error("block must be a multiple of 64 in [64, 1024]");
+    delete P;
+    return KPM_E_INVALID;
+  }
+  P->Ew = (int)std::min<int64_t>(P->E, std::max(1, P->block / P->n_sub));
+  P->n_rg = (int)ceil_div(P->E, P->Ew);
+  P->Tx = std::max(1, P->block / (P->n_sub * P->Ew));
+  if (!(tune && tune->rows > 0)) {
+    // Default rows per tile: the largest power of two <= 64 that still gives
+    // at least 2048 tiles (8 per CU), so that small lattices fill the chip.
+    int64_t cols = 0;
+    for (int l = 0; l < n_lat; ++l) cols += ceil_div(lat[l].L1, P->Tx) * P->n_rg;
+    int ty = 64;
+    while (ty > 1) {
+      int64_t nt = 0;
+      for (int l = 0; l < n_lat; ++l) nt += ceil_div(lat[l].L1, P->Tx) * P->n_rg * ceil_div(lat[l].L2, ty);
+      if (nt >= 2048) break;
+      ty >>= 1;
+    }
+    (void)cols;
+    P->Ty = ty;
+  }
+
+  // Tile work list ordered (lattice, r-group, row band, column band).
+  std::vector<int4> tiles;
+  for (int l = 0; l < n_lat; ++l)
+    for (int g = 0; g < P->n_rg; ++g)
+      for (int y0 = 0; y0 < lat[l].L2; y0 += P->Ty)
+        for (int x0 = 0; x0 < lat[l].L1; x0 += P->Tx) tiles.push_back(make_int4(l, g, x0, y0));
+  P->n_tiles = (int)tiles.size();
+  // Default: a persistent grid of at most 2048 workgroups (8 per CU).
+  int grid = (tune && tune->grid > 0) ? tune->grid : (int)std::min<int64_t>(2048, ceil_div(P->n_tiles, 8) * 8);
+  if (grid % 8 != 0 || grid < 8) {
+    set_error("grid must be a positive multiple of 8");
+    delete P;
+    return KPM_E_INVALID;
+  }
+  P->grid = grid;
+  // Moment slots: walk each workgroup's static tile sequence; a new slot opens
+  // whenever the (lattice, r-group) changes.  Slots are numbered so that those
+  // of one (lattice, r-group) are contiguous.
+  struct SlotKey { int lr, wg, seq; };
+  std::vector<SlotKey> keys_list;
+  std::vector<int> tile_slot_tmp(P->n_tiles, -1);
+  const int gx = grid / 8;
+  for (int b = 0; b < grid; ++b) {
+    const int x = b & 7, j = b >> 3;
+    const int tb = (int)(((int64_t)x * P->n_tiles) >> 3), te = (int)(((int64_t)(x + 1) * P->n_tiles) >> 3);
+    int prev_lr = -1, seq = 0, cur = -1;
+    for (int ti = tb + j; ti < te; ti += gx) {
+      const int lr = tiles[ti].x * P->n_rg + tiles[ti].y;
+      if (lr != prev_lr) {
+        cur = (int)keys_list.size();
+        keys_list.push_back({lr, b, seq++});
+        prev_lr = lr;
+      }
+      tile_slot_tmp[ti] = cur;
+    }
+  }
+  std::vector<int> order(keys_list.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (keys_list[a].lr != keys_list[b].lr) return keys_list[a].lr < keys_list[b].lr;
+    if (keys_list[a].wg != keys_list[b].wg) return keys_list[a].wg < keys_list[b].wg;
+    return keys_list[a].seq < keys_list[b].seq;
+  });
+  std::vector<int> new_id(order.size());
+  for (size_t i = 0; i < order.size(); ++i) new_id[order[i]] = (int)i;
+  std::vector<int> slot_of(P->n_tiles);
+  for (int ti = 0; ti < P->n_tiles; ++ti) slot_of[ti] = new_id[tile_slot_tmp[ti]];
+  P->n_slots = (int)order.size();
+  std::vector<int2> ranges(n_lat * P->n_rg, make_int2(0, 0));
+  for (size_t i = 0; i < order.size(); ++i) {
+    const int lr = keys_list[order[i]].lr;
+    if (ranges[lr].y == 0) ranges[lr].x = (int)i;
+    ranges[lr].y++;
+  }
+  const int Rw = P->Ew * P->NC;
+  const double part_step_bytes = (double)P->n_slots * Rw * 2 * 8;
+  const double budget = 2.0e9;
+  P->steps_per_chunk = (int)std::max<double>(1.0, std::min<double>(P->n_steps, std::floor(budget / part_step_bytes)));
+
+  // Algorithmic bytes per step: read v_n and v_{n-1}, write v_{n+1}, per-site arrays.
+  P->bytes_per_step = 3.0 * (double)P->n_orb * P->Rp * 2 * P->tsize +
+                      (P->has_onsite ? (double)P->n_sites * P->tsize : 0.0) + (P->has_mask ? (double)P->n_sites : 0.0);
+
+  // Device allocations.
+  const size_t vec_bytes = (size_t)P->n_orb * P->Rp * 2 * P->tsize;
+  int st = KPM_OK;
+  auto A = [&](void** ptr, size_t bytes) {
+    if (st == KPM_OK) st = plan_alloc(P, ptr, bytes);
+  };
+  A(&P->X, vec_bytes);
+  A(&P->Y, vec_bytes);
+  if (P->has_onsite) A(&P->onsite, (size_t)P->n_sites * P->tsize);
+  if (P->has_mask) A((void**)&P->mask, (size_t)P->n_sites);
+  if (P->has_phase) A(&P->phase, (size_t)P->n_phase * 2 * P->tsize);
+  A(&P->latdev, (size_t)n_lat * (P->prec == KPM_FP32 ? sizeof(LatDev<float>) : sizeof(LatDev<double>)));
+  A((void**)&P->tiles, tiles.size() * sizeof(int4));
+  A((void**)&P->slot_of, slot_of.size() * sizeof(int));
+  A((void**)&P->ranges, ranges.size() * sizeof(int2));
+  A((void**)&P->part, (size_t)part_step_bytes * P->steps_per_chunk);
+  A((void**)&P->dots, (size_t)n_lat * P->Rp * P->n_steps * 2 * sizeof(double));
+  A((void**)&P->keys, (size_t)n_lat * P->Rp * sizeof(uint64_t));
+  if (!P->sites.empty()) A((void**)&P->d_sites, P->sites.size() * sizeof(int64_t));
+  A((void**)&P->active, (size_t)n_lat * sizeof(unsigned long long));
+  A((void**)&P->mlat, (size_t)n_lat * sizeof(ModelLat));
+  A((void**)&P->plat, (size_t)n_lat * sizeof(PhaseLat));
+  A((void**)&P->flag, sizeof(int));
+  A((void**)&P->mu_dev, (size_t)n_lat * R * P->M * sizeof(double));
+  A((void**)&P->mean_dev, (size_t)n_lat * P->M * sizeof(double));
+  if (st != KPM_OK) {
+    plan_free(P);
+    delete P;
+    return st;
+  }
+
+  // Host-built tables.
+  std::vector<uint64_t> keys((size_t)n_lat * P->Rp, 0);
+  for (int l = 0; l < n_lat; ++l)
+    for (int r = 0; r < P->Rp; ++r) keys[(size_t)l * P->Rp + r] = sm_key(kPurposePhase, p->vector_seed, l, r);
+  std::vector<ModelLat> ml(n_lat);
+  std::vector<PhaseLat> pl(n_lat);
+  const Geometry g = honeycomb_geometry();
+  for (int l = 0; l < n_lat; ++l) {
+    const kpm_lattice_t& L = lat[l];
+    ml[l].site_off = P->site_off[l];
+    ml[l].n_sites = (int64_t)L.L1 * L.L2 * P->n_sub;
+    ml[l].W = L.anderson_w;
+    ml[l].p = L.vacancy_p;
+    ml[l].de_p = 0.5 * (L.e_max + L.e_min);
+    ml[l].de_m = 0.5 * (L.e_max - L.e_min);
+    ml[l].key_anderson = sm_key(kPurposeAnderson, L.disorder_seed, 0, 0);
+    ml[l].key_vacancy = sm_key(kPurposeVacancy, L.disorder_seed, 0, 0);
+    ml[l].n_spin = P->n_spin;
+    pl[l].off = P->phase_off[l];
+    pl[l].L1 = L.L1;
+    pl[l].flux = L.flux;
+    pl[l].fA0 = g.fA[0];
+    pl[l].fA1 = g.fA[1];
+    pl[l].fB0 = g.fB[0];
+    pl[l].fB1 = g.fB[1];
+  }
+  hipError_t e = hipSuccess;
+  auto H2D = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  if (P->prec == KPM_FP32) {
+    std::vector<LatDev<float>> ld;
+    fill_latdev<float>(P, ld);
+    H2D(P->latdev, ld.data(), ld.size() * sizeof(ld[0]));
+  } else {
+    std::vector<LatDev<double>> ld;
+    fill_latdev<double>(P, ld);
+    H2D(P->latdev, ld.data(), ld.size() * sizeof(ld[0]));
+  }
+  H2D(P->tiles, tiles.data(), tiles.size() * sizeof(int4));
+  H2D(P->slot_of, slot_of.data(), slot_of.size() * sizeof(int));
+  H2D(P->ranges, ranges.data(), ranges.size() * sizeof(int2));
+  H2D(P->keys, keys.data(), keys.size() * sizeof(uint64_t));
+  if (!P->sites.empty()) H2D(P->d_sites, P->sites.data(), P->sites.size() * sizeof(int64_t));
+  H2D(P->mlat, ml.data(), ml.size() * sizeof(ModelLat));
+  H2D(P->plat, pl.data(), pl.size() * sizeof(PhaseLat));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+  for (auto& ev : P->ev)
+    if (e == hipSuccess) e = hipEventCreate(&ev);
+  if (e != hipSuccess) {
+    set_error("plan setup failed: %s", hipGetErrorString(e));
+    plan_free(P);
+    delete P;
+    return KPM_E_DEVICE;
+  }
+  P->step_fn = (P->prec == KPM_FP32) ? pick_step_kind<float>(P->kind, P->has_onsite, P->has_mask, P->has_phase)
+                                     : pick_step_kind<double>(P->kind, P->has_onsite, P->has_mask, P->has_phase);
+  *out = P;
+  return KPM_OK;
+}
+
+template <typename T>
+static hipError_t launch_prep(kpm_plan* P, hipStream_t s) {
+  T* X = (T*)P->X;
+  hipLaunchKernelGGL(zero_u64, dim3(ceil_div(P->n_lat, 256)), dim3(256), 0, s, P->active, P->n_lat);
+  for (int l = 0; l < P->n_lat; ++l) {
+    const kpm_lattice_t& L = P->lats[l];
+    const int64_t ns = (int64_t)L.L1 * L.L2 * P->n_sub;
+    hipLaunchKernelGGL(model_kernel<T>, dim3(ceil_div(ns, 256)), dim3(256), 0, s, P->mlat, l, (T*)P->onsite,
+                       P->mask, P->active);
+    if (P->has_phase)
+      hipLaunchKernelGGL(phase_kernel<T>, dim3(ceil_div((int64_t)L.L1 * 3, 256)), dim3(256), 0, s, P->plat, l,
+                         (T*)P->phase);
+    const int64_t norb = ns * P->n_spin;
+    if (P->p.start == KPM_START_RANDOM_PHASE) {
+      hipLaunchKernelGGL(start_phase_kernel<T>, dim3(ceil_div(norb * P->E, 256)), dim3(256), 0, s, X,
+                         P->vec_off[l], norb, P->n_spin, P->R, P->Rp, P->keys + (size_t)l * P->Rp, P->mask,
+                         P->site_off[l]);
+    } else {
+      const int64_t n = norb * P->Rp * 2;
+      hipLaunchKernelGGL(fill_zero_kernel<T>, dim3(ceil_div(n, 256)), dim3(256), 0, s, X + P->vec_off[l], n);
+      hipLaunchKernelGGL(start_sites_kernel<T>, dim3(ceil_div(P->R, 256)), dim3(256), 0, s, X, P->vec_off[l],
+                         P->d_sites, P->R, P->Rp);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_loop(kpm_plan* P, hipStream_t s) {
+  StepArgs<T> a;
+  a.lats = (const LatDev<T>*)P->latdev;
+  a.tiles = P->tiles;
+  a.slot_of = P->slot_of;
+  a.n_tiles = P->n_tiles;
+  a.onsite = (const T*)P->onsite;
+  a.mask = P->mask;
+  a.phase = (const T*)P->phase;
+  a.Tx = P->Tx;
+  a.Ty = P->Ty;
+  a.E = P->E;
+  a.Ew = P->Ew;
+  a.Rp = P->Rp;
+  const int Rw = P->Ew * P->NC;
+  const int64_t part_stride = (int64_t)P->n_slots * Rw * 2;
+  const size_t lds = (size_t)P->block * 2 * P->NC * sizeof(double);
+  void* args[] = {&a};
+  int chunk0 = 0;
+  for (int k = 0; k < P->n_steps; ++k) {
+    const bool odd = (k & 1) != 0;
+    a.v = (const T*)(odd ? P->Y : P->X);
+    a.w = (T*)(odd ? P->X : P->Y);
+    a.a = (k == 0) ? (T)1 : (T)2;
+    a.b = (k == 0) ? (T)0 : (T)1;
+    a.read_w = (k == 0) ? 0 : 1;
+    a.part = P->part + (int64_t)(k - chunk0) * part_stride;
+    hipError_t le = hipLaunchKernel(P->step_fn, dim3(P->grid), dim3(P->block), args, lds, s);
+    if (le != hipSuccess) return le;
+    if (k - chunk0 + 1 == P->steps_per_chunk || k == P->n_steps - 1) {
+      const int nsc = k - chunk0 + 1;
+      hipLaunchKernelGGL(reduce_slots_kernel, dim3(nsc, P->n_lat * P->n_rg, (unsigned)ceil_div(2 * Rw, 64)),
+                         dim3(1024), 0, s, P->part, part_stride, Rw, P->ranges, P->n_rg, P->Rp, P->n_steps, chunk0,
+                         P->dots);
+      chunk0 = k + 1;
+    }
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_finish(kpm_plan* P, hipStream_t s) {
+  hipLaunchKernelGGL(zero_int, dim3(1), dim3(1), 0, s, P->flag);
+  const int64_t n = (int64_t)P->n_lat * P->R * P->M;
+  hipLaunchKernelGGL(finish_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, P->dots, P->n_lat, P->R, P->Rp,
+                     P->n_steps, P->M, P->active, P->p.start == KPM_START_SITES ? 1 : 0, P->mu_dev, P->flag);
+  hipLaunchKernelGGL(mean_kernel, dim3(ceil_div((int64_t)P->n_lat * P->M, 256)), dim3(256), 0, s, P->mu_dev,
+                     P->n_lat, P->R, P->M, P->mean_dev);
+  return hipGetLastError();
+}
+
+static int plan_run(kpm_plan* P, double* mu_pv, double* mu_mean, int32_t on_dev, void* stream) {
+  KPM_CHECK_ARG(P != nullptr, "plan is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const bool f32 = P->prec == KPM_FP32;
+  KPM_TRY_HIP(hipEventRecord(P->ev[0], s));
+  KPM_TRY_HIP(f32 ? launch_prep<float>(P, s) : launch_prep<double>(P, s));
+  KPM_TRY_HIP(hipEventRecord(P->ev[1], s));
+  if (P->use_graph) {
+    if (!P->graph_loop) {
+      // Capture the step loop once on the plan's private stream.
+      hipGraph_t g = nullptr;
+      KPM_TRY_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t le = f32 ? launch_loop<float>(P, P->cap_stream) : launch_loop<double>(P, P->cap_stream);
+      hipError_t ce = hipStreamEndCapture(P->cap_stream, &g);
+      if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        set_error("graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));
+        return KPM_E_DEVICE;
+      }
+      hipError_t ie = hipGraphInstantiate(&P->graph_loop, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        P->graph_loop = nullptr;
+        set_error("graph instantiate failed: %s", hipGetErrorString(ie));
+        return KPM_E_DEVICE;
+      }
+    }
+    KPM_TRY_HIP(hipGraphLaunch(P->graph_loop, s));
+  } else {
+    KPM_TRY_HIP(f32 ? launch_loop<float>(P, s) : launch_loop<double>(P, s));
+  }
+  KPM_TRY_HIP(hipEventRecord(P->ev[2], s));
+  KPM_TRY_HIP(launch_finish(P, s));
+  const size_t mu_bytes = (size_t)P->n_lat * P->R * P->M * sizeof(double);
+  const size_t mean_bytes = (size_t)P->n_lat * P->M * sizeof(double);
+  const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (mu_pv) KPM_TRY_HIP(hipMemcpyAsync(mu_pv, P->mu_dev, mu_bytes, kind, s));
+  if (mu_mean) KPM_TRY_HIP(hipMemcpyAsync(mu_mean, P->mean_dev, mean_bytes, kind, s));
+  KPM_TRY_HIP(hipEventRecord(P->ev[3], s));
+  P->timed = true;
+  // The spectrum check needs the flag on the host: synchronise on the run's end.
+  int flag = 0;
+  std::vector<unsigned long long> act(P->n_lat);
+  KPM_TRY_HIP(hipMemcpyAsync(&flag, P->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  KPM_TRY_HIP(hipMemcpyAsync(act.data(), P->active, act.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  KPM_TRY_HIP(hipStreamSynchronize(s));
+  P->n_active_total = 0;
+  for (auto a : act) P->n_active_total += (int64_t)a;
+  if (flag != 0) {
+    set_error("moment %d is non-finite or exceeds 1 + 1e-6 in magnitude: the spectrum bounds are too tight",
+              flag - 1);
+    return KPM_E_SPECTRUM;
+  }
+  return KPM_OK;
+}
+
+}  // namespace kpm
+
+extern "C" {
+
+int kpm_version(void) { return 1; }
+
+const char* kpm_last_error(void) { return kpm::g_err.c_str(); }
+
+int kpm_plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, const kpm_tune_t* tune,
+                    kpm_plan_t** plan) {
+  try {
+    kpm::clear_error();
+    return kpm::plan_create(lat, n_lat, p, tune, plan);
+  } catch (...) {
+    kpm::set_error("internal error (exception) in kpm_plan_create");
+    return KPM_E_DEVICE;
+  }
+}
+
+int kpm_plan_run(kpm_plan_t* plan, double* mu_per_vector, double* mu_mean, int32_t out_on_device, void* hip_stream) {
+  try {
+    kpm::clear_error();
+    return kpm::plan_run(plan, mu_per_vector, mu_mean, out_on_device, hip_stream);
+  } catch (...) {
+    kpm::set_error("internal error (exception) in kpm_plan_run");
+    return KPM_E_DEVICE;
+  }
+}
+
+int kpm_plan_info(kpm_plan_t* P, kpm_plan_info_t* info) {
+  KPM_CHECK_ARG(P != nullptr && info != nullptr, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n_steps = P->n_steps;
+  info->n_tiles = P->n_tiles;
+  info->grid = P->grid;
+  info->block = P->block;
+  info->rows = P->Ty;
+  info->tile_cells_x = P->Tx;
+  info->r_padded = P->Rp;
+  info->n_orbitals = P->n_orb;
+  info->bytes_per_step = P->bytes_per_step;
+  info->n_active_total = P->n_active_total;
+  if (P->timed) {
+    float ms = 0.f;
+    KPM_TRY_HIP(hipEventSynchronize(P->ev[3]));
+    KPM_TRY_HIP(hipEventElapsedTime(&ms, P->ev[1], P->ev[2]));
+    info->last_loop_ms = ms;
+    KPM_TRY_HIP(hipEventElapsedTime(&ms, P->ev[0], P->ev[3]));
+    info->last_run_ms = ms;
+  }
+  return KPM_OK;
+}
+
+int kpm_plan_destroy(kpm_plan_t* plan) {
+  if (!plan) return KPM_OK;
+  kpm::plan_free(plan);
+  delete plan;
+  return KPM_OK;
+}
+
+int kpm_moments_dos(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, double* mu_per_vector,
+                    double* mu_mean, int32_t out_on_device, void* hip_stream) {
+  kpm_plan_t* plan = nullptr;
+  kpm_tune_t tune;
+  std::memset(&tune, 0, sizeof(tune));
+  tune.use_graph = 0;   // a one-shot run gains nothing from capturing the loop
+  int st = kpm_plan_create(lat, n_lat, p, &tune, &plan);
+  if (st != KPM_OK) return st;
+  st = kpm_plan_run(plan, mu_per_vector, mu_mean, out_on_device, hip_stream);
+  std::string keep = kpm::g_err;
+  kpm_plan_destroy(plan);
+  kpm::g_err = keep;
+  return st;
+}
+
+}  // extern "C"

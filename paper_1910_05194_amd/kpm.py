@@ -1,0 +1,249 @@
+"""Thin ctypes binding of libkpm (include/kpm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  If libkpm.so is missing the import of this module raises; there is
+no CPU fallback.  Device outputs are torch tensors (torch supplies device
+memory and streams); host outputs are numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkpm.so")
+
+KPM_OK = 0
+KPM_E_INVALID = -1
+KPM_E_NOMEM = -2
+KPM_E_DEVICE = -3
+KPM_E_SPECTRUM = -4
+KPM_E_UNSUPPORTED = -5
+
+HONEYCOMB, HONEYCOMB_SPIN, SQUARE = 0, 1, 2
+FP32, FP64 = 0, 1
+START_RANDOM_PHASE, START_SITES = 0, 1
+GAMMA_FP64, GAMMA_FP32, GAMMA_SPLIT_BF16 = 0, 1, 2
+
+
+class KPMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libkpm error {code}: {msg}")
+        self.code = code
+
+
+class c_lattice(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("L1", ctypes.c_int32), ("L2", ctypes.c_int32),
+                ("t", ctypes.c_double), ("rashba", ctypes.c_double), ("flux", ctypes.c_double),
+                ("anderson_w", ctypes.c_double), ("vacancy_p", ctypes.c_double),
+                ("disorder_seed", ctypes.c_uint64), ("e_min", ctypes.c_double), ("e_max", ctypes.c_double)]
+
+
+class c_dos_params(ctypes.Structure):
+    _fields_ = [("num_moments", ctypes.c_int32), ("num_random", ctypes.c_int32),
+                ("vector_seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("start", ctypes.c_int32),
+                ("sites", ctypes.POINTER(ctypes.c_int64)), ("num_sites", ctypes.c_int32)]
+
+
+class c_tune(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("rows", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+class c_plan_info(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("n_tiles", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("rows", ctypes.c_int32), ("tile_cells_x", ctypes.c_int32),
+                ("r_padded", ctypes.c_int32), ("n_orbitals", ctypes.c_int64), ("bytes_per_step", ctypes.c_double),
+                ("last_loop_ms", ctypes.c_double), ("last_run_ms", ctypes.c_double),
+                ("n_active_total", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1910_05194_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "kpm_version": (ctypes.c_int, []),
+        "kpm_last_error": (ctypes.c_char_p, []),
+        "kpm_moments_dos": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, ctypes.POINTER(c_dos_params),
+                                           _P, _P, ctypes.c_int32, _P]),
+        "kpm_plan_create": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, ctypes.POINTER(c_dos_params),
+                                           ctypes.POINTER(c_tune), ctypes.POINTER(_P)]),
+        "kpm_plan_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
+        "kpm_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(c_plan_info)]),
+        "kpm_plan_destroy": (ctypes.c_int, [_P]),
+        "kpm_reconstruct_jackson": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
+                                                   ctypes.c_double, _P, ctypes.c_int32, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _check(code: int):
+    if code != KPM_OK:
+        raise KPMError(code, LIB.kpm_last_error().decode(errors="replace"))
+
+
+def last_error() -> str:
+    return LIB.kpm_last_error().decode(errors="replace")
+
+
+def c_lattices(lattices) -> ctypes.Array:
+    arr = (c_lattice * len(lattices))()
+    for i, L in enumerate(lattices):
+        arr[i] = c_lattice(int(L.kind), int(L.L1), int(L.L2), float(L.t), float(getattr(L, "rashba", 0.0)),
+                           float(getattr(L, "flux", 0.0)), float(getattr(L, "anderson_w", 0.0)),
+                           float(getattr(L, "vacancy_p", 0.0)), int(getattr(L, "disorder_seed", 0)) & (2**64 - 1),
+                           float(L.e_min), float(L.e_max))
+    return arr
+
+
+def c_params(par):
+    sites = getattr(par, "sites", None)
+    start = int(getattr(par, "start", START_RANDOM_PHASE))
+    keep = None
+    p = c_dos_params()
+    p.num_moments = int(par.num_moments)
+    p.num_random = int(par.num_random)
+    p.vector_seed = int(par.vector_seed) & (2**64 - 1)
+    p.precision = int(par.precision)
+    p.start = start
+    if start == START_SITES and sites is not None:
+        keep = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+        p.sites = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        p.num_sites = int(keep.size)
+    return p, keep
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+def _num_vectors(par) -> int:
+    if int(getattr(par, "start", START_RANDOM_PHASE)) == START_SITES:
+        return len(par.sites)
+    return int(par.num_random)
+
+
+def moments_dos(lattices: Sequence, par, out_device=None, stream=None):
+    """kpm_moments_dos.  Returns (mu_per_vector [n_lat, R, M], mu_mean [n_lat, M]).
+
+    out_device=None -> numpy arrays (host outputs); otherwise a torch device
+    (e.g. "cuda:0") on which torch float64 tensors are allocated and filled.
+    """
+    lats = c_lattices(lattices)
+    p, keep = c_params(par)
+    R = _num_vectors(par)
+    shape_pv = (len(lattices), R, int(par.num_moments))
+    shape_mean = (len(lattices), int(par.num_moments))
+    if out_device is None:
+        mu = np.zeros(shape_pv)
+        mean = np.zeros(shape_mean)
+        code = LIB.kpm_moments_dos(lats, len(lattices), ctypes.byref(p), mu.ctypes.data, mean.ctypes.data, 0,
+                                   _stream_handle(stream))
+    else:
+        import torch
+        mu = torch.zeros(shape_pv, dtype=torch.float64, device=out_device)
+        mean = torch.zeros(shape_mean, dtype=torch.float64, device=out_device)
+        if stream is None:
+            stream = torch.cuda.current_stream(mu.device)
+        code = LIB.kpm_moments_dos(lats, len(lattices), ctypes.byref(p), mu.data_ptr(), mean.data_ptr(), 1,
+                                   _stream_handle(stream))
+    del keep
+    _check(code)
+    return mu, mean
+
+
+class Plan:
+    """kpm_plan_*: a reusable, graph-captured DOS/LDOS moment pipeline."""
+
+    def __init__(self, lattices: Sequence, par, block: int = 0, rows: int = 0, grid: int = 0,
+                 use_graph: bool = True):
+        self.n_lat = len(lattices)
+        self.R = _num_vectors(par)
+        self.M = int(par.num_moments)
+        lats = c_lattices(lattices)
+        p, keep = c_params(par)
+        tune = c_tune(int(block), int(rows), int(grid), 1 if use_graph else 0)
+        h = _P()
+        _check(LIB.kpm_plan_create(lats, self.n_lat, ctypes.byref(p), ctypes.byref(tune), ctypes.byref(h)))
+        del keep
+        self._h = h
+
+    def run(self, mu_per_vector=None, mu_mean=None, stream=None, check: bool = True):
+        """Run the plan.  Outputs are torch device tensors (float64) or numpy arrays."""
+        import torch
+        on_dev = None
+        ptrs = []
+        for t in (mu_per_vector, mu_mean):
+            if t is None:
+                ptrs.append(None)
+            elif isinstance(t, np.ndarray):
+                assert t.dtype == np.float64 and t.flags.c_contiguous
+                ptrs.append(t.ctypes.data)
+                on_dev = 0 if on_dev is None else on_dev
+                assert on_dev == 0, "outputs must all be host or all be device"
+            else:
+                assert t.dtype == torch.float64 and t.is_contiguous()
+                ptrs.append(t.data_ptr())
+                on_dev = 1 if on_dev is None else on_dev
+                assert on_dev == 1, "outputs must all be host or all be device"
+                if stream is None:
+                    stream = torch.cuda.current_stream(t.device)
+        code = LIB.kpm_plan_run(self._h, ptrs[0], ptrs[1], on_dev or 0, _stream_handle(stream))
+        if check:
+            _check(code)
+        return code
+
+    def info(self) -> dict:
+        i = c_plan_info()
+        _check(LIB.kpm_plan_info(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in c_plan_info._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            LIB.kpm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reconstruct_jackson(mu, energies, e_min: float, e_max: float, stream=None):
+    """kpm_reconstruct_jackson on host numpy arrays or device torch tensors."""
+    if isinstance(mu, np.ndarray):
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        en = np.ascontiguousarray(energies, dtype=np.float64)
+        rho = np.zeros(en.shape)
+        _check(LIB.kpm_reconstruct_jackson(mu.ctypes.data, mu.size, en.ctypes.data, en.size, float(e_min),
+                                           float(e_max), rho.ctypes.data, 0, _stream_handle(stream)))
+        return rho
+    import torch
+    mu = mu.contiguous().to(torch.float64)
+    en = energies.contiguous().to(torch.float64)
+    rho = torch.zeros_like(en)
+    if stream is None:
+        stream = torch.cuda.current_stream(mu.device)
+    _check(LIB.kpm_reconstruct_jackson(mu.data_ptr(), mu.numel(), en.data_ptr(), en.numel(), float(e_min),
+                                       float(e_max), rho.data_ptr(), 1, _stream_handle(stream)))
+    return rho

@@ -1,0 +1,206 @@
+"""GPU parity: DOS/LDOS moments from libkpm vs the FP64 oracle, element by element.
+
+Tolerances:
+* FP64 path: max |dmu_n| <= 1e-6 (absolute, |mu_n| <= 1); measured ~1e-13.
+* FP32 path: the recursion stores FP32 vectors, so each step adds a relative
+  rounding error ~ (Z + 2) * 2^-24 ~ 3e-7 to the vector; errors are
+  accumulated over ceil(M/2) steps and enter the doubling formula twice, so
+  |dmu_n| <= 4 * (M/2) * 3e-7 is the bound used here (5e-5 at M = 64).
+"""
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import kpm as okpm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_05194_amd import kpm
+    return kpm
+
+
+def fp32_tol(M):
+    return 4 * (M / 2) * 3e-7
+
+
+def oracle_moments(lat, par, lat_index=0):
+    mu_r, mu, _ = okpm.dos_moments(lat, par, lat_index=lat_index)
+    return mu_r, mu
+
+
+def test_graphene_64_fp64_parity(K):
+    """64x64 honeycomb + Anderson W=1, FP64, M=256, R=4 (element-wise vs oracle)."""
+    lat, par = wl.graphene_small()
+    mu_g, mean_g = K.moments_dos([lat], par)
+    mu_o, mean_o = oracle_moments(lat, par)
+    err = np.max(np.abs(mu_g[0] - mu_o))
+    print("max |dmu| fp64 graphene 64x64:", err)
+    assert err <= 1e-6
+    assert err <= 1e-11
+    assert np.max(np.abs(mean_g[0] - mean_o)) <= 1e-11
+
+
+RAGGED = [
+    wl.Lattice(kind=wl.HONEYCOMB, L1=37, L2=23, t=-2.7, anderson_w=1.0, vacancy_p=0.03, disorder_seed=17,
+               e_min=-9.0, e_max=8.7),
+    wl.Lattice(kind=wl.HONEYCOMB, L1=19, L2=29, t=-2.7, flux=3 / 19, anderson_w=0.5, disorder_seed=2),
+    wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=13, L2=11, t=-2.7, rashba=0.2, flux=2 / 13, anderson_w=0.8,
+               vacancy_p=0.02, disorder_seed=5),
+    wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=16, L2=9, t=-2.7, rashba=0.35, disorder_seed=6),
+    wl.Lattice(kind=wl.SQUARE, L1=29, L2=17, t=-2.7, anderson_w=2.0, vacancy_p=0.05, disorder_seed=9,
+               e_min=-12.0, e_max=12.0),
+]
+
+
+@pytest.mark.parametrize("lat", RAGGED, ids=lambda l: f"{wl.KIND_NAMES[l.kind]}{l.L1}x{l.L2}")
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("R", [1, 3, 8])
+def test_ragged_lattices(K, lat, prec, R):
+    M = 64
+    par = wl.DosParams(num_moments=M, num_random=R, vector_seed=5194, precision=prec)
+    mu_g, _ = K.moments_dos([lat], par)
+    mu_o, _ = oracle_moments(lat, par)
+    err = np.max(np.abs(mu_g[0] - mu_o))
+    tol = 1e-10 if prec == wl.FP64 else fp32_tol(M)
+    print(f"{lat.kind} {lat.L1}x{lat.L2} prec={prec} R={R}: max|dmu|={err:.3e} tol={tol:.1e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
+def test_ldos_sites(K, prec):
+    lat = RAGGED[2]
+    from oracle import lattice as olat
+    model = olat.build(lat)
+    sites = [int(model.orb_index[i]) for i in (0, 1, 5, 100, model.n_active - 1)]
+    par = wl.DosParams(num_moments=48, start=wl.START_SITES, sites=sites, precision=prec)
+    mu_g, _ = K.moments_dos([lat], par)
+    mu_o, _, _ = okpm.dos_moments(lat, par, model=model)
+    err = np.max(np.abs(mu_g[0] - mu_o))
+    assert err <= (1e-10 if prec == wl.FP64 else fp32_tol(48))
+
+
+def test_ldos_vacant_site_rejected(K):
+    lat = RAGGED[0]
+    from oracle import lattice as olat
+    model = olat.build(lat)
+    vac_site = int(np.nonzero(~model.site_active)[0][0])
+    par = wl.DosParams(num_moments=8, start=wl.START_SITES, sites=[vac_site])
+    with pytest.raises(K.KPMError) as e:
+        K.moments_dos([lat], par)
+    assert e.value.code == K.KPM_E_INVALID
+
+
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
+def test_uneven_batch(K, prec):
+    lats = [wl.Lattice(kind=wl.HONEYCOMB, L1=L, L2=L2, t=-2.7, vacancy_p=0.01 * (i + 1),
+                       disorder_seed=100 + i)
+            for i, (L, L2) in enumerate([(8, 8), (33, 17), (2, 5), (64, 40), (21, 22)])]
+    M, R = 80, 4
+    par = wl.DosParams(num_moments=M, num_random=R, vector_seed=77, precision=prec)
+    mu_g, mean_g = K.moments_dos(lats, par)
+    for i, lat in enumerate(lats):
+        mu_o, mean_o = oracle_moments(lat, par, lat_index=i)
+        err = np.max(np.abs(mu_g[i] - mu_o))
+        assert err <= (1e-10 if prec == wl.FP64 else fp32_tol(M)), (i, err)
+
+
+def test_plan_graph_replay_deterministic(K):
+    import torch
+    lats = [wl.Lattice(kind=wl.HONEYCOMB, L1=L, L2=L, t=-2.7, vacancy_p=0.005, disorder_seed=i)
+            for i, L in enumerate([48, 96, 31])]
+    par = wl.DosParams(num_moments=128, num_random=4, vector_seed=5, precision=wl.FP32)
+    ref, _ = K.moments_dos(lats, par)
+    plan = K.Plan(lats, par, use_graph=True)
+    eager = K.Plan(lats, par, use_graph=False)
+    outs = []
+    for it in range(3):
+        mu = torch.zeros((3, 4, 128), dtype=torch.float64, device="cuda")
+        plan.run(mu)
+        torch.cuda.synchronize()
+        outs.append(mu.cpu().numpy())
+        # Unrelated eager work between replays.
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+    mu_e = np.zeros((3, 4, 128))
+    eager.run(mu_e)
+    for o in outs:
+        assert np.array_equal(o, outs[0])
+    assert np.array_equal(outs[0], mu_e)
+    assert np.array_equal(outs[0], ref)
+    info = plan.info()
+    assert info["n_steps"] == 64 and info["last_loop_ms"] > 0
+    plan.close()
+    eager.close()
+
+
+@pytest.mark.parametrize("tune", [dict(block=64, rows=1, grid=8), dict(block=128, rows=3, grid=16),
+                                  dict(block=512, rows=8, grid=0), dict(block=1024, rows=64, grid=24)])
+def test_launch_shapes_agree(K, tune):
+    lat = RAGGED[0]
+    par = wl.DosParams(num_moments=40, num_random=5, vector_seed=3, precision=wl.FP64)
+    mu_o, _ = oracle_moments(lat, par)
+    plan = K.Plan([lat], par, **tune)
+    mu = np.zeros((1, 5, 40))
+    plan.run(mu)
+    assert np.max(np.abs(mu[0] - mu_o)) <= 1e-10
+    plan.close()
+
+
+def test_large_r_groups(K):
+    """R large enough to need several r-groups per tile (LDOS exact trace of a tiny lattice)."""
+    lat = wl.Lattice(kind=wl.HONEYCOMB, L1=10, L2=12, t=-2.7, anderson_w=1.0, disorder_seed=4)
+    from oracle import lattice as olat
+    model = olat.build(lat)
+    sites = list(range(model.n_active))          # 240 basis vectors
+    par = wl.DosParams(num_moments=32, start=wl.START_SITES, sites=sites, precision=wl.FP64)
+    plan = K.Plan([lat], par, block=64)
+    mu = np.zeros((1, len(sites), 32))
+    mean = np.zeros((1, 32))
+    plan.run(mu, mean)
+    mu_o, mean_o, _ = okpm.dos_moments(lat, par, model=model)
+    assert np.max(np.abs(mu[0] - mu_o)) <= 1e-10
+    assert np.max(np.abs(mean[0] - mean_o)) <= 1e-12
+    plan.close()
+
+
+def test_spectrum_escape_detected(K):
+    lat, par = wl.graphene_small()
+    lat = lat.replace(e_min=-6.0, e_max=6.0)      # clean graphene band edge is 8.1 eV
+    with pytest.raises(K.KPMError) as e:
+        K.moments_dos([lat], par.replace(num_moments=128))
+    assert e.value.code == K.KPM_E_SPECTRUM
+
+
+def test_device_outputs_and_stream(K):
+    import torch
+    lat, par = wl.graphene_small()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        mu, mean = K.moments_dos([lat], par, out_device="cuda")
+    s.synchronize()
+    mu_h, mean_h = K.moments_dos([lat], par)
+    assert np.array_equal(mu.cpu().numpy(), mu_h)
+    assert np.array_equal(mean.cpu().numpy(), mean_h)
+
+
+def test_jackson_reconstruction(K):
+    import torch
+    lat, par = wl.graphene_small()
+    mu_o, mean_o = oracle_moments(lat, par)
+    E = wl.energy_grid(-9.0, 9.0, 1024)
+    ref = okpm.dos(mean_o, E, lat.e_min, lat.e_max)
+    rho = K.reconstruct_jackson(mean_o, E, lat.e_min, lat.e_max)
+    assert np.max(np.abs(rho - ref)) <= 1e-12 * np.max(np.abs(ref))
+    rho_d = K.reconstruct_jackson(torch.tensor(mean_o, device="cuda"), torch.tensor(E, device="cuda"),
+                                  lat.e_min, lat.e_max)
+    assert np.array_equal(rho_d.cpu().numpy(), rho)
+    # Prefix reconstruction with fewer moments (post-processing a subset).
+    rho64 = K.reconstruct_jackson(mean_o[:64], E, lat.e_min, lat.e_max)
+    ref64 = okpm.dos(mean_o[:64], E, lat.e_min, lat.e_max)
+    assert np.max(np.abs(rho64 - ref64)) <= 1e-12 * np.max(np.abs(ref64))
