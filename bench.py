@@ -62,9 +62,11 @@ def main():
     ap.add_argument("--R", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time a plain 4 GiB device copy (HBM ceiling; counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding).",
+        print("bench.py runs on exactly one GPU: the multi-GPU sharding of the recursion is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -139,6 +141,22 @@ def main():
             "max_abs_dmu_fp32_vs_fp64": dmu,
         }
         p64.close()
+
+    if args.copy_probe:
+        nbytes = 4 << 30
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        ev0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        extra["copy_probe"] = {"bytes_moved": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
+        del src, dst
 
     cpu = None
     if not args.no_cpu:

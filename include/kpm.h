@@ -177,6 +177,19 @@ int kpm_reconstruct_jackson(const double* mu, int32_t M, const double* energies_
                             double e_min, double e_max, double* rho, int32_t on_device,
                             void* hip_stream);
 
+/*
+ * HBM bandwidth probe (measurement support for the roofline; not part of the
+ * method).  Streams float4 arrays of bytes_per_array bytes with a grid-stride
+ * kernel of the given shape: pattern 0 = copy (dst = src), 1 = read-only
+ * reduction, 2 = in-place w = 2 v - w (two reads and one write per element,
+ * the memory pattern of a Chebyshev step).  nontemporal != 0 uses streaming
+ * loads/stores.  Allocates and frees its own arrays; synchronises the stream.
+ * Outputs: average milliseconds per launch over iters launches (after one
+ * warm-up launch) and the bytes moved per launch.
+ */
+int kpm_bandwidth_probe(int32_t pattern, int64_t bytes_per_array, int32_t iters, int32_t grid, int32_t block,
+                        int32_t nontemporal, void* hip_stream, double* ms_per_iter, double* bytes_moved_per_iter);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,13 @@
 // bitwise reproducible.
 
 #include "kpm_internal.h"
+#include "kpm_plan.h"
+
+// Cache policy of the step kernel's streams: bit 0 = nontemporal store of
+// v_{n+1}, bit 1 = nontemporal load of v_{n-1} (both are touched once per step).
+#ifndef KPM_STEP_NT
+#define KPM_STEP_NT 0
+#endif
 
 #include <algorithm>
 #include <cmath>
@@ -46,7 +53,7 @@ void clear_error() { g_err.clear(); }
 // ---------------------------------------------------------------------------
 // Geometry (paper Sec. 3(d) listing): honeycomb a = 0.24595 nm, a_cc = 0.142 nm.
 // ---------------------------------------------------------------------------
-constexpr double kAHc = 0.24595, kAccHc = 0.142;
+constexpr double kAHc = 0.24595, kAccHc = 0.142, kASq = 0.24595;
 // Honeycomb bond classes: A(n) - B(n + d_k).
 constexpr int kBondD1[3] = {0, 1, 0};
 constexpr int kBondD2[3] = {0, -1, -1};
@@ -82,6 +89,7 @@ struct LatDev {
   T onsite_const;       // -de+/de- (used when there is no per-site array)
   T hop;                // t/de-
   T blk[3][8];          // spin lattice: H_{A,B'} / de- for bond class k (2x2 complex, row-major), no phase
+  T vc[2][2][4];        // velocity: (r_i - r_j)_dir * de- for [dir][sublattice of i][neighbour k]
 };
 
 template <typename T>
@@ -91,13 +99,16 @@ struct StepArgs {
   const int* slot_of;     // moment slot of each tile
   int n_tiles;
   const T* __restrict__ v;
-  T* __restrict__ w;
+  const T* __restrict__ w;   // v_{n-1} (read when read_w)
+  T* __restrict__ out;       // v_{n+1} (may equal w: in place)
+  T* __restrict__ vel;       // velocity output h~^dir v_n (VEL)
   const T* onsite;
   const uint8_t* mask;
   const T* phase;         // complex interleaved
   double* part;           // [n_slots][Rw][2] for this step
   T a, b;                 // v_{n+1} = a H~ v_n - b v_{n-1}
-  int read_w;
+  T vel_scale;            // vel = vel_scale * [r^dir, H] v_n  (physical units, eV nm)
+  int read_w, write_out, dots, vdir;
   int Tx, Ty, E, Ew, Rp;
 };
 
@@ -120,7 +131,7 @@ __device__ inline void cmul_acc(T& ore, T& oim, T are, T aim, T bre, T bim) {
 // The Chebyshev step: one launch = one grid-wide step of eq. e6 over every
 // tile of every lattice in the batch, with the two doubling dot products.
 // ---------------------------------------------------------------------------
-template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE>
+template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE, bool VEL>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
   using P = Pack<T>;
   constexpr int NC = P::NC;
@@ -160,6 +171,11 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
       T onsite_const, hop;
       T blk[3][8];
     } L;
+    T vcs[NNB];
+    if constexpr (VEL) {
+#pragma unroll
+      for (int k = 0; k < NNB; ++k) vcs[k] = Lg.vc[A.vdir][s][k];
+    }
     L.site_off = Lg.site_off;
     L.vec_off = Lg.vec_off;
     L.phase_off = Lg.phase_off;
@@ -177,7 +193,8 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
     const bool act = (grp < n_grp) && (xl < A.Tx) && (n1 < L1) && (c < A.E) && (tid < n_grp * Ew);
     if (act) {
       const T* __restrict__ vb = A.v + L.vec_off;
-      T* __restrict__ wb = A.w + L.vec_off;
+      const T* __restrict__ wb = A.w + L.vec_off;
+      T* __restrict__ ob = A.out + L.vec_off;
       const int n1p = (n1 + 1 == L1) ? 0 : n1 + 1;
       const int n1m = (n1 == 0) ? L1 - 1 : n1 - 1;
       // Hopping coefficients of this column (Peierls phases depend on n1 only).
@@ -225,28 +242,32 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
         P vo[NSPIN], wo[NSPIN], vn[NNB][NSPIN];
 #pragma unroll
         for (int sp = 0; sp < NSPIN; ++sp) {
-          vo[sp] = *reinterpret_cast<const P*>(vb + (site * NSPIN + sp) * Rp * 2 + coff);
-          if (A.read_w) wo[sp] = *reinterpret_cast<const P*>(wb + (site * NSPIN + sp) * Rp * 2 + coff);
+          vo[sp] = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
+          if (A.read_w) {
+            if constexpr ((KPM_STEP_NT & 2) != 0) wo[sp] = ld_pack_nt(wb + (site * NSPIN + sp) * Rp * 2 + coff);
+            else wo[sp] = ld_pack(wb + (site * NSPIN + sp) * Rp * 2 + coff);
+          }
 #pragma unroll
-          for (int k = 0; k < NNB; ++k)
-            vn[k][sp] = *reinterpret_cast<const P*>(vb + (nb[k] * NSPIN + sp) * Rp * 2 + coff);
+          for (int k = 0; k < NNB; ++k) vn[k][sp] = ld_pack(vb + (nb[k] * NSPIN + sp) * Rp * 2 + coff);
         }
         T ons = L.onsite_const;
         if constexpr (ONSITE) ons = A.onsite[L.site_off + site];
         bool alive = true;
         if constexpr (MASK) alive = A.mask[L.site_off + site] != 0;
 
-        P out[NSPIN];
+        P out[NSPIN], vout[NSPIN];
 #pragma unroll
         for (int sp = 0; sp < NSPIN; ++sp) {
 #pragma unroll
           for (int j = 0; j < NC; ++j) {
             T hr = ons * vo[sp].v[2 * j], hi = ons * vo[sp].v[2 * j + 1];
-            if constexpr (KIND == KPM_HONEYCOMB_SPIN) {
-              // out_sigma = sum_k phase_k * sum_s' B_k[sigma][s'] v_k,s'  (A side)
-              //           = sum_k conj(phase_k) * sum_s' conj(B_k[s'][sigma]) v_k,s'  (B side)
+            T gr = 0, gi = 0;   // velocity accumulator
 #pragma unroll
-              for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < NNB; ++k) {
+              // term_k = (hop from neighbour k) applied to v_k, rescaled units.
+              T tr = 0, ti = 0;
+              if constexpr (KIND == KPM_HONEYCOMB_SPIN) {
+                // A side: B_k[sigma][s'] v_k,s';  B side: conj(B_k[s'][sigma]) v_k,s'.
                 T br = 0, bi = 0;
 #pragma unroll
                 for (int s2 = 0; s2 < 2; ++s2) {
@@ -260,27 +281,21 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
                   }
                   cmul_acc(br, bi, er, ei, vn[k][s2].v[2 * j], vn[k][s2].v[2 * j + 1]);
                 }
+                if constexpr (PHASE) cmul_acc(tr, ti, hre[k], him[k], br, bi);
+                else { tr = br; ti = bi; }
+              } else {
                 if constexpr (PHASE) {
-                  cmul_acc(hr, hi, hre[k], him[k], br, bi);
+                  cmul_acc(tr, ti, hre[k], him[k], vn[k][0].v[2 * j], vn[k][0].v[2 * j + 1]);
                 } else {
-                  hr += br;
-                  hi += bi;
+                  tr = L.hop * vn[k][0].v[2 * j];
+                  ti = L.hop * vn[k][0].v[2 * j + 1];
                 }
               }
-            } else {
-              if constexpr (PHASE) {
-#pragma unroll
-                for (int k = 0; k < NNB; ++k)
-                  cmul_acc(hr, hi, hre[k], him[k], vn[k][0].v[2 * j], vn[k][0].v[2 * j + 1]);
-              } else {
-                T sr = 0, si = 0;
-#pragma unroll
-                for (int k = 0; k < NNB; ++k) {
-                  sr += vn[k][0].v[2 * j];
-                  si += vn[k][0].v[2 * j + 1];
-                }
-                hr += L.hop * sr;
-                hi += L.hop * si;
+              hr += tr;
+              hi += ti;
+              if constexpr (VEL) {
+                gr += vcs[k] * tr;
+                gi += vcs[k] * ti;
               }
             }
             T orr = A.a * hr, oi = A.a * hi;
@@ -288,22 +303,34 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
               orr -= A.b * wo[sp].v[2 * j];
               oi -= A.b * wo[sp].v[2 * j + 1];
             }
-            if (!alive) { orr = 0; oi = 0; }
+            if (!alive) { orr = 0; oi = 0; gr = 0; gi = 0; }
             out[sp].v[2 * j] = orr;
             out[sp].v[2 * j + 1] = oi;
+            if constexpr (VEL) {
+              vout[sp].v[2 * j] = A.vel_scale * gr;
+              vout[sp].v[2 * j + 1] = A.vel_scale * gi;
+            }
             const double xr = (double)vo[sp].v[2 * j], xi = (double)vo[sp].v[2 * j + 1];
             vv[j] += xr * xr + xi * xi;
             wv[j] += (double)orr * xr + (double)oi * xi;
           }
-          *reinterpret_cast<P*>(wb + (site * NSPIN + sp) * Rp * 2 + coff) = out[sp];
+          const int64_t eo = (site * NSPIN + sp) * Rp * 2 + coff;
+          if (A.write_out) {
+            if constexpr ((KPM_STEP_NT & 1) != 0) st_pack_nt(ob + eo, out[sp]);
+            else st_pack(ob + eo, out[sp]);
+          }
+          if constexpr (VEL) {
+            if constexpr ((KPM_STEP_NT & 1) != 0) st_pack_nt(A.vel + L.vec_off + eo, vout[sp]);
+            else st_pack(A.vel + L.vec_off + eo, vout[sp]);
+          }
         }
       }
     }
     // Flush the accumulators when the next tile of this workgroup belongs to
     // another moment slot (another lattice / r-group) or this was the last.
     const int tn = ti + gx;
-    const int slot = A.slot_of[ti];
-    if (tn >= t_end || A.slot_of[tn] != slot) {
+    const int slot = A.dots ? A.slot_of[ti] : 0;
+    if (A.dots && (tn >= t_end || A.slot_of[tn] != slot)) {
 #pragma unroll
       for (int j = 0; j < NC; ++j) {
         lds[tid * 2 * NC + 2 * j] = vv[j];
@@ -500,71 +527,35 @@ __global__ void zero_int(int* p) { *p = 0; }
 // ---------------------------------------------------------------------------
 // Plan
 // ---------------------------------------------------------------------------
-template <typename T, int KIND>
+template <typename T, int KIND, bool VEL>
 static void* pick_step(bool onsite, bool mask, bool phase) {
   const int k = (onsite ? 4 : 0) | (mask ? 2 : 0) | (phase ? 1 : 0);
   switch (k) {
-    case 0: return (void*)step_kernel<T, KIND, false, false, false>;
-    case 1: return (void*)step_kernel<T, KIND, false, false, true>;
-    case 2: return (void*)step_kernel<T, KIND, false, true, false>;
-    case 3: return (void*)step_kernel<T, KIND, false, true, true>;
-    case 4: return (void*)step_kernel<T, KIND, true, false, false>;
-    case 5: return (void*)step_kernel<T, KIND, true, false, true>;
-    case 6: return (void*)step_kernel<T, KIND, true, true, false>;
-    default: return (void*)step_kernel<T, KIND, true, true, true>;
+    case 0: return (void*)step_kernel<T, KIND, false, false, false, VEL>;
+    case 1: return (void*)step_kernel<T, KIND, false, false, true, VEL>;
+    case 2: return (void*)step_kernel<T, KIND, false, true, false, VEL>;
+    case 3: return (void*)step_kernel<T, KIND, false, true, true, VEL>;
+    case 4: return (void*)step_kernel<T, KIND, true, false, false, VEL>;
+    case 5: return (void*)step_kernel<T, KIND, true, false, true, VEL>;
+    case 6: return (void*)step_kernel<T, KIND, true, true, false, VEL>;
+    default: return (void*)step_kernel<T, KIND, true, true, true, VEL>;
   }
 }
 
-template <typename T>
+template <typename T, bool VEL>
 static void* pick_step_kind(int kind, bool onsite, bool mask, bool phase) {
-  if (kind == KPM_HONEYCOMB) return pick_step<T, KPM_HONEYCOMB>(onsite, mask, phase);
-  if (kind == KPM_HONEYCOMB_SPIN) return pick_step<T, KPM_HONEYCOMB_SPIN>(onsite, mask, phase);
-  return pick_step<T, KPM_SQUARE>(onsite, mask, false);
+  if (kind == KPM_HONEYCOMB) return pick_step<T, KPM_HONEYCOMB, VEL>(onsite, mask, phase);
+  if (kind == KPM_HONEYCOMB_SPIN) return pick_step<T, KPM_HONEYCOMB_SPIN, VEL>(onsite, mask, phase);
+  // The square lattice has no Peierls table: only the (onsite, mask) variants exist.
+  const int k = (onsite ? 2 : 0) | (mask ? 1 : 0);
+  switch (k) {
+    case 0: return (void*)step_kernel<T, KPM_SQUARE, false, false, false, VEL>;
+    case 1: return (void*)step_kernel<T, KPM_SQUARE, false, true, false, VEL>;
+    case 2: return (void*)step_kernel<T, KPM_SQUARE, true, false, false, VEL>;
+    default: return (void*)step_kernel<T, KPM_SQUARE, true, true, false, VEL>;
+  }
 }
 
-}  // namespace kpm
-
-struct kpm_plan {
-  std::vector<kpm_lattice_t> lats;
-  kpm_dos_params_t p;
-  std::vector<int64_t> sites;
-  int n_lat = 0, kind = 0, prec = 0, n_sub = 0, n_spin = 0;
-  int M = 0, R = 0, Rp = 0, NC = 0, E = 0, Ew = 0, n_rg = 0, Tx = 0, Ty = 0, block = 0, grid = 0;
-  int n_steps = 0, n_tiles = 0, n_slots = 0, steps_per_chunk = 0;
-  bool has_onsite = false, has_mask = false, has_phase = false, use_graph = true;
-  int64_t n_orb = 0, n_sites = 0, n_phase = 0;
-  std::vector<int64_t> site_off, vec_off, phase_off;
-  size_t tsize = 0;
-  // device memory
-  void* X = nullptr;
-  void* Y = nullptr;
-  void* onsite = nullptr;
-  uint8_t* mask = nullptr;
-  void* phase = nullptr;
-  void* latdev = nullptr;
-  int4* tiles = nullptr;
-  int* slot_of = nullptr;
-  int2* ranges = nullptr;
-  double* part = nullptr;
-  double* dots = nullptr;
-  uint64_t* keys = nullptr;
-  int64_t* d_sites = nullptr;
-  unsigned long long* active = nullptr;
-  kpm::ModelLat* mlat = nullptr;
-  kpm::PhaseLat* plat = nullptr;
-  int* flag = nullptr;
-  double* mu_dev = nullptr;
-  double* mean_dev = nullptr;
-  void* step_fn = nullptr;
-  hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph_loop = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool timed = false;
-  double bytes_per_step = 0.0;
-  int64_t n_active_total = 0;
-};
-
-namespace kpm {
 
 static int validate_lattice(const kpm_lattice_t& L, int idx) {
   KPM_CHECK_ARG(L.kind == KPM_HONEYCOMB || L.kind == KPM_HONEYCOMB_SPIN || L.kind == KPM_SQUARE,
@@ -603,6 +594,21 @@ static void fill_latdev(kpm_plan* P, std::vector<LatDev<T>>& out) {
     d.phase_off = P->phase_off[l];
     d.onsite_const = (T)(-de_p / de_m);
     d.hop = (T)(L.t / de_m);
+    // Velocity [r^dir, H]_ij = (r_i - r_j)_dir H_ij; the kernel applies it to the
+    // rescaled hop terms, hence the factor de-.
+    if (L.kind == KPM_SQUARE) {
+      const double d_sq[4][2] = {{-kASq, 0.0}, {kASq, 0.0}, {0.0, -kASq}, {0.0, kASq}};
+      for (int dir = 0; dir < 2; ++dir)
+        for (int k = 0; k < 4; ++k) d.vc[dir][0][k] = (T)(d_sq[k][dir] * de_m);
+    } else {
+      for (int k = 0; k < 3; ++k)
+        for (int dir = 0; dir < 2; ++dir) {
+          // d_k = r_A(n) - r_B(n + d_k): seen from A (+d_k) and from B (-d_k).
+          const double dk = g.tauA[dir] - (kBondD1[k] * g.a1[dir] + kBondD2[k] * g.a2[dir] + g.tauB[dir]);
+          d.vc[dir][0][k] = (T)(dk * de_m);
+          d.vc[dir][1][k] = (T)(-dk * de_m);
+        }
+    }
     if (L.kind == KPM_HONEYCOMB_SPIN) {
       typedef std::complex<double> cd;
       const cd I(0.0, 1.0);
@@ -639,7 +645,7 @@ static int plan_alloc(kpm_plan* P, void** ptr, size_t bytes) {
   return KPM_OK;
 }
 
-static void plan_free(kpm_plan* P) {
+void plan_free(kpm_plan* P) {
   void* bufs[] = {P->X, P->Y, P->onsite, P->mask, P->phase, P->latdev, P->tiles, P->slot_of, P->ranges,
                   P->part, P->dots, P->keys, P->d_sites, P->active, P->mlat, P->plat, P->flag,
                   P->mu_dev, P->mean_dev};
@@ -651,7 +657,7 @@ static void plan_free(kpm_plan* P) {
     if (e) (void)hipEventDestroy(e);
 }
 
-static int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
+int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
                        const kpm_tune_t* tune, kpm_plan** out) {
   KPM_CHECK_ARG(out != nullptr, "plan output pointer is NULL");
   *out = nullptr;
@@ -914,8 +920,12 @@ static int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_pa
     delete P;
     return KPM_E_DEVICE;
   }
-  P->step_fn = (P->prec == KPM_FP32) ? pick_step_kind<float>(P->kind, P->has_onsite, P->has_mask, P->has_phase)
-                                     : pick_step_kind<double>(P->kind, P->has_onsite, P->has_mask, P->has_phase);
+  P->step_fn = (P->prec == KPM_FP32)
+                   ? pick_step_kind<float, false>(P->kind, P->has_onsite, P->has_mask, P->has_phase)
+                   : pick_step_kind<double, false>(P->kind, P->has_onsite, P->has_mask, P->has_phase);
+  P->step_fn_vel = (P->prec == KPM_FP32)
+                       ? pick_step_kind<float, true>(P->kind, P->has_onsite, P->has_mask, P->has_phase)
+                       : pick_step_kind<double, true>(P->kind, P->has_onsite, P->has_mask, P->has_phase);
   *out = P;
   return KPM_OK;
 }
@@ -948,7 +958,7 @@ static hipError_t launch_prep(kpm_plan* P, hipStream_t s) {
 }
 
 template <typename T>
-static hipError_t launch_loop(kpm_plan* P, hipStream_t s) {
+static hipError_t launch_step_t(kpm_plan* P, hipStream_t s, const StepLaunch& L) {
   StepArgs<T> a;
   a.lats = (const LatDev<T>*)P->latdev;
   a.tiles = P->tiles;
@@ -962,20 +972,58 @@ static hipError_t launch_loop(kpm_plan* P, hipStream_t s) {
   a.E = P->E;
   a.Ew = P->Ew;
   a.Rp = P->Rp;
-  const int Rw = P->Ew * P->NC;
-  const int64_t part_stride = (int64_t)P->n_slots * Rw * 2;
+  a.v = (const T*)L.v;
+  a.w = (const T*)(L.w ? L.w : L.v);
+  a.out = (T*)L.out;
+  a.vel = (T*)L.vel;
+  a.a = (T)L.a;
+  a.b = (T)L.b;
+  a.vel_scale = (T)L.vel_scale;
+  a.read_w = L.read_w;
+  a.write_out = L.write_out;
+  a.dots = L.dots;
+  a.vdir = L.vdir;
+  a.part = L.part;
   const size_t lds = (size_t)P->block * 2 * P->NC * sizeof(double);
   void* args[] = {&a};
+  return hipLaunchKernel(L.vel ? P->step_fn_vel : P->step_fn, dim3(P->grid), dim3(P->block), args, lds, s);
+}
+
+hipError_t plan_launch_step(kpm_plan* P, hipStream_t s, const StepLaunch& L) {
+  return P->prec == KPM_FP32 ? launch_step_t<float>(P, s, L) : launch_step_t<double>(P, s, L);
+}
+
+hipError_t plan_launch_prep(kpm_plan* P, hipStream_t s) {
+  return P->prec == KPM_FP32 ? launch_prep<float>(P, s) : launch_prep<double>(P, s);
+}
+
+int plan_set_vector_base(kpm_plan* P, int64_t r0) {
+  std::vector<uint64_t> keys((size_t)P->n_lat * P->Rp, 0);
+  for (int l = 0; l < P->n_lat; ++l)
+    for (int r = 0; r < P->Rp; ++r)
+      keys[(size_t)l * P->Rp + r] = sm_key(kPurposePhase, P->p.vector_seed, l, (uint64_t)(r0 + r));
+  KPM_TRY_HIP(hipMemcpy(P->keys, keys.data(), keys.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+  P->r_base = r0;
+  return KPM_OK;
+}
+
+// The DOS recursion: v_0 = start, v_1 = H~ v_0, v_{k+1} = 2 H~ v_k - v_{k-1},
+// in place over two buffers, with the doubling dot products of every step.
+static hipError_t launch_loop(kpm_plan* P, hipStream_t s) {
+  const int Rw = P->Ew * P->NC;
+  const int64_t part_stride = (int64_t)P->n_slots * Rw * 2;
   int chunk0 = 0;
   for (int k = 0; k < P->n_steps; ++k) {
     const bool odd = (k & 1) != 0;
-    a.v = (const T*)(odd ? P->Y : P->X);
-    a.w = (T*)(odd ? P->X : P->Y);
-    a.a = (k == 0) ? (T)1 : (T)2;
-    a.b = (k == 0) ? (T)0 : (T)1;
-    a.read_w = (k == 0) ? 0 : 1;
-    a.part = P->part + (int64_t)(k - chunk0) * part_stride;
-    hipError_t le = hipLaunchKernel(P->step_fn, dim3(P->grid), dim3(P->block), args, lds, s);
+    StepLaunch L;
+    L.v = odd ? P->Y : P->X;
+    L.w = odd ? P->X : P->Y;
+    L.out = odd ? P->X : P->Y;
+    L.a = (k == 0) ? 1.0 : 2.0;
+    L.b = (k == 0) ? 0.0 : 1.0;
+    L.read_w = (k == 0) ? 0 : 1;
+    L.part = P->part + (int64_t)(k - chunk0) * part_stride;
+    hipError_t le = plan_launch_step(P, s, L);
     if (le != hipSuccess) return le;
     if (k - chunk0 + 1 == P->steps_per_chunk || k == P->n_steps - 1) {
       const int nsc = k - chunk0 + 1;
@@ -1001,16 +1049,15 @@ static hipError_t launch_finish(kpm_plan* P, hipStream_t s) {
 static int plan_run(kpm_plan* P, double* mu_pv, double* mu_mean, int32_t on_dev, void* stream) {
   KPM_CHECK_ARG(P != nullptr, "plan is NULL");
   hipStream_t s = (hipStream_t)stream;
-  const bool f32 = P->prec == KPM_FP32;
   KPM_TRY_HIP(hipEventRecord(P->ev[0], s));
-  KPM_TRY_HIP(f32 ? launch_prep<float>(P, s) : launch_prep<double>(P, s));
+  KPM_TRY_HIP(plan_launch_prep(P, s));
   KPM_TRY_HIP(hipEventRecord(P->ev[1], s));
   if (P->use_graph) {
     if (!P->graph_loop) {
       // Capture the step loop once on the plan's private stream.
       hipGraph_t g = nullptr;
       KPM_TRY_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t le = f32 ? launch_loop<float>(P, P->cap_stream) : launch_loop<double>(P, P->cap_stream);
+      hipError_t le = launch_loop(P, P->cap_stream);
       hipError_t ce = hipStreamEndCapture(P->cap_stream, &g);
       if (le != hipSuccess || ce != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -1027,7 +1074,7 @@ static int plan_run(kpm_plan* P, double* mu_pv, double* mu_mean, int32_t on_dev,
     }
     KPM_TRY_HIP(hipGraphLaunch(P->graph_loop, s));
   } else {
-    KPM_TRY_HIP(f32 ? launch_loop<float>(P, s) : launch_loop<double>(P, s));
+    KPM_TRY_HIP(launch_loop(P, s));
   }
   KPM_TRY_HIP(hipEventRecord(P->ev[2], s));
   KPM_TRY_HIP(launch_finish(P, s));

@@ -70,6 +70,26 @@ struct alignas(16) Pack {
   T v[2 * NC];
 };
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ inline Pack<T> ld_pack(const T* p) {
+  return __builtin_bit_cast(Pack<T>, *reinterpret_cast<const u32x4*>(p));
+}
+// Streaming (nontemporal) forms: data touched once per step.
+template <typename T>
+__device__ inline Pack<T> ld_pack_nt(const T* p) {
+  return __builtin_bit_cast(Pack<T>, __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)));
+}
+template <typename T>
+__device__ inline void st_pack(T* p, const Pack<T>& v) {
+  *reinterpret_cast<u32x4*>(p) = __builtin_bit_cast(u32x4, v);
+}
+template <typename T>
+__device__ inline void st_pack_nt(T* p, const Pack<T>& v) {
+  __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4*>(p));
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace kpm

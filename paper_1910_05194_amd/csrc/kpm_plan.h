@@ -1,0 +1,74 @@
+// Internal plan of libkpm (DOS/LDOS and conductivity chains).  Not part of the ABI.
+#pragma once
+
+#include "kpm_internal.h"
+
+#include <vector>
+
+namespace kpm {
+struct ModelLat;
+struct PhaseLat;
+
+// One launch of the Chebyshev step kernel over the plan's tile list.
+struct StepLaunch {
+  const void* v = nullptr;     // v_n
+  const void* w = nullptr;     // v_{n-1}
+  void* out = nullptr;         // v_{n+1}
+  void* vel = nullptr;         // velocity output (nullptr = none)
+  double a = 2.0, b = 1.0;     // v_{n+1} = a H~ v_n - b v_{n-1}
+  double vel_scale = 1.0;
+  int read_w = 1, write_out = 1, dots = 1, vdir = 0;
+  double* part = nullptr;      // moment slots for this step (dots)
+};
+
+hipError_t plan_launch_step(kpm_plan* P, hipStream_t s, const StepLaunch& L);
+hipError_t plan_launch_prep(kpm_plan* P, hipStream_t s);
+int plan_set_vector_base(kpm_plan* P, int64_t r0);
+int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, const kpm_tune_t* tune,
+                kpm_plan** out);
+void plan_free(kpm_plan* P);
+}  // namespace kpm
+
+struct kpm_plan {
+  std::vector<kpm_lattice_t> lats;
+  kpm_dos_params_t p;
+  std::vector<int64_t> sites;
+  int n_lat = 0, kind = 0, prec = 0, n_sub = 0, n_spin = 0;
+  int M = 0, R = 0, Rp = 0, NC = 0, E = 0, Ew = 0, n_rg = 0, Tx = 0, Ty = 0, block = 0, grid = 0;
+  int n_steps = 0, n_tiles = 0, n_slots = 0, steps_per_chunk = 0;
+  bool has_onsite = false, has_mask = false, has_phase = false, use_graph = true;
+  int64_t n_orb = 0, n_sites = 0, n_phase = 0;
+  std::vector<int64_t> site_off, vec_off, phase_off;
+  size_t tsize = 0;
+  // device memory
+  void* X = nullptr;
+  void* Y = nullptr;
+  void* onsite = nullptr;
+  uint8_t* mask = nullptr;
+  void* phase = nullptr;
+  void* latdev = nullptr;
+  int4* tiles = nullptr;
+  int* slot_of = nullptr;
+  int2* ranges = nullptr;
+  double* part = nullptr;
+  double* dots = nullptr;
+  uint64_t* keys = nullptr;
+  int64_t* d_sites = nullptr;
+  unsigned long long* active = nullptr;
+  kpm::ModelLat* mlat = nullptr;
+  kpm::PhaseLat* plat = nullptr;
+  int* flag = nullptr;
+  double* mu_dev = nullptr;
+  double* mean_dev = nullptr;
+  void* step_fn = nullptr;
+  void* step_fn_vel = nullptr;
+  int64_t r_base = 0;          // global index of the plan's first random vector
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_loop = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
+  double bytes_per_step = 0.0;
+  int64_t n_active_total = 0;
+};
+
+

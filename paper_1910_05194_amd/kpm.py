@@ -81,6 +81,8 @@ def _load():
         "kpm_plan_destroy": (ctypes.c_int, [_P]),
         "kpm_reconstruct_jackson": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
                                                    ctypes.c_double, _P, ctypes.c_int32, _P]),
+        "kpm_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.c_int32, _P, _D, _D]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -247,3 +249,14 @@ def reconstruct_jackson(mu, energies, e_min: float, e_max: float, stream=None):
     _check(LIB.kpm_reconstruct_jackson(mu.data_ptr(), mu.numel(), en.data_ptr(), en.numel(), float(e_min),
                                        float(e_max), rho.data_ptr(), 1, _stream_handle(stream)))
     return rho
+
+
+def bandwidth_probe(pattern: int, bytes_per_array: int, iters: int = 10, grid: int = 4096, block: int = 256,
+                    nontemporal: bool = False, stream=None) -> dict:
+    """kpm_bandwidth_probe: returns {"ms": ..., "bytes": ..., "GBs": ...} per launch."""
+    ms = ctypes.c_double()
+    nb = ctypes.c_double()
+    _check(LIB.kpm_bandwidth_probe(int(pattern), int(bytes_per_array), int(iters), int(grid), int(block),
+                                   1 if nontemporal else 0, _stream_handle(stream), ctypes.byref(ms),
+                                   ctypes.byref(nb)))
+    return {"ms": ms.value, "bytes": nb.value, "GBs": nb.value / (ms.value * 1e-3) / 1e9}
