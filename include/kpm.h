@@ -177,6 +177,79 @@ int kpm_reconstruct_jackson(const double* mu, int32_t M, const double* energies_
                             double e_min, double e_max, double* rho, int32_t on_device,
                             void* hip_stream);
 
+/* Conductivity moment request (KITE Calculation.conductivity_dc/optical, direction = alpha beta). */
+typedef struct kpm_cond_params_t {
+  int32_t num_moments;     /* M >= 2: Gamma is M x M */
+  int32_t num_random;      /* R >= 1 random-phase vectors */
+  uint64_t vector_seed;
+  int32_t alpha, beta;     /* 0 = x, 1 = y */
+  int32_t gamma_mode;      /* KPM_GAMMA_SPLIT_BF16 (MFMA, FP32 blocks) | KPM_GAMMA_FP64 (FP64 dot products) */
+  int32_t precision;       /* KPM_FP32 | KPM_FP64: Chebyshev vectors and stored blocks */
+  int32_t max_batch;       /* most vectors per batch (0 = as many as fit in device memory) */
+} kpm_cond_params_t;
+
+/*
+ * Rank-2 Gamma tensor (paper eq. Gammanm with the stochastic trace of Sec. 2(c)):
+ *   Gamma_nm = 1/(R N) sum_r <r| h~^a T_n(H~) h~^b T_m(H~) |r> / ((1+d_n0)(1+d_m0)),
+ * h~^a = [r^a, H] in eV nm (the paper's h~ = (i hbar) h, anti-Hermitian), from
+ * the physical H (bond vectors d_ij = r_i - r_j, so the operator is defined on
+ * the torus), N = number of active orbitals, |r> random phases as for the DOS
+ * (lattice index 0, vector r).  Computed as <L_n|R_m> with L_n = T_n(H~)(-h~^a r)
+ * and R_m = h~^b T_m(H~) r: both chains are stored as [M][orbitals x vectors]
+ * blocks (vectors batched to fit memory) and contracted by a GEMM
+ * (split-BF16 x 3 on MFMA with FP32 accumulation per K chunk and FP64 across
+ * chunks, or FP64).
+ * Output gamma [M][M][2] (re, im) FP64, host (out_on_device = 0) or device.
+ * Errors: as kpm_moments_dos; KPM_E_INVALID also for bad alpha/beta/mode or
+ * split-BF16 with FP64 blocks; KPM_E_NOMEM when one vector's blocks
+ * (2 M N complex values) do not fit.
+ */
+int kpm_moments_cond(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma, int32_t out_on_device,
+                     void* hip_stream);
+
+/*
+ * T = 0 longitudinal conductivity from Gamma (alpha = beta), in units of e^2/h:
+ *   sigma(E) = -2 pi^2 (N/Omega) / de-^2 sum_nm g_n g_m D_n(eps) D_m(eps) Re Gamma_nm,
+ *   D_n(eps) = 2 T_n(eps)/(pi sqrt(1 - eps^2))  (eq. delta_function_cheb_expansion),
+ * g_n the Jackson kernel, N/Omega = orbitals_per_nm2.  This is the Fermi-surface
+ * (Kubo-Greenwood) limit of the first-order conductivity (eq. cond 1st order) at
+ * T = 0, omega -> 0; the paper's KITE-tools use the full Kubo-Bastin form.
+ * gamma [M][M][2], energies_ev [K], sigma [K]; host or device pointers.
+ */
+int kpm_reconstruct_sigma(const double* gamma, int32_t M, const double* energies_ev, int32_t K, double e_min,
+                          double e_max, double orbitals_per_nm2, double* sigma, int32_t on_device, void* hip_stream);
+
+/*
+ * Moment-extrapolation MLP (the paper has no learned component: this is the
+ * learned part of this implementation, specified by its shape alone).
+ * Network n_in -> n_hidden -> n_hidden -> n_out, exact GELU x Phi(x) after the
+ * first two layers, FP32 parameters in device memory owned by the handle.
+ * Parameters are exchanged in packed order W1 [n_in][n_hidden], b1, W2
+ * [n_hidden][n_hidden], b2, W3 [n_hidden][n_out], b3 (row-major: y = x W + b).
+ * Initialisation: W ~ U(-sqrt(3/fan_in), +sqrt(3/fan_in)) from the SplitMix64
+ * stream (purpose 5, seed, layer), b = 0.
+ * Loss: L = 1/(B n_out) sum_{b,j} (w_j (Y_bj - T_bj))^2 with caller-supplied
+ * weights w (the Jackson factors of the predicted orders).
+ * x [B][n_in], target [B][n_out], weights [n_out], y [B][n_out]: FP32 device
+ * pointers.  forward: use_bf16 = 1 runs the GEMMs with BF16 operands and FP32
+ * accumulation (MFMA), 0 in FP32 (MFMA).  train_step: forward, loss, backward
+ * and one Adam step (beta1 0.9, beta2 0.999, eps 1e-8), loss written to the
+ * device double loss_dev_out (may be NULL).  gradients: forward + backward
+ * only; gradients copied to grads_host in packed order (FP32), loss to *loss.
+ * Work is enqueued on hip_stream; get/set_params synchronise the device.
+ */
+typedef struct kpm_mlp kpm_mlp_t;
+int kpm_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, uint64_t seed, kpm_mlp_t** mlp);
+int kpm_mlp_destroy(kpm_mlp_t* mlp);
+int kpm_mlp_num_params(const kpm_mlp_t* mlp, int64_t* n);
+int kpm_mlp_get_params(kpm_mlp_t* mlp, float* params_host);
+int kpm_mlp_set_params(kpm_mlp_t* mlp, const float* params_host);
+int kpm_mlp_forward(kpm_mlp_t* mlp, const float* x, int32_t batch, float* y, int32_t use_bf16, void* hip_stream);
+int kpm_mlp_train_step(kpm_mlp_t* mlp, const float* x, const float* target, const float* weights, int32_t batch,
+                       float lr, double* loss_dev_out, void* hip_stream);
+int kpm_mlp_gradients(kpm_mlp_t* mlp, const float* x, const float* target, const float* weights, int32_t batch,
+                      float* grads_host, double* loss, void* hip_stream);
+
 /*
  * HBM bandwidth probe (measurement support for the roofline; not part of the
  * method).  Streams float4 arrays of bytes_per_array bytes with a grid-stride

@@ -1,0 +1,194 @@
+// Rank-2 conductivity moments Gamma_nm (paper eq. Gammanm) with the
+// stochastic trace (Sec. 2(c)):
+//
+//   Gamma_nm = 1/(R N) sum_r <L_n^r | R_m^r> / ((1 + d_n0)(1 + d_m0)),
+//   L_n = T_n(H~) (-h~^a |r>),   R_m = h~^b T_m(H~) |r>,
+//
+// where h~^a = [r^a, H] (eq. generalized velocity times i hbar) is
+// anti-Hermitian, so <r| h~^a T_n h~^b T_m |r> = <L_n | R_m>.  Both chains run
+// through the Chebyshev step kernel: the L chain stores every T_n(H~) w as a
+// row of the block L; the R chain applies the velocity stencil to T_m |r> in
+// the same pass that produces T_{m+1} |r> and stores it as a row of R.  The
+// double sum over n, m is a GEMM over the stored blocks (orbitals x vectors
+// form the contraction index).  Vectors are processed in batches sized to the
+// free device memory.
+
+#include "kpm_internal.h"
+#include "kpm_plan.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace kpm {
+
+hipError_t gamma_accumulate_bf16(const float* L, const float* R, int M, int64_t Kq, int64_t ld, int KS,
+                                 double* part, double* acc, hipStream_t s);
+template <typename T>
+hipError_t gamma_accumulate_fp64(const T* L, const T* R, int M, int64_t Kc, int64_t ld, int KS, double* part,
+                                 double* acc, hipStream_t s);
+
+__global__ void zero_f64(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// Gamma = acc / (R N_active) / ((1 + d_n0)(1 + d_m0)).
+__global__ void gamma_scale_kernel(const double* acc, int M, int R, const unsigned long long* active, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)M * M * 2) return;
+  const int64_t nm = i >> 1;
+  const int n = (int)(nm / M), m = (int)(nm % M);
+  const double d = (n == 0 ? 2.0 : 1.0) * (m == 0 ? 2.0 : 1.0);
+  out[i] = acc[i] / ((double)R * (double)active[0]) / d;
+}
+
+static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma, int32_t on_dev,
+                    void* stream) {
+  KPM_CHECK_ARG(lat && p && gamma, "NULL argument");
+  KPM_CHECK_ARG(p->num_moments >= 2, "num_moments must be >= 2");
+  KPM_CHECK_ARG(p->num_random >= 1, "num_random must be >= 1");
+  KPM_CHECK_ARG((p->alpha == 0 || p->alpha == 1) && (p->beta == 0 || p->beta == 1), "alpha, beta must be 0 (x) or 1 (y)");
+  KPM_CHECK_ARG(p->gamma_mode == KPM_GAMMA_FP64 || p->gamma_mode == KPM_GAMMA_SPLIT_BF16,
+                "gamma_mode must be KPM_GAMMA_FP64 or KPM_GAMMA_SPLIT_BF16");
+  KPM_CHECK_ARG(p->precision == KPM_FP32 || p->precision == KPM_FP64, "precision must be KPM_FP32 or KPM_FP64");
+  KPM_CHECK_ARG(!(p->gamma_mode == KPM_GAMMA_SPLIT_BF16 && p->precision != KPM_FP32),
+                "KPM_GAMMA_SPLIT_BF16 needs FP32 blocks (precision = KPM_FP32)");
+  hipStream_t s = (hipStream_t)stream;
+  const int M = p->num_moments, Rtot = p->num_random;
+  const int n_sub = lat->kind == KPM_SQUARE ? 1 : 2;
+  const int n_spin = lat->kind == KPM_HONEYCOMB_SPIN ? 2 : 1;
+  const int64_t n_orb = (int64_t)lat->L1 * lat->L2 * n_sub * n_spin;
+  const size_t tsize = p->precision == KPM_FP32 ? 4 : 8;
+
+  // Vectors per batch: two [M][n_orb][Rb] blocks must fit in free memory.
+  size_t free_b = 0, total_b = 0;
+  KPM_TRY_HIP(hipMemGetInfo(&free_b, &total_b));
+  const double per_vec = 2.0 * M * (double)n_orb * 2 * tsize + 2.0 * (double)n_orb * 2 * tsize;
+  const double usable = 0.85 * (double)free_b - 4.0e9;   // plan buffers and moment partials
+  int rb_max = (int)std::max(0.0, std::floor(usable / per_vec));
+  if (p->max_batch > 0) rb_max = std::min(rb_max, p->max_batch);
+  if (rb_max < 1) {
+    set_error("not enough device memory for one vector: need %.1f GB of Chebyshev blocks", per_vec / 1e9);
+    return KPM_E_NOMEM;
+  }
+  rb_max = std::min(rb_max, Rtot);
+  const int n_batch = (int)ceil_div(Rtot, rb_max);
+  const int Rb = (int)ceil_div(Rtot, n_batch);
+
+  kpm_dos_params_t dp;
+  std::memset(&dp, 0, sizeof(dp));
+  dp.num_moments = M;
+  dp.num_random = Rb;
+  dp.vector_seed = p->vector_seed;
+  dp.precision = p->precision;
+  dp.start = KPM_START_RANDOM_PHASE;
+  kpm_tune_t tune;
+  std::memset(&tune, 0, sizeof(tune));
+  tune.use_graph = 0;
+  kpm_plan* P = nullptr;
+  KPM_TRY(plan_create(lat, 1, &dp, &tune, &P));
+
+  const int64_t vec_elems = n_orb * P->Rp * 2;   // T elements per Chebyshev vector
+  const int KS = 64;
+  void *Lb = nullptr, *Rblk = nullptr;
+  double *acc = nullptr, *part = nullptr, *gdev = nullptr;
+  int st = KPM_OK;
+  auto fail = [&](hipError_t e, const char* what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    (void)hipGetLastError();
+    st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
+  };
+  hipError_t e = hipMalloc(&Lb, (size_t)M * vec_elems * tsize);
+  if (e == hipSuccess) e = hipMalloc(&Rblk, (size_t)M * vec_elems * tsize);
+  if (e == hipSuccess) e = hipMalloc(&acc, (size_t)M * M * 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&part, (size_t)KS * M * M * 2 * sizeof(double));
+  if (e == hipSuccess && !on_dev) e = hipMalloc(&gdev, (size_t)M * M * 2 * sizeof(double));
+  if (e != hipSuccess) fail(e, "allocating Gamma blocks");
+  double* gout = on_dev ? gamma : gdev;
+  if (st == KPM_OK) {
+    hipLaunchKernelGGL(zero_f64, dim3((unsigned)ceil_div((int64_t)M * M * 2, 256)), dim3(256), 0, s, acc,
+                       (int64_t)M * M * 2);
+  }
+  for (int b = 0; b < n_batch && st == KPM_OK; ++b) {
+    const int r0 = b * Rb;
+    P->R = std::min(Rb, Rtot - r0);   // vectors of this batch beyond Rtot start as zero
+    st = plan_set_vector_base(P, r0);
+    if (st != KPM_OK) break;
+    e = plan_launch_prep(P, s);
+    if (e != hipSuccess) { fail(e, "model/start kernels"); break; }
+    auto row = [&](void* base, int n) { return (void*)((char*)base + (size_t)n * vec_elems * tsize); };
+    // L chain: L_0 = -h~^a xi, L_1 = H~ L_0, L_n = 2 H~ L_{n-1} - L_{n-2}.
+    for (int n = 0; n < M && e == hipSuccess; ++n) {
+      StepLaunch S;
+      S.dots = 0;
+      if (n == 0) {
+        S.v = P->X; S.out = P->Y; S.write_out = 0; S.read_w = 0; S.a = 0.0; S.b = 0.0;
+        S.vel = row(Lb, 0); S.vdir = p->alpha; S.vel_scale = -1.0;
+      } else if (n == 1) {
+        S.v = row(Lb, 0); S.out = row(Lb, 1); S.read_w = 0; S.a = 1.0; S.b = 0.0;
+      } else {
+        S.v = row(Lb, n - 1); S.w = row(Lb, n - 2); S.out = row(Lb, n); S.a = 2.0; S.b = 1.0;
+      }
+      e = plan_launch_step(P, s, S);
+    }
+    // R chain: v_0 = xi, v_1 = H~ v_0, v_{m+1} = 2 H~ v_m - v_{m-1} (in place),
+    // with R_m = h~^b v_m from the same pass.
+    for (int m = 0; m < M && e == hipSuccess; ++m) {
+      StepLaunch S;
+      S.dots = 0;
+      S.vdir = p->beta;
+      S.vel_scale = 1.0;
+      S.vel = row(Rblk, m);
+      if (m == 0) {
+        S.v = P->X; S.out = P->Y; S.read_w = 0; S.a = 1.0; S.b = 0.0;
+      } else {
+        const bool odd = (m & 1) != 0;
+        S.v = odd ? P->Y : P->X;
+        S.w = odd ? P->X : P->Y;
+        S.out = odd ? P->X : P->Y;
+      }
+      S.write_out = (m < M - 1) ? 1 : 0;
+      e = plan_launch_step(P, s, S);
+    }
+    if (e != hipSuccess) { fail(e, "Chebyshev chains"); break; }
+    if (p->gamma_mode == KPM_GAMMA_SPLIT_BF16) {
+      e = gamma_accumulate_bf16((const float*)Lb, (const float*)Rblk, M, vec_elems, vec_elems, KS, part, acc, s);
+    } else if (p->precision == KPM_FP32) {
+      e = gamma_accumulate_fp64<float>((const float*)Lb, (const float*)Rblk, M, vec_elems / 2, vec_elems, KS, part,
+                                       acc, s);
+    } else {
+      e = gamma_accumulate_fp64<double>((const double*)Lb, (const double*)Rblk, M, vec_elems / 2, vec_elems, KS,
+                                        part, acc, s);
+    }
+    if (e != hipSuccess) fail(e, "Gamma GEMM");
+  }
+  if (st == KPM_OK) {
+    hipLaunchKernelGGL(gamma_scale_kernel, dim3((unsigned)ceil_div((int64_t)M * M * 2, 256)), dim3(256), 0, s, acc, M,
+                       Rtot, P->active, gout);
+    e = hipGetLastError();
+    if (e == hipSuccess && !on_dev)
+      e = hipMemcpyAsync(gamma, gdev, (size_t)M * M * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) fail(e, "Gamma output");
+  } else {
+    (void)hipStreamSynchronize(s);
+  }
+  for (void* ptr : {Lb, Rblk, (void*)acc, (void*)part, (void*)gdev})
+    if (ptr) (void)hipFree(ptr);
+  plan_free(P);
+  delete P;
+  return st;
+}
+
+}  // namespace kpm
+
+extern "C" int kpm_moments_cond(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma,
+                                int32_t out_on_device, void* hip_stream) {
+  try {
+    kpm::clear_error();
+    return kpm::cond_run(lat, p, gamma, out_on_device, hip_stream);
+  } catch (...) {
+    kpm::set_error("internal error (exception) in kpm_moments_cond");
+    return KPM_E_DEVICE;
+  }
+}

@@ -48,6 +48,12 @@ class c_dos_params(ctypes.Structure):
                 ("sites", ctypes.POINTER(ctypes.c_int64)), ("num_sites", ctypes.c_int32)]
 
 
+class c_cond_params(ctypes.Structure):
+    _fields_ = [("num_moments", ctypes.c_int32), ("num_random", ctypes.c_int32),
+                ("vector_seed", ctypes.c_uint64), ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
+                ("gamma_mode", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
 class c_tune(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("rows", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32)]
@@ -81,6 +87,19 @@ def _load():
         "kpm_plan_destroy": (ctypes.c_int, [_P]),
         "kpm_reconstruct_jackson": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
                                                    ctypes.c_double, _P, ctypes.c_int32, _P]),
+        "kpm_moments_cond": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.POINTER(c_cond_params), _P,
+                                            ctypes.c_int32, _P]),
+        "kpm_reconstruct_sigma": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.c_double, _P, ctypes.c_int32, _P]),
+        "kpm_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                          ctypes.POINTER(_P)]),
+        "kpm_mlp_destroy": (ctypes.c_int, [_P]),
+        "kpm_mlp_num_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+        "kpm_mlp_get_params": (ctypes.c_int, [_P, _P]),
+        "kpm_mlp_set_params": (ctypes.c_int, [_P, _P]),
+        "kpm_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
+        "kpm_mlp_train_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P]),
+        "kpm_mlp_gradients": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P, _D, _P]),
         "kpm_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                                ctypes.c_int32, ctypes.c_int32, _P, _D, _D]),
     }
@@ -260,3 +279,119 @@ def bandwidth_probe(pattern: int, bytes_per_array: int, iters: int = 10, grid: i
                                    1 if nontemporal else 0, _stream_handle(stream), ctypes.byref(ms),
                                    ctypes.byref(nb)))
     return {"ms": ms.value, "bytes": nb.value, "GBs": nb.value / (ms.value * 1e-3) / 1e9}
+
+
+def moments_cond(lattice, par, precision: int = FP32, max_batch: int = 0, out_device=None, stream=None):
+    """kpm_moments_cond: Gamma_nm as a complex array [M, M] (numpy) or a float64 [M, M, 2] torch tensor."""
+    lat = c_lattices([lattice])
+    p = c_cond_params(int(par.num_moments), int(par.num_random), int(par.vector_seed) & (2**64 - 1),
+                      int(par.alpha), int(par.beta), int(par.gamma_mode), int(precision), int(max_batch))
+    M = int(par.num_moments)
+    if out_device is None:
+        g = np.zeros((M, M, 2))
+        _check(LIB.kpm_moments_cond(lat, ctypes.byref(p), g.ctypes.data, 0, _stream_handle(stream)))
+        return g[..., 0] + 1j * g[..., 1]
+    import torch
+    g = torch.zeros((M, M, 2), dtype=torch.float64, device=out_device)
+    if stream is None:
+        stream = torch.cuda.current_stream(g.device)
+    _check(LIB.kpm_moments_cond(lat, ctypes.byref(p), g.data_ptr(), 1, _stream_handle(stream)))
+    return g
+
+
+def reconstruct_sigma(gamma, energies, e_min: float, e_max: float, orbitals_per_nm2: float, stream=None):
+    """kpm_reconstruct_sigma: sigma_xx(E) in e^2/h from Gamma ([M, M] complex numpy or [M, M, 2] torch)."""
+    if isinstance(gamma, np.ndarray):
+        g = np.ascontiguousarray(np.stack([gamma.real, gamma.imag], axis=-1)) if np.iscomplexobj(gamma) else \
+            np.ascontiguousarray(gamma, dtype=np.float64)
+        en = np.ascontiguousarray(energies, dtype=np.float64)
+        out = np.zeros(en.shape)
+        _check(LIB.kpm_reconstruct_sigma(g.ctypes.data, g.shape[0], en.ctypes.data, en.size, float(e_min),
+                                         float(e_max), float(orbitals_per_nm2), out.ctypes.data, 0,
+                                         _stream_handle(stream)))
+        return out
+    import torch
+    g = gamma.contiguous()
+    en = energies.contiguous().to(torch.float64)
+    out = torch.zeros_like(en)
+    if stream is None:
+        stream = torch.cuda.current_stream(g.device)
+    _check(LIB.kpm_reconstruct_sigma(g.data_ptr(), g.shape[0], en.data_ptr(), en.numel(), float(e_min),
+                                     float(e_max), float(orbitals_per_nm2), out.data_ptr(), 1,
+                                     _stream_handle(stream)))
+    return out
+
+
+class MLP:
+    """kpm_mlp_*: the moment-extrapolation network (device-resident FP32 parameters)."""
+
+    def __init__(self, n_in: int = 256, n_hidden: int = 1024, n_out: int = 1792, seed: int = 7):
+        self.n_in, self.n_hidden, self.n_out = n_in, n_hidden, n_out
+        h = _P()
+        _check(LIB.kpm_mlp_create(n_in, n_hidden, n_out, int(seed) & (2**64 - 1), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int64()
+        _check(LIB.kpm_mlp_num_params(h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def shapes(self):
+        i, h, o = self.n_in, self.n_hidden, self.n_out
+        return [(i, h), (h,), (h, h), (h,), (h, o), (o,)]
+
+    def get_params(self):
+        flat = np.zeros(self.n_params, dtype=np.float32)
+        _check(LIB.kpm_mlp_get_params(self._h, flat.ctypes.data))
+        return self._unpack(flat)
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.float32).ravel() for p in params]))
+        assert flat.size == self.n_params
+        _check(LIB.kpm_mlp_set_params(self._h, flat.ctypes.data))
+
+    def _unpack(self, flat):
+        out, o = [], 0
+        for shp in self.shapes():
+            n = int(np.prod(shp))
+            out.append(flat[o:o + n].reshape(shp))
+            o += n
+        return out
+
+    def forward(self, x, bf16: bool = False, stream=None):
+        import torch
+        x = x.contiguous()
+        assert x.dtype == torch.float32 and x.shape[1] == self.n_in
+        y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device=x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        _check(LIB.kpm_mlp_forward(self._h, x.data_ptr(), x.shape[0], y.data_ptr(), 1 if bf16 else 0,
+                                   _stream_handle(stream)))
+        return y
+
+    def train_step(self, x, target, weights, lr: float, loss_out=None, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        _check(LIB.kpm_mlp_train_step(self._h, x.data_ptr(), target.data_ptr(), weights.data_ptr(), x.shape[0],
+                                      float(lr), None if loss_out is None else loss_out.data_ptr(),
+                                      _stream_handle(stream)))
+
+    def gradients(self, x, target, weights, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        flat = np.zeros(self.n_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(LIB.kpm_mlp_gradients(self._h, x.data_ptr(), target.data_ptr(), weights.data_ptr(), x.shape[0],
+                                     flat.ctypes.data, ctypes.byref(loss), _stream_handle(stream)))
+        return self._unpack(flat), loss.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            LIB.kpm_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,112 @@
+"""Full-size parity on sampled outputs, in the launch configuration bench.py times.
+
+* graphene 4096^2 + Anderson, M=2048, R=32: FP32 (default plan, as benchmarked)
+  and FP64; the oracle computes moments n < 12 of vectors r = 0 and r = 31 on
+  the full 33.5M-orbital lattice; all 2048 moments are checked for the
+  invariants mu_0 = 1, |mu_n| <= 1 and FP32-vs-FP64 agreement.
+* spinful Rashba + flux honeycomb 1024^2, Gamma 512x512, R=8, split-BF16:
+  the oracle computes the 6x6 block n, m < 6 over all 8 vectors.
+* 64 uneven vacancy lattices (256^2 .. 2048^2), M=1024, R=4, FP32: the oracle
+  computes moments n < 16 of the smallest and of one mid-size lattice.
+"""
+import numpy as np
+import pytest
+
+import workload as wl
+from oracle import cond as ocond
+from oracle import kpm as okpm
+from oracle import lattice as olat
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1910_05194_amd import kpm
+    return kpm
+
+
+def _oracle_prefix(lat, par, rs, n_max, lat_index=0):
+    model = olat.build(lat)
+    Ht = okpm.rescale(model.H, lat.e_min, lat.e_max)
+    out = {}
+    for r in rs:
+        v = okpm.random_phase_vectors(model, r + 1, par.vector_seed, lat_index)[r:r + 1] if r < 4 else None
+        if v is None:
+            # Only vector r is needed: generate it alone with the same keying.
+            from oracle import rng
+            u = rng.uniform(rng.stream_key(rng.PHASE, par.vector_seed, lat_index, r),
+                            model.orb_index.astype(np.uint64))
+            v = np.exp(2j * np.pi * u)[None, :]
+        out[r] = okpm.moments(Ht, v, n_max, model.n_active)[0].real
+    return out
+
+
+@pytest.mark.timeout(900)
+def test_graphene_4096_full_size(K):
+    import torch
+    L, M, R = 4096, 2048, 32
+    lat, par = wl.graphene_large(precision=wl.FP32, L=L, M=M, R=R)
+    plan = K.Plan([lat], par)
+    mu32 = torch.zeros((1, R, M), dtype=torch.float64, device="cuda")
+    plan.run(mu32)
+    plan.close()
+    lat64, par64 = wl.graphene_large(precision=wl.FP64, L=L, M=M, R=R)
+    plan = K.Plan([lat64], par64)
+    mu64 = torch.zeros((1, R, M), dtype=torch.float64, device="cuda")
+    plan.run(mu64)
+    plan.close()
+    mu32 = mu32.cpu().numpy()[0]
+    mu64 = mu64.cpu().numpy()[0]
+    assert np.all(np.abs(mu32[:, 0] - 1) < 1e-6) and np.all(np.abs(mu64[:, 0] - 1) < 1e-12)
+    assert np.all(np.abs(mu32) <= 1 + 1e-6) and np.all(np.abs(mu64) <= 1 + 1e-12)
+    d = np.max(np.abs(mu32 - mu64))
+    print(f"full size: max |mu_fp32 - mu_fp64| = {d:.3e}")
+    assert d <= 4 * (M / 2) * 3e-7
+    nmax = 12
+    ref = _oracle_prefix(lat64, par64, [0, 31], nmax)
+    for r, mo in ref.items():
+        e64 = np.max(np.abs(mu64[r, :nmax] - mo))
+        e32 = np.max(np.abs(mu32[r, :nmax] - mo))
+        print(f"r={r}: fp64 {e64:.2e}, fp32 {e32:.2e} vs oracle (n < {nmax})")
+        assert e64 <= 1e-10
+        assert e32 <= 4 * (nmax / 2) * 3e-7
+
+
+@pytest.mark.timeout(900)
+def test_rashba_flux_gamma_full_size(K):
+    lat, par = wl.rashba_flux()
+    G = K.moments_cond(lat, par, precision=wl.FP32)
+    assert G.shape == (512, 512) and np.all(np.isfinite(G))
+    idx = np.arange(6)
+    Go, _ = ocond.cond_gamma(lat, par, n_idx=idx, m_idx=idx)
+    e = float(np.linalg.norm(G[:6, :6] - Go) / np.linalg.norm(Go))
+    print(f"Gamma full size, block n,m<6: rel err {e:.2e}; Gamma_00 = {G[0, 0]}")
+    assert e <= 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_uneven_batch_full_size(K):
+    import torch
+    lats, par = wl.uneven_batch()
+    plan = K.Plan(lats, par)
+    mu = torch.zeros((len(lats), par.num_random, par.num_moments), dtype=torch.float64, device="cuda")
+    plan.run(mu)
+    info = plan.info()
+    plan.close()
+    mu = mu.cpu().numpy()
+    assert np.all(np.abs(mu[:, :, 0] - 1) < 1e-6)
+    assert np.all(np.abs(mu) <= 1 + 1e-6)
+    sizes = [l.L1 for l in lats]
+    picks = [int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2])]
+    nmax = 16
+    for i in picks:
+        ref = _oracle_prefix(lats[i], par, [0, 3], nmax, lat_index=i)
+        for r, mo in ref.items():
+            e = np.max(np.abs(mu[i, r, :nmax] - mo))
+            print(f"lattice {i} (L={sizes[i]}), r={r}: fp32 vs oracle {e:.2e}")
+            assert e <= 4 * (nmax / 2) * 3e-7
+    print("uneven batch:", info["n_orbitals"], "orbitals,", info["n_tiles"], "tiles")
