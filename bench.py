@@ -1,18 +1,24 @@
-"""Benchmark: DOS moment throughput of the Chebyshev hot path on one MI355X.
+"""Benchmark of the Chebyshev/KPM hot path on one MI355X.
 
-Workload (the headline configuration): honeycomb graphene 4096 x 4096 cells
-(33,554,432 orbitals), NN t = -2.7 eV, Anderson W = 1 eV, bounds +-8.5 eV,
-M = 2048 moments, R = 32 random-phase complex64 vectors batched in one
-recursion, FP32 recursion with FP64 moment accumulation.  One bench "step" is
-one complete pass of the path: disorder/model build, start vectors,
-ceil(M/2) = 1024 Chebyshev step launches with fused moments, the moment
-reduction, and the Jackson DOS reconstruction on 1024 energies.
+Headline workload: honeycomb graphene 4096 x 4096 cells (33,554,432 orbitals),
+NN t = -2.7 eV, Anderson W = 1 eV, bounds +-8.5 eV, M = 2048 moments, R = 32
+random-phase complex64 vectors batched in one recursion, FP32 recursion with
+FP64 moment accumulation.  One bench "step" is one complete pass of the DOS
+path on that input: disorder/model build, start vectors, ceil(M/2) = 1024
+Chebyshev step launches with fused moments (replayed hipGraph), the moment
+reduction, and the Jackson DOS reconstruction on 1024 energies.  The launch
+shape comes from the library's autotuner (run before the timed region).
 
 value = orbital * moment * vector updates per second = N * M * R / t_step.
-The same pass is also run once in FP64 and the FP32 result is compared with
-it (DOS error on the 1024-point grid and max |d mu_n|).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Further legs (each reported in its own JSON object): the same pass in FP64
+(and the FP32-vs-FP64 DOS error), the 64x64 FP64 parity workload, the
+Gamma_nm conductivity workload (spinful Rashba + flux 1024^2, 512 x 512,
+R = 8, split-BF16 MFMA), the batched uneven workload (64 vacancy lattices
+256^2..2048^2, M = 1024, R = 4), the learned moment extrapolation (training
+and evaluation), and the CPU oracle on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs c1,c3,c4,c5]
 """
 from __future__ import annotations
 
@@ -26,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def log(*a):
@@ -33,10 +40,9 @@ def log(*a):
 
 
 def cpu_baseline(lat_full, par_full):
-    """Time the oracle on a bounded sample of the same model: 1024x1024 cells
-    (2.1M orbitals, same t, W, bounds, seeds), R = 1, M = 192, one thread.
-    Includes the oracle's model build."""
-    import numpy as np
+    """The oracle on a bounded sample of the headline model: the same t, W,
+    bounds and seeds at 1024 x 1024 cells (2.1M orbitals), R = 1, M = 192, one
+    thread, model build included."""
     from threadpoolctl import threadpool_limits
     from oracle import kpm as okpm
     L, M, R = 1024, 192, 1
@@ -48,8 +54,114 @@ def cpu_baseline(lat_full, par_full):
         dt = time.perf_counter() - t0
     n = lat.n_orbitals
     return {"value": n * M * R / dt, "unit": "orbital*moment*vector updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle (scipy CSR, FP64) on the same model at 1024x1024 cells, R=1, M={M}, "
-                      f"model build included: {dt:.2f} s"}
+            "sample": f"oracle (scipy CSR, FP64, one thread) on the headline model at 1024x1024 cells, R=1, "
+                      f"M={M}, model build included: {dt:.2f} s"}
+
+
+def leg_small(kpm, wl, np):
+    """64x64 FP64 parity workload: time per pass and max |dmu| against the oracle."""
+    import torch
+    from oracle import kpm as okpm
+    lat, par = wl.graphene_small()
+    plan = kpm.Plan([lat], par)
+    mu = torch.zeros((1, par.num_random, par.num_moments), dtype=torch.float64, device="cuda")
+    plan.run(mu)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run(mu)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    plan.close()
+    mu_o, _, _ = okpm.dos_moments(lat, par)
+    err = float(np.max(np.abs(mu.cpu().numpy()[0] - mu_o)))
+    return {"workload": "graphene 64x64 + Anderson W=1, FP64, M=256, R=4", "ms_per_pass": dt * 1e3,
+            "updates_per_s": lat.n_orbitals * par.num_moments * par.num_random / dt,
+            "max_abs_dmu_vs_oracle": err}
+
+
+def leg_gamma(kpm, wl, np):
+    """Gamma_nm 512x512 on the spinful Rashba + flux 1024^2 lattice, R = 8, split-BF16 MFMA."""
+    lat, par = wl.rashba_flux()
+    t0 = time.perf_counter()
+    G = kpm.moments_cond(lat, par, precision=wl.FP32)
+    dt = time.perf_counter() - t0
+    st = kpm.cond_last_stats()
+    E = np.linspace(-3.0, 3.0, 7)
+    n_orb = lat.n_orbitals
+    area = lat.L1 * lat.L2 * wl.A_HONEYCOMB ** 2 * np.sqrt(3) / 2
+    sig = kpm.reconstruct_sigma(G, E, lat.e_min, lat.e_max, n_orb / area)
+    gemm_tf = st["gemm_mfma_flops"] / (st["gemm_ms"] * 1e-3) / 1e12
+    return {"workload": "spinful honeycomb 1024^2, Rashba 0.2 eV, flux 1/1024, Gamma 512x512, R=8, split-BF16",
+            "wall_s": dt, "total_ms": st["total_ms"], "chain_ms": st["chain_ms"],
+            "chain_GBs": st["chain_bytes"] / (st["chain_ms"] * 1e-3) / 1e9,
+            "gemm_ms": st["gemm_ms"], "gemm_mfma_TFLOPs": gemm_tf,
+            "gemm_useful_TFLOPs": st["gemm_useful_flops"] / (st["gemm_ms"] * 1e-3) / 1e12,
+            "mfma_utilisation_bf16": gemm_tf / BF16_PEAK_TFLOPS, "batches": st["n_batches"],
+            "gamma_00": [G[0, 0].real, G[0, 0].imag], "sigma_xx_e2h": dict(zip(map(float, E), map(float, sig)))}
+
+
+def leg_batch(kpm, wl, np):
+    """64 uneven vacancy lattices in one persistent kernel per step (hipGraph)."""
+    import torch
+    lats, par = wl.uneven_batch()
+    plan = kpm.Plan(lats, par)
+    mu = torch.zeros((len(lats), par.num_random, par.num_moments), dtype=torch.float64, device="cuda")
+    plan.run(mu)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(mu)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    i = plan.info()
+    plan.close()
+    n = i["n_orbitals"]
+    return {"workload": "64 honeycomb lattices L~U{256..2048}, vacancies 0.5%, M=1024, R=4, FP32",
+            "orbitals": n, "s_per_pass": dt, "updates_per_s": n * par.num_moments * par.num_random / dt,
+            "step_GBs": i["bytes_per_step"] / (i["last_loop_ms"] / i["n_steps"] * 1e-3) / 1e9,
+            "kernel": i["kernel"], "tiles": i["n_tiles"]}
+
+
+def leg_mlp(kpm, wl, np, n_train=20000, L_train=128, R_train=16, epochs=60, n_eval=8):
+    """Learned extrapolation 256 -> 2048 moments: data from the recursion, training with the
+    library's kernels, BF16 inference, acceptance checks, DOS error against the full recursion."""
+    import torch
+    from paper_1910_05194_amd import extrapolate as ex
+    t0 = time.perf_counter()
+    lats = [wl.mlp_training_lattice(i, L=L_train) for i in range(n_train)]
+    mu = ex.generate_moments(lats, 2048, R_train, 5194)
+    t_data = time.perf_counter() - t0
+    net = kpm.MLP(256, 1024, 1792, seed=7)
+    t0 = time.perf_counter()
+    hist = ex.train(net, mu, epochs=epochs, batch=256, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    evl = [wl.mlp_eval_lattice(i, L=2048) for i in range(n_eval)]
+    t0 = time.perf_counter()
+    full = ex.generate_moments(evl, 2048, 16, 777, batch=4)
+    t_full = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    head = ex.generate_moments(evl, 256, 16, 777, batch=4)
+    ext = ex.extrapolate(net, head, bf16=True)
+    torch.cuda.synchronize()
+    t_fast = time.perf_counter() - t0
+    e_tr, e_ml, acc = [], [], []
+    for i, L in enumerate(evl):
+        E = wl.energy_grid(L.e_min, L.e_max, 1024)
+        rf = kpm.reconstruct_jackson(full[i], E, L.e_min, L.e_max)
+        rt = kpm.reconstruct_jackson(head[i], E, L.e_min, L.e_max)
+        rm = kpm.reconstruct_jackson(ext[i].cpu().numpy(), E, L.e_min, L.e_max)
+        e_tr.append(ex.dos_error(rt, rf))
+        e_ml.append(ex.dos_error(rm, rf))
+        acc.append(ex.accept(ext[i:i + 1], L.e_min, L.e_max, E)[0])
+    net.close()
+    return {"workload": f"MLP 256->1024->1024->1792; train {n_train} lattices {L_train}^2 R={R_train}; "
+                        f"eval {n_eval} honeycomb 2048^2 R=16",
+            "data_s": t_data, "train_s": t_train, "epochs": epochs, "final_val_loss": hist["val"][-1],
+            "full_recursion_s": t_full, "truncated_plus_mlp_s": t_fast,
+            "dos_error_truncated_256": float(np.mean(e_tr)), "dos_error_mlp_2048": float(np.mean(e_ml)),
+            "gain": float(np.mean(e_tr) / np.mean(e_ml)), "accepted": int(sum(acc)), "fallbacks": int(n_eval - sum(acc))}
 
 
 def main():
@@ -62,6 +174,8 @@ def main():
     ap.add_argument("--R", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
+    ap.add_argument("--legs", default="c1,c3,c4,c5", help="extra legs: c1,c3,c4,c5 (empty for none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain 4 GiB device copy (HBM ceiling; counter calibration)")
     args = ap.parse_args()
@@ -78,10 +192,17 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    legs = [x for x in args.legs.split(",") if x]
     lat, par = wl.graphene_large(precision=wl.FP32, L=args.L, M=args.M, R=args.R)
     E = torch.tensor(wl.energy_grid(lat.e_min, lat.e_max, 1024), device=dev)
-    log(f"[bench] plan: graphene {args.L}x{args.L}, M={args.M}, R={args.R}, FP32")
-    plan = kpm.Plan([lat], par)
+    tune = {}
+    if not args.no_tune:
+        log("[bench] autotune (FP32)")
+        best = kpm.autotune([lat], par.replace(num_moments=32), probe_steps=16)
+        tune = {k: best[k] for k in ("kernel", "block", "rows", "grid")}
+        log(f"[bench] tuned: {best}")
+    log(f"[bench] plan: graphene {args.L}x{args.L}, M={args.M}, R={args.R}, FP32, {tune}")
+    plan = kpm.Plan([lat], par, **tune)
     mu = torch.zeros((1, args.R, args.M), dtype=torch.float64, device=dev)
     mean = torch.zeros((1, args.M), dtype=torch.float64, device=dev)
 
@@ -105,9 +226,9 @@ def main():
     N = lat.n_orbitals
     value = N * args.M * args.R / dt
     # Step kernel: algorithmic bytes per launch / average launch duration over
-    # the timed region (hipEvents around the captured step loop, on the run's
-    # stream; the loop also holds the moment-reduction kernels, so this is a
-    # lower bound on the step kernel's own rate).
+    # the timed region (hipEvents around the graph of step launches on the
+    # run's stream; the graph also holds the few moment-reduction launches, so
+    # this is a lower bound on the step kernel's own rate).
     avg_step_ms = float(np.mean(loop_ms)) / info["n_steps"]
     achieved = info["bytes_per_step"] / (avg_step_ms * 1e-3) / 1e9
     mu32 = mu[0].cpu().numpy()
@@ -118,7 +239,11 @@ def main():
     if not args.no_fp64:
         log("[bench] FP64 pass")
         lat64, par64 = wl.graphene_large(precision=wl.FP64, L=args.L, M=args.M, R=args.R)
-        p64 = kpm.Plan([lat64], par64)
+        tune64 = {}
+        if not args.no_tune:
+            b64 = kpm.autotune([lat64], par64.replace(num_moments=32), probe_steps=16)
+            tune64 = {k: b64[k] for k in ("kernel", "block", "rows", "grid")}
+        p64 = kpm.Plan([lat64], par64, **tune64)
         mu64 = torch.zeros_like(mu)
         mean64 = torch.zeros_like(mean)
         p64.run(mu64, mean64, stream=stream)
@@ -132,14 +257,13 @@ def main():
         rho64 = rho64.cpu().numpy()
         dmu = float(np.max(np.abs(mu32 - mu64[0].cpu().numpy())))
         e_dos = float(np.sum(np.abs(rho32 - rho64)) / np.sum(np.abs(rho64)))
-        extra = {
-            "fp64_value": N * args.M * args.R / dt64,
-            "fp64_ms_per_step": dt64 * 1e3,
-            "fp64_step_kernel_GBs": i64["bytes_per_step"] / (i64["last_loop_ms"] / i64["n_steps"] * 1e-3) / 1e9,
-            "dos_error_fp32_vs_fp64": e_dos,
-            "dos_maxabs_fp32_vs_fp64_per_eV": float(np.max(np.abs(rho32 - rho64))),
-            "max_abs_dmu_fp32_vs_fp64": dmu,
+        extra["fp64"] = {
+            "value": N * args.M * args.R / dt64, "ms_per_step": dt64 * 1e3, "tune": tune64,
+            "step_kernel_GBs": i64["bytes_per_step"] / (i64["last_loop_ms"] / i64["n_steps"] * 1e-3) / 1e9,
         }
+        extra["dos_error_fp32_vs_fp64"] = e_dos
+        extra["dos_maxabs_fp32_vs_fp64_per_eV"] = float(np.max(np.abs(rho32 - rho64)))
+        extra["max_abs_dmu_fp32_vs_fp64"] = dmu
         p64.close()
 
     if args.copy_probe:
@@ -158,6 +282,12 @@ def main():
         extra["copy_probe"] = {"bytes_moved": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
         del src, dst
 
+    for name, fn in (("c1", leg_small), ("c3", leg_gamma), ("c4", leg_batch), ("c5", leg_mlp)):
+        if name in legs:
+            log(f"[bench] leg {name}")
+            extra[{"c1": "small_fp64", "c3": "gamma", "c4": "uneven_batch", "c5": "mlp_extrapolation"}[name]] = \
+                fn(kpm, wl, np)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
@@ -173,11 +303,11 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"graphene honeycomb {args.L}x{args.L} + Anderson W=1 eV, M={args.M}, "
                                f"R={args.R} complex64, FP32 recursion / FP64 moments, Jackson 1024 E",
-                   "orbitals": N, "moments": args.M, "vectors": args.R},
+                   "orbitals": N, "moments": args.M, "vectors": args.R, "launch": tune},
         "step_rate": N * info["n_steps"] * args.R / dt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "step_kernel<float, honeycomb, onsite>",
+                     "kernel": "kpm::step_kernel (FP32, honeycomb, on-site array)",
                      "bytes_per_launch": info["bytes_per_step"], "avg_launch_ms": avg_step_ms},
         "cpu_baseline": cpu,
     }

@@ -103,6 +103,7 @@ typedef struct kpm_tune_t {
   int32_t rows;            /* lattice rows (along a2) per tile */
   int32_t grid;            /* persistent workgroups (multiple of 8); 0 = one per tile */
   int32_t use_graph;       /* 1 = replay the step loop as a captured hipGraph (default), 0 = eager */
+  int32_t kernel;          /* 0 = default (LDS row ring), 1 = direct neighbour loads, 2 = LDS row ring */
 } kpm_tune_t;
 
 typedef struct kpm_plan_info_t {
@@ -110,6 +111,7 @@ typedef struct kpm_plan_info_t {
   int32_t n_tiles;               /* tiles in the work list */
   int32_t grid, block, rows, tile_cells_x;
   int32_t r_padded;              /* vectors per orbital as stored (R rounded up) */
+  int32_t kernel;                /* step kernel variant in use (1 direct, 2 LDS ring) */
   int64_t n_orbitals;            /* orbitals in the batch, vacancies included */
   double bytes_per_step;         /* algorithmic HBM bytes of one step launch */
   double last_loop_ms;           /* step loop of the last run (hipEvents on the run's stream) */
@@ -147,6 +149,20 @@ const char* kpm_last_error(void);
  */
 int kpm_moments_dos(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
                     double* mu_per_vector, double* mu_mean, int32_t out_on_device, void* hip_stream);
+
+/*
+ * Launch-shape autotuner (the analogue of the paper's user-tuned TILE size,
+ * Sec. 3(b) and Table 1).  Runs the recursion for probe_steps steps with each
+ * candidate (kernel variant x block x rows x grid) on the given workload,
+ * timed with hipEvents on hip_stream, and returns the fastest in *best (and its
+ * algorithmic GB/s in *best_gbs, may be NULL).  If cache_path is non-NULL the
+ * result is appended to that text file; kpm_plan_create reads the file named
+ * by the environment variable KPM_TUNE_CACHE whenever it is called without a
+ * launch shape (tune NULL or all of block, rows, grid, kernel zero).  Allocates
+ * one full-size plan at a time.
+ */
+int kpm_autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, int32_t probe_steps,
+                 const char* cache_path, kpm_tune_t* best, double* best_gbs, void* hip_stream);
 
 /* Reusable form of kpm_moments_dos: create allocates the device workspace
  * (two vector buffers of n_orbitals * R_padded complex values, per-site disorder
@@ -207,6 +223,20 @@ typedef struct kpm_cond_params_t {
 int kpm_moments_cond(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma, int32_t out_on_device,
                      void* hip_stream);
 
+/* Timing and work of the last kpm_moments_cond call on the calling thread
+ * (hipEvents on the call's stream). */
+typedef struct kpm_cond_stats_t {
+  int32_t n_batches, vectors_per_batch;
+  double chain_ms;            /* both Chebyshev chains, all batches */
+  double gemm_ms;             /* Gamma GEMM + its chunk reduction, all batches */
+  double total_ms;            /* the whole call */
+  double chain_bytes;         /* algorithmic HBM bytes of the chain launches */
+  double gemm_useful_flops;   /* 4 M^2 (2 N R) real flops = 8 M^2 N R */
+  double gemm_mfma_flops;     /* flops issued to the matrix cores (x3 for split-BF16) */
+  double gemm_operand_bytes;  /* both stored blocks read once */
+} kpm_cond_stats_t;
+int kpm_cond_last_stats(kpm_cond_stats_t* stats);
+
 /*
  * T = 0 longitudinal conductivity from Gamma (alpha = beta), in units of e^2/h:
  *   sigma(E) = -2 pi^2 (N/Omega) / de-^2 sum_nm g_n g_m D_n(eps) D_m(eps) Re Gamma_nm,
@@ -249,6 +279,12 @@ int kpm_mlp_train_step(kpm_mlp_t* mlp, const float* x, const float* target, cons
                        float lr, double* loss_dev_out, void* hip_stream);
 int kpm_mlp_gradients(kpm_mlp_t* mlp, const float* x, const float* target, const float* weights, int32_t batch,
                       float* grads_host, double* loss, void* hip_stream);
+/* Optional per-column standardisation: x [n_rows][n_in] and target [n_rows][n_out]
+ * (device) give column means and standard deviations; from then on forward
+ * maps x -> (x - mean)/sd before the network and y' -> mean + sd y' after it,
+ * and training uses the standardised targets with weights w * sd_out (the same
+ * loss in original units).  Gradients then refer to the standardised network. */
+int kpm_mlp_fit_scaling(kpm_mlp_t* mlp, const float* x, const float* target, int64_t n_rows, void* hip_stream);
 
 /*
  * HBM bandwidth probe (measurement support for the roofline; not part of the

@@ -42,8 +42,11 @@ __global__ void gamma_scale_kernel(const double* acc, int M, int R, const unsign
   out[i] = acc[i] / ((double)R * (double)active[0]) / d;
 }
 
+static thread_local kpm_cond_stats_t g_stats;
+
 static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma, int32_t on_dev,
                     void* stream) {
+  std::memset(&g_stats, 0, sizeof(g_stats));
   KPM_CHECK_ARG(lat && p && gamma, "NULL argument");
   KPM_CHECK_ARG(p->num_moments >= 2, "num_moments must be >= 2");
   KPM_CHECK_ARG(p->num_random >= 1, "num_random must be >= 1");
@@ -105,6 +108,18 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   if (e == hipSuccess && !on_dev) e = hipMalloc(&gdev, (size_t)M * M * 2 * sizeof(double));
   if (e != hipSuccess) fail(e, "allocating Gamma blocks");
   double* gout = on_dev ? gamma : gdev;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (auto& x : ev)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  if (e != hipSuccess && st == KPM_OK) fail(e, "creating events");
+  if (st == KPM_OK) e = hipEventRecord(ev[3], s);
+  g_stats.n_batches = n_batch;
+  g_stats.vectors_per_batch = Rb;
+  const double vec_bytes = (double)vec_elems * tsize;
+  const double site_bytes = (P->has_onsite ? (double)P->n_sites * tsize : 0.0) + (P->has_mask ? (double)P->n_sites : 0.0);
+  auto step_bytes = [&](const StepLaunch& S) {
+    return vec_bytes * (1.0 + S.read_w + S.write_out + (S.vel ? 1.0 : 0.0)) + site_bytes;
+  };
   if (st == KPM_OK) {
     hipLaunchKernelGGL(zero_f64, dim3((unsigned)ceil_div((int64_t)M * M * 2, 256)), dim3(256), 0, s, acc,
                        (int64_t)M * M * 2);
@@ -117,6 +132,7 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
     e = plan_launch_prep(P, s);
     if (e != hipSuccess) { fail(e, "model/start kernels"); break; }
     auto row = [&](void* base, int n) { return (void*)((char*)base + (size_t)n * vec_elems * tsize); };
+    e = hipEventRecord(ev[0], s);
     // L chain: L_0 = -h~^a xi, L_1 = H~ L_0, L_n = 2 H~ L_{n-1} - L_{n-2}.
     for (int n = 0; n < M && e == hipSuccess; ++n) {
       StepLaunch S;
@@ -130,6 +146,7 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
         S.v = row(Lb, n - 1); S.w = row(Lb, n - 2); S.out = row(Lb, n); S.a = 2.0; S.b = 1.0;
       }
       e = plan_launch_step(P, s, S);
+      g_stats.chain_bytes += step_bytes(S);
     }
     // R chain: v_0 = xi, v_1 = H~ v_0, v_{m+1} = 2 H~ v_m - v_{m-1} (in place),
     // with R_m = h~^b v_m from the same pass.
@@ -149,8 +166,14 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
       }
       S.write_out = (m < M - 1) ? 1 : 0;
       e = plan_launch_step(P, s, S);
+      g_stats.chain_bytes += step_bytes(S);
     }
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
     if (e != hipSuccess) { fail(e, "Chebyshev chains"); break; }
+    // Flops: 2 real GEMMs (Re, Im) of M x M over 2 vec_elems/2 reals = 4 M^2 vec_elems.
+    g_stats.gemm_useful_flops += 4.0 * M * (double)M * (double)vec_elems;
+    g_stats.gemm_mfma_flops += (p->gamma_mode == KPM_GAMMA_SPLIT_BF16 ? 3.0 : 1.0) * 4.0 * M * (double)M * vec_elems;
+    g_stats.gemm_operand_bytes += 2.0 * M * vec_bytes;
     if (p->gamma_mode == KPM_GAMMA_SPLIT_BF16) {
       e = gamma_accumulate_bf16((const float*)Lb, (const float*)Rblk, M, vec_elems, vec_elems, KS, part, acc, s);
     } else if (p->precision == KPM_FP32) {
@@ -160,6 +183,13 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
       e = gamma_accumulate_fp64<double>((const double*)Lb, (const double*)Rblk, M, vec_elems / 2, vec_elems, KS,
                                         part, acc, s);
     }
+    if (e == hipSuccess) e = hipEventRecord(ev[2], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+    float ms_c = 0.f, ms_g = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_c, ev[0], ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms_g, ev[1], ev[2]);
+    g_stats.chain_ms += ms_c;
+    g_stats.gemm_ms += ms_g;
     if (e != hipSuccess) fail(e, "Gamma GEMM");
   }
   if (st == KPM_OK) {
@@ -173,6 +203,14 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   } else {
     (void)hipStreamSynchronize(s);
   }
+  if (st == KPM_OK) {
+    float ms_t = 0.f;
+    if (hipEventRecord(ev[2], s) == hipSuccess && hipEventSynchronize(ev[2]) == hipSuccess &&
+        hipEventElapsedTime(&ms_t, ev[3], ev[2]) == hipSuccess)
+      g_stats.total_ms = ms_t;
+  }
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
   for (void* ptr : {Lb, Rblk, (void*)acc, (void*)part, (void*)gdev})
     if (ptr) (void)hipFree(ptr);
   plan_free(P);
@@ -181,6 +219,15 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
 }
 
 }  // namespace kpm
+
+extern "C" int kpm_cond_last_stats(kpm_cond_stats_t* out) {
+  if (!out) {
+    kpm::set_error("NULL argument");
+    return KPM_E_INVALID;
+  }
+  *out = kpm::g_stats;
+  return KPM_OK;
+}
 
 extern "C" int kpm_moments_cond(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma,
                                 int32_t out_on_device, void* hip_stream) {

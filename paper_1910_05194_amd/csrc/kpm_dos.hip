@@ -128,8 +128,223 @@ __device__ inline void cmul_acc(T& ore, T& oim, T are, T aim, T bre, T bim) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-site arithmetic of one Chebyshev step (shared by both step kernels).
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+struct LatRegs {
+  int64_t site_off, vec_off, phase_off;
+  T onsite_const, hop;
+  T blk[3][8];
+  int L1, L2;
+};
+
+template <typename T, int KIND>
+__device__ inline void load_lat(const LatDev<T>& Lg, LatRegs<T, KIND>& L) {
+  L.site_off = Lg.site_off;
+  L.vec_off = Lg.vec_off;
+  L.phase_off = Lg.phase_off;
+  L.onsite_const = Lg.onsite_const;
+  L.hop = Lg.hop;
+  L.L1 = Lg.L1;
+  L.L2 = Lg.L2;
+  if constexpr (KIND == KPM_HONEYCOMB_SPIN) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) L.blk[k][q] = Lg.blk[k][q];
+  }
+}
+
+// Hopping coefficients of column n1 for sublattice s (Peierls phases depend on
+// n1 only; the table is indexed by the A site's cell, the B' image unwrapped).
+template <typename T, int KIND, bool PHASE>
+__device__ inline void column_coefficients(const StepArgs<T>& A, const LatRegs<T, KIND>& L, int s, int n1, int n1m,
+                                           T* hre, T* him) {
+  constexpr int NNB = KindTraits<KIND>::NNB;
+#pragma unroll
+  for (int k = 0; k < NNB; ++k) {
+    hre[k] = L.hop;
+    him[k] = (T)0;
+  }
+  if constexpr (PHASE) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int na = (s == 0) ? n1 : ((k == 1) ? n1m : n1);
+      const T pre = A.phase[2 * (L.phase_off + (int64_t)na * 3 + k)];
+      const T pim = A.phase[2 * (L.phase_off + (int64_t)na * 3 + k) + 1];
+      hre[k] = pre;
+      him[k] = (s == 0) ? pim : -pim;   // B side: conjugate
+      if constexpr (KIND != KPM_HONEYCOMB_SPIN) {
+        hre[k] *= L.hop;
+        him[k] *= L.hop;
+      }
+    }
+  }
+}
+
+// out = a (H~ v)_i - b w_i, vel = vel_scale [r^dir, H] v at one site (all
+// spins, all complex values of the pack), and the doubling dot products.
+template <typename T, int KIND, bool PHASE, bool VEL>
+__device__ inline void site_update(const StepArgs<T>& A, const LatRegs<T, KIND>& L, int s, const T* hre,
+                                   const T* him, const T* vcs, T ons, bool alive,
+                                   const Pack<T> (&vo)[KindTraits<KIND>::NSPIN],
+                                   const Pack<T> (&wo)[KindTraits<KIND>::NSPIN],
+                                   const Pack<T> (&vn)[KindTraits<KIND>::NNB][KindTraits<KIND>::NSPIN],
+                                   Pack<T> (&out)[KindTraits<KIND>::NSPIN], Pack<T> (&vout)[KindTraits<KIND>::NSPIN],
+                                   double* vv, double* wv) {
+  constexpr int NC = Pack<T>::NC;
+  constexpr int NSPIN = KindTraits<KIND>::NSPIN;
+  constexpr int NNB = KindTraits<KIND>::NNB;
+#pragma unroll
+  for (int sp = 0; sp < NSPIN; ++sp) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      T hr = ons * vo[sp].v[2 * j], hi = ons * vo[sp].v[2 * j + 1];
+      T gr = 0, gi = 0;   // velocity accumulator
+#pragma unroll
+      for (int k = 0; k < NNB; ++k) {
+        // term_k = (hop from neighbour k) applied to v_k, rescaled units.
+        T tr = 0, ti = 0;
+        if constexpr (KIND == KPM_HONEYCOMB_SPIN) {
+          // A side: B_k[sigma][s'] v_k,s';  B side: conj(B_k[s'][sigma]) v_k,s'.
+          T br = 0, bi = 0;
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) {
+            T er, ei;
+            if (s == 0) {
+              er = L.blk[k][2 * (sp * 2 + s2)];
+              ei = L.blk[k][2 * (sp * 2 + s2) + 1];
+            } else {
+              er = L.blk[k][2 * (s2 * 2 + sp)];
+              ei = -L.blk[k][2 * (s2 * 2 + sp) + 1];
+            }
+            cmul_acc(br, bi, er, ei, vn[k][s2].v[2 * j], vn[k][s2].v[2 * j + 1]);
+          }
+          if constexpr (PHASE) cmul_acc(tr, ti, hre[k], him[k], br, bi);
+          else { tr = br; ti = bi; }
+        } else {
+          if constexpr (PHASE) {
+            cmul_acc(tr, ti, hre[k], him[k], vn[k][0].v[2 * j], vn[k][0].v[2 * j + 1]);
+          } else {
+            tr = L.hop * vn[k][0].v[2 * j];
+            ti = L.hop * vn[k][0].v[2 * j + 1];
+          }
+        }
+        hr += tr;
+        hi += ti;
+        if constexpr (VEL) {
+          gr += vcs[k] * tr;
+          gi += vcs[k] * ti;
+        }
+      }
+      T orr = A.a * hr, oi = A.a * hi;
+      if (A.read_w) {
+        orr -= A.b * wo[sp].v[2 * j];
+        oi -= A.b * wo[sp].v[2 * j + 1];
+      }
+      if (!alive) { orr = 0; oi = 0; gr = 0; gi = 0; }
+      out[sp].v[2 * j] = orr;
+      out[sp].v[2 * j + 1] = oi;
+      if constexpr (VEL) {
+        vout[sp].v[2 * j] = A.vel_scale * gr;
+        vout[sp].v[2 * j + 1] = A.vel_scale * gi;
+      }
+      const double xr = (double)vo[sp].v[2 * j], xi = (double)vo[sp].v[2 * j + 1];
+      vv[j] += xr * xr + xi * xi;
+      wv[j] += (double)orr * xr + (double)oi * xi;
+    }
+  }
+}
+
+template <typename T, int KIND, bool VEL>
+__device__ inline void store_site(const StepArgs<T>& A, T* ob, T* velb, int64_t site, int64_t coff,
+                                  const Pack<T> (&out)[KindTraits<KIND>::NSPIN],
+                                  const Pack<T> (&vout)[KindTraits<KIND>::NSPIN]) {
+  constexpr int NSPIN = KindTraits<KIND>::NSPIN;
+#pragma unroll
+  for (int sp = 0; sp < NSPIN; ++sp) {
+    const int64_t eo = (site * NSPIN + sp) * A.Rp * 2 + coff;
+    if (A.write_out) {
+      if constexpr ((KPM_STEP_NT & 1) != 0) st_pack_nt(ob + eo, out[sp]);
+      else st_pack(ob + eo, out[sp]);
+    }
+    if constexpr (VEL) {
+      if constexpr ((KPM_STEP_NT & 1) != 0) st_pack_nt(velb + eo, vout[sp]);
+      else st_pack(velb + eo, vout[sp]);
+    }
+  }
+}
+
+template <typename T, int KIND>
+__device__ inline void load_w(const StepArgs<T>& A, const T* wb, int64_t site, int64_t coff,
+                              Pack<T> (&wo)[KindTraits<KIND>::NSPIN]) {
+  constexpr int NSPIN = KindTraits<KIND>::NSPIN;
+#pragma unroll
+  for (int sp = 0; sp < NSPIN; ++sp) {
+    if (A.read_w) {
+      if constexpr ((KPM_STEP_NT & 2) != 0) wo[sp] = ld_pack_nt(wb + (site * NSPIN + sp) * A.Rp * 2 + coff);
+      else wo[sp] = ld_pack(wb + (site * NSPIN + sp) * A.Rp * 2 + coff);
+    }
+  }
+}
+
+// Reduce the per-thread dot products of one moment slot over the workgroup
+// (fixed-order LDS tree) and write them to part[slot].
+template <int NC>
+__device__ inline void flush_slot(double* lds, double* part, int slot, int tid, int Ew, int grp, int n_grp,
+                                  double* vv, double* wv) {
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    lds[tid * 2 * NC + 2 * j] = vv[j];
+    lds[tid * 2 * NC + 2 * j + 1] = wv[j];
+    vv[j] = wv[j] = 0.0;
+  }
+  __syncthreads();
+  int p2 = 1;
+  while (p2 < n_grp) p2 <<= 1;
+  for (int st = p2 >> 1; st > 0; st >>= 1) {
+    if (grp < st && grp + st < n_grp) {
+#pragma unroll
+      for (int q = 0; q < 2 * NC; ++q) lds[tid * 2 * NC + q] += lds[(tid + st * Ew) * 2 * NC + q];
+    }
+    __syncthreads();
+  }
+  if (tid < Ew) {
+    double* dst = part + ((int64_t)slot * Ew * NC + tid * NC) * 2;
+#pragma unroll
+    for (int q = 0; q < 2 * NC; ++q) dst[q] = lds[tid * 2 * NC + q];
+  }
+  __syncthreads();
+}
+
+// Neighbour sites of (n1, y, s): honeycomb A(n) <- B(n), B(n+(1,-1)), B(n+(0,-1));
+// B(n) <- A(n), A(n-(1,-1)), A(n-(0,-1)); square: (+-1, 0), (0, +-1).
+template <int KIND>
+__device__ inline void neighbours(int s, int n1, int n1p, int n1m, int y, int ym, int yp, int L1, int64_t* nb) {
+  if constexpr (KIND == KPM_SQUARE) {
+    nb[0] = (int64_t)y * L1 + n1p;
+    nb[1] = (int64_t)y * L1 + n1m;
+    nb[2] = (int64_t)yp * L1 + n1;
+    nb[3] = (int64_t)ym * L1 + n1;
+  } else {
+    if (s == 0) {
+      nb[0] = ((int64_t)y * L1 + n1) * 2 + 1;
+      nb[1] = ((int64_t)ym * L1 + n1p) * 2 + 1;
+      nb[2] = ((int64_t)ym * L1 + n1) * 2 + 1;
+    } else {
+      nb[0] = ((int64_t)y * L1 + n1) * 2;
+      nb[1] = ((int64_t)yp * L1 + n1m) * 2;
+      nb[2] = ((int64_t)yp * L1 + n1) * 2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // The Chebyshev step: one launch = one grid-wide step of eq. e6 over every
 // tile of every lattice in the batch, with the two doubling dot products.
+//
+// Variant 1 (direct): each thread reads its neighbours from global memory;
+// the row-by-row walk makes them L1/L2 hits in the common case.
 // ---------------------------------------------------------------------------
 template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE, bool VEL>
 __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
@@ -164,196 +379,199 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
 
   for (int ti = t_begin + jx; ti < t_end; ti += gx) {
     const int4 tl = A.tiles[ti];
-    const LatDev<T>& Lg = A.lats[tl.x];
-    // Lattice constants into registers (the stores below cannot alias them).
-    struct {
-      int64_t site_off, vec_off, phase_off;
-      T onsite_const, hop;
-      T blk[3][8];
-    } L;
+    LatRegs<T, KIND> L;
+    load_lat<T, KIND>(A.lats[tl.x], L);
     T vcs[NNB];
     if constexpr (VEL) {
 #pragma unroll
-      for (int k = 0; k < NNB; ++k) vcs[k] = Lg.vc[A.vdir][s][k];
+      for (int k = 0; k < NNB; ++k) vcs[k] = A.lats[tl.x].vc[A.vdir][s][k];
     }
-    L.site_off = Lg.site_off;
-    L.vec_off = Lg.vec_off;
-    L.phase_off = Lg.phase_off;
-    L.onsite_const = Lg.onsite_const;
-    L.hop = Lg.hop;
-    if constexpr (KIND == KPM_HONEYCOMB_SPIN) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) L.blk[k][q] = Lg.blk[k][q];
-    }
-    const int L1 = Lg.L1, L2 = Lg.L2;
+    const int L1 = L.L1, L2 = L.L2;
     const int n1 = tl.z + xl;
     const int c = tl.y * Ew + cl;
-    const bool act = (grp < n_grp) && (xl < A.Tx) && (n1 < L1) && (c < A.E) && (tid < n_grp * Ew);
+    const bool act = (grp < n_grp) && (xl < A.Tx) && (n1 < L1) && (c < A.E);
     if (act) {
       const T* __restrict__ vb = A.v + L.vec_off;
       const T* __restrict__ wb = A.w + L.vec_off;
       T* __restrict__ ob = A.out + L.vec_off;
+      T* __restrict__ velb = VEL ? A.vel + L.vec_off : nullptr;
       const int n1p = (n1 + 1 == L1) ? 0 : n1 + 1;
       const int n1m = (n1 == 0) ? L1 - 1 : n1 - 1;
-      // Hopping coefficients of this column (Peierls phases depend on n1 only).
       T hre[NNB], him[NNB];
-#pragma unroll
-      for (int k = 0; k < NNB; ++k) { hre[k] = L.hop; him[k] = (T)0; }
-      if constexpr (PHASE) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          // Table index = the A site's cell n1 (the B' image is unwrapped).
-          const int na = (s == 0) ? n1 : ((k == 1) ? n1m : n1);
-          const T pre = A.phase[2 * (L.phase_off + (int64_t)na * 3 + k)];
-          const T pim = A.phase[2 * (L.phase_off + (int64_t)na * 3 + k) + 1];
-          hre[k] = pre;
-          him[k] = (s == 0) ? pim : -pim;   // B side: conjugate
-          if constexpr (KIND != KPM_HONEYCOMB_SPIN) {
-            hre[k] *= L.hop;
-            him[k] *= L.hop;
-          }
-        }
-      }
+      column_coefficients<T, KIND, PHASE>(A, L, s, n1, n1m, hre, him);
       const int yend = min(tl.w + A.Ty, L2);
+      const int64_t coff = (int64_t)c * NC * 2;
       for (int y = tl.w; y < yend; ++y) {
         const int ym = (y == 0) ? L2 - 1 : y - 1;
         const int yp = (y + 1 == L2) ? 0 : y + 1;
         const int64_t site = ((int64_t)y * L1 + n1) * NSUB + s;
         int64_t nb[NNB];
-        if constexpr (KIND == KPM_SQUARE) {
-          nb[0] = (int64_t)y * L1 + n1p;
-          nb[1] = (int64_t)y * L1 + n1m;
-          nb[2] = (int64_t)yp * L1 + n1;
-          nb[3] = (int64_t)ym * L1 + n1;
-        } else {
-          if (s == 0) {   // A(n) <- B(n), B(n + (1,-1)), B(n + (0,-1))
-            nb[0] = ((int64_t)y * L1 + n1) * 2 + 1;
-            nb[1] = ((int64_t)ym * L1 + n1p) * 2 + 1;
-            nb[2] = ((int64_t)ym * L1 + n1) * 2 + 1;
-          } else {        // B(n) <- A(n), A(n - (1,-1)), A(n - (0,-1))
-            nb[0] = ((int64_t)y * L1 + n1) * 2;
-            nb[1] = ((int64_t)yp * L1 + n1m) * 2;
-            nb[2] = ((int64_t)yp * L1 + n1) * 2;
-          }
-        }
-        const int64_t coff = (int64_t)c * NC * 2;
+        neighbours<KIND>(s, n1, n1p, n1m, y, ym, yp, L1, nb);
         P vo[NSPIN], wo[NSPIN], vn[NNB][NSPIN];
 #pragma unroll
         for (int sp = 0; sp < NSPIN; ++sp) {
           vo[sp] = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
-          if (A.read_w) {
-            if constexpr ((KPM_STEP_NT & 2) != 0) wo[sp] = ld_pack_nt(wb + (site * NSPIN + sp) * Rp * 2 + coff);
-            else wo[sp] = ld_pack(wb + (site * NSPIN + sp) * Rp * 2 + coff);
-          }
 #pragma unroll
           for (int k = 0; k < NNB; ++k) vn[k][sp] = ld_pack(vb + (nb[k] * NSPIN + sp) * Rp * 2 + coff);
         }
+        load_w<T, KIND>(A, wb, site, coff, wo);
         T ons = L.onsite_const;
         if constexpr (ONSITE) ons = A.onsite[L.site_off + site];
         bool alive = true;
         if constexpr (MASK) alive = A.mask[L.site_off + site] != 0;
-
         P out[NSPIN], vout[NSPIN];
-#pragma unroll
-        for (int sp = 0; sp < NSPIN; ++sp) {
-#pragma unroll
-          for (int j = 0; j < NC; ++j) {
-            T hr = ons * vo[sp].v[2 * j], hi = ons * vo[sp].v[2 * j + 1];
-            T gr = 0, gi = 0;   // velocity accumulator
-#pragma unroll
-            for (int k = 0; k < NNB; ++k) {
-              // term_k = (hop from neighbour k) applied to v_k, rescaled units.
-              T tr = 0, ti = 0;
-              if constexpr (KIND == KPM_HONEYCOMB_SPIN) {
-                // A side: B_k[sigma][s'] v_k,s';  B side: conj(B_k[s'][sigma]) v_k,s'.
-                T br = 0, bi = 0;
-#pragma unroll
-                for (int s2 = 0; s2 < 2; ++s2) {
-                  T er, ei;
-                  if (s == 0) {
-                    er = L.blk[k][2 * (sp * 2 + s2)];
-                    ei = L.blk[k][2 * (sp * 2 + s2) + 1];
-                  } else {
-                    er = L.blk[k][2 * (s2 * 2 + sp)];
-                    ei = -L.blk[k][2 * (s2 * 2 + sp) + 1];
-                  }
-                  cmul_acc(br, bi, er, ei, vn[k][s2].v[2 * j], vn[k][s2].v[2 * j + 1]);
-                }
-                if constexpr (PHASE) cmul_acc(tr, ti, hre[k], him[k], br, bi);
-                else { tr = br; ti = bi; }
-              } else {
-                if constexpr (PHASE) {
-                  cmul_acc(tr, ti, hre[k], him[k], vn[k][0].v[2 * j], vn[k][0].v[2 * j + 1]);
-                } else {
-                  tr = L.hop * vn[k][0].v[2 * j];
-                  ti = L.hop * vn[k][0].v[2 * j + 1];
-                }
-              }
-              hr += tr;
-              hi += ti;
-              if constexpr (VEL) {
-                gr += vcs[k] * tr;
-                gi += vcs[k] * ti;
-              }
-            }
-            T orr = A.a * hr, oi = A.a * hi;
-            if (A.read_w) {
-              orr -= A.b * wo[sp].v[2 * j];
-              oi -= A.b * wo[sp].v[2 * j + 1];
-            }
-            if (!alive) { orr = 0; oi = 0; gr = 0; gi = 0; }
-            out[sp].v[2 * j] = orr;
-            out[sp].v[2 * j + 1] = oi;
-            if constexpr (VEL) {
-              vout[sp].v[2 * j] = A.vel_scale * gr;
-              vout[sp].v[2 * j + 1] = A.vel_scale * gi;
-            }
-            const double xr = (double)vo[sp].v[2 * j], xi = (double)vo[sp].v[2 * j + 1];
-            vv[j] += xr * xr + xi * xi;
-            wv[j] += (double)orr * xr + (double)oi * xi;
-          }
-          const int64_t eo = (site * NSPIN + sp) * Rp * 2 + coff;
-          if (A.write_out) {
-            if constexpr ((KPM_STEP_NT & 1) != 0) st_pack_nt(ob + eo, out[sp]);
-            else st_pack(ob + eo, out[sp]);
-          }
-          if constexpr (VEL) {
-            if constexpr ((KPM_STEP_NT & 1) != 0) st_pack_nt(A.vel + L.vec_off + eo, vout[sp]);
-            else st_pack(A.vel + L.vec_off + eo, vout[sp]);
-          }
-        }
+        site_update<T, KIND, PHASE, VEL>(A, L, s, hre, him, vcs, ons, alive, vo, wo, vn, out, vout, vv, wv);
+        store_site<T, KIND, VEL>(A, ob, velb, site, coff, out, vout);
       }
     }
     // Flush the accumulators when the next tile of this workgroup belongs to
     // another moment slot (another lattice / r-group) or this was the last.
     const int tn = ti + gx;
     const int slot = A.dots ? A.slot_of[ti] : 0;
-    if (A.dots && (tn >= t_end || A.slot_of[tn] != slot)) {
+    if (A.dots && (tn >= t_end || A.slot_of[tn] != slot)) flush_slot<NC>(lds, A.part, slot, tid, Ew, grp, n_grp, vv, wv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Variant 2 (LDS ring): the workgroup streams its tile row by row through a
+// four-slot ring of rows in LDS (cells x0-1 .. x0+Tx, both sublattices), so
+// every element of v_n is fetched from HBM once per tile and all neighbour
+// reads are LDS reads.  A-sites of row y need B rows y and y-1 (already in the
+// ring); B-sites need A rows y and y+1, so the walk loads row y+1 before
+// updating row y.  One barrier per row: the slot written at row y+1 was last
+// read two rows earlier.
+// ---------------------------------------------------------------------------
+template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE, bool VEL>
+__global__ void __launch_bounds__(1024) step_kernel_ring(StepArgs<T> A) {
+  using P = Pack<T>;
+  constexpr int NC = P::NC;
+  constexpr int NSUB = KindTraits<KIND>::NSUB;
+  constexpr int NSPIN = KindTraits<KIND>::NSPIN;
+  constexpr int NNB = KindTraits<KIND>::NNB;
+  extern __shared__ double lds[];
+
+  const int tid = threadIdx.x;
+  const int Ew = A.Ew;
+  const int cl = tid % Ew;
+  const int grp = tid / Ew;
+  const int n_grp = blockDim.x / Ew;
+  const int s = grp % NSUB;
+  const int xl = grp / NSUB;
+  const int Rp = A.Rp;
+  const int Tx = A.Tx;
+  // Ring layout: ring[slot][cell = xl + 1 in 0 .. Tx+1][sub][spin][chunk cl] as packs.
+  P* ring = reinterpret_cast<P*>(lds + (size_t)blockDim.x * 2 * NC);
+  const int row_packs = (Tx + 2) * NSUB * NSPIN * Ew;
+  auto ring_at = [&](int slot, int cell, int sub, int sp, int ch) -> P& {
+    return ring[(size_t)slot * row_packs + (((size_t)cell * NSUB + sub) * NSPIN + sp) * Ew + ch];
+  };
+
+  const int xcd = blockIdx.x & 7;
+  const int jx = blockIdx.x >> 3;
+  const int gx = gridDim.x >> 3;
+  const int t_begin = (int)(((int64_t)xcd * A.n_tiles) >> 3);
+  const int t_end = (int)(((int64_t)(xcd + 1) * A.n_tiles) >> 3);
+
+  double vv[NC], wv[NC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        lds[tid * 2 * NC + 2 * j] = vv[j];
-        lds[tid * 2 * NC + 2 * j + 1] = wv[j];
-        vv[j] = wv[j] = 0.0;
-      }
-      __syncthreads();
-      int p2 = 1;
-      while (p2 < n_grp) p2 <<= 1;
-      for (int st = p2 >> 1; st > 0; st >>= 1) {
-        if (grp < st && grp + st < n_grp) {
+  for (int j = 0; j < NC; ++j) vv[j] = wv[j] = 0.0;
+
+  for (int ti = t_begin + jx; ti < t_end; ti += gx) {
+    const int4 tl = A.tiles[ti];
+    LatRegs<T, KIND> L;
+    load_lat<T, KIND>(A.lats[tl.x], L);
+    T vcs[NNB];
+    if constexpr (VEL) {
 #pragma unroll
-          for (int q = 0; q < 2 * NC; ++q) lds[tid * 2 * NC + q] += lds[(tid + st * Ew) * 2 * NC + q];
-        }
-        __syncthreads();
-      }
-      if (tid < Ew) {
-        double* dst = A.part + ((int64_t)slot * Ew * NC + tid * NC) * 2;
-#pragma unroll
-        for (int q = 0; q < 2 * NC; ++q) dst[q] = lds[tid * 2 * NC + q];
-      }
-      __syncthreads();
+      for (int k = 0; k < NNB; ++k) vcs[k] = A.lats[tl.x].vc[A.vdir][s][k];
     }
+    const int L1 = L.L1, L2 = L.L2;
+    const int x0 = tl.z, y0 = tl.w;
+    const int tx_eff = min(Tx, L1 - x0);          // valid cells of this tile column
+    const int n1 = x0 + xl;
+    const int c = tl.y * Ew + cl;
+    const bool lane_ok = (grp < n_grp) && (c < A.E);
+    const bool act = lane_ok && (xl < tx_eff);
+    const int64_t coff = (int64_t)c * NC * 2;
+    const T* __restrict__ vb = A.v + L.vec_off;
+    const T* __restrict__ wb = A.w + L.vec_off;
+    T* __restrict__ ob = A.out + L.vec_off;
+    T* __restrict__ velb = VEL ? A.vel + L.vec_off : nullptr;
+    // Halo cells: the left neighbour column x0-1 and the right one x0+tx_eff
+    // (both wrapped).  They are loaded by the threads of the first and last
+    // valid cell column (one extra load each per row).
+    const int hl = (x0 == 0) ? L1 - 1 : x0 - 1;
+    const int hr = (x0 + tx_eff == L1) ? 0 : x0 + tx_eff;
+    // Honeycomb: only B-sites read the left column (sublattice A) and only
+    // A-sites read the right column (sublattice B).
+    const bool load_left = lane_ok && (xl == 0) && (KIND == KPM_SQUARE || s == 0);
+    const bool load_right = lane_ok && (xl == tx_eff - 1) && (KIND == KPM_SQUARE || s == 1);
+    auto load_row = [&](int yy, int slot) {
+      // yy in [0, L2): this thread's own cell and, for edge threads, one halo cell.
+      if (act) {
+        const int64_t site = ((int64_t)yy * L1 + n1) * NSUB + s;
+#pragma unroll
+        for (int sp = 0; sp < NSPIN; ++sp) ring_at(slot, xl + 1, s, sp, cl) = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
+      }
+      if (load_left) {
+        const int64_t site = ((int64_t)yy * L1 + hl) * NSUB + s;
+#pragma unroll
+        for (int sp = 0; sp < NSPIN; ++sp) ring_at(slot, 0, s, sp, cl) = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
+      }
+      if (load_right) {
+        const int64_t site = ((int64_t)yy * L1 + hr) * NSUB + s;
+#pragma unroll
+        for (int sp = 0; sp < NSPIN; ++sp)
+          ring_at(slot, tx_eff + 1, s, sp, cl) = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
+      }
+    };
+    const int n1m = (n1 == 0) ? L1 - 1 : n1 - 1;
+    T hre[NNB], him[NNB];
+    column_coefficients<T, KIND, PHASE>(A, L, s, act ? n1 : 0, act ? n1m : 0, hre, him);
+    const int yend = min(y0 + A.Ty, L2);
+    // Prologue: rows y0-1 and y0 into slots 3 and 0 (slot of row y0+k is k & 3).
+    load_row(y0 == 0 ? L2 - 1 : y0 - 1, 3);
+    load_row(y0, 0);
+    for (int y = y0; y < yend; ++y) {
+      const int k = y - y0;
+      const int sy = k & 3, sm = (k + 3) & 3, sp1 = (k + 1) & 3;
+      load_row(y + 1 == L2 ? 0 : y + 1, sp1);
+      __syncthreads();
+      if (act) {
+        const int64_t site = ((int64_t)y * L1 + n1) * NSUB + s;
+        P vo[NSPIN], wo[NSPIN], vn[NNB][NSPIN];
+#pragma unroll
+        for (int sp = 0; sp < NSPIN; ++sp) {
+          vo[sp] = ring_at(sy, xl + 1, s, sp, cl);
+          if constexpr (KIND == KPM_SQUARE) {
+            vn[0][sp] = ring_at(sy, xl + 2, 0, sp, cl);
+            vn[1][sp] = ring_at(sy, xl, 0, sp, cl);
+            vn[2][sp] = ring_at(sp1, xl + 1, 0, sp, cl);
+            vn[3][sp] = ring_at(sm, xl + 1, 0, sp, cl);
+          } else if (s == 0) {
+            vn[0][sp] = ring_at(sy, xl + 1, 1, sp, cl);
+            vn[1][sp] = ring_at(sm, xl + 2, 1, sp, cl);
+            vn[2][sp] = ring_at(sm, xl + 1, 1, sp, cl);
+          } else {
+            vn[0][sp] = ring_at(sy, xl + 1, 0, sp, cl);
+            vn[1][sp] = ring_at(sp1, xl, 0, sp, cl);
+            vn[2][sp] = ring_at(sp1, xl + 1, 0, sp, cl);
+          }
+        }
+        load_w<T, KIND>(A, wb, site, coff, wo);
+        T ons = L.onsite_const;
+        if constexpr (ONSITE) ons = A.onsite[L.site_off + site];
+        bool alive = true;
+        if constexpr (MASK) alive = A.mask[L.site_off + site] != 0;
+        P out[NSPIN], vout[NSPIN];
+        site_update<T, KIND, PHASE, VEL>(A, L, s, hre, him, vcs, ons, alive, vo, wo, vn, out, vout, vv, wv);
+        store_site<T, KIND, VEL>(A, ob, velb, site, coff, out, vout);
+      }
+    }
+    __syncthreads();   // the next tile reuses the ring
+    const int tn = ti + gx;
+    const int slot = A.dots ? A.slot_of[ti] : 0;
+    if (A.dots && (tn >= t_end || A.slot_of[tn] != slot)) flush_slot<NC>(lds, A.part, slot, tid, Ew, grp, n_grp, vv, wv);
   }
 }
 
@@ -527,32 +745,38 @@ __global__ void zero_int(int* p) { *p = 0; }
 // ---------------------------------------------------------------------------
 // Plan
 // ---------------------------------------------------------------------------
+template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE, bool VEL>
+static void* pick_variant(int variant) {
+  if (variant == 2) return (void*)step_kernel_ring<T, KIND, ONSITE, MASK, PHASE, VEL>;
+  return (void*)step_kernel<T, KIND, ONSITE, MASK, PHASE, VEL>;
+}
+
 template <typename T, int KIND, bool VEL>
-static void* pick_step(bool onsite, bool mask, bool phase) {
+static void* pick_step(int variant, bool onsite, bool mask, bool phase) {
   const int k = (onsite ? 4 : 0) | (mask ? 2 : 0) | (phase ? 1 : 0);
   switch (k) {
-    case 0: return (void*)step_kernel<T, KIND, false, false, false, VEL>;
-    case 1: return (void*)step_kernel<T, KIND, false, false, true, VEL>;
-    case 2: return (void*)step_kernel<T, KIND, false, true, false, VEL>;
-    case 3: return (void*)step_kernel<T, KIND, false, true, true, VEL>;
-    case 4: return (void*)step_kernel<T, KIND, true, false, false, VEL>;
-    case 5: return (void*)step_kernel<T, KIND, true, false, true, VEL>;
-    case 6: return (void*)step_kernel<T, KIND, true, true, false, VEL>;
-    default: return (void*)step_kernel<T, KIND, true, true, true, VEL>;
+    case 0: return pick_variant<T, KIND, false, false, false, VEL>(variant);
+    case 1: return pick_variant<T, KIND, false, false, true, VEL>(variant);
+    case 2: return pick_variant<T, KIND, false, true, false, VEL>(variant);
+    case 3: return pick_variant<T, KIND, false, true, true, VEL>(variant);
+    case 4: return pick_variant<T, KIND, true, false, false, VEL>(variant);
+    case 5: return pick_variant<T, KIND, true, false, true, VEL>(variant);
+    case 6: return pick_variant<T, KIND, true, true, false, VEL>(variant);
+    default: return pick_variant<T, KIND, true, true, true, VEL>(variant);
   }
 }
 
 template <typename T, bool VEL>
-static void* pick_step_kind(int kind, bool onsite, bool mask, bool phase) {
-  if (kind == KPM_HONEYCOMB) return pick_step<T, KPM_HONEYCOMB, VEL>(onsite, mask, phase);
-  if (kind == KPM_HONEYCOMB_SPIN) return pick_step<T, KPM_HONEYCOMB_SPIN, VEL>(onsite, mask, phase);
+static void* pick_step_kind(int kind, int variant, bool onsite, bool mask, bool phase) {
+  if (kind == KPM_HONEYCOMB) return pick_step<T, KPM_HONEYCOMB, VEL>(variant, onsite, mask, phase);
+  if (kind == KPM_HONEYCOMB_SPIN) return pick_step<T, KPM_HONEYCOMB_SPIN, VEL>(variant, onsite, mask, phase);
   // The square lattice has no Peierls table: only the (onsite, mask) variants exist.
   const int k = (onsite ? 2 : 0) | (mask ? 1 : 0);
   switch (k) {
-    case 0: return (void*)step_kernel<T, KPM_SQUARE, false, false, false, VEL>;
-    case 1: return (void*)step_kernel<T, KPM_SQUARE, false, true, false, VEL>;
-    case 2: return (void*)step_kernel<T, KPM_SQUARE, true, false, false, VEL>;
-    default: return (void*)step_kernel<T, KPM_SQUARE, true, true, false, VEL>;
+    case 0: return pick_variant<T, KPM_SQUARE, false, false, false, VEL>(variant);
+    case 1: return pick_variant<T, KPM_SQUARE, false, true, false, VEL>(variant);
+    case 2: return pick_variant<T, KPM_SQUARE, true, false, false, VEL>(variant);
+    default: return pick_variant<T, KPM_SQUARE, true, true, false, VEL>(variant);
   }
 }
 
@@ -661,6 +885,14 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
                        const kpm_tune_t* tune, kpm_plan** out) {
   KPM_CHECK_ARG(out != nullptr, "plan output pointer is NULL");
   *out = nullptr;
+  // No launch shape given: use the autotune cache (KPM_TUNE_CACHE) if it has one.
+  kpm_tune_t cached;
+  if (lat != nullptr && n_lat >= 1 && p != nullptr &&
+      (!tune || (tune->block == 0 && tune->rows == 0 && tune->grid == 0 && tune->kernel == 0))) {
+    std::memset(&cached, 0, sizeof(cached));
+    cached.use_graph = tune ? tune->use_graph : 1;
+    if (tune_cache_lookup(lat, n_lat, p, &cached)) tune = &cached;
+  }
   KPM_CHECK_ARG(lat != nullptr && n_lat >= 1, "need at least one lattice");
   KPM_CHECK_ARG(p != nullptr, "params is NULL");
   KPM_CHECK_ARG(p->num_moments >= 2, "num_moments must be >= 2");
@@ -920,12 +1152,20 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     delete P;
     return KPM_E_DEVICE;
   }
+  // Kernel variant: 2 = LDS row ring (default), 1 = direct loads.  The ring
+  // needs 4 rows of (Tx + 2) cells in LDS; fall back to direct loads when
+  // that exceeds 64 KiB.
+  const size_t ring_bytes = (size_t)P->block * 2 * P->NC * sizeof(double) +
+                            4 * (size_t)(P->Tx + 2) * P->n_sub * P->n_spin * P->Ew * 16;
+  P->variant = (tune && tune->kernel > 0) ? tune->kernel : 2;
+  if (P->variant == 2 && ring_bytes > 65536) P->variant = 1;
+  P->lds_bytes = (P->variant == 2) ? ring_bytes : (size_t)P->block * 2 * P->NC * sizeof(double);
   P->step_fn = (P->prec == KPM_FP32)
-                   ? pick_step_kind<float, false>(P->kind, P->has_onsite, P->has_mask, P->has_phase)
-                   : pick_step_kind<double, false>(P->kind, P->has_onsite, P->has_mask, P->has_phase);
+                   ? pick_step_kind<float, false>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase)
+                   : pick_step_kind<double, false>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase);
   P->step_fn_vel = (P->prec == KPM_FP32)
-                       ? pick_step_kind<float, true>(P->kind, P->has_onsite, P->has_mask, P->has_phase)
-                       : pick_step_kind<double, true>(P->kind, P->has_onsite, P->has_mask, P->has_phase);
+                       ? pick_step_kind<float, true>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase)
+                       : pick_step_kind<double, true>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase);
   *out = P;
   return KPM_OK;
 }
@@ -984,9 +1224,8 @@ static hipError_t launch_step_t(kpm_plan* P, hipStream_t s, const StepLaunch& L)
   a.dots = L.dots;
   a.vdir = L.vdir;
   a.part = L.part;
-  const size_t lds = (size_t)P->block * 2 * P->NC * sizeof(double);
   void* args[] = {&a};
-  return hipLaunchKernel(L.vel ? P->step_fn_vel : P->step_fn, dim3(P->grid), dim3(P->block), args, lds, s);
+  return hipLaunchKernel(L.vel ? P->step_fn_vel : P->step_fn, dim3(P->grid), dim3(P->block), args, P->lds_bytes, s);
 }
 
 hipError_t plan_launch_step(kpm_plan* P, hipStream_t s, const StepLaunch& L) {
@@ -1140,6 +1379,7 @@ int kpm_plan_info(kpm_plan_t* P, kpm_plan_info_t* info) {
   info->rows = P->Ty;
   info->tile_cells_x = P->Tx;
   info->r_padded = P->Rp;
+  info->kernel = P->variant;
   info->n_orbitals = P->n_orb;
   info->bytes_per_step = P->bytes_per_step;
   info->n_active_total = P->n_active_total;

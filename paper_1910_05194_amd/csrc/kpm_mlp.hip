@@ -170,6 +170,39 @@ __global__ void init_uniform_kernel(float* p, int64_t n, uint64_t key, float sca
   p[i] = (float)((2.0 * sm_uniform(key, (uint64_t)i) - 1.0) * scale);
 }
 
+// Column statistics of a [n][cols] table (FP64, fixed order): shift = mean,
+// scale = standard deviation (1 where it vanishes).
+__global__ void column_stats_kernel(const float* X, int64_t n, int cols, float* shift, float* scale) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += X[i * cols + j];
+  const double mean = s / (double)n;
+  double v = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double d = X[i * cols + j] - mean;
+    v += d * d;
+  }
+  const double sd = sqrt(v / (double)n);
+  shift[j] = (float)mean;
+  scale[j] = sd > 0.0 ? (float)sd : 1.0f;
+}
+
+// out = (in - shift) / scale  (forward = 1)  or  out = shift + scale * in (forward = 0), column-wise.
+__global__ void affine_kernel(const float* in, float* out, int64_t rows, int cols, const float* shift,
+                              const float* scale, int forward) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * cols) return;
+  const int j = (int)(i % cols);
+  out[i] = forward ? (in[i] - shift[j]) / scale[j] : shift[j] + scale[j] * in[i];
+}
+
+// w' = w * scale (loss weights in normalised output units).
+__global__ void mul_kernel(const float* a, const float* b, float* out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] * b[i];
+}
+
 __global__ void fill_f32(float* p, int64_t n, float v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -191,6 +224,10 @@ struct kpm_mlp {
   float *dA = nullptr, *dZ = nullptr;
   double* partial = nullptr;
   double* loss_dev = nullptr;
+  // Optional per-column standardisation of inputs and outputs.
+  bool scaled = false;
+  float *x_shift = nullptr, *x_scale = nullptr, *y_shift = nullptr, *y_scale = nullptr;
+  float *Xn = nullptr, *Tn = nullptr, *wn = nullptr;   // workspace: normalised batch, weights
 };
 
 namespace kpm {
@@ -213,6 +250,10 @@ static int mlp_reserve(kpm_mlp* N, int B) {
   KPM_TRY_HIP(hipMalloc(&N->dY, o * 4));
   KPM_TRY_HIP(hipMalloc(&N->dA, wmax * 4));
   KPM_TRY_HIP(hipMalloc(&N->dZ, wmax * 4));
+  if (N->Xn) (void)hipFree(N->Xn);
+  if (N->Tn) (void)hipFree(N->Tn);
+  KPM_TRY_HIP(hipMalloc(&N->Xn, (int64_t)B * N->n_in * 4));
+  KPM_TRY_HIP(hipMalloc(&N->Tn, o * 4));
   N->cap_b = B;
   return KPM_OK;
 }
@@ -268,6 +309,24 @@ static void forward_backward(kpm_mlp* N, const float* X, const float* T, const f
   gemm<true, false, false, EPI_NONE>(X, ni, N->dZ, nh, G + N->off[0], nh, nullptr, nullptr, ni, nh, B, s);
   hipLaunchKernelGGL(bias_grad_kernel, dim3((unsigned)ceil_div(nh, 256)), dim3(256), 0, s, N->dZ, B, nh,
                      G + N->off[1]);
+}
+
+// With standardisation the network sees x' = (x - mx)/sx and predicts
+// y' = (y - my)/sy; the loss (w (y - t))^2 = (w sy (y' - t'))^2 is unchanged.
+static void normalised_forward_backward(kpm_mlp* N, const float* X, const float* T, const float* w, int B,
+                                        hipStream_t s) {
+  if (!N->scaled) {
+    forward_backward(N, X, T, w, B, s);
+    return;
+  }
+  const int64_t nx = (int64_t)B * N->n_in, ny = (int64_t)B * N->n_out;
+  hipLaunchKernelGGL(affine_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, s, X, N->Xn, (int64_t)B, N->n_in,
+                     N->x_shift, N->x_scale, 1);
+  hipLaunchKernelGGL(affine_kernel, dim3((unsigned)ceil_div(ny, 256)), dim3(256), 0, s, T, N->Tn, (int64_t)B, N->n_out,
+                     N->y_shift, N->y_scale, 1);
+  hipLaunchKernelGGL(mul_kernel, dim3((unsigned)ceil_div(N->n_out, 256)), dim3(256), 0, s, w, N->y_scale, N->wn,
+                     N->n_out);
+  forward_backward(N, N->Xn, N->Tn, N->wn, B, s);
 }
 
 }  // namespace kpm
@@ -326,7 +385,7 @@ int kpm_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, uint64_t seed,
 int kpm_mlp_destroy(kpm_mlp_t* N) {
   if (!N) return KPM_OK;
   void* bufs[] = {N->par, N->grad, N->m, N->v, N->Z1, N->A1, N->Z2, N->A2, N->Y, N->dY, N->dA, N->dZ, N->partial,
-                  N->loss_dev};
+                  N->loss_dev, N->x_shift, N->x_scale, N->y_shift, N->y_scale, N->Xn, N->Tn, N->wn};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete N;
@@ -382,8 +441,39 @@ int kpm_mlp_forward(kpm_mlp_t* N, const float* x, int32_t batch, float* y, int32
   KPM_CHECK_ARG(N && x && y && batch >= 1, "bad arguments");
   KPM_TRY(mlp_reserve(N, batch));
   hipStream_t s = (hipStream_t)hip_stream;
-  forward(N, x, batch, use_bf16 != 0, y, s);
+  if (N->scaled) {
+    const int64_t nx = (int64_t)batch * N->n_in, ny = (int64_t)batch * N->n_out;
+    hipLaunchKernelGGL(affine_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, s, x, N->Xn, (int64_t)batch,
+                       N->n_in, N->x_shift, N->x_scale, 1);
+    forward(N, N->Xn, batch, use_bf16 != 0, y, s);
+    hipLaunchKernelGGL(affine_kernel, dim3((unsigned)ceil_div(ny, 256)), dim3(256), 0, s, y, y, (int64_t)batch,
+                       N->n_out, N->y_shift, N->y_scale, 0);
+  } else {
+    forward(N, x, batch, use_bf16 != 0, y, s);
+  }
   KPM_TRY_HIP(hipGetLastError());
+  return KPM_OK;
+}
+
+int kpm_mlp_fit_scaling(kpm_mlp_t* N, const float* x, const float* target, int64_t n_rows, void* hip_stream) {
+  using namespace kpm;
+  clear_error();
+  KPM_CHECK_ARG(N && x && target && n_rows >= 1, "bad arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (!N->x_shift) {
+    KPM_TRY_HIP(hipMalloc(&N->x_shift, N->n_in * 4));
+    KPM_TRY_HIP(hipMalloc(&N->x_scale, N->n_in * 4));
+    KPM_TRY_HIP(hipMalloc(&N->y_shift, N->n_out * 4));
+    KPM_TRY_HIP(hipMalloc(&N->y_scale, N->n_out * 4));
+    KPM_TRY_HIP(hipMalloc(&N->wn, N->n_out * 4));
+  }
+  hipLaunchKernelGGL(column_stats_kernel, dim3((unsigned)ceil_div(N->n_in, 64)), dim3(64), 0, s, x, n_rows, N->n_in,
+                     N->x_shift, N->x_scale);
+  hipLaunchKernelGGL(column_stats_kernel, dim3((unsigned)ceil_div(N->n_out, 64)), dim3(64), 0, s, target, n_rows,
+                     N->n_out, N->y_shift, N->y_scale);
+  KPM_TRY_HIP(hipGetLastError());
+  KPM_TRY_HIP(hipStreamSynchronize(s));
+  N->scaled = true;
   return KPM_OK;
 }
 
@@ -394,7 +484,7 @@ int kpm_mlp_gradients(kpm_mlp_t* N, const float* x, const float* target, const f
   KPM_CHECK_ARG(N && x && target && weights && batch >= 1, "bad arguments");
   KPM_TRY(mlp_reserve(N, batch));
   hipStream_t s = (hipStream_t)hip_stream;
-  forward_backward(N, x, target, weights, batch, s);
+  normalised_forward_backward(N, x, target, weights, batch, s);
   KPM_TRY_HIP(hipGetLastError());
   KPM_TRY_HIP(hipStreamSynchronize(s));
   if (loss) KPM_TRY_HIP(hipMemcpy(loss, N->loss_dev, sizeof(double), hipMemcpyDeviceToHost));
@@ -410,7 +500,7 @@ int kpm_mlp_train_step(kpm_mlp_t* N, const float* x, const float* target, const 
   KPM_CHECK_ARG(lr > 0.f && std::isfinite(lr), "lr must be > 0");
   KPM_TRY(mlp_reserve(N, batch));
   hipStream_t s = (hipStream_t)hip_stream;
-  forward_backward(N, x, target, weights, batch, s);
+  normalised_forward_backward(N, x, target, weights, batch, s);
   N->t += 1;
   const double b1 = 0.9, b2 = 0.999;
   const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)N->t)));

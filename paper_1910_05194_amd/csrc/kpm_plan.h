@@ -27,6 +27,7 @@ int plan_set_vector_base(kpm_plan* P, int64_t r0);
 int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, const kpm_tune_t* tune,
                 kpm_plan** out);
 void plan_free(kpm_plan* P);
+bool tune_cache_lookup(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, kpm_tune_t* t);
 }  // namespace kpm
 
 struct kpm_plan {
@@ -62,6 +63,8 @@ struct kpm_plan {
   double* mean_dev = nullptr;
   void* step_fn = nullptr;
   void* step_fn_vel = nullptr;
+  int variant = 2;             // 1 = direct-load step kernel, 2 = LDS row ring
+  size_t lds_bytes = 0;
   int64_t r_base = 0;          // global index of the plan's first random vector
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_loop = nullptr;

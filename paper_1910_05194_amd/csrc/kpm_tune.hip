@@ -1,0 +1,149 @@
+// Launch-shape autotuner for the Chebyshev step kernel.
+//
+// The paper leaves the TILE size of its CPU blocking to the user, who must
+// tune it per machine (Sec. 3(b); Sec. 5, Table 1).  Here the analogous
+// choices are the kernel variant, workgroup size, rows per tile and the
+// persistent grid; kpm_autotune measures each candidate on the real workload
+// (a short recursion of probe_steps steps, timed with hipEvents on the
+// caller's stream) and records the fastest in a plain-text cache keyed by
+// (lattice kind, precision, padded vectors per orbital, floor(log2 orbitals)).
+// kpm_plan_create consults the cache named by the KPM_TUNE_CACHE environment
+// variable when the caller passes no launch shape.
+
+#include "kpm_internal.h"
+#include "kpm_plan.h"
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace kpm {
+
+struct TuneKey {
+  int kind, prec, rp, log2n;
+};
+
+static TuneKey make_key(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p) {
+  const int n_sub = lat[0].kind == KPM_SQUARE ? 1 : 2;
+  const int n_spin = lat[0].kind == KPM_HONEYCOMB_SPIN ? 2 : 1;
+  int64_t n_orb = 0;
+  for (int l = 0; l < n_lat; ++l) n_orb += (int64_t)lat[l].L1 * lat[l].L2 * n_sub * n_spin;
+  const int R = p->start == KPM_START_SITES ? p->num_sites : p->num_random;
+  const int nc = p->precision == KPM_FP32 ? 2 : 1;
+  TuneKey k;
+  k.kind = lat[0].kind;
+  k.prec = p->precision;
+  k.rp = (R + nc - 1) / nc * nc;
+  k.log2n = n_orb > 0 ? (int)std::floor(std::log2((double)n_orb)) : 0;
+  return k;
+}
+
+static std::mutex g_cache_mu;
+
+// Returns true and fills *t when the cache file has an entry for the key.
+bool tune_cache_lookup(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, kpm_tune_t* t) {
+  const char* path = std::getenv("KPM_TUNE_CACHE");
+  if (!path || !*path) return false;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  std::ifstream f(path);
+  if (!f) return false;
+  const TuneKey k = make_key(lat, n_lat, p);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream is(line);
+    int kind, prec, rp, lg, kern, block, rows, grid;
+    double gbs;
+    if (!(is >> kind >> prec >> rp >> lg >> kern >> block >> rows >> grid >> gbs)) continue;
+    if (kind == k.kind && prec == k.prec && rp == k.rp && lg == k.log2n) {
+      t->kernel = kern;
+      t->block = block;
+      t->rows = rows;
+      t->grid = grid;
+      found = true;   // the last matching line wins
+    }
+  }
+  return found;
+}
+
+static int tune_cache_store(const char* path, const TuneKey& k, const kpm_tune_t& t, double gbs) {
+  if (!path || !*path) return KPM_OK;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  std::ofstream f(path, std::ios::app);
+  if (!f) {
+    set_error("cannot append to tune cache %s", path);
+    return KPM_E_INVALID;
+  }
+  f << k.kind << ' ' << k.prec << ' ' << k.rp << ' ' << k.log2n << ' ' << t.kernel << ' ' << t.block << ' ' << t.rows
+    << ' ' << t.grid << ' ' << gbs << '\n';
+  return KPM_OK;
+}
+
+static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, int32_t probe_steps,
+                    const char* cache_path, kpm_tune_t* best, double* best_gbs, void* stream) {
+  KPM_CHECK_ARG(lat && p && best && n_lat >= 1, "NULL argument");
+  KPM_CHECK_ARG(probe_steps >= 2 && probe_steps <= 4096, "probe_steps must be in [2, 4096]");
+  kpm_dos_params_t q = *p;
+  q.num_moments = 2 * probe_steps;
+  const int kernels[2] = {1, 2};
+  const int blocks[2] = {256, 512};
+  const int rows_c[3] = {32, 128, 512};
+  const int grids[2] = {1024, 2048};
+  double best_rate = -1.0;
+  kpm_tune_t bt;
+  std::memset(&bt, 0, sizeof(bt));
+  for (int kv : kernels)
+    for (int b : blocks)
+      for (int r : rows_c)
+        for (int g : grids) {
+          kpm_tune_t t;
+          std::memset(&t, 0, sizeof(t));
+          t.kernel = kv;
+          t.block = b;
+          t.rows = r;
+          t.grid = g;
+          t.use_graph = 1;
+          kpm_plan* P = nullptr;
+          int st = plan_create(lat, n_lat, &q, &t, &P);
+          if (st != KPM_OK) return st;
+          if (P->variant != kv) {   // the ring did not fit in LDS: skip the duplicate
+            plan_free(P);
+            delete P;
+            continue;
+          }
+          st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
+          if (st == KPM_OK) st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
+          kpm_plan_info_t info;
+          if (st == KPM_OK) st = kpm_plan_info(P, &info);
+          plan_free(P);
+          delete P;
+          if (st != KPM_OK && st != KPM_E_SPECTRUM) return st;
+          const double rate = info.bytes_per_step * info.n_steps / (info.last_loop_ms * 1e-3) / 1e9;
+          if (rate > best_rate) {
+            best_rate = rate;
+            bt = t;
+          }
+        }
+  *best = bt;
+  if (best_gbs) *best_gbs = best_rate;
+  return tune_cache_store(cache_path, make_key(lat, n_lat, p), bt, best_rate);
+}
+
+}  // namespace kpm
+
+extern "C" int kpm_autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, int32_t probe_steps,
+                            const char* cache_path, kpm_tune_t* best, double* best_gbs, void* hip_stream) {
+  try {
+    kpm::clear_error();
+    return kpm::autotune(lat, n_lat, p, probe_steps, cache_path, best, best_gbs, hip_stream);
+  } catch (...) {
+    kpm::set_error("internal error (exception) in kpm_autotune");
+    return KPM_E_DEVICE;
+  }
+}

@@ -54,15 +54,22 @@ class c_cond_params(ctypes.Structure):
                 ("gamma_mode", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
 
 
+class c_cond_stats(ctypes.Structure):
+    _fields_ = [("n_batches", ctypes.c_int32), ("vectors_per_batch", ctypes.c_int32), ("chain_ms", ctypes.c_double),
+                ("gemm_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("chain_bytes", ctypes.c_double),
+                ("gemm_useful_flops", ctypes.c_double), ("gemm_mfma_flops", ctypes.c_double),
+                ("gemm_operand_bytes", ctypes.c_double)]
+
+
 class c_tune(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("rows", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("kernel", ctypes.c_int32)]
 
 
 class c_plan_info(ctypes.Structure):
     _fields_ = [("n_steps", ctypes.c_int32), ("n_tiles", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("rows", ctypes.c_int32), ("tile_cells_x", ctypes.c_int32),
-                ("r_padded", ctypes.c_int32), ("n_orbitals", ctypes.c_int64), ("bytes_per_step", ctypes.c_double),
+                ("r_padded", ctypes.c_int32), ("kernel", ctypes.c_int32), ("n_orbitals", ctypes.c_int64), ("bytes_per_step", ctypes.c_double),
                 ("last_loop_ms", ctypes.c_double), ("last_run_ms", ctypes.c_double),
                 ("n_active_total", ctypes.c_int64)]
 
@@ -100,6 +107,10 @@ def _load():
         "kpm_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
         "kpm_mlp_train_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P]),
         "kpm_mlp_gradients": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P, _D, _P]),
+        "kpm_mlp_fit_scaling": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P]),
+        "kpm_cond_last_stats": (ctypes.c_int, [ctypes.POINTER(c_cond_stats)]),
+        "kpm_autotune": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, ctypes.POINTER(c_dos_params),
+                                        ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(c_tune), _D, _P]),
         "kpm_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                                ctypes.c_int32, ctypes.c_int32, _P, _D, _D]),
     }
@@ -196,13 +207,13 @@ class Plan:
     """kpm_plan_*: a reusable, graph-captured DOS/LDOS moment pipeline."""
 
     def __init__(self, lattices: Sequence, par, block: int = 0, rows: int = 0, grid: int = 0,
-                 use_graph: bool = True):
+                 use_graph: bool = True, kernel: int = 0):
         self.n_lat = len(lattices)
         self.R = _num_vectors(par)
         self.M = int(par.num_moments)
         lats = c_lattices(lattices)
         p, keep = c_params(par)
-        tune = c_tune(int(block), int(rows), int(grid), 1 if use_graph else 0)
+        tune = c_tune(int(block), int(rows), int(grid), 1 if use_graph else 0, int(kernel))
         h = _P()
         _check(LIB.kpm_plan_create(lats, self.n_lat, ctypes.byref(p), ctypes.byref(tune), ctypes.byref(h)))
         del keep
@@ -299,6 +310,13 @@ def moments_cond(lattice, par, precision: int = FP32, max_batch: int = 0, out_de
     return g
 
 
+def cond_last_stats() -> dict:
+    """kpm_cond_last_stats of the calling thread."""
+    st = c_cond_stats()
+    _check(LIB.kpm_cond_last_stats(ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in c_cond_stats._fields_}
+
+
 def reconstruct_sigma(gamma, energies, e_min: float, e_max: float, orbitals_per_nm2: float, stream=None):
     """kpm_reconstruct_sigma: sigma_xx(E) in e^2/h from Gamma ([M, M] complex numpy or [M, M, 2] torch)."""
     if isinstance(gamma, np.ndarray):
@@ -385,6 +403,16 @@ class MLP:
                                      flat.ctypes.data, ctypes.byref(loss), _stream_handle(stream)))
         return self._unpack(flat), loss.value
 
+    def fit_scaling(self, x, target, stream=None):
+        """Standardise inputs and outputs column by column (statistics of x, target on the device)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        x = x.contiguous()
+        target = target.contiguous()
+        _check(LIB.kpm_mlp_fit_scaling(self._h, x.data_ptr(), target.data_ptr(), x.shape[0],
+                                       _stream_handle(stream)))
+
     def close(self):
         if getattr(self, "_h", None):
             LIB.kpm_mlp_destroy(self._h)
@@ -395,3 +423,16 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def autotune(lattices: Sequence, par, probe_steps: int = 16, cache_path: Optional[str] = None, stream=None) -> dict:
+    """kpm_autotune: the fastest launch shape for this workload (optionally appended to a cache file)."""
+    lats = c_lattices(lattices)
+    p, keep = c_params(par)
+    best = c_tune()
+    gbs = ctypes.c_double()
+    _check(LIB.kpm_autotune(lats, len(lattices), ctypes.byref(p), int(probe_steps),
+                            None if cache_path is None else cache_path.encode(), ctypes.byref(best),
+                            ctypes.byref(gbs), _stream_handle(stream)))
+    del keep
+    return {"kernel": best.kernel, "block": best.block, "rows": best.rows, "grid": best.grid, "GBs": gbs.value}

@@ -1,0 +1,114 @@
+"""C-ABI checks that need no GPU: exported symbols, struct layouts, argument validation.
+
+Validation errors are returned before any device call, so they run on a CPU host.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kpm.h")
+LIB = os.path.join(ROOT, "paper_1910_05194_amd", "libkpm.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libkpm.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(kpm_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_function_is_exported():
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (kpm_\w+)", out))
+    assert set(names) <= exported
+    # Nothing exported that the header does not declare.
+    assert exported <= set(names), exported - set(names)
+
+
+STRUCTS = {
+    "kpm_lattice_t": "c_lattice",
+    "kpm_dos_params_t": "c_dos_params",
+    "kpm_tune_t": "c_tune",
+    "kpm_plan_info_t": "c_plan_info",
+    "kpm_cond_params_t": "c_cond_params",
+    "kpm_cond_stats_t": "c_cond_stats",
+}
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    from paper_1910_05194_amd import kpm
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "kpm.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(kpm, pyname)
+        src.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            src.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    src.append("  return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for ln in lines:
+        if ln:
+            parts = ln.split()
+            got[(parts[0], parts[1])] = int(parts[2])
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(kpm, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
+
+
+def test_argument_validation_without_device():
+    import workload as wl
+    from paper_1910_05194_amd import kpm
+    lat, par = wl.graphene_small()
+    bad = [
+        ([lat.replace(L1=1)], par, "L1, L2"),
+        ([lat.replace(e_min=9.0)], par, "e_min < e_max"),
+        ([lat.replace(flux=0.1)], par, "flux*L1"),
+        ([lat.replace(kind=wl.SQUARE, flux=1 / 64)], par, "square"),
+        ([lat.replace(rashba=0.1)], par, "Rashba"),
+        ([lat.replace(vacancy_p=1.0)], par, "vacancy_p"),
+        ([lat, lat.replace(kind=wl.SQUARE)], par, "same kind"),
+        ([lat], par.replace(num_moments=1), "num_moments"),
+        ([lat], par.replace(num_random=0), "num_random"),
+        ([lat], par.replace(precision=7), "precision"),
+        ([lat], par.replace(start=wl.START_SITES, sites=[lat.n_orbitals]), "out of range"),
+    ]
+    for lats, p, msg in bad:
+        with pytest.raises(kpm.KPMError) as e:
+            kpm.moments_dos(lats, p)
+        assert e.value.code == kpm.KPM_E_INVALID
+        assert msg in str(e.value), (msg, str(e.value))
+    with pytest.raises(kpm.KPMError) as e:
+        kpm.Plan([lat], par, block=100)
+    assert e.value.code == kpm.KPM_E_INVALID
+    lat3, par3 = wl.rashba_flux(L=8, M=8, R=1)
+    for p, msg in [(par3.replace(alpha=2), "alpha"), (par3.replace(gamma_mode=9), "gamma_mode")]:
+        with pytest.raises(kpm.KPMError) as e:
+            kpm.moments_cond(lat3, p)
+        assert msg in str(e.value)
+    with pytest.raises(kpm.KPMError):
+        kpm.moments_cond(lat3, par3, precision=wl.FP64)   # split-BF16 needs FP32 blocks
+    import numpy as np
+    with pytest.raises(kpm.KPMError):
+        kpm.reconstruct_jackson(np.zeros(0), np.zeros(4), -1.0, 1.0)
+    with pytest.raises(kpm.KPMError):
+        kpm.reconstruct_jackson(np.ones(4), np.zeros(4), 1.0, -1.0)
+    with pytest.raises(kpm.KPMError):
+        kpm.bandwidth_probe(7, 1 << 20)
+    with pytest.raises(kpm.KPMError):
+        kpm.MLP(0, 16, 16)
+    assert kpm.last_error() != ""

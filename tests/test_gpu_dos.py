@@ -204,3 +204,50 @@ def test_jackson_reconstruction(K):
     rho64 = K.reconstruct_jackson(mean_o[:64], E, lat.e_min, lat.e_max)
     ref64 = okpm.dos(mean_o[:64], E, lat.e_min, lat.e_max)
     assert np.max(np.abs(rho64 - ref64)) <= 1e-12 * np.max(np.abs(ref64))
+
+
+@pytest.mark.parametrize("lat", RAGGED + [wl.Lattice(kind=wl.HONEYCOMB, L1=2, L2=3, t=-2.7, anderson_w=0.3,
+                                                      disorder_seed=1)],
+                         ids=lambda l: f"{wl.KIND_NAMES[l.kind]}{l.L1}x{l.L2}")
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
+def test_ring_and_direct_kernels_bitwise_equal(K, lat, prec):
+    """The LDS-ring and direct-load step kernels share the per-site arithmetic and
+    the reduction order; they agree to rounding (the compiler may contract the
+    two kernels' sums into FMAs differently), for several tile shapes."""
+    par = wl.DosParams(num_moments=40, num_random=5, vector_seed=8, precision=prec)
+    outs = []
+    for kernel in (1, 2):
+        # (block 384 keeps the ring of the spinful FP64 case within 64 KiB of LDS)
+        for tune in (dict(block=64, rows=3), dict(block=256, rows=0), dict(block=384, rows=7, grid=16)):
+            plan = K.Plan([lat], par, kernel=kernel, **tune)
+            assert plan.info()["kernel"] == kernel
+            mu = np.zeros((1, 5, 40))
+            plan.run(mu)
+            plan.close()
+            outs.append(mu)
+    tol_pair = 1e-12 if prec == wl.FP64 else 2e-6
+    for o in outs[1:]:
+        assert np.max(np.abs(o - outs[0])) <= tol_pair
+    mu_o, _ = oracle_moments(lat, par)
+    tol = 1e-10 if prec == wl.FP64 else fp32_tol(40)
+    assert np.max(np.abs(outs[4][0] - mu_o)) <= tol
+
+
+def test_autotune_cache(K, tmp_path, monkeypatch):
+    lat = wl.Lattice(kind=wl.HONEYCOMB, L1=96, L2=80, t=-2.7, anderson_w=1.0, disorder_seed=3)
+    par = wl.DosParams(num_moments=64, num_random=4, vector_seed=1, precision=wl.FP32)
+    cache = str(tmp_path / "tune.txt")
+    best = K.autotune([lat], par, probe_steps=4, cache_path=cache)
+    assert best["kernel"] in (1, 2) and best["block"] in (256, 512) and best["GBs"] > 0
+    line = open(cache).read().strip().split()
+    assert [int(v) for v in line[4:8]] == [best["kernel"], best["block"], best["rows"], best["grid"]]
+    monkeypatch.setenv("KPM_TUNE_CACHE", cache)
+    plan = K.Plan([lat], par)
+    info = plan.info()
+    assert (info["kernel"], info["block"], info["rows"], info["grid"]) == \
+        (best["kernel"], best["block"], best["rows"], best["grid"])
+    mu = np.zeros((1, 4, 64))
+    plan.run(mu)
+    plan.close()
+    mu_o, _ = oracle_moments(lat, par)
+    assert np.max(np.abs(mu[0] - mu_o)) <= fp32_tol(64)
