@@ -21,10 +21,10 @@
 
 namespace kpm {
 
-hipError_t gamma_accumulate_bf16(const float* L, const float* R, int M, int64_t Kq, int64_t ld, int KS,
-                                 double* part, double* acc, hipStream_t s);
+hipError_t gamma_accumulate_bf16(const __bf16* Lh, const __bf16* Ll, const __bf16* Rh, const __bf16* Rl, int M,
+                                 int Mp, int64_t Kc, int KS, double* part, double* acc, hipStream_t s);
 template <typename T>
-hipError_t gamma_accumulate_fp64(const T* L, const T* R, int M, int64_t Kc, int64_t ld, int KS, double* part,
+hipError_t gamma_accumulate_fp64(const T* L, const T* R, int M, int Mp, int64_t Kc, int KS, double* part,
                                  double* acc, hipStream_t s);
 
 __global__ void zero_f64(double* p, int64_t n) {
@@ -92,8 +92,16 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   KPM_TRY(plan_create(lat, 1, &dp, &tune, &P));
 
   const int64_t vec_elems = n_orb * P->Rp * 2;   // T elements per Chebyshev vector
+  // Rows of the Gamma blocks: complex length padded to the 16-element K block (zeros).
+  const int64_t kpad = ceil_div(n_orb * P->Rp, 16) * 16;
+  const int64_t row_elems = 2 * kpad;
+  // Rows of the blocked store: M rounded up to the GEMM's 128-row tile (zeros).
+  const int Mp = (int)ceil_div(M, 128) * 128;
   const int KS = 64;
-  void *Lb = nullptr, *Rblk = nullptr;
+  // Split-BF16 mode stores each block as two BF16 planes (hi, lo): the same
+  // bytes as FP32; the FP64 mode stores the blocks in the vectors' precision.
+  const bool split = p->gamma_mode == KPM_GAMMA_SPLIT_BF16;
+  void *Lb = nullptr, *Rblk = nullptr, *Llo = nullptr, *Rlo = nullptr;
   double *acc = nullptr, *part = nullptr, *gdev = nullptr;
   int st = KPM_OK;
   auto fail = [&](hipError_t e, const char* what) {
@@ -101,8 +109,15 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
     (void)hipGetLastError();
     st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
   };
-  hipError_t e = hipMalloc(&Lb, (size_t)M * vec_elems * tsize);
-  if (e == hipSuccess) e = hipMalloc(&Rblk, (size_t)M * vec_elems * tsize);
+  const size_t plane_bytes = split ? (size_t)Mp * row_elems * 2 : (size_t)Mp * row_elems * tsize;
+  hipError_t e = hipMalloc(&Lb, plane_bytes);
+  if (e == hipSuccess) e = hipMalloc(&Rblk, plane_bytes);
+  if (e == hipSuccess && split) e = hipMalloc(&Llo, plane_bytes);
+  if (e == hipSuccess && split) e = hipMalloc(&Rlo, plane_bytes);
+  if (e == hipSuccess && (kpad != n_orb * P->Rp || Mp != M)) {   // padding rows / K block stay zero
+    for (void* b : {Lb, Rblk, Llo, Rlo})
+      if (b && e == hipSuccess) e = hipMemsetAsync(b, 0, plane_bytes, s);
+  }
   if (e == hipSuccess) e = hipMalloc(&acc, (size_t)M * M * 2 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&part, (size_t)KS * M * M * 2 * sizeof(double));
   if (e == hipSuccess && !on_dev) e = hipMalloc(&gdev, (size_t)M * M * 2 * sizeof(double));
@@ -118,7 +133,8 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   const double vec_bytes = (double)vec_elems * tsize;
   const double site_bytes = (P->has_onsite ? (double)P->n_sites * tsize : 0.0) + (P->has_mask ? (double)P->n_sites : 0.0);
   auto step_bytes = [&](const StepLaunch& S) {
-    return vec_bytes * (1.0 + S.read_w + S.write_out + (S.vel ? 1.0 : 0.0)) + site_bytes;
+    // The block copy costs one vector (FP32/FP64) or two BF16 planes (the same bytes in FP32).
+    return vec_bytes * (1.0 + S.read_w + S.write_out + (S.vel ? 1.0 : 0.0) + (S.blk ? 1.0 : 0.0)) + site_bytes;
   };
   if (st == KPM_OK) {
     hipLaunchKernelGGL(zero_f64, dim3((unsigned)ceil_div((int64_t)M * M * 2, 256)), dim3(256), 0, s, acc,
@@ -131,31 +147,45 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
     if (st != KPM_OK) break;
     e = plan_launch_prep(P, s);
     if (e != hipSuccess) { fail(e, "model/start kernels"); break; }
-    auto row = [&](void* base, int n) { return (void*)((char*)base + (size_t)n * vec_elems * tsize); };
     e = hipEventRecord(ev[0], s);
-    // L chain: L_0 = -h~^a xi, L_1 = H~ L_0, L_n = 2 H~ L_{n-1} - L_{n-2}.
+    // L chain: L_0 = -h~^a xi, L_1 = H~ L_0, L_n = 2 H~ L_{n-1} - L_{n-2}, kept in the
+    // plan's two vector buffers (L_n in X for odd n, in Y for even n >= 2) and
+    // copied row by row into the K-blocked block Lb.
     for (int n = 0; n < M && e == hipSuccess; ++n) {
       StepLaunch S;
       S.dots = 0;
+      S.blk = Lb;
+      S.blk_lo = Llo;
+      S.blk_row = n;
+      S.blk_rows = Mp;
       if (n == 0) {
         S.v = P->X; S.out = P->Y; S.write_out = 0; S.read_w = 0; S.a = 0.0; S.b = 0.0;
-        S.vel = row(Lb, 0); S.vdir = p->alpha; S.vel_scale = -1.0;
+        S.velocity = true; S.vel = P->Y; S.vdir = p->alpha; S.vel_scale = -1.0; S.blk_src = 1;
       } else if (n == 1) {
-        S.v = row(Lb, 0); S.out = row(Lb, 1); S.read_w = 0; S.a = 1.0; S.b = 0.0;
+        S.v = P->Y; S.out = P->X; S.read_w = 0; S.a = 1.0; S.b = 0.0;
       } else {
-        S.v = row(Lb, n - 1); S.w = row(Lb, n - 2); S.out = row(Lb, n); S.a = 2.0; S.b = 1.0;
+        const bool even = (n & 1) == 0;
+        S.v = even ? P->X : P->Y;
+        S.w = even ? P->Y : P->X;
+        S.out = even ? P->Y : P->X;
       }
       e = plan_launch_step(P, s, S);
       g_stats.chain_bytes += step_bytes(S);
     }
-    // R chain: v_0 = xi, v_1 = H~ v_0, v_{m+1} = 2 H~ v_m - v_{m-1} (in place),
-    // with R_m = h~^b v_m from the same pass.
+    // R chain: start again from xi; v_0 = xi, v_1 = H~ v_0, v_{m+1} = 2 H~ v_m - v_{m-1}
+    // (in place), with R_m = h~^b v_m from the same pass stored K-blocked in Rblk.
+    if (e == hipSuccess) e = plan_launch_prep(P, s);
     for (int m = 0; m < M && e == hipSuccess; ++m) {
       StepLaunch S;
       S.dots = 0;
+      S.velocity = true;
       S.vdir = p->beta;
       S.vel_scale = 1.0;
-      S.vel = row(Rblk, m);
+      S.blk = Rblk;
+      S.blk_lo = Rlo;
+      S.blk_src = 1;
+      S.blk_row = m;
+      S.blk_rows = Mp;
       if (m == 0) {
         S.v = P->X; S.out = P->Y; S.read_w = 0; S.a = 1.0; S.b = 0.0;
       } else {
@@ -171,17 +201,16 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
     if (e == hipSuccess) e = hipEventRecord(ev[1], s);
     if (e != hipSuccess) { fail(e, "Chebyshev chains"); break; }
     // Flops: 2 real GEMMs (Re, Im) of M x M over 2 vec_elems/2 reals = 4 M^2 vec_elems.
-    g_stats.gemm_useful_flops += 4.0 * M * (double)M * (double)vec_elems;
-    g_stats.gemm_mfma_flops += (p->gamma_mode == KPM_GAMMA_SPLIT_BF16 ? 3.0 : 1.0) * 4.0 * M * (double)M * vec_elems;
-    g_stats.gemm_operand_bytes += 2.0 * M * vec_bytes;
+    g_stats.gemm_useful_flops += 4.0 * M * (double)M * (double)row_elems;
+    g_stats.gemm_mfma_flops += (p->gamma_mode == KPM_GAMMA_SPLIT_BF16 ? 3.0 : 1.0) * 4.0 * M * (double)M * row_elems;
+    g_stats.gemm_operand_bytes += 2.0 * M * (double)row_elems * 4.0;
     if (p->gamma_mode == KPM_GAMMA_SPLIT_BF16) {
-      e = gamma_accumulate_bf16((const float*)Lb, (const float*)Rblk, M, vec_elems, vec_elems, KS, part, acc, s);
+      e = gamma_accumulate_bf16((const __bf16*)Lb, (const __bf16*)Llo, (const __bf16*)Rblk, (const __bf16*)Rlo, M,
+                                Mp, kpad, KS, part, acc, s);
     } else if (p->precision == KPM_FP32) {
-      e = gamma_accumulate_fp64<float>((const float*)Lb, (const float*)Rblk, M, vec_elems / 2, vec_elems, KS, part,
-                                       acc, s);
+      e = gamma_accumulate_fp64<float>((const float*)Lb, (const float*)Rblk, M, Mp, kpad, KS, part, acc, s);
     } else {
-      e = gamma_accumulate_fp64<double>((const double*)Lb, (const double*)Rblk, M, vec_elems / 2, vec_elems, KS,
-                                        part, acc, s);
+      e = gamma_accumulate_fp64<double>((const double*)Lb, (const double*)Rblk, M, Mp, kpad, KS, part, acc, s);
     }
     if (e == hipSuccess) e = hipEventRecord(ev[2], s);
     if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
@@ -211,7 +240,7 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   }
   for (auto& x : ev)
     if (x) (void)hipEventDestroy(x);
-  for (void* ptr : {Lb, Rblk, (void*)acc, (void*)part, (void*)gdev})
+  for (void* ptr : {Lb, Rblk, Llo, Rlo, (void*)acc, (void*)part, (void*)gdev})
     if (ptr) (void)hipFree(ptr);
   plan_free(P);
   delete P;

@@ -101,16 +101,24 @@ struct StepArgs {
   const T* __restrict__ v;
   const T* __restrict__ w;   // v_{n-1} (read when read_w)
   T* __restrict__ out;       // v_{n+1} (may equal w: in place)
-  T* __restrict__ vel;       // velocity output h~^dir v_n (VEL)
+  T* __restrict__ vel;       // velocity output h~^dir v_n (VEL; may be null)
+  T* __restrict__ blk;       // K-blocked copy of out (blk_src 0) or vel (blk_src 1), may be null
+  __bf16* __restrict__ blk_lo;   // split-BF16 store: blk holds the hi plane (as __bf16), blk_lo the lo plane
   const T* onsite;
   const uint8_t* mask;
   const T* phase;         // complex interleaved
   double* part;           // [n_slots][Rw][2] for this step
   T a, b;                 // v_{n+1} = a H~ v_n - b v_{n-1}
   T vel_scale;            // vel = vel_scale * [r^dir, H] v_n  (physical units, eV nm)
-  int read_w, write_out, dots, vdir;
+  int read_w, write_out, dots, vdir, blk_src;
+  int64_t blk_row, blk_rows;   // row of this vector in the blocked [K/16][rows][16] store
   int Tx, Ty, E, Ew, Rp;
 };
+
+// K-blocked store used by the Gamma GEMM: complex element e of row n lives at
+// ((e / 16) * rows + n) * 16 + e % 16, so that 32 consecutive rows of one
+// 16-element block are 4 KiB of contiguous memory.
+constexpr int kBlkK = 16;
 
 template <int KIND>
 struct KindTraits;
@@ -257,7 +265,7 @@ __device__ inline void site_update(const StepArgs<T>& A, const LatRegs<T, KIND>&
 }
 
 template <typename T, int KIND, bool VEL>
-__device__ inline void store_site(const StepArgs<T>& A, T* ob, T* velb, int64_t site, int64_t coff,
+__device__ inline void store_site(const StepArgs<T>& A, T* ob, T* velb, int64_t vec_off_c, int64_t site, int64_t coff,
                                   const Pack<T> (&out)[KindTraits<KIND>::NSPIN],
                                   const Pack<T> (&vout)[KindTraits<KIND>::NSPIN]) {
   constexpr int NSPIN = KindTraits<KIND>::NSPIN;
@@ -269,8 +277,29 @@ __device__ inline void store_site(const StepArgs<T>& A, T* ob, T* velb, int64_t 
       else st_pack(ob + eo, out[sp]);
     }
     if constexpr (VEL) {
-      if constexpr ((KPM_STEP_NT & 1) != 0) st_pack_nt(velb + eo, vout[sp]);
-      else st_pack(velb + eo, vout[sp]);
+      if (velb) {
+        if constexpr ((KPM_STEP_NT & 1) != 0) st_pack_nt(velb + eo, vout[sp]);
+        else st_pack(velb + eo, vout[sp]);
+      }
+    }
+    if (A.blk) {
+      const int64_t e = eo / 2 + vec_off_c;   // complex index in the batch vector
+      const int64_t b = (e / kBlkK) * A.blk_rows * kBlkK + A.blk_row * kBlkK + (e % kBlkK);
+      const Pack<T>& src = (VEL && A.blk_src == 1) ? vout[sp] : out[sp];
+      if (A.blk_lo == nullptr) {
+        st_pack(A.blk + 2 * b, src);
+      } else if constexpr (sizeof(T) == 4) {
+        // x = hi + lo with hi = bf16(x), lo = bf16(x - hi): 4 reals -> 4 + 4 bf16.
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 hi, lo;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          hi[q] = (__bf16)src.v[q];
+          lo[q] = (__bf16)(src.v[q] - (float)hi[q]);
+        }
+        *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(A.blk) + 2 * b) = hi;
+        *reinterpret_cast<bf16x4*>(A.blk_lo + 2 * b) = lo;
+      }
     }
   }
 }
@@ -394,7 +423,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
       const T* __restrict__ vb = A.v + L.vec_off;
       const T* __restrict__ wb = A.w + L.vec_off;
       T* __restrict__ ob = A.out + L.vec_off;
-      T* __restrict__ velb = VEL ? A.vel + L.vec_off : nullptr;
+      T* __restrict__ velb = (VEL && A.vel) ? A.vel + L.vec_off : nullptr;
       const int n1p = (n1 + 1 == L1) ? 0 : n1 + 1;
       const int n1m = (n1 == 0) ? L1 - 1 : n1 - 1;
       T hre[NNB], him[NNB];
@@ -421,7 +450,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
         if constexpr (MASK) alive = A.mask[L.site_off + site] != 0;
         P out[NSPIN], vout[NSPIN];
         site_update<T, KIND, PHASE, VEL>(A, L, s, hre, him, vcs, ons, alive, vo, wo, vn, out, vout, vv, wv);
-        store_site<T, KIND, VEL>(A, ob, velb, site, coff, out, vout);
+        store_site<T, KIND, VEL>(A, ob, velb, L.vec_off / 2, site, coff, out, vout);
       }
     }
     // Flush the accumulators when the next tile of this workgroup belongs to
@@ -496,7 +525,7 @@ __global__ void __launch_bounds__(1024) step_kernel_ring(StepArgs<T> A) {
     const T* __restrict__ vb = A.v + L.vec_off;
     const T* __restrict__ wb = A.w + L.vec_off;
     T* __restrict__ ob = A.out + L.vec_off;
-    T* __restrict__ velb = VEL ? A.vel + L.vec_off : nullptr;
+    T* __restrict__ velb = (VEL && A.vel) ? A.vel + L.vec_off : nullptr;
     // Halo cells: the left neighbour column x0-1 and the right one x0+tx_eff
     // (both wrapped).  They are loaded by the threads of the first and last
     // valid cell column (one extra load each per row).
@@ -565,7 +594,7 @@ __global__ void __launch_bounds__(1024) step_kernel_ring(StepArgs<T> A) {
         if constexpr (MASK) alive = A.mask[L.site_off + site] != 0;
         P out[NSPIN], vout[NSPIN];
         site_update<T, KIND, PHASE, VEL>(A, L, s, hre, him, vcs, ons, alive, vo, wo, vn, out, vout, vv, wv);
-        store_site<T, KIND, VEL>(A, ob, velb, site, coff, out, vout);
+        store_site<T, KIND, VEL>(A, ob, velb, L.vec_off / 2, site, coff, out, vout);
       }
     }
     __syncthreads();   // the next tile reuses the ring
@@ -1216,6 +1245,11 @@ static hipError_t launch_step_t(kpm_plan* P, hipStream_t s, const StepLaunch& L)
   a.w = (const T*)(L.w ? L.w : L.v);
   a.out = (T*)L.out;
   a.vel = (T*)L.vel;
+  a.blk = (T*)L.blk;
+  a.blk_lo = (__bf16*)L.blk_lo;
+  a.blk_src = L.blk_src;
+  a.blk_row = L.blk_row;
+  a.blk_rows = L.blk_rows;
   a.a = (T)L.a;
   a.b = (T)L.b;
   a.vel_scale = (T)L.vel_scale;
@@ -1225,7 +1259,8 @@ static hipError_t launch_step_t(kpm_plan* P, hipStream_t s, const StepLaunch& L)
   a.vdir = L.vdir;
   a.part = L.part;
   void* args[] = {&a};
-  return hipLaunchKernel(L.vel ? P->step_fn_vel : P->step_fn, dim3(P->grid), dim3(P->block), args, P->lds_bytes, s);
+  return hipLaunchKernel(L.velocity ? P->step_fn_vel : P->step_fn, dim3(P->grid), dim3(P->block), args,
+                         P->lds_bytes, s);
 }
 
 hipError_t plan_launch_step(kpm_plan* P, hipStream_t s, const StepLaunch& L) {

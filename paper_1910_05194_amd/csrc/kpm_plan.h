@@ -14,7 +14,12 @@ struct StepLaunch {
   const void* v = nullptr;     // v_n
   const void* w = nullptr;     // v_{n-1}
   void* out = nullptr;         // v_{n+1}
-  void* vel = nullptr;         // velocity output (nullptr = none)
+  bool velocity = false;       // compute the velocity stencil h~^vdir v_n
+  void* vel = nullptr;         // its standard-layout output (nullptr = not stored)
+  void* blk = nullptr;         // K-blocked store (Gamma blocks), nullptr = none
+  void* blk_lo = nullptr;      // non-null: store split BF16, hi plane in blk, lo plane here (FP32 only)
+  int blk_src = 0;             // 0: store v_{n+1}, 1: store the velocity
+  int64_t blk_row = 0, blk_rows = 0;
   double a = 2.0, b = 1.0;     // v_{n+1} = a H~ v_n - b v_{n-1}
   double vel_scale = 1.0;
   int read_w = 1, write_out = 1, dots = 1, vdir = 0;
