@@ -99,7 +99,7 @@ typedef struct kpm_dos_params_t {
 
 /* Optional launch shape of the Chebyshev step kernel (0 = library choice / autotune cache). */
 typedef struct kpm_tune_t {
-  int32_t block;           /* threads per workgroup (64..1024, multiple of 64) */
+  int32_t block;           /* threads per workgroup (64..512, multiple of 64) */
   int32_t rows;            /* lattice rows (along a2) per tile */
   int32_t grid;            /* persistent workgroups (multiple of 8); 0 = one per tile */
   int32_t use_graph;       /* 1 = replay the step loop as a captured hipGraph (default), 0 = eager */

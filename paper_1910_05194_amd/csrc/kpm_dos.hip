@@ -119,6 +119,9 @@ struct StepArgs {
 // ((e / 16) * rows + n) * 16 + e % 16, so that 32 consecutive rows of one
 // 16-element block are 4 KiB of contiguous memory.
 constexpr int kBlkK = 16;
+// Largest step workgroup.  Two waves per SIMD leave each wave 256 VGPRs, which
+// the spinful (2x2 hopping) kernels need to run without scratch spills.
+constexpr int kMaxStepBlock = 512;
 
 template <int KIND>
 struct KindTraits;
@@ -376,7 +379,7 @@ __device__ inline void neighbours(int s, int n1, int n1p, int n1m, int y, int ym
 // the row-by-row walk makes them L1/L2 hits in the common case.
 // ---------------------------------------------------------------------------
 template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE, bool VEL>
-__global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
+__global__ void __launch_bounds__(kMaxStepBlock) step_kernel(StepArgs<T> A) {
   using P = Pack<T>;
   constexpr int NC = P::NC;
   constexpr int NSUB = KindTraits<KIND>::NSUB;
@@ -471,7 +474,7 @@ __global__ void __launch_bounds__(1024) step_kernel(StepArgs<T> A) {
 // read two rows earlier.
 // ---------------------------------------------------------------------------
 template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE, bool VEL>
-__global__ void __launch_bounds__(1024) step_kernel_ring(StepArgs<T> A) {
+__global__ void __launch_bounds__(kMaxStepBlock) step_kernel_ring(StepArgs<T> A) {
   using P = Pack<T>;
   constexpr int NC = P::NC;
   constexpr int NSUB = KindTraits<KIND>::NSUB;
@@ -1008,8 +1011,8 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   P->block = (tune && tune->block > 0) ? tune->block : 256;
   P->Ty = (tune && tune->rows > 0) ? tune->rows : 64;
   P->use_graph = tune ? (tune->use_graph != 0) : true;
-  if (P->block < 64 || P->block > 1024 || (P->block % 64) != 0) {
-    set_error("block must be a multiple of 64 in [64, 1024]");
+  if (P->block < 64 || P->block > kMaxStepBlock || (P->block % 64) != 0) {
+    set_error("block must be a multiple of 64 in [64, %d]", kMaxStepBlock);
     delete P;
     return KPM_E_INVALID;
   }

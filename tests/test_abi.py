@@ -92,9 +92,10 @@ def test_argument_validation_without_device():
             kpm.moments_dos(lats, p)
         assert e.value.code == kpm.KPM_E_INVALID
         assert msg in str(e.value), (msg, str(e.value))
-    with pytest.raises(kpm.KPMError) as e:
-        kpm.Plan([lat], par, block=100)
-    assert e.value.code == kpm.KPM_E_INVALID
+    for blk in (100, 1024):
+        with pytest.raises(kpm.KPMError) as e:
+            kpm.Plan([lat], par, block=blk)
+        assert e.value.code == kpm.KPM_E_INVALID
     lat3, par3 = wl.rashba_flux(L=8, M=8, R=1)
     for p, msg in [(par3.replace(alpha=2), "alpha"), (par3.replace(gamma_mode=9), "gamma_mode")]:
         with pytest.raises(kpm.KPMError) as e:

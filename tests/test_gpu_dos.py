@@ -140,7 +140,7 @@ def test_plan_graph_replay_deterministic(K):
 
 
 @pytest.mark.parametrize("tune", [dict(block=64, rows=1, grid=8), dict(block=128, rows=3, grid=16),
-                                  dict(block=512, rows=8, grid=0), dict(block=1024, rows=64, grid=24)])
+                                  dict(block=512, rows=8, grid=0), dict(block=512, rows=64, grid=24)])
 def test_launch_shapes_agree(K, tune):
     lat = RAGGED[0]
     par = wl.DosParams(num_moments=40, num_random=5, vector_seed=3, precision=wl.FP64)
