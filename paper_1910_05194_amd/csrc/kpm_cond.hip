@@ -92,8 +92,8 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   KPM_TRY(plan_create(lat, 1, &dp, &tune, &P));
 
   const int64_t vec_elems = n_orb * P->Rp * 2;   // T elements per Chebyshev vector
-  // Rows of the Gamma blocks: complex length padded to the 16-element K block (zeros).
-  const int64_t kpad = ceil_div(n_orb * P->Rp, 16) * 16;
+  // Rows of the Gamma blocks: complex length padded to whole K blocks (zeros).
+  const int64_t kpad = ceil_div(n_orb * P->Rp, kBlkK) * kBlkK;
   const int64_t row_elems = 2 * kpad;
   // Rows of the blocked store: M rounded up to the GEMM's 128-row tile (zeros).
   const int Mp = (int)ceil_div(M, 128) * 128;

@@ -111,14 +111,13 @@ struct StepArgs {
   T a, b;                 // v_{n+1} = a H~ v_n - b v_{n-1}
   T vel_scale;            // vel = vel_scale * [r^dir, H] v_n  (physical units, eV nm)
   int read_w, write_out, dots, vdir, blk_src;
-  int64_t blk_row, blk_rows;   // row of this vector in the blocked [K/16][rows][16] store
+  int64_t blk_row, blk_rows;   // row of this vector in the blocked [K/kBlkK][rows][kBlkK] store
   int Tx, Ty, E, Ew, Rp;
 };
 
 // K-blocked store used by the Gamma GEMM: complex element e of row n lives at
 // ((e / 16) * rows + n) * 16 + e % 16, so that 32 consecutive rows of one
 // 16-element block are 4 KiB of contiguous memory.
-constexpr int kBlkK = 16;
 // Largest step workgroup.  Two waves per SIMD leave each wave 256 VGPRs, which
 // the spinful (2x2 hopping) kernels need to run without scratch spills.
 constexpr int kMaxStepBlock = 512;

@@ -2,10 +2,9 @@
 // Gammanm; storage and cost of Gamma in Sec. 2(b), "Numerical storage of Gamma").
 //
 // Blocks: L[n][k] and R[m][k] complex, n, m < M, k < K (orbitals x vectors),
-// stored K-blocked: element (n, k) at complex index ((k / 16) Mp + n) 16 + k % 16
-// (Mp >= M rows, a multiple of the 128-row tile, padding rows zero),
-// so that one 16-element K block of 32 consecutive rows is 4 KiB contiguous.
-// The kernels accumulate
+// stored K-blocked: element (n, k) at complex index ((k / kBlkK) Mp + n) kBlkK + k % kBlkK
+// (Mp >= M rows, a multiple of the 128-row tile, padding rows zero; K padded
+// to whole blocks with zeros).  The kernels accumulate
 //      G[n][m] += sum_k conj(L[n][k]) R[m][k]
 // into an FP64 [M][M][2] array.  Written over interleaved (re, im) reals q:
 //      Re G = sum_q Lq Rq,   Im G = sum_q Lq R'q,   R'(2k) = Im R(k), R'(2k+1) = -Re R(k),
@@ -28,6 +27,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // 64 x 64 complex (2 x 2 MFMA tiles of 32 x 32 for Re and for Im).
 constexpr int kGTile = 128;
 constexpr int kGWave = 64;
+// K values (complex) per LDS stage, and the LDS row pitch in bf16: 64 reals
+// plus 16 bytes, so that the 32 rows read by one ds_read_b128 fall on
+// distinct banks.
+constexpr int kGStage = 32;
+constexpr int kGPitch = 2 * kGStage + 8;
+static_assert(kBlkK % kGStage == 0, "an LDS stage must not straddle a K block");
 
 // (x0, x1, x2, ...) -> (x1, -x0, x3, -x2, ...): the imaginary-part operand.
 __device__ inline bf16x8 swap_neg(const bf16x8& b) {
@@ -41,13 +46,23 @@ __device__ inline bf16x8 swap_neg(const bf16x8& b) {
 }
 
 // grid = 8-multiple of (K splits x tiles); block = 256.  The blocks arrive
-// already split into BF16 planes (hi, lo) in the K-blocked layout; Kq = reals
-// per row (whole K blocks of 32 reals), kchunk = reals per split (multiple of 32).
-// part[ks][n][m][2] (FP64) receives the chunk's result.
+// already split into BF16 planes (hi, lo) in the K-blocked layout; Kc = complex
+// values per row (whole K blocks), kchunk = complex values per split (a
+// multiple of kGStage).  part[ks][n][m][2] (FP64) receives the chunk's result.
+//
+// Each stage moves a 128-row x 32-complex slab of the four planes (64 KiB)
+// from HBM into one of two LDS buffers through registers: the loads of stage
+// s + 1 are in flight while the waves run the 96 MFMAs of stage s out of the
+// other buffer; one barrier per stage.
+typedef __bf16 GammaSlab[4][kGTile][kGPitch];   // planes Lh, Ll, Rh, Rl of one stage
+
 __global__ void __launch_bounds__(256) gamma_bf16_kernel(const __bf16* __restrict__ Lh, const __bf16* __restrict__ Ll,
                                                          const __bf16* __restrict__ Rh, const __bf16* __restrict__ Rl,
-                                                         int M, int Mp, int64_t Kq, int64_t kchunk, int ntile,
+                                                         int M, int Mp, int64_t Kc, int64_t kchunk, int ntile,
                                                          int n_logical, double* __restrict__ part) {
+  // Two distinct LDS objects (not one array indexed by a runtime parity), so
+  // that the compiler may interleave the stores of one with reads of the other.
+  __shared__ __attribute__((aligned(16))) GammaSlab lds0, lds1;
   // XCD-aware: the workgroups of XCD x take a contiguous range of logical ids,
   // so that the tiles sharing a K chunk run on one L2.
   const int G = gridDim.x;
@@ -58,94 +73,140 @@ __global__ void __launch_bounds__(256) gamma_bf16_kernel(const __bf16* __restric
   const int tile = logical % tiles;
   const int ks = logical / tiles;
   const int tn = tile % ntile, tm = tile / ntile;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wn = wave & 1, wm = wave >> 1;
-  const int n_base = tn * kGTile + wn * kGWave;
-  const int m_base = tm * kGTile + wm * kGWave;
-  const int64_t k_begin = (int64_t)ks * kchunk;
-  const int64_t k_end = min(Kq, k_begin + kchunk);
   const int r32 = lane & 31, kg = lane >> 5;
-  const int64_t block_stride = (int64_t)Mp * 32;   // reals between consecutive K blocks of one row
+  const int n_base = tn * kGTile + wn * kGWave, m_base = tm * kGTile + wm * kGWave;
+  const int64_t k_begin = (int64_t)ks * kchunk;
+  const int64_t k_end = min(Kc, k_begin + kchunk);
+  const int64_t n_stage = (k_end - k_begin) / kGStage;
 
-  // Each lane owns 16 consecutive reals of its row in every K block (offset
-  // 16 kg); MFMA step s uses reals [8 s, 8 s + 8) of them.  A and B use the same
-  // order of k, so the contraction is unchanged.  The blocks have Mp >= the
-  // tiles' rows, padded with zeros, so no load needs a guard.
-  int64_t aoff[2], boff[2];
+  // Staging: thread t carries, for each plane p, rows 32 q + t/8 (q < 4) of the
+  // slab, 16 bytes at column 8 (t % 8); 8 threads read one 128-byte line.
+  const int srow = t >> 3, scol = (t & 7) * 8;
+  const __bf16* const planes[4] = {Lh, Ll, Rh, Rl};
+  // Byte offsets of this thread's rows inside a K block (constant over the
+  // stages; rows < Mp <= 2^22 keeps them in 32 bits); the stage adds a
+  // wave-uniform offset to the plane base.
+  uint32_t voff[2][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    aoff[i] = (int64_t)(n_base + 32 * i + r32) * 32 + 16 * kg;
-    boff[i] = (int64_t)(m_base + 32 * i + r32) * 32 + 16 * kg;
-  }
+  for (int side = 0; side < 2; ++side)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = (side == 0 ? tn : tm) * kGTile + 32 * q + srow;
+      voff[side][q] = (uint32_t)(((int64_t)row * (2 * kBlkK) + scol) * sizeof(__bf16));
+    }
+  typedef bf16x8 Staging[4][4];
+  Staging stgA, stgB;
+  auto fetch = [&](Staging& stg, int64_t k0) {
+    const int64_t soff = ((k0 / kBlkK) * (int64_t)Mp * (2 * kBlkK) + 2 * (k0 % kBlkK)) * (int64_t)sizeof(__bf16);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const char* base = reinterpret_cast<const char*>(planes[p]) + soff;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) stg[p][q] = *reinterpret_cast<const bf16x8*>(base + voff[p >> 1][q]);
+    }
+  };
+  auto stash = [&](const Staging& stg, GammaSlab& dst) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8*>(&dst[p][32 * q + srow][scol]) = stg[p][q];
+  };
+
   f32x16 re[2][2], im[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      re[i][j] = f32x16{};
+      im[i][j] = f32x16{};
+    }
+  const int an = wn * kGWave + r32, bm = wm * kGWave + r32;
+  // MFMA operands of one 16-real K step: rows an + 32 i of L (hi, lo) and
+  // bm + 32 j of R (hi, lo).
+  struct Ops {
+    bf16x8 ah[2], al[2], bh[2], bl[2];
+  };
+  auto read_ops = [&](const GammaSlab& src, int kk, Ops& o) {
+    const int c = 16 * kk + 8 * kg;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) re[i][j][e] = im[i][j][e] = 0.f;
-
-  // Two K blocks in flight: buffer 0 holds even blocks, buffer 1 odd ones; the
-  // loop is unrolled by two so that every buffer index is a constant.
-  bf16x8 ah0[2][2], al0[2][2], bh0[2][2], bl0[2][2];
-  bf16x8 ah1[2][2], al1[2][2], bh1[2][2], bl1[2][2];
-  auto load = [&](int64_t q0, bf16x8 (&ah)[2][2], bf16x8 (&al)[2][2], bf16x8 (&bh)[2][2], bf16x8 (&bl)[2][2]) {
-    const int64_t kb = (q0 >> 5) * block_stride;
+    for (int i = 0; i < 2; ++i) {
+      o.ah[i] = *reinterpret_cast<const bf16x8*>(&src[0][an + 32 * i][c]);
+      o.al[i] = *reinterpret_cast<const bf16x8*>(&src[1][an + 32 * i][c]);
+      o.bh[i] = *reinterpret_cast<const bf16x8*>(&src[2][bm + 32 * i][c]);
+      o.bl[i] = *reinterpret_cast<const bf16x8*>(&src[3][bm + 32 * i][c]);
+    }
+  };
+  auto mfma = [&](const Ops& o) {
+    bf16x8 b2h[2], b2l[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      b2h[j] = swap_neg(o.bh[j]);
+      b2l[j] = swap_neg(o.bl[j]);
+    }
+    // The three split products are issued round-robin over the eight
+    // accumulators, so consecutive MFMAs never depend on each other.
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int st = 0; st < 2; ++st) {
-        ah[i][st] = *reinterpret_cast<const bf16x8*>(Lh + kb + aoff[i] + 8 * st);
-        al[i][st] = *reinterpret_cast<const bf16x8*>(Ll + kb + aoff[i] + 8 * st);
-        bh[i][st] = *reinterpret_cast<const bf16x8*>(Rh + kb + boff[i] + 8 * st);
-        bl[i][st] = *reinterpret_cast<const bf16x8*>(Rl + kb + boff[i] + 8 * st);
+      for (int j = 0; j < 2; ++j) {
+        re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[i], o.bh[j], re[i][j], 0, 0, 0);
+        im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[i], b2h[j], im[i][j], 0, 0, 0);
       }
-  };
-  auto compute = [&](const bf16x8 (&ah)[2][2], const bf16x8 (&al)[2][2], const bf16x8 (&bh)[2][2],
-                     const bf16x8 (&bl)[2][2]) {
 #pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      bf16x8 b2hi[2], b2lo[2];
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        b2hi[j] = swap_neg(bh[j][st]);
-        b2lo[j] = swap_neg(bl[j][st]);
+        re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[i], o.bl[j], re[i][j], 0, 0, 0);
+        im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ah[i], b2l[j], im[i][j], 0, 0, 0);
       }
-      // The three split products are issued round-robin over the eight
-      // accumulators, so consecutive MFMAs never depend on each other.
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i][st], bh[j][st], re[i][j], 0, 0, 0);
-          im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i][st], b2hi[j], im[i][j], 0, 0, 0);
-        }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i][st], bl[j][st], re[i][j], 0, 0, 0);
-          im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i][st], b2lo[j], im[i][j], 0, 0, 0);
-        }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i][st], bh[j][st], re[i][j], 0, 0, 0);
-          im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i][st], b2hi[j], im[i][j], 0, 0, 0);
-        }
-    }
+      for (int j = 0; j < 2; ++j) {
+        re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.al[i], o.bh[j], re[i][j], 0, 0, 0);
+        im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.al[i], b2h[j], im[i][j], 0, 0, 0);
+      }
   };
-  if (k_begin < k_end) load(k_begin, ah0, al0, bh0, bl0);
-  if (k_begin + 32 < k_end) load(k_begin + 32, ah1, al1, bh1, bl1);
-  for (int64_t q0 = k_begin; q0 < k_end; q0 += 64) {
-    compute(ah0, al0, bh0, bl0);
-    if (q0 + 64 < k_end) load(q0 + 64, ah0, al0, bh0, bl0);
-    if (q0 + 32 < k_end) {
-      compute(ah1, al1, bh1, bl1);
-      if (q0 + 96 < k_end) load(q0 + 96, ah1, al1, bh1, bl1);
-    }
+  // One stage: the loads of the slab two stages ahead go out first (into the
+  // staging set just emptied), the operands of the next K step are read from
+  // LDS before the MFMAs of the current one, and the next slab (loaded one
+  // stage earlier) is stored into the other buffer at the end.  Past the last
+  // stage the fetch re-reads the chunk's first slab (in bounds, never used).
+  auto stage = [&](const GammaSlab& cur, GammaSlab& nxt, Staging& load_set, const Staging& store_set,
+                   int64_t s_load) {
+    Ops o0, o1;
+    read_ops(cur, 0, o0);
+    fetch(load_set, k_begin + (s_load < n_stage ? s_load : 0) * kGStage);
+    // Keep the slab loads at the head of the stage (the scheduler would
+    // otherwise sink them next to their use and expose their latency).
+    __builtin_amdgcn_sched_barrier(0);
+    read_ops(cur, 1, o1);
+    mfma(o0);
+    read_ops(cur, 2, o0);
+    mfma(o1);
+    read_ops(cur, 3, o1);
+    mfma(o0);
+    mfma(o1);
+    stash(store_set, nxt);
+    __syncthreads();
+  };
+  static_assert(kGStage / 8 == 4, "stage body is written for four K steps");
+
+  // Stage s reads buffer s % 2, stores slab s + 1 (held in staging set
+  // (s + 1) % 2) and loads slab s + 2 into staging set s % 2.
+  fetch(stgA, k_begin);
+  fetch(stgB, k_begin + (1 < n_stage ? 1 : 0) * kGStage);
+  stash(stgA, lds0);
+  __syncthreads();
+  int64_t s = 0;
+  for (; s + 2 <= n_stage; s += 2) {
+    stage(lds0, lds1, stgA, stgB, s + 2);
+    stage(lds1, lds0, stgB, stgA, s + 3);
   }
+  if (s < n_stage) stage(lds0, lds1, stgA, stgB, s + 2);
+
   // Accumulator layout of a 32x32 MFMA tile: lane l, element e holds
   // row 8 (e/4) + 4 (l/32) + e%4, column l%32.
   double* pb = part + (int64_t)ks * M * M * 2;
@@ -177,11 +238,12 @@ __global__ void __launch_bounds__(256) gamma_fp64_kernel(const T* __restrict__ L
   double ar = 0.0, ai = 0.0;
   for (int64_t k0 = k_begin; k0 < k_end; k0 += 16) {
     // thread (ty, tx) stages L[n0+ty][k0+tx] and R[m0+ty][k0+tx]; k0 is a multiple
-    // of 16, so k0 + tx lies in K block k0/16 at position tx.
-    const int64_t kb = (k0 / 16) * (int64_t)Mp;
+    // of 16 and kBlkK of 16, so k0 + tx lies in K block k0 / kBlkK.
+    const int64_t kb = (k0 / kBlkK) * (int64_t)Mp;
+    const int64_t kq = k0 % kBlkK + tx;
     const int n = n0 + ty, m = m0 + ty;
     const bool kin = k0 + tx < k_end;
-    const int64_t li = 2 * ((kb + n) * 16 + tx), ri = 2 * ((kb + m) * 16 + tx);
+    const int64_t li = 2 * ((kb + n) * kBlkK + kq), ri = 2 * ((kb + m) * kBlkK + kq);
     ls[ty][tx][0] = (kin && n < M) ? (double)L[li] : 0.0;
     ls[ty][tx][1] = (kin && n < M) ? (double)L[li + 1] : 0.0;
     rs[ty][tx][0] = (kin && m < M) ? (double)R[ri] : 0.0;
@@ -214,16 +276,16 @@ __global__ void gamma_reduce_kernel(const double* __restrict__ part, int KS, int
 }
 
 // Split-BF16 accumulation over K-blocked BF16 planes (hi, lo) of Kc complex
-// values per row (a multiple of 16); part holds KS * M * M * 2 doubles.
+// values per row (a multiple of kBlkK); part holds KS * M * M * 2 doubles.
 hipError_t gamma_accumulate_bf16(const __bf16* Lh, const __bf16* Ll, const __bf16* Rh, const __bf16* Rl, int M,
                                  int Mp, int64_t Kc, int KS, double* part, double* acc, hipStream_t s) {
-  const int64_t Kq = 2 * Kc;
+  if (Kc % kBlkK != 0 || Mp % kGTile != 0 || Mp < M) return hipErrorInvalidValue;
   const int ntile = (int)ceil_div(M, kGTile);
-  const int64_t kchunk = ceil_div(ceil_div(Kq, KS), 32) * 32;
-  const int ks_used = (int)ceil_div(Kq, kchunk);
+  const int64_t kchunk = ceil_div(ceil_div(Kc, KS), kGStage) * kGStage;
+  const int ks_used = (int)ceil_div(Kc, kchunk);
   const int n_logical = ks_used * ntile * ntile;
   const int grid = (int)ceil_div(n_logical, 8) * 8;
-  hipLaunchKernelGGL(gamma_bf16_kernel, dim3(grid), dim3(256), 0, s, Lh, Ll, Rh, Rl, M, Mp, Kq, kchunk, ntile,
+  hipLaunchKernelGGL(gamma_bf16_kernel, dim3(grid), dim3(256), 0, s, Lh, Ll, Rh, Rl, M, Mp, Kc, kchunk, ntile,
                      n_logical, part);
   const int64_t n = (int64_t)M * M * 2;
   hipLaunchKernelGGL(gamma_reduce_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part, ks_used, n, acc);

@@ -92,4 +92,10 @@ __device__ inline void st_pack_nt(T* p, const Pack<T>& v) {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// K blocking of the stored Chebyshev blocks of the conductivity path: element
+// (row n, complex k) lives at complex index ((k / kBlkK) * rows + n) * kBlkK + k % kBlkK.
+// One row chunk is 1 KiB per BF16 plane, so each recursion step writes whole
+// DRAM-page-sized pieces, and the Gamma GEMM reads whole 128-byte lines.
+constexpr int kBlkK = 256;
+
 }  // namespace kpm
