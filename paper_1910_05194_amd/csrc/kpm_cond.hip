@@ -95,8 +95,8 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   // Rows of the Gamma blocks: complex length padded to whole K blocks (zeros).
   const int64_t kpad = ceil_div(n_orb * P->Rp, kBlkK) * kBlkK;
   const int64_t row_elems = 2 * kpad;
-  // Rows of the blocked store: M rounded up to the GEMM's 128-row tile (zeros).
-  const int Mp = (int)ceil_div(M, 128) * 128;
+  // Rows of the blocked store: M rounded up to whole GEMM tiles (zero rows).
+  const int Mp = (int)ceil_div(M, kGammaRowAlign) * kGammaRowAlign;
   const int KS = 64;
   // Split-BF16 mode stores each block as two BF16 planes (hi, lo): the same
   // bytes as FP32; the FP64 mode stores the blocks in the vectors' precision.

@@ -23,14 +23,18 @@ namespace kpm {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Workgroup tile: 128 (n) x 128 (m) complex; 4 waves in a 2 x 2 grid, each
-// 64 x 64 complex (2 x 2 MFMA tiles of 32 x 32 for Re and for Im).
-constexpr int kGTile = 128;
+// Workgroup tile: 128 (n) x 256 (m) complex; 8 waves (two per SIMD) in a
+// 2 x 4 grid, each 64 x 64 complex (2 x 2 MFMA tiles of 32 x 32 for Re and for
+// Im).  Padded row counts are multiples of kGammaRowAlign, so every tile lies
+// inside the stored blocks.
+constexpr int kGTileN = 128;
+constexpr int kGTileM = 256;
 constexpr int kGWave = 64;
-// K values (complex) per LDS stage, and the LDS row pitch in bf16: 64 reals
-// plus 16 bytes, so that the 32 rows read by one ds_read_b128 fall on
-// distinct banks.
-constexpr int kGStage = 32;
+static_assert(kGammaRowAlign % kGTileM == 0 && kGammaRowAlign % kGTileN == 0, "tiles must divide the row padding");
+// K values (complex) per LDS stage, and the LDS row pitch in bf16: 32 reals
+// plus 16 bytes, so that the rows read by one ds_read_b128 fall on distinct
+// banks.
+constexpr int kGStage = 16;
 constexpr int kGPitch = 2 * kGStage + 8;
 static_assert(kBlkK % kGStage == 0, "an LDS stage must not straddle a K block");
 
@@ -45,20 +49,26 @@ __device__ inline bf16x8 swap_neg(const bf16x8& b) {
   return r;
 }
 
-// grid = 8-multiple of (K splits x tiles); block = 256.  The blocks arrive
+// One stage of the four planes: L hi/lo for the 128 n rows, R hi/lo for the
+// 256 m rows (61440 bytes).
+struct GammaSlab {
+  __bf16 l[2][kGTileN][kGPitch];
+  __bf16 r[2][kGTileM][kGPitch];
+};
+
+// grid = 8-multiple of (K splits x tiles); block = 512.  The blocks arrive
 // already split into BF16 planes (hi, lo) in the K-blocked layout; Kc = complex
 // values per row (whole K blocks), kchunk = complex values per split (a
 // multiple of kGStage).  part[ks][n][m][2] (FP64) receives the chunk's result.
 //
-// Each stage moves a 128-row x 32-complex slab of the four planes (64 KiB)
-// from HBM into one of two LDS buffers through registers: the loads of stage
-// s + 1 are in flight while the waves run the 96 MFMAs of stage s out of the
-// other buffer; one barrier per stage.
-typedef __bf16 GammaSlab[4][kGTile][kGPitch];   // planes Lh, Ll, Rh, Rl of one stage
-
-__global__ void __launch_bounds__(256) gamma_bf16_kernel(const __bf16* __restrict__ Lh, const __bf16* __restrict__ Ll,
+// Each stage moves a 16-complex slab of the four planes (48 KiB) from HBM into
+// one of two LDS buffers through registers: the loads of stages s + 1 and
+// s + 2 are in flight while the waves run the 48 MFMAs each of stage s out of
+// the other buffer; one barrier per stage.  Two waves share each SIMD, so one wave's
+// MFMAs cover the other's LDS and barrier waits.
+__global__ void __launch_bounds__(512) gamma_bf16_kernel(const __bf16* __restrict__ Lh, const __bf16* __restrict__ Ll,
                                                          const __bf16* __restrict__ Rh, const __bf16* __restrict__ Rl,
-                                                         int M, int Mp, int64_t Kc, int64_t kchunk, int ntile,
+                                                         int M, int Mp, int64_t Kc, int64_t kchunk, int ntn, int ntm,
                                                          int n_logical, double* __restrict__ part) {
   // Two distinct LDS objects (not one array indexed by a runtime parity), so
   // that the compiler may interleave the stores of one with reads of the other.
@@ -69,49 +79,50 @@ __global__ void __launch_bounds__(256) gamma_bf16_kernel(const __bf16* __restric
   const int xcd = blockIdx.x & 7, jx = blockIdx.x >> 3, per = G >> 3;
   const int logical = xcd * per + jx;
   if (logical >= n_logical) return;
-  const int tiles = ntile * ntile;
+  const int tiles = ntn * ntm;
   const int tile = logical % tiles;
   const int ks = logical / tiles;
-  const int tn = tile % ntile, tm = tile / ntile;
+  const int tn = tile % ntn, tm = tile / ntn;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wn = wave & 1, wm = wave >> 1;
   const int r32 = lane & 31, kg = lane >> 5;
-  const int n_base = tn * kGTile + wn * kGWave, m_base = tm * kGTile + wm * kGWave;
+  const int n_base = tn * kGTileN + wn * kGWave, m_base = tm * kGTileM + wm * kGWave;
   const int64_t k_begin = (int64_t)ks * kchunk;
   const int64_t k_end = min(Kc, k_begin + kchunk);
   const int64_t n_stage = (k_end - k_begin) / kGStage;
 
-  // Staging: thread t carries, for each plane p, rows 32 q + t/8 (q < 4) of the
-  // slab, 16 bytes at column 8 (t % 8); 8 threads read one 128-byte line.
-  const int srow = t >> 3, scol = (t & 7) * 8;
-  const __bf16* const planes[4] = {Lh, Ll, Rh, Rl};
-  // Byte offsets of this thread's rows inside a K block (constant over the
-  // stages; rows < Mp <= 2^22 keeps them in 32 bits); the stage adds a
-  // wave-uniform offset to the plane base.
-  uint32_t voff[2][4];
-#pragma unroll
-  for (int side = 0; side < 2; ++side)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int row = (side == 0 ? tn : tm) * kGTile + 32 * q + srow;
-      voff[side][q] = (uint32_t)(((int64_t)row * (2 * kBlkK) + scol) * sizeof(__bf16));
-    }
-  typedef bf16x8 Staging[4][4];
+  // Staging: a slab is 3072 16-byte units, L hi (512), L lo (512), R hi (1024),
+  // R lo (1024); unit u of a plane is row u / 4, bf16 column 8 (u % 4).  Thread
+  // t carries units t (L hi, L lo), t and t + 512 (R hi, R lo).  Their byte
+  // offsets inside a K block are constant over the stages (rows < Mp <= 2^22
+  // keeps them in 32 bits); the stage adds a wave-uniform offset to the base.
+  const int srow = t >> 2, scol = (t & 3) * 8;
+  uint32_t voff[3];
+  voff[0] = (uint32_t)(((int64_t)(tn * kGTileN + srow) * (2 * kBlkK) + scol) * sizeof(__bf16));
+  voff[1] = (uint32_t)(((int64_t)(tm * kGTileM + srow) * (2 * kBlkK) + scol) * sizeof(__bf16));
+  voff[2] = (uint32_t)(((int64_t)(tm * kGTileM + 128 + srow) * (2 * kBlkK) + scol) * sizeof(__bf16));
+  typedef bf16x8 Staging[6];
   Staging stgA, stgB;
   auto fetch = [&](Staging& stg, int64_t k0) {
     const int64_t soff = ((k0 / kBlkK) * (int64_t)Mp * (2 * kBlkK) + 2 * (k0 % kBlkK)) * (int64_t)sizeof(__bf16);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const char* base = reinterpret_cast<const char*>(planes[p]) + soff;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) stg[p][q] = *reinterpret_cast<const bf16x8*>(base + voff[p >> 1][q]);
-    }
+    const char* lh = reinterpret_cast<const char*>(Lh) + soff;
+    const char* ll = reinterpret_cast<const char*>(Ll) + soff;
+    const char* rh = reinterpret_cast<const char*>(Rh) + soff;
+    const char* rl = reinterpret_cast<const char*>(Rl) + soff;
+    stg[0] = *reinterpret_cast<const bf16x8*>(lh + voff[0]);
+    stg[1] = *reinterpret_cast<const bf16x8*>(ll + voff[0]);
+    stg[2] = *reinterpret_cast<const bf16x8*>(rh + voff[1]);
+    stg[3] = *reinterpret_cast<const bf16x8*>(rh + voff[2]);
+    stg[4] = *reinterpret_cast<const bf16x8*>(rl + voff[1]);
+    stg[5] = *reinterpret_cast<const bf16x8*>(rl + voff[2]);
   };
   auto stash = [&](const Staging& stg, GammaSlab& dst) {
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) *reinterpret_cast<bf16x8*>(&dst[p][32 * q + srow][scol]) = stg[p][q];
+    *reinterpret_cast<bf16x8*>(&dst.l[0][srow][scol]) = stg[0];
+    *reinterpret_cast<bf16x8*>(&dst.l[1][srow][scol]) = stg[1];
+    *reinterpret_cast<bf16x8*>(&dst.r[0][srow][scol]) = stg[2];
+    *reinterpret_cast<bf16x8*>(&dst.r[0][128 + srow][scol]) = stg[3];
+    *reinterpret_cast<bf16x8*>(&dst.r[1][srow][scol]) = stg[4];
+    *reinterpret_cast<bf16x8*>(&dst.r[1][128 + srow][scol]) = stg[5];
   };
 
   f32x16 re[2][2], im[2][2];
@@ -132,10 +143,10 @@ __global__ void __launch_bounds__(256) gamma_bf16_kernel(const __bf16* __restric
     const int c = 16 * kk + 8 * kg;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      o.ah[i] = *reinterpret_cast<const bf16x8*>(&src[0][an + 32 * i][c]);
-      o.al[i] = *reinterpret_cast<const bf16x8*>(&src[1][an + 32 * i][c]);
-      o.bh[i] = *reinterpret_cast<const bf16x8*>(&src[2][bm + 32 * i][c]);
-      o.bl[i] = *reinterpret_cast<const bf16x8*>(&src[3][bm + 32 * i][c]);
+      o.ah[i] = *reinterpret_cast<const bf16x8*>(&src.l[0][an + 32 * i][c]);
+      o.al[i] = *reinterpret_cast<const bf16x8*>(&src.l[1][an + 32 * i][c]);
+      o.bh[i] = *reinterpret_cast<const bf16x8*>(&src.r[0][bm + 32 * i][c]);
+      o.bl[i] = *reinterpret_cast<const bf16x8*>(&src.r[1][bm + 32 * i][c]);
     }
   };
   auto mfma = [&](const Ops& o) {
@@ -170,10 +181,10 @@ __global__ void __launch_bounds__(256) gamma_bf16_kernel(const __bf16* __restric
       }
   };
   // One stage: the loads of the slab two stages ahead go out first (into the
-  // staging set just emptied), the operands of the next K step are read from
-  // LDS before the MFMAs of the current one, and the next slab (loaded one
-  // stage earlier) is stored into the other buffer at the end.  Past the last
-  // stage the fetch re-reads the chunk's first slab (in bounds, never used).
+  // staging set just emptied), the operands of the second K step are read
+  // before the MFMAs of the first, and the next slab (loaded one stage
+  // earlier) is stored into the other buffer at the end.  Past the last stage
+  // the fetch re-reads the chunk's first slab (in bounds, never used).
   auto stage = [&](const GammaSlab& cur, GammaSlab& nxt, Staging& load_set, const Staging& store_set,
                    int64_t s_load) {
     Ops o0, o1;
@@ -184,15 +195,11 @@ __global__ void __launch_bounds__(256) gamma_bf16_kernel(const __bf16* __restric
     __builtin_amdgcn_sched_barrier(0);
     read_ops(cur, 1, o1);
     mfma(o0);
-    read_ops(cur, 2, o0);
-    mfma(o1);
-    read_ops(cur, 3, o1);
-    mfma(o0);
     mfma(o1);
     stash(store_set, nxt);
     __syncthreads();
   };
-  static_assert(kGStage / 8 == 4, "stage body is written for four K steps");
+  static_assert(kGStage / 8 == 2, "stage body is written for two K steps");
 
   // Stage s reads buffer s % 2, stores slab s + 1 (held in staging set
   // (s + 1) % 2) and loads slab s + 2 into staging set s % 2.
@@ -279,13 +286,13 @@ __global__ void gamma_reduce_kernel(const double* __restrict__ part, int KS, int
 // values per row (a multiple of kBlkK); part holds KS * M * M * 2 doubles.
 hipError_t gamma_accumulate_bf16(const __bf16* Lh, const __bf16* Ll, const __bf16* Rh, const __bf16* Rl, int M,
                                  int Mp, int64_t Kc, int KS, double* part, double* acc, hipStream_t s) {
-  if (Kc % kBlkK != 0 || Mp % kGTile != 0 || Mp < M) return hipErrorInvalidValue;
-  const int ntile = (int)ceil_div(M, kGTile);
+  if (Kc % kBlkK != 0 || Mp % kGammaRowAlign != 0 || Mp < M) return hipErrorInvalidValue;
+  const int ntn = (int)ceil_div(M, kGTileN), ntm = (int)ceil_div(M, kGTileM);
   const int64_t kchunk = ceil_div(ceil_div(Kc, KS), kGStage) * kGStage;
   const int ks_used = (int)ceil_div(Kc, kchunk);
-  const int n_logical = ks_used * ntile * ntile;
+  const int n_logical = ks_used * ntn * ntm;
   const int grid = (int)ceil_div(n_logical, 8) * 8;
-  hipLaunchKernelGGL(gamma_bf16_kernel, dim3(grid), dim3(256), 0, s, Lh, Ll, Rh, Rl, M, Mp, Kc, kchunk, ntile,
+  hipLaunchKernelGGL(gamma_bf16_kernel, dim3(grid), dim3(512), 0, s, Lh, Ll, Rh, Rl, M, Mp, Kc, kchunk, ntn, ntm,
                      n_logical, part);
   const int64_t n = (int64_t)M * M * 2;
   hipLaunchKernelGGL(gamma_reduce_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part, ks_used, n, acc);

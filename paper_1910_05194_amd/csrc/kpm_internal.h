@@ -97,5 +97,7 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // One row chunk is 1 KiB per BF16 plane, so each recursion step writes whole
 // DRAM-page-sized pieces, and the Gamma GEMM reads whole 128-byte lines.
 constexpr int kBlkK = 256;
+// Row padding of the stored blocks (zero rows), a multiple of every Gamma GEMM tile.
+constexpr int kGammaRowAlign = 256;
 
 }  // namespace kpm
