@@ -80,7 +80,7 @@ def train(net: "kpm.MLP", mu: np.ndarray, epochs: int, batch: int = 256, lr: flo
         net.fit_scaling(X[ti].contiguous(), T[ti].contiguous())
     steps_per_epoch = max(1, len(tr) // batch)
     total = epochs * steps_per_epoch
-    hist = {"train": [], "val": []}
+    hist = {"train": [], "val": [], "val_idx": val}
     step = 0
     for ep in range(epochs):
         order = g.permutation(tr)
@@ -110,19 +110,100 @@ def extrapolate(net: "kpm.MLP", mu_head, bf16: bool = True):
                       y.to(torch.float64)], dim=1)
 
 
-def accept(mu_full, e_min: float, e_max: float, energies, tol: float = 1e-3) -> List[bool]:
-    """Acceptance checks of an extrapolated table: |mu_n| <= 1 and a non-negative Jackson DOS."""
+def overlap_error(net: "kpm.MLP", mu_head, n_check: int = 64, bf16: bool = True) -> np.ndarray:
+    """Kernel-weighted relative error of the network on orders n_in .. n_in+n_check-1.
+
+    mu_head [n, >= n_in + n_check] holds moments the recursion computed; the
+    network sees only the first n_in and its prediction of the next n_check is
+    compared with the computed ones:  ||g (mu_hat - mu)|| / ||g mu|| over that
+    window, with g the Jackson factors of the full expansion.
+    """
+    import torch
+    mu_head = np.asarray(mu_head, dtype=np.float64)
+    n_in = net.n_in
+    assert mu_head.shape[1] >= n_in + n_check and n_check <= net.n_out
+    x = torch.as_tensor(mu_head[:, :n_in], dtype=torch.float32, device="cuda").contiguous()
+    y = net.forward(x, bf16=bf16).to(torch.float64).cpu().numpy()[:, :n_check]
+    g = loss_weights(n_in, net.n_out)[:n_check]
+    ref = mu_head[:, n_in:n_in + n_check]
+    den = np.sqrt(np.sum((g * ref) ** 2, axis=1))
+    return np.sqrt(np.sum((g * (y - ref)) ** 2, axis=1)) / np.maximum(den, 1e-300)
+
+
+def fit_acceptance(net: "kpm.MLP", mu_val, n_check: int = 64, factor: float = 2.0) -> float:
+    """Acceptance threshold on the overlap error: factor x its 99th percentile on held-out tables."""
+    e = overlap_error(net, mu_val, n_check)
+    return float(factor * np.percentile(e, 99))
+
+
+def accept(mu_full, e_min: float, e_max: float, energies, overlap=None, overlap_tol: float = np.inf,
+           neg_tol: float = 0.02) -> List[bool]:
+    """Acceptance checks of extrapolated tables [n, M].
+
+    A table passes when it is finite with |mu_n| <= 1, its Jackson DOS dips
+    below zero by at most neg_tol of its maximum (the damped series of true
+    moments is non-negative), and, if given, its overlap error (prediction
+    against recursion moments just past the network's input) is at most
+    overlap_tol.  Tables that fail go back to the full recursion.
+    """
     import torch
     ok = []
     en = torch.as_tensor(energies, dtype=torch.float64, device="cuda")
     for i in range(mu_full.shape[0]):
-        row = mu_full[i]
+        row = torch.as_tensor(mu_full[i], dtype=torch.float64, device="cuda")
         if not bool(torch.isfinite(row).all()) or float(row.abs().max()) > 1.0 + 1e-6:
             ok.append(False)
             continue
+        if overlap is not None and not (float(overlap[i]) <= overlap_tol):
+            ok.append(False)
+            continue
         rho = kpm.reconstruct_jackson(row.contiguous(), en, e_min, e_max)
-        ok.append(float(rho.min()) >= -tol * float(rho.abs().max()))
+        ok.append(float(rho.min()) >= -neg_tol * float(rho.abs().max()))
     return ok
+
+
+def splice(net: "kpm.MLP", mu_head, bf16: bool = True) -> np.ndarray:
+    """Full tables [n, n_in + n_out]: the computed head (all of it) followed by the
+    network's prediction for the orders past it."""
+    import torch
+    mu_head = np.asarray(mu_head, dtype=np.float64)
+    n_in, M = net.n_in, net.n_in + net.n_out
+    x = torch.as_tensor(mu_head[:, :n_in], dtype=torch.float32, device="cuda").contiguous()
+    y = net.forward(x, bf16=bf16).to(torch.float64).cpu().numpy()
+    out = np.concatenate([mu_head[:, :n_in], y], axis=1)
+    h = min(mu_head.shape[1], M)
+    out[:, :h] = mu_head[:, :h]
+    return out
+
+
+def learned_moments(net: "kpm.MLP", lattices: Sequence, num_random: int, vector_seed: int, n_check: int = 64,
+                    overlap_tol: float = 1.0, neg_tol: float = 0.05, n_energies: int = 1024, batch: int = 64):
+    """Moment tables [n, n_in + n_out] from the truncated recursion plus the network,
+    with the full recursion as fallback.
+
+    The recursion computes n_in + n_check moments per lattice; the network
+    extends each table; a table is kept when it passes ``accept`` (overlap
+    error on the n_check computed orders at most overlap_tol, a Jackson DOS on
+    n_energies midpoints that is non-negative within neg_tol, |mu_n| <= 1);
+    the lattices that fail are recomputed by the full recursion.  The random
+    vectors are keyed by a lattice's place in its batch, so a fallback for
+    every lattice reproduces the full run exactly, while a partial one draws
+    fresh vectors for the rejected lattices.  Returns (tables, accepted flags,
+    overlap errors).
+    """
+    M = net.n_in + net.n_out
+    head = generate_moments(lattices, net.n_in + n_check, num_random, vector_seed, batch=batch)
+    ov = overlap_error(net, head, n_check)
+    out = splice(net, head)
+    ok = []
+    for i, L in enumerate(lattices):
+        E = L.e_min + (np.arange(n_energies) + 0.5) * (L.e_max - L.e_min) / n_energies
+        ok.append(accept(out[i:i + 1], L.e_min, L.e_max, E, overlap=ov[i:i + 1], overlap_tol=overlap_tol,
+                         neg_tol=neg_tol)[0])
+    bad = [i for i, a in enumerate(ok) if not a]
+    if bad:
+        out[bad] = generate_moments([lattices[i] for i in bad], M, num_random, vector_seed, batch=batch)
+    return out, ok, ov
 
 
 def dos_error(rho, rho_ref) -> float:

@@ -114,3 +114,92 @@ def test_adam_step_matches_oracle_and_overfits(K):
     print("overfit loss", l0, "->", l1)
     assert l1 < 0.01 * l0
     net.close()
+
+
+def test_fit_scaling_matches_standardised_oracle(K):
+    """After fit_scaling the network maps x -> (x - mean)/sd, y' -> mean + sd y', and
+    trains on standardised targets with weights w * sd (population statistics;
+    a constant column gets sd 1)."""
+    import torch
+    net = K.MLP(48, 64, 40, seed=3)
+    params = net.get_params()
+    X, T, w = _data(50, 48, 40, seed=12)          # column 0 is constant (mu_0 = 1)
+    X[:, 5] += 3.0
+    T = (T * 7.0 + 0.2).astype(np.float32)
+    xd, td, wd = (torch.tensor(a, device="cuda") for a in (X, T, w))
+    net.fit_scaling(xd, td)
+    X64, T64 = X.astype(np.float64), T.astype(np.float64)
+    mx, sx = X64.mean(0), X64.std(0)
+    mt, st = T64.mean(0), T64.std(0)
+    assert sx[0] == 0.0
+    sx[sx == 0.0] = 1.0
+    p64 = [p.astype(np.float64) for p in params]
+    Yn, cache = omlp.forward(p64, (X64 - mx) / sx)
+    y = net.forward(xd).cpu().numpy()
+    assert rel(y, mt + st * Yn) <= 1e-5
+    Tn, wn = (T64 - mt) / st, w.astype(np.float64) * st
+    grads, loss = net.gradients(xd, td, wd)
+    L = omlp.loss(Yn, Tn, wn)
+    assert abs(loss - L) <= 1e-5 * L
+    for gg, GG in zip(grads, omlp.backward(p64, cache, Yn, Tn, wn)):
+        assert rel(gg, GG) <= 1e-4
+    net.close()
+
+
+def test_acceptance_rules(K):
+    from paper_1910_05194_amd import extrapolate as ex
+    E = np.linspace(-0.99, 0.99, 256)
+    good = np.zeros((1, 32))
+    good[0, 0] = 1.0
+    good[0, 2] = 0.2                               # smooth positive DOS
+    assert ex.accept(good, -1.0, 1.0, E)[0]
+    assert not ex.accept(good, -1.0, 1.0, E, overlap=[1.5], overlap_tol=1.0)[0]
+    assert ex.accept(good, -1.0, 1.0, E, overlap=[0.5], overlap_tol=1.0)[0]
+    nan = good.copy()
+    nan[0, 7] = np.nan
+    assert not ex.accept(nan, -1.0, 1.0, E)[0]
+    big = good.copy()
+    big[0, 3] = 1.5                                # |mu_n| <= 1 holds for any DOS
+    assert not ex.accept(big, -1.0, 1.0, E)[0]
+    neg = good.copy()
+    neg[0, 2] = -1.0                               # rho ~ 1 - 2 g_2 T_2(x) < 0 near the band edges
+    assert not ex.accept(neg, -1.0, 1.0, E)[0]
+
+
+def test_learned_extrapolation_gains_over_truncation_and_falls_back(K):
+    """A network trained on recursion moments of random disordered lattices beats
+    plain truncation on held-out lattices; rejected tables come from the full
+    recursion.
+
+    Small version of the learned-extrapolation workload: 256^2-cell lattices
+    (orders up to 256 do not wrap around the torus), 64 -> 192 moments, hidden
+    width 256.  Training: 384 lattices, R = 8; evaluation: 8 held-out lattices,
+    R = 32, DOS error E = sum|rho - rho_full| / sum|rho_full| on 512 midpoints.
+    """
+    from paper_1910_05194_amd import extrapolate as ex
+    import workload as wl
+    n_in, M, n_chk = 64, 256, 32
+    train = [wl.mlp_training_lattice(i, L=256) for i in range(384)]
+    mu = ex.generate_moments(train, M, 8, 11, batch=64)
+    net = K.MLP(n_in, 256, M - n_in, seed=5)
+    ex.train(net, mu, epochs=120, batch=64, lr=1e-3)
+    evl = [wl.mlp_training_lattice(i, L=256, seed=777) for i in range(8)]
+    full = ex.generate_moments(evl, M, 32, 3, batch=64)
+    tables, ok, ov = ex.learned_moments(net, evl, 32, 3, n_check=n_chk, overlap_tol=np.inf, neg_tol=np.inf)
+    assert all(ok)
+    # Every computed order is kept; the network only fills the rest.
+    assert np.array_equal(tables[:, :n_in + n_chk], full[:, :n_in + n_chk])
+    e_tr, e_ml = [], []
+    for i, L in enumerate(evl):
+        E = wl.energy_grid(L.e_min, L.e_max, 512)
+        rf = K.reconstruct_jackson(full[i], E, L.e_min, L.e_max)
+        e_tr.append(ex.dos_error(K.reconstruct_jackson(full[i, :n_in + n_chk], E, L.e_min, L.e_max), rf))
+        e_ml.append(ex.dos_error(K.reconstruct_jackson(tables[i], E, L.e_min, L.e_max), rf))
+    gain = np.mean(e_tr) / np.mean(e_ml)
+    print(f"E_trunc({n_in + n_chk}) {np.mean(e_tr):.4f}  E_mlp {np.mean(e_ml):.4f}  gain {gain:.2f}  overlap {np.round(ov, 3)}")
+    assert gain > 1.2
+    # Rejecting everything hands every lattice to the full recursion (same vectors).
+    fb, ok0, _ = ex.learned_moments(net, evl, 32, 3, n_check=n_chk, overlap_tol=0.0)
+    assert not any(ok0)
+    assert np.array_equal(fb, full)
+    net.close()
