@@ -186,6 +186,34 @@ def leg_mlp(kpm, wl, np, n_train=4000, L_train=1024, R_train=2, epochs=200, n_ev
             "ood_rejected": int(np.sum(ov_ood > 1.0)), "ood_total": len(ood)}
 
 
+def step_kernel_source_hash() -> str:
+    """SHA-256 over the sources that define the recursion step kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1910_05194_amd", "csrc")
+    for f in ("kpm_dos.hip", "kpm_plan.h", "kpm_internal.h"):
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(info, args):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when that
+    summary was taken on other kernel sources or another launch shape."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "step_kernel_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    launch = [info["kernel"], info["block"], info["rows"], info["grid"]]
+    if rec.get("source_sha256") != step_kernel_source_hash() or rec.get("launch") != launch \
+            or rec.get("workload") != [args.L, args.R]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +225,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the recursion steps one by one instead of replaying a hipGraph (for profilers)")
+    ap.add_argument("--launch", default="", help="pin the FP32 launch shape: kernel,block,rows,grid (skips the autotuner)")
     ap.add_argument("--legs", default="c1,c3,c4,c5", help="extra legs: c1,c3,c4,c5 (empty for none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain 4 GiB device copy (HBM ceiling; counter calibration)")
@@ -218,13 +249,15 @@ def main():
     lat, par = wl.graphene_large(precision=wl.FP32, L=args.L, M=args.M, R=args.R)
     E = torch.tensor(wl.energy_grid(lat.e_min, lat.e_max, 1024), device=dev)
     tune = {}
-    if not args.no_tune:
+    if args.launch:
+        tune = dict(zip(("kernel", "block", "rows", "grid"), (int(x) for x in args.launch.split(","))))
+    elif not args.no_tune:
         log("[bench] autotune (FP32)")
         best = kpm.autotune([lat], par.replace(num_moments=32), probe_steps=16)
         tune = {k: best[k] for k in ("kernel", "block", "rows", "grid")}
         log(f"[bench] tuned: {best}")
     log(f"[bench] plan: graphene {args.L}x{args.L}, M={args.M}, R={args.R}, FP32, {tune}")
-    plan = kpm.Plan([lat], par, **tune)
+    plan = kpm.Plan([lat], par, use_graph=not args.no_graph, **tune)
     mu = torch.zeros((1, args.R, args.M), dtype=torch.float64, device=dev)
     mean = torch.zeros((1, args.M), dtype=torch.float64, device=dev)
 
@@ -289,20 +322,11 @@ def main():
         p64.close()
 
     if args.copy_probe:
-        nbytes = 4 << 30
-        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 5
-        ev0.record()
-        for _ in range(reps):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / reps
-        extra["copy_probe"] = {"bytes_moved": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
-        del src, dst
+        # The library's plain copy kernel (kpm::probe_copy) over 4 GiB arrays:
+        # the HBM ceiling of a streaming pattern and the calibration of the
+        # FETCH_SIZE / WRITE_SIZE counters (4 GiB read and 4 GiB written per launch).
+        r = kpm.bandwidth_probe(0, 4 << 30, iters=5)
+        extra["copy_probe"] = {"kernel": "kpm::probe_copy", "bytes_moved": r["bytes"], "ms": r["ms"], "GBs": r["GBs"]}
 
     for name, fn in (("c1", leg_small), ("c3", leg_gamma), ("c4", leg_batch), ("c5", leg_mlp)):
         if name in legs:
@@ -328,8 +352,10 @@ def main():
                    "orbitals": N, "moments": args.M, "vectors": args.R, "launch": tune},
         "step_rate": N * info["n_steps"] * args.R / dt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "kpm::step_kernel (FP32, honeycomb, on-site array)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(info, args),
+                     "kernel": ("kpm::step_kernel_ring" if info["kernel"] == 2 else "kpm::step_kernel")
+                               + " (FP32, honeycomb, on-site array)",
                      "bytes_per_launch": info["bytes_per_step"], "avg_launch_ms": avg_step_ms},
         "cpu_baseline": cpu,
     }

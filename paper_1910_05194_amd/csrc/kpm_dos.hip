@@ -287,7 +287,12 @@ __device__ inline void store_site(const StepArgs<T>& A, T* ob, T* velb, int64_t 
     if (A.blk) {
       const int64_t e = eo / 2 + vec_off_c;   // complex index in the batch vector
       const int64_t b = (e / kBlkK) * A.blk_rows * kBlkK + A.blk_row * kBlkK + (e % kBlkK);
-      const Pack<T>& src = (VEL && A.blk_src == 1) ? vout[sp] : out[sp];
+      // Select values, not a reference: a runtime choice between the two
+      // private arrays would place both in scratch memory.
+      Pack<T> src = out[sp];
+      if constexpr (VEL) {
+        if (A.blk_src == 1) src = vout[sp];
+      }
       if (A.blk_lo == nullptr) {
         st_pack(A.blk + 2 * b, src);
       } else if constexpr (sizeof(T) == 4) {
