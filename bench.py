@@ -208,10 +208,11 @@ def measured_traffic(info, args):
     except (OSError, ValueError):
         return None
     launch = [info["kernel"], info["block"], info["rows"], info["grid"]]
-    if rec.get("source_sha256") != step_kernel_source_hash() or rec.get("launch") != launch \
-            or rec.get("workload") != [args.L, args.R]:
-        return None
-    return rec["hbm_bytes_per_launch"]
+    sha = step_kernel_source_hash()
+    for r in rec.get("records", []):
+        if r.get("source_sha256") == sha and r.get("launch") == launch and r.get("workload") == [args.L, args.R]:
+            return r["hbm_bytes_per_launch"]
+    return None
 
 
 def main():
@@ -229,6 +230,8 @@ def main():
                     help="launch the recursion steps one by one instead of replaying a hipGraph (for profilers)")
     ap.add_argument("--launch", default="", help="pin the FP32 launch shape: kernel,block,rows,grid (skips the autotuner)")
     ap.add_argument("--legs", default="c1,c3,c4,c5", help="extra legs: c1,c3,c4,c5 (empty for none)")
+    ap.add_argument("--mlp-train", type=int, default=4000,
+                    help="training lattices (1024^2 cells each) of the learned-extrapolation leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain 4 GiB device copy (HBM ceiling; counter calibration)")
     args = ap.parse_args()
@@ -331,8 +334,9 @@ def main():
     for name, fn in (("c1", leg_small), ("c3", leg_gamma), ("c4", leg_batch), ("c5", leg_mlp)):
         if name in legs:
             log(f"[bench] leg {name}")
+            kw = {"n_train": args.mlp_train} if name == "c5" else {}
             extra[{"c1": "small_fp64", "c3": "gamma", "c4": "uneven_batch", "c5": "mlp_extrapolation"}[name]] = \
-                fn(kpm, wl, np)
+                fn(kpm, wl, np, **kw)
 
     cpu = None
     if not args.no_cpu:

@@ -13,6 +13,9 @@
 #include "kpm_internal.h"
 #include "kpm_plan.h"
 
+#include <algorithm>
+#include <vector>
+
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -85,6 +88,23 @@ static int tune_cache_store(const char* path, const TuneKey& k, const kpm_tune_t
   return KPM_OK;
 }
 
+// Rate (GB/s of algorithmic step traffic) of one plan run.
+static int timed_run(kpm_plan* P, void* stream, double* gbs) {
+  int st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
+  if (st != KPM_OK && st != KPM_E_SPECTRUM) return st;
+  kpm_plan_info_t info;
+  st = kpm_plan_info(P, &info);
+  if (st != KPM_OK) return st;
+  *gbs = info.bytes_per_step * info.n_steps / (info.last_loop_ms * 1e-3) / 1e9;
+  return KPM_OK;
+}
+
+// Two phases: every candidate runs probe_steps steps (after one untimed run
+// that also instantiates its graph); the three fastest then run 4 probe_steps
+// steps in three rounds (each round times every finalist once), and the best
+// median wins.  The second
+// phase keeps a short first probe from deciding between shapes a few percent
+// apart.
 static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, int32_t probe_steps,
                     const char* cache_path, kpm_tune_t* best, double* best_gbs, void* stream) {
   KPM_CHECK_ARG(lat && p && best && n_lat >= 1, "NULL argument");
@@ -95,9 +115,7 @@ static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
   const int blocks[2] = {256, 512};
   const int rows_c[3] = {32, 128, 512};
   const int grids[2] = {1024, 2048};
-  double best_rate = -1.0;
-  kpm_tune_t bt;
-  std::memset(&bt, 0, sizeof(bt));
+  std::vector<std::pair<double, kpm_tune_t>> screened;
   for (int kv : kernels)
     for (int b : blocks)
       for (int r : rows_c)
@@ -117,22 +135,51 @@ static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
             delete P;
             continue;
           }
+          double rate = 0.0;
           st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
-          if (st == KPM_OK) st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
-          kpm_plan_info_t info;
-          if (st == KPM_OK) st = kpm_plan_info(P, &info);
+          if (st == KPM_OK || st == KPM_E_SPECTRUM) st = timed_run(P, stream, &rate);
           plan_free(P);
           delete P;
           if (st != KPM_OK && st != KPM_E_SPECTRUM) return st;
-          const double rate = info.bytes_per_step * info.n_steps / (info.last_loop_ms * 1e-3) / 1e9;
-          if (rate > best_rate) {
-            best_rate = rate;
-            bt = t;
-          }
+          screened.push_back({rate, t});
         }
-  *best = bt;
-  if (best_gbs) *best_gbs = best_rate;
-  return tune_cache_store(cache_path, make_key(lat, n_lat, p), bt, best_rate);
+  if (screened.empty()) {
+    set_error("autotune: no candidate launch shape");
+    return KPM_E_INVALID;
+  }
+  std::sort(screened.begin(), screened.end(),
+            [](const std::pair<double, kpm_tune_t>& x, const std::pair<double, kpm_tune_t>& y) { return x.first > y.first; });
+  const int n_fin = (int)std::min<size_t>(3, screened.size());
+  kpm_dos_params_t q2 = *p;
+  q2.num_moments = 8 * probe_steps;
+  // One plan alive at a time (the finalists may each need much of the HBM).
+  std::vector<std::vector<double>> rates(n_fin);
+  for (int rep = 0; rep < 3; ++rep)
+    for (int i = 0; i < n_fin; ++i) {
+      kpm_plan* P = nullptr;
+      int st = plan_create(lat, n_lat, &q2, &screened[i].second, &P);
+      if (st != KPM_OK) return st;
+      double r = 0.0;
+      st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
+      if (st == KPM_OK || st == KPM_E_SPECTRUM) st = timed_run(P, stream, &r);
+      plan_free(P);
+      delete P;
+      if (st != KPM_OK && st != KPM_E_SPECTRUM) return st;
+      rates[i].push_back(r);
+    }
+  int bi = 0;
+  double bmed = -1.0;
+  for (int i = 0; i < n_fin; ++i) {
+    std::sort(rates[i].begin(), rates[i].end());
+    const double med = rates[i][rates[i].size() / 2];
+    if (med > bmed) {
+      bmed = med;
+      bi = i;
+    }
+  }
+  *best = screened[bi].second;
+  if (best_gbs) *best_gbs = bmed;
+  return tune_cache_store(cache_path, make_key(lat, n_lat, p), *best, bmed);
 }
 
 }  // namespace kpm
