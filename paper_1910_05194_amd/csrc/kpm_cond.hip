@@ -88,6 +88,7 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   kpm_tune_t tune;
   std::memset(&tune, 0, sizeof(tune));
   tune.use_graph = 0;
+  tune.kernel = 2;   // single steps (the chains interleave velocity and block stores)
   kpm_plan* P = nullptr;
   KPM_TRY(plan_create(lat, 1, &dp, &tune, &P));
 

@@ -612,6 +612,278 @@ __global__ void __launch_bounds__(kMaxStepBlock) step_kernel_ring(StepArgs<T> A)
 }
 
 // ---------------------------------------------------------------------------
+// Two Chebyshev steps per sweep (temporal blocking) for the spinless lattices
+// without Peierls phases:
+//     v_{n+1} = a1 H~ v_n - b1 v_{n-1},   v_{n+2} = 2 H~ v_{n+1} - v_n,
+// with the doubling dot products of both steps, from one pass over v_n and
+// v_{n-1}.  Per pair of steps HBM moves two vectors in and two out, instead of
+// three per step.
+//
+// A tile is a band of Tx - 2 interior cell columns and Ty rows of one
+// (lattice, r-group).  The workgroup's thread columns cover the interior plus
+// one column on each side, so that v_{n+1} is available on a one-cell halo
+// (recomputed by the neighbouring tiles too); v_n comes with one more halo
+// column on each side.  Rows are marched upwards: row y of v_n enters a
+// 4-slot LDS ring, v_{n+1}(y) goes to a 3-slot ring, and v_{n+2}(y - 1) is
+// formed from that ring.  Both outputs go to buffers that no tile reads in
+// the same sweep (neighbouring tiles still read v_n and v_{n-1} on halos).
+// two = 0 runs the first half only (an odd last step).
+// ---------------------------------------------------------------------------
+// Workgroup barrier for LDS data: waits for this wave's LDS operations only.
+// __syncthreads() also drains the global loads in flight, which would defeat
+// the one-row-ahead register prefetch below.  The memory clobber keeps the
+// compiler from moving LDS accesses across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <typename T>
+struct Step2Args {
+  const LatDev<T>* __restrict__ lats;
+  const int4* __restrict__ tiles;   // (lattice, r-group, x0, y0), x0 the first interior column
+  const int* __restrict__ slot_of;
+  int n_tiles;
+  const T* __restrict__ v;          // v_n
+  const T* __restrict__ w;          // v_{n-1} (read when read_w1)
+  T* __restrict__ out1;             // v_{n+1}
+  T* __restrict__ out2;             // v_{n+2}
+  const T* __restrict__ onsite;
+  const uint8_t* __restrict__ mask;
+  double* part1;                    // slot partials of step n
+  double* part2;                    // slot partials of step n + 1
+  T a1, b1;
+  int read_w1, two;
+  int Tx, Ty, E, Ew, Rp;            // Tx = thread columns (interior + 2)
+};
+
+// out = a (H~ v)_i - b w_i at one site (no Peierls phase, one spin), and the
+// doubling dot products when acc.
+template <typename T, int KIND>
+__device__ inline void site_update2(T a, T b, bool read_w, T hop, T ons, bool alive, const Pack<T>& vo,
+                                    const Pack<T>& wo, const Pack<T> (&vn)[KindTraits<KIND>::NNB], Pack<T>& out,
+                                    bool acc, double* vv, double* wv) {
+  constexpr int NC = Pack<T>::NC;
+  constexpr int NNB = KindTraits<KIND>::NNB;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    T hr = ons * vo.v[2 * j], hi = ons * vo.v[2 * j + 1];
+#pragma unroll
+    for (int k = 0; k < NNB; ++k) {
+      hr += hop * vn[k].v[2 * j];
+      hi += hop * vn[k].v[2 * j + 1];
+    }
+    T orr = a * hr, oi = a * hi;
+    if (read_w) {
+      orr -= b * wo.v[2 * j];
+      oi -= b * wo.v[2 * j + 1];
+    }
+    if (!alive) {
+      orr = 0;
+      oi = 0;
+    }
+    out.v[2 * j] = orr;
+    out.v[2 * j + 1] = oi;
+    if (acc) {
+      const double xr = (double)vo.v[2 * j], xi = (double)vo.v[2 * j + 1];
+      vv[j] += xr * xr + xi * xi;
+      wv[j] += (double)orr * xr + (double)oi * xi;
+    }
+  }
+}
+
+template <typename T, int KIND, bool ONSITE, bool MASK>
+__global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
+  using P = Pack<T>;
+  constexpr int NC = P::NC;
+  constexpr int NSUB = KindTraits<KIND>::NSUB;
+  constexpr int NNB = KindTraits<KIND>::NNB;
+  static_assert(KindTraits<KIND>::NSPIN == 1, "spinless lattices only");
+  extern __shared__ double lds[];
+
+  const int tid = threadIdx.x;
+  const int Ew = A.Ew;
+  const int cl = tid % Ew;
+  const int grp = tid / Ew;
+  const int n_grp = blockDim.x / Ew;
+  const int s = grp % NSUB;
+  const int xl = grp / NSUB;
+  const int Rp = A.Rp;
+  const int Tx = A.Tx;
+  // v_n ring: [4 slots][Tx + 2 cells][sub][chunk]; v_{n+1} ring: [3][Tx][sub][chunk].
+  // The moment flush reuses the same LDS between tiles.
+  P* ring0 = reinterpret_cast<P*>(lds);
+  const int row0 = (Tx + 2) * NSUB * Ew;
+  P* ring1 = ring0 + 4 * row0;
+  const int row1 = Tx * NSUB * Ew;
+  auto r0 = [&](int slot, int cell, int sub) -> P& { return ring0[slot * row0 + (cell * NSUB + sub) * Ew + cl]; };
+  auto r1 = [&](int slot, int cell, int sub) -> P& { return ring1[slot * row1 + (cell * NSUB + sub) * Ew + cl]; };
+
+  const int xcd = blockIdx.x & 7;
+  const int jx = blockIdx.x >> 3;
+  const int gx = gridDim.x >> 3;
+  const int t_begin = (int)(((int64_t)xcd * A.n_tiles) >> 3);
+  const int t_end = (int)(((int64_t)(xcd + 1) * A.n_tiles) >> 3);
+
+  double vv1[NC], wv1[NC], vv2[NC], wv2[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) vv1[j] = wv1[j] = vv2[j] = wv2[j] = 0.0;
+
+  for (int ti = t_begin + jx; ti < t_end; ti += gx) {
+    const int4 tl = A.tiles[ti];
+    const LatDev<T>& Lg = A.lats[tl.x];
+    const int L1 = Lg.L1, L2 = Lg.L2;
+    const int64_t site_off = Lg.site_off;
+    const T hop = Lg.hop, ons_c = Lg.onsite_const;
+    const int x0 = tl.z, y0 = tl.w;
+    const int n_in = min(Tx - 2, L1 - x0);       // interior columns of this tile
+    const int wcols = n_in + 2;                  // thread columns in use
+    const int xe = (x0 == 0) ? L1 - 1 : x0 - 1;  // column of thread column 0
+    const int n1 = (xe + xl) % L1;
+    const int c = tl.y * Ew + cl;
+    const bool lane_ok = (grp < n_grp) && (c < A.E);
+    const bool act = lane_ok && (xl < wcols);
+    const bool inner = act && (xl >= 1) && (xl <= n_in);
+    const int64_t coff = (int64_t)c * NC * 2;
+    const T* __restrict__ vb = A.v + Lg.vec_off;
+    const T* __restrict__ wb = A.w + Lg.vec_off;
+    T* __restrict__ o1 = A.out1 + Lg.vec_off;
+    T* __restrict__ o2 = A.out2 + Lg.vec_off;
+    // Halo cells of v_n: left of thread column 0, right of thread column wcols - 1.
+    const int hl = (xe == 0) ? L1 - 1 : xe - 1;
+    const int hr = (xe + wcols) % L1;
+    const bool load_left = lane_ok && (xl == 0) && (KIND == KPM_SQUARE || s == 0);
+    const bool load_right = lane_ok && (xl == wcols - 1) && (KIND == KPM_SQUARE || s == 1);
+    auto wrap = [&](int y) {
+      y %= L2;
+      return y < 0 ? y + L2 : y;
+    };
+    // Everything a row needs from HBM (v_n with halos for row y + 1, v_{n-1},
+    // on-site potential and vacancy flag for row y) is loaded into registers
+    // one iteration ahead, as one group: the phases themselves only touch LDS
+    // and store, so the in-order load counter never makes them wait for the
+    // next row's loads.  Two register sets alternate (the loop is unrolled by
+    // two), so no loaded value is copied after the next loads were issued.
+    struct RowSet {
+      P own, left, right, w;
+      T ons;
+      bool alive;
+    };
+    RowSet sa, sb;
+    auto fetch_row = [&](RowSet& S, int yy) {
+      if (act) S.own = ld_pack(vb + (((int64_t)yy * L1 + n1) * NSUB + s) * Rp * 2 + coff);
+      if (load_left) S.left = ld_pack(vb + (((int64_t)yy * L1 + hl) * NSUB + s) * Rp * 2 + coff);
+      if (load_right) S.right = ld_pack(vb + (((int64_t)yy * L1 + hr) * NSUB + s) * Rp * 2 + coff);
+    };
+    auto store_row = [&](const RowSet& S, int slot) {
+      if (act) r0(slot, xl + 1, s) = S.own;
+      if (load_left) r0(slot, 0, s) = S.left;
+      if (load_right) r0(slot, wcols + 1, s) = S.right;
+    };
+    auto fetch_site = [&](RowSet& S, int yy) {
+      S.ons = ons_c;
+      S.alive = true;
+      if (act) {
+        const int64_t site = ((int64_t)yy * L1 + n1) * NSUB + s;
+        if (A.read_w1) S.w = ld_pack(wb + site * Rp * 2 + coff);
+        if constexpr (ONSITE) S.ons = A.onsite[site_off + site];
+        if constexpr (MASK) S.alive = A.mask[site_off + site] != 0;
+      }
+    };
+    const int ty = min(A.Ty, L2 - y0);
+    T ons_prev = ons_c;
+    bool alive_prev = true;
+    int q = 0;
+    // One row: v_{n+1}(y) on all thread columns, then v_{n+2}(y - 1) on the
+    // interior.  cur holds v_n row y + 1 and the site data of row y.
+    auto row = [&](int j, const RowSet& cur, RowSet& nxt) {
+      const int y = y0 - 1 + j;
+      // All of cur has arrived (vmcnt(0); expcnt and lgkmcnt left at their
+      // maxima), so no later use of it waits for the loads issued below.
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      store_row(cur, (j + 2) & 3);
+      __builtin_amdgcn_sched_barrier(0);
+      if (j + 1 < ty + 2) {
+        fetch_row(nxt, wrap(y + 2));
+        fetch_site(nxt, wrap(y + 1));
+      }
+      lds_barrier();
+      const int sy = (j + 1) & 3, sm = j & 3, sp = (j + 2) & 3;
+      if (act) {
+        const int64_t site = ((int64_t)wrap(y) * L1 + n1) * NSUB + s;
+        P vn[NNB];
+        if constexpr (KIND == KPM_SQUARE) {
+          vn[0] = r0(sy, xl + 2, 0);
+          vn[1] = r0(sy, xl, 0);
+          vn[2] = r0(sp, xl + 1, 0);
+          vn[3] = r0(sm, xl + 1, 0);
+        } else if (s == 0) {
+          vn[0] = r0(sy, xl + 1, 1);
+          vn[1] = r0(sm, xl + 2, 1);
+          vn[2] = r0(sm, xl + 1, 1);
+        } else {
+          vn[0] = r0(sy, xl + 1, 0);
+          vn[1] = r0(sp, xl, 0);
+          vn[2] = r0(sp, xl + 1, 0);
+        }
+        const P vo = r0(sy, xl + 1, s);
+        const bool own = inner && (y >= y0) && (y < y0 + ty);
+        P o;
+        site_update2<T, KIND>(A.a1, A.b1, A.read_w1 != 0, hop, cur.ons, cur.alive, vo, cur.w, vn, o, own, vv1, wv1);
+        r1(q, xl, s) = o;
+        if (own) st_pack(o1 + site * Rp * 2 + coff, o);
+      }
+      lds_barrier();
+      if (A.two && inner && j >= 2) {
+        // v_{n+2}(y - 1) from v_{n+1} rows y - 2, y - 1, y and v_n(y - 1).
+        const int qm = (q + 1) % 3, q0 = (q + 2) % 3, qp = q;
+        const int64_t site = ((int64_t)wrap(y - 1) * L1 + n1) * NSUB + s;
+        P vn[NNB];
+        if constexpr (KIND == KPM_SQUARE) {
+          vn[0] = r1(q0, xl + 1, 0);
+          vn[1] = r1(q0, xl - 1, 0);
+          vn[2] = r1(qp, xl, 0);
+          vn[3] = r1(qm, xl, 0);
+        } else if (s == 0) {
+          vn[0] = r1(q0, xl, 1);
+          vn[1] = r1(qm, xl + 1, 1);
+          vn[2] = r1(qm, xl, 1);
+        } else {
+          vn[0] = r1(q0, xl, 0);
+          vn[1] = r1(qp, xl - 1, 0);
+          vn[2] = r1(qp, xl, 0);
+        }
+        const P vo = r1(q0, xl, s);
+        const P wo2 = r0(sm, xl + 1, s);
+        P o;
+        site_update2<T, KIND>((T)2, (T)1, true, hop, ons_prev, alive_prev, vo, wo2, vn, o, true, vv2, wv2);
+        st_pack(o2 + site * Rp * 2 + coff, o);
+      }
+      ons_prev = cur.ons;             // row y, for the next phase 2
+      alive_prev = cur.alive;
+      q = (q == 2) ? 0 : q + 1;
+    };
+    // v_n row r sits in slot (r - (y0 - 2)) & 3; v_{n+1} row y0 - 1 + j in slot j % 3.
+    fetch_row(sa, wrap(y0 - 2));
+    store_row(sa, 0);
+    fetch_row(sa, wrap(y0 - 1));
+    store_row(sa, 1);
+    fetch_row(sa, wrap(y0));
+    fetch_site(sa, wrap(y0 - 1));
+    int j = 0;
+    for (; j + 1 < ty + 2; j += 2) {
+      row(j, sa, sb);
+      row(j + 1, sb, sa);
+    }
+    if (j < ty + 2) row(j, sa, sb);
+    __syncthreads();   // the next tile (or the moment flush) reuses the LDS
+    const int tn = ti + gx;
+    const int slot = A.slot_of[ti];
+    if (tn >= t_end || A.slot_of[tn] != slot) {
+      flush_slot<NC>(lds, A.part1, slot, tid, Ew, grp, n_grp, vv1, wv1);
+      if (A.two) flush_slot<NC>(lds, A.part2, slot, tid, Ew, grp, n_grp, vv2, wv2);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Model build: Anderson potential, vacancy mask, active-orbital count.
 // ---------------------------------------------------------------------------
 struct ModelLat {
@@ -802,6 +1074,17 @@ static void* pick_step(int variant, bool onsite, bool mask, bool phase) {
   }
 }
 
+template <typename T, int KIND>
+static void* pick_step2(bool onsite, bool mask) {
+  if (onsite) return mask ? (void*)step2_kernel<T, KIND, true, true> : (void*)step2_kernel<T, KIND, true, false>;
+  return mask ? (void*)step2_kernel<T, KIND, false, true> : (void*)step2_kernel<T, KIND, false, false>;
+}
+
+template <typename T>
+static void* pick_step2_kind(int kind, bool onsite, bool mask) {
+  return kind == KPM_SQUARE ? pick_step2<T, KPM_SQUARE>(onsite, mask) : pick_step2<T, KPM_HONEYCOMB>(onsite, mask);
+}
+
 template <typename T, bool VEL>
 static void* pick_step_kind(int kind, int variant, bool onsite, bool mask, bool phase) {
   if (kind == KPM_HONEYCOMB) return pick_step<T, KPM_HONEYCOMB, VEL>(variant, onsite, mask, phase);
@@ -906,7 +1189,7 @@ static int plan_alloc(kpm_plan* P, void** ptr, size_t bytes) {
 }
 
 void plan_free(kpm_plan* P) {
-  void* bufs[] = {P->X, P->Y, P->onsite, P->mask, P->phase, P->latdev, P->tiles, P->slot_of, P->ranges,
+  void* bufs[] = {P->X, P->Y, P->Z, P->W, P->onsite, P->mask, P->phase, P->latdev, P->tiles, P->slot_of, P->ranges,
                   P->part, P->dots, P->keys, P->d_sites, P->active, P->mlat, P->plat, P->flag,
                   P->mu_dev, P->mean_dev};
   for (void* b : bufs)
@@ -1020,18 +1303,44 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     delete P;
     return KPM_E_INVALID;
   }
-  P->Ew = (int)std::min<int64_t>(P->E, std::max(1, P->block / P->n_sub));
+  // Kernel variant: 3 = two steps per sweep (spinless lattices without
+  // Peierls phases, room for two more vectors), 2 = LDS row ring, 1 = direct
+  // loads.  The default is the fastest eligible one.
+  const int want = (tune && tune->kernel > 0) ? tune->kernel : 3;
+  if (want < 1 || want > 3) {
+    set_error("kernel must be 0 (default), 1, 2 or 3");
+    delete P;
+    return KPM_E_INVALID;
+  }
+  P->variant = want;
+  if (P->variant == 3) {
+    const double vec_b = (double)P->n_orb * P->Rp * 2 * P->tsize;
+    size_t free_b = 0, total_b = 0;
+    const bool room = hipMemGetInfo(&free_b, &total_b) == hipSuccess && (double)free_b > 4.0 * vec_b + 2.0e9;
+    if (P->kind == KPM_HONEYCOMB_SPIN || P->has_phase || !room) P->variant = 2;
+  }
+  if (P->variant == 3) {
+    // Chunks per r-group such that a tile has ~32 thread columns (30 interior).
+    P->Ew = (int)std::min<int64_t>(P->E, std::max(1, P->block / (P->n_sub * 32)));
+    P->Tx = P->block / (P->n_sub * P->Ew);
+    if (P->Tx < 3) P->variant = 2;
+  }
+  if (P->variant != 3) {
+    P->Ew = (int)std::min<int64_t>(P->E, std::max(1, P->block / P->n_sub));
+    P->Tx = std::max(1, P->block / (P->n_sub * P->Ew));
+  }
   P->n_rg = (int)ceil_div(P->E, P->Ew);
-  P->Tx = std::max(1, P->block / (P->n_sub * P->Ew));
+  // Cells a tile owns along n1 (the two-step kernel spends two thread columns on halos).
+  const int xstep = (P->variant == 3) ? P->Tx - 2 : P->Tx;
   if (!(tune && tune->rows > 0)) {
     // Default rows per tile: the largest power of two <= 64 that still gives
     // at least 2048 tiles (8 per CU), so that small lattices fill the chip.
     int64_t cols = 0;
-    for (int l = 0; l < n_lat; ++l) cols += ceil_div(lat[l].L1, P->Tx) * P->n_rg;
+    for (int l = 0; l < n_lat; ++l) cols += ceil_div(lat[l].L1, xstep) * P->n_rg;
     int ty = 64;
     while (ty > 1) {
       int64_t nt = 0;
-      for (int l = 0; l < n_lat; ++l) nt += ceil_div(lat[l].L1, P->Tx) * P->n_rg * ceil_div(lat[l].L2, ty);
+      for (int l = 0; l < n_lat; ++l) nt += ceil_div(lat[l].L1, xstep) * P->n_rg * ceil_div(lat[l].L2, ty);
       if (nt >= 2048) break;
       ty >>= 1;
     }
@@ -1044,7 +1353,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   for (int l = 0; l < n_lat; ++l)
     for (int g = 0; g < P->n_rg; ++g)
       for (int y0 = 0; y0 < lat[l].L2; y0 += P->Ty)
-        for (int x0 = 0; x0 < lat[l].L1; x0 += P->Tx) tiles.push_back(make_int4(l, g, x0, y0));
+        for (int x0 = 0; x0 < lat[l].L1; x0 += xstep) tiles.push_back(make_int4(l, g, x0, y0));
   P->n_tiles = (int)tiles.size();
   // Default: a persistent grid of at most 2048 workgroups (8 per CU).
   int grid = (tune && tune->grid > 0) ? tune->grid : (int)std::min<int64_t>(2048, ceil_div(P->n_tiles, 8) * 8);
@@ -1097,10 +1406,16 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   const double part_step_bytes = (double)P->n_slots * Rw * 2 * 8;
   const double budget = 2.0e9;
   P->steps_per_chunk = (int)std::max<double>(1.0, std::min<double>(P->n_steps, std::floor(budget / part_step_bytes)));
+  // The two-step kernel writes the partials of a step pair into one chunk.
+  if (P->variant == 3) P->steps_per_chunk = std::max(2, P->steps_per_chunk & ~1);
 
-  // Algorithmic bytes per step: read v_n and v_{n-1}, write v_{n+1}, per-site arrays.
-  P->bytes_per_step = 3.0 * (double)P->n_orb * P->Rp * 2 * P->tsize +
-                      (P->has_onsite ? (double)P->n_sites * P->tsize : 0.0) + (P->has_mask ? (double)P->n_sites : 0.0);
+  // Algorithmic bytes per step: read v_n and v_{n-1}, write v_{n+1}, per-site
+  // arrays; the two-step kernel reads two vectors and writes two per pair.
+  const double site_arrays =
+      (P->has_onsite ? (double)P->n_sites * P->tsize : 0.0) + (P->has_mask ? (double)P->n_sites : 0.0);
+  P->bytes_per_step = (P->variant == 3)
+                          ? 2.0 * (double)P->n_orb * P->Rp * 2 * P->tsize + 0.5 * site_arrays
+                          : 3.0 * (double)P->n_orb * P->Rp * 2 * P->tsize + site_arrays;
 
   // Device allocations.
   const size_t vec_bytes = (size_t)P->n_orb * P->Rp * 2 * P->tsize;
@@ -1110,6 +1425,10 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   };
   A(&P->X, vec_bytes);
   A(&P->Y, vec_bytes);
+  if (P->variant == 3) {
+    A(&P->Z, vec_bytes);
+    A(&P->W, vec_bytes);
+  }
   if (P->has_onsite) A(&P->onsite, (size_t)P->n_sites * P->tsize);
   if (P->has_mask) A((void**)&P->mask, (size_t)P->n_sites);
   if (P->has_phase) A(&P->phase, (size_t)P->n_phase * 2 * P->tsize);
@@ -1188,14 +1507,21 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     delete P;
     return KPM_E_DEVICE;
   }
-  // Kernel variant: 2 = LDS row ring (default), 1 = direct loads.  The ring
-  // needs 4 rows of (Tx + 2) cells in LDS; fall back to direct loads when
-  // that exceeds 64 KiB.
+  // LDS: the ring variant needs 4 rows of (Tx + 2) cells (fall back to direct
+  // loads when that exceeds 64 KiB); the two-step kernel its two rings.
   const size_t ring_bytes = (size_t)P->block * 2 * P->NC * sizeof(double) +
                             4 * (size_t)(P->Tx + 2) * P->n_sub * P->n_spin * P->Ew * 16;
-  P->variant = (tune && tune->kernel > 0) ? tune->kernel : 2;
   if (P->variant == 2 && ring_bytes > 65536) P->variant = 1;
-  P->lds_bytes = (P->variant == 2) ? ring_bytes : (size_t)P->block * 2 * P->NC * sizeof(double);
+  if (P->variant == 3) {
+    // Two row rings; the moment flush reuses the same LDS between tiles.
+    const size_t rings = (4 * (size_t)(P->Tx + 2) + 3 * (size_t)P->Tx) * P->n_sub * P->Ew * 16;
+    P->lds_bytes = std::max(rings, (size_t)P->block * 2 * P->NC * sizeof(double));
+  } else {
+    P->lds_bytes = (P->variant == 2) ? ring_bytes : (size_t)P->block * 2 * P->NC * sizeof(double);
+  }
+  if (P->variant == 3)
+    P->step2_fn = (P->prec == KPM_FP32) ? pick_step2_kind<float>(P->kind, P->has_onsite, P->has_mask)
+                                        : pick_step2_kind<double>(P->kind, P->has_onsite, P->has_mask);
   P->step_fn = (P->prec == KPM_FP32)
                    ? pick_step_kind<float, false>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase)
                    : pick_step_kind<double, false>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase);
@@ -1271,6 +1597,8 @@ static hipError_t launch_step_t(kpm_plan* P, hipStream_t s, const StepLaunch& L)
 }
 
 hipError_t plan_launch_step(kpm_plan* P, hipStream_t s, const StepLaunch& L) {
+  // Single steps need the single-step tile list (the two-step plan's tiles overlap).
+  if (P->variant == 3) return hipErrorInvalidValue;
   return P->prec == KPM_FP32 ? launch_step_t<float>(P, s, L) : launch_step_t<double>(P, s, L);
 }
 
@@ -1290,7 +1618,74 @@ int plan_set_vector_base(kpm_plan* P, int64_t r0) {
 
 // The DOS recursion: v_0 = start, v_1 = H~ v_0, v_{k+1} = 2 H~ v_k - v_{k-1},
 // in place over two buffers, with the doubling dot products of every step.
+template <typename T>
+static hipError_t launch_step2_t(kpm_plan* P, hipStream_t s, const void* v, const void* w, void* out1, void* out2,
+                                 int first, int two, double* part1, double* part2) {
+  Step2Args<T> a;
+  a.lats = (const LatDev<T>*)P->latdev;
+  a.tiles = P->tiles;
+  a.slot_of = P->slot_of;
+  a.n_tiles = P->n_tiles;
+  a.v = (const T*)v;
+  a.w = (const T*)(w ? w : v);
+  a.out1 = (T*)out1;
+  a.out2 = (T*)out2;
+  a.onsite = (const T*)P->onsite;
+  a.mask = P->mask;
+  a.part1 = part1;
+  a.part2 = part2;
+  a.a1 = first ? (T)1 : (T)2;
+  a.b1 = first ? (T)0 : (T)1;
+  a.read_w1 = first ? 0 : 1;
+  a.two = two;
+  a.Tx = P->Tx;
+  a.Ty = P->Ty;
+  a.E = P->E;
+  a.Ew = P->Ew;
+  a.Rp = P->Rp;
+  void* args[] = {&a};
+  return hipLaunchKernel(P->step2_fn, dim3(P->grid), dim3(P->block), args, P->lds_bytes, s);
+}
+
+// Two-step recursion: launches cover steps (k, k+1); the outputs go to the two
+// buffers the launch does not read (four vectors rotate), an odd last step
+// runs the first half alone.
+static hipError_t launch_loop2(kpm_plan* P, hipStream_t s) {
+  const int Rw = P->Ew * P->NC;
+  const int64_t part_stride = (int64_t)P->n_slots * Rw * 2;
+  void* cur = P->X;    // v_k
+  void* prev = P->W;   // v_{k-1} (unused for k = 0)
+  void* fa = P->Y;
+  void* fb = P->Z;
+  int chunk0 = 0;
+  for (int k = 0; k < P->n_steps; k += 2) {
+    const int two = (k + 1 < P->n_steps) ? 1 : 0;
+    double* p1 = P->part + (int64_t)(k - chunk0) * part_stride;
+    double* p2 = two ? p1 + part_stride : nullptr;
+    hipError_t le = (P->prec == KPM_FP32)
+                        ? launch_step2_t<float>(P, s, cur, prev, fa, fb, k == 0 ? 1 : 0, two, p1, p2)
+                        : launch_step2_t<double>(P, s, cur, prev, fa, fb, k == 0 ? 1 : 0, two, p1, p2);
+    if (le != hipSuccess) return le;
+    void* oc = cur;
+    void* op = prev;
+    cur = fb;
+    prev = fa;
+    fa = oc;
+    fb = op;
+    const int last = k + two;
+    if (last - chunk0 + 1 >= P->steps_per_chunk || last == P->n_steps - 1) {
+      const int nsc = last - chunk0 + 1;
+      hipLaunchKernelGGL(reduce_slots_kernel, dim3(nsc, P->n_lat * P->n_rg, (unsigned)ceil_div(2 * Rw, 64)),
+                         dim3(1024), 0, s, P->part, part_stride, Rw, P->ranges, P->n_rg, P->Rp, P->n_steps, chunk0,
+                         P->dots);
+      chunk0 = last + 1;
+    }
+  }
+  return hipGetLastError();
+}
+
 static hipError_t launch_loop(kpm_plan* P, hipStream_t s) {
+  if (P->variant == 3) return launch_loop2(P, s);
   const int Rw = P->Ew * P->NC;
   const int64_t part_stride = (int64_t)P->n_slots * Rw * 2;
   int chunk0 = 0;

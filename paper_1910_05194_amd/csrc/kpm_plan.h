@@ -49,6 +49,8 @@ struct kpm_plan {
   // device memory
   void* X = nullptr;
   void* Y = nullptr;
+  void* Z = nullptr;           // two more vectors for the two-step kernel (variant 3)
+  void* W = nullptr;
   void* onsite = nullptr;
   uint8_t* mask = nullptr;
   void* phase = nullptr;
@@ -68,7 +70,8 @@ struct kpm_plan {
   double* mean_dev = nullptr;
   void* step_fn = nullptr;
   void* step_fn_vel = nullptr;
-  int variant = 2;             // 1 = direct-load step kernel, 2 = LDS row ring
+  void* step2_fn = nullptr;    // two-step kernel (variant 3)
+  int variant = 2;             // 1 = direct-load step kernel, 2 = LDS row ring, 3 = two steps per sweep
   size_t lds_bytes = 0;
   int64_t r_base = 0;          // global index of the plan's first random vector
   hipStream_t cap_stream = nullptr;

@@ -111,7 +111,7 @@ static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
   KPM_CHECK_ARG(probe_steps >= 2 && probe_steps <= 4096, "probe_steps must be in [2, 4096]");
   kpm_dos_params_t q = *p;
   q.num_moments = 2 * probe_steps;
-  const int kernels[2] = {1, 2};
+  const int kernels[3] = {1, 2, 3};
   const int blocks[2] = {256, 512};
   const int rows_c[3] = {32, 128, 512};
   const int grids[2] = {1024, 2048};

@@ -238,7 +238,7 @@ def test_autotune_cache(K, tmp_path, monkeypatch):
     par = wl.DosParams(num_moments=64, num_random=4, vector_seed=1, precision=wl.FP32)
     cache = str(tmp_path / "tune.txt")
     best = K.autotune([lat], par, probe_steps=4, cache_path=cache)
-    assert best["kernel"] in (1, 2) and best["block"] in (256, 512) and best["GBs"] > 0
+    assert best["kernel"] in (1, 2, 3) and best["block"] in (256, 512) and best["GBs"] > 0
     line = open(cache).read().strip().split()
     assert [int(v) for v in line[4:8]] == [best["kernel"], best["block"], best["rows"], best["grid"]]
     monkeypatch.setenv("KPM_TUNE_CACHE", cache)
@@ -251,3 +251,83 @@ def test_autotune_cache(K, tmp_path, monkeypatch):
     plan.close()
     mu_o, _ = oracle_moments(lat, par)
     assert np.max(np.abs(mu[0] - mu_o)) <= fp32_tol(64)
+
+
+TWO_STEP = [
+    wl.Lattice(kind=wl.HONEYCOMB, L1=37, L2=23, t=-2.7, anderson_w=1.0, vacancy_p=0.03, disorder_seed=17,
+               e_min=-9.0, e_max=8.7),
+    wl.Lattice(kind=wl.HONEYCOMB, L1=64, L2=70, t=-2.7, anderson_w=0.7, disorder_seed=3),
+    wl.Lattice(kind=wl.HONEYCOMB, L1=2, L2=2, t=-2.7, anderson_w=0.3, disorder_seed=1),
+    wl.Lattice(kind=wl.HONEYCOMB, L1=3, L2=5, t=-2.7, disorder_seed=1),
+    wl.Lattice(kind=wl.SQUARE, L1=29, L2=17, t=-2.7, anderson_w=2.0, vacancy_p=0.05, disorder_seed=9,
+               e_min=-12.0, e_max=12.0),
+    wl.Lattice(kind=wl.SQUARE, L1=5, L2=3, t=-2.7, disorder_seed=2, e_min=-11.0, e_max=11.0),
+]
+
+
+@pytest.mark.parametrize("lat", TWO_STEP, ids=lambda l: f"{wl.KIND_NAMES[l.kind]}{l.L1}x{l.L2}")
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
+def test_two_step_kernel_matches_single_step_and_oracle(K, lat, prec):
+    """The two-steps-per-sweep kernel (variant 3) against the single-step ring
+    kernel and the oracle: even and odd step counts (M = 2 is one step, M = 41
+    ends on a half sweep), tile shapes down to one row and one r-chunk, halo
+    columns that wrap onto the tile itself on tiny lattices."""
+    for M, R in ((2, 3), (8, 5), (41, 2)):
+        par = wl.DosParams(num_moments=M, num_random=R, vector_seed=8, precision=prec)
+        ref = K.Plan([lat], par, kernel=2)
+        mu_r = np.zeros((1, R, M))
+        ref.run(mu_r)
+        ref.close()
+        mu_o, _ = oracle_moments(lat, par)
+        tol = 1e-10 if prec == wl.FP64 else fp32_tol(max(M, 8))
+        for tune in (dict(block=64, rows=1), dict(block=128, rows=3, grid=16), dict(block=512, rows=0)):
+            plan = K.Plan([lat], par, kernel=3, **tune)
+            assert plan.info()["kernel"] == 3
+            mu = np.zeros((1, R, M))
+            plan.run(mu)
+            plan.close()
+            assert np.max(np.abs(mu - mu_r)) <= (1e-12 if prec == wl.FP64 else 2e-6), (M, tune)
+            assert np.max(np.abs(mu[0] - mu_o)) <= tol, (M, tune)
+
+
+@pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
+def test_two_step_uneven_batch_and_ldos(K, prec):
+    """Uneven lattices of both spinless kinds in one two-step plan, several
+    r-groups per tile (R = 40), and LDOS start vectors."""
+    lats = [wl.Lattice(kind=wl.HONEYCOMB, L1=L, L2=L2, t=-2.7, vacancy_p=0.01 * (i + 1), anderson_w=0.5,
+                       disorder_seed=100 + i)
+            for i, (L, L2) in enumerate([(8, 8), (33, 17), (2, 5), (64, 40), (91, 22)])]
+    M, R = 30, 40
+    par = wl.DosParams(num_moments=M, num_random=R, vector_seed=77, precision=prec)
+    plan = K.Plan(lats, par, kernel=3, block=256)
+    assert plan.info()["kernel"] == 3
+    mu = np.zeros((len(lats), R, M))
+    plan.run(mu)
+    plan.close()
+    for i, lat in enumerate(lats):
+        mu_o, _ = oracle_moments(lat, par, lat_index=i)
+        assert np.max(np.abs(mu[i] - mu_o)) <= (1e-10 if prec == wl.FP64 else fp32_tol(M)), i
+    lat = TWO_STEP[4]
+    from oracle import lattice as olat
+    model = olat.build(lat)
+    sites = [int(model.orb_index[i]) for i in (0, 3, 77, model.n_active - 1)]
+    par = wl.DosParams(num_moments=24, start=wl.START_SITES, sites=sites, precision=prec)
+    plan = K.Plan([lat], par, kernel=3)
+    mu = np.zeros((1, len(sites), 24))
+    plan.run(mu)
+    plan.close()
+    mu_o, _, _ = okpm.dos_moments(lat, par, model=model)
+    assert np.max(np.abs(mu[0] - mu_o)) <= (1e-10 if prec == wl.FP64 else fp32_tol(24))
+
+
+def test_two_step_kernel_falls_back_where_ineligible(K):
+    """Spinful lattices and Peierls phases take the single-step ring kernel."""
+    par = wl.DosParams(num_moments=16, num_random=2, vector_seed=3, precision=wl.FP32)
+    for lat in (RAGGED[1], RAGGED[2]):
+        plan = K.Plan([lat], par, kernel=3)
+        assert plan.info()["kernel"] == 2
+        mu = np.zeros((1, 2, 16))
+        plan.run(mu)
+        plan.close()
+        mu_o, _ = oracle_moments(lat, par)
+        assert np.max(np.abs(mu[0] - mu_o)) <= fp32_tol(16)
