@@ -122,6 +122,12 @@ struct StepArgs {
 // the spinful (2x2 hopping) kernels need to run without scratch spills.
 constexpr int kMaxStepBlock = 512;
 
+// Workgroup barrier for LDS data: waits for this wave's LDS operations only.
+// __syncthreads() also drains the global loads in flight, which would defeat
+// the one-row-ahead register prefetch of the step kernels.  The memory clobber keeps the
+// compiler from moving LDS accesses across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <int KIND>
 struct KindTraits;
 template <>
@@ -542,40 +548,63 @@ __global__ void __launch_bounds__(kMaxStepBlock) step_kernel_ring(StepArgs<T> A)
     // A-sites read the right column (sublattice B).
     const bool load_left = lane_ok && (xl == 0) && (KIND == KPM_SQUARE || s == 0);
     const bool load_right = lane_ok && (xl == tx_eff - 1) && (KIND == KPM_SQUARE || s == 1);
-    auto load_row = [&](int yy, int slot) {
+    // Rows go through registers one iteration ahead of their use (two sets,
+    // the loop unrolled by two), together with the site data of the row
+    // being formed, so that a row's HBM latency overlaps the previous row's
+    // work; the barrier covers LDS only.
+    struct RowSet {
+      P own[NSPIN], left[NSPIN], right[NSPIN], w[NSPIN];
+      T ons;
+      bool alive;
+    };
+    RowSet sa, sb;
+    auto fetch_row = [&](RowSet& S, int yy) {
       // yy in [0, L2): this thread's own cell and, for edge threads, one halo cell.
       if (act) {
         const int64_t site = ((int64_t)yy * L1 + n1) * NSUB + s;
 #pragma unroll
-        for (int sp = 0; sp < NSPIN; ++sp) ring_at(slot, xl + 1, s, sp, cl) = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
+        for (int sp = 0; sp < NSPIN; ++sp) S.own[sp] = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
       }
       if (load_left) {
         const int64_t site = ((int64_t)yy * L1 + hl) * NSUB + s;
 #pragma unroll
-        for (int sp = 0; sp < NSPIN; ++sp) ring_at(slot, 0, s, sp, cl) = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
+        for (int sp = 0; sp < NSPIN; ++sp) S.left[sp] = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
       }
       if (load_right) {
         const int64_t site = ((int64_t)yy * L1 + hr) * NSUB + s;
 #pragma unroll
-        for (int sp = 0; sp < NSPIN; ++sp)
-          ring_at(slot, tx_eff + 1, s, sp, cl) = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
+        for (int sp = 0; sp < NSPIN; ++sp) S.right[sp] = ld_pack(vb + (site * NSPIN + sp) * Rp * 2 + coff);
+      }
+    };
+    auto store_row = [&](const RowSet& S, int slot) {
+#pragma unroll
+      for (int sp = 0; sp < NSPIN; ++sp) {
+        if (act) ring_at(slot, xl + 1, s, sp, cl) = S.own[sp];
+        if (load_left) ring_at(slot, 0, s, sp, cl) = S.left[sp];
+        if (load_right) ring_at(slot, tx_eff + 1, s, sp, cl) = S.right[sp];
+      }
+    };
+    auto fetch_site = [&](RowSet& S, int yy) {
+      S.ons = L.onsite_const;
+      S.alive = true;
+      if (act) {
+        const int64_t site = ((int64_t)yy * L1 + n1) * NSUB + s;
+        if (A.read_w) load_w<T, KIND>(A, wb, site, coff, S.w);
+        if constexpr (ONSITE) S.ons = A.onsite[L.site_off + site];
+        if constexpr (MASK) S.alive = A.mask[L.site_off + site] != 0;
       }
     };
     const int n1m = (n1 == 0) ? L1 - 1 : n1 - 1;
     T hre[NNB], him[NNB];
     column_coefficients<T, KIND, PHASE>(A, L, s, act ? n1 : 0, act ? n1m : 0, hre, him);
     const int yend = min(y0 + A.Ty, L2);
-    // Prologue: rows y0-1 and y0 into slots 3 and 0 (slot of row y0+k is k & 3).
-    load_row(y0 == 0 ? L2 - 1 : y0 - 1, 3);
-    load_row(y0, 0);
-    for (int y = y0; y < yend; ++y) {
-      const int k = y - y0;
+    // Row y = y0 + k from the ring (rows y - 1, y, y + 1) and cur's site data.
+    auto compute_row = [&](int k, const RowSet& cur) {
+      const int y = y0 + k;
       const int sy = k & 3, sm = (k + 3) & 3, sp1 = (k + 1) & 3;
-      load_row(y + 1 == L2 ? 0 : y + 1, sp1);
-      __syncthreads();
       if (act) {
         const int64_t site = ((int64_t)y * L1 + n1) * NSUB + s;
-        P vo[NSPIN], wo[NSPIN], vn[NNB][NSPIN];
+        P vo[NSPIN], vn[NNB][NSPIN];
 #pragma unroll
         for (int sp = 0; sp < NSPIN; ++sp) {
           vo[sp] = ring_at(sy, xl + 1, s, sp, cl);
@@ -594,14 +623,52 @@ __global__ void __launch_bounds__(kMaxStepBlock) step_kernel_ring(StepArgs<T> A)
             vn[2][sp] = ring_at(sp1, xl + 1, 0, sp, cl);
           }
         }
-        load_w<T, KIND>(A, wb, site, coff, wo);
-        T ons = L.onsite_const;
-        if constexpr (ONSITE) ons = A.onsite[L.site_off + site];
-        bool alive = true;
-        if constexpr (MASK) alive = A.mask[L.site_off + site] != 0;
         P out[NSPIN], vout[NSPIN];
-        site_update<T, KIND, PHASE, VEL>(A, L, s, hre, him, vcs, ons, alive, vo, wo, vn, out, vout, vv, wv);
+        site_update<T, KIND, PHASE, VEL>(A, L, s, hre, him, vcs, cur.ons, cur.alive, vo, cur.w, vn, out, vout, vv,
+                                         wv);
         store_site<T, KIND, VEL>(A, ob, velb, L.vec_off / 2, site, coff, out, vout);
+      }
+    };
+    // Prologue: rows y0-1 and y0 into slots 3 and 0 (slot of row y0+k is k & 3).
+    fetch_row(sa, y0 == 0 ? L2 - 1 : y0 - 1);
+    store_row(sa, 3);
+    fetch_row(sa, y0);
+    store_row(sa, 0);
+    // The spinful FP64 kernel has no registers for a second set: it loads
+    // each row right before its use.
+    constexpr bool kPrefetch = !(KIND == KPM_HONEYCOMB_SPIN && sizeof(T) == 8);
+    if constexpr (kPrefetch) {
+      // One row: cur holds v_n row y + 1 and the site data of row y.
+      auto row = [&](int k, const RowSet& cur, RowSet& nxt) {
+        const int y = y0 + k;
+        // All of cur has arrived (vmcnt(0); expcnt and lgkmcnt left at their
+        // maxima), so no later use of it waits for the loads issued below.
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        store_row(cur, (k + 1) & 3);
+        __builtin_amdgcn_sched_barrier(0);
+        if (y + 1 < yend) {
+          fetch_row(nxt, y + 2 >= L2 ? y + 2 - L2 : y + 2);
+          fetch_site(nxt, y + 1);
+        }
+        lds_barrier();
+        compute_row(k, cur);
+      };
+      fetch_row(sa, y0 + 1 == L2 ? 0 : y0 + 1);
+      fetch_site(sa, y0);
+      int k = 0;
+      for (; y0 + k + 1 < yend; k += 2) {
+        row(k, sa, sb);
+        row(k + 1, sb, sa);
+      }
+      if (y0 + k < yend) row(k, sa, sb);
+    } else {
+      for (int k = 0; y0 + k < yend; ++k) {
+        const int y = y0 + k;
+        fetch_row(sa, y + 1 == L2 ? 0 : y + 1);
+        fetch_site(sa, y);
+        store_row(sa, (k + 1) & 3);
+        lds_barrier();
+        compute_row(k, sa);
       }
     }
     __syncthreads();   // the next tile reuses the ring
@@ -629,12 +696,6 @@ __global__ void __launch_bounds__(kMaxStepBlock) step_kernel_ring(StepArgs<T> A)
 // the same sweep (neighbouring tiles still read v_n and v_{n-1} on halos).
 // two = 0 runs the first half only (an odd last step).
 // ---------------------------------------------------------------------------
-// Workgroup barrier for LDS data: waits for this wave's LDS operations only.
-// __syncthreads() also drains the global loads in flight, which would defeat
-// the one-row-ahead register prefetch below.  The memory clobber keeps the
-// compiler from moving LDS accesses across it.
-__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
 template <typename T>
 struct Step2Args {
   const LatDev<T>* __restrict__ lats;
