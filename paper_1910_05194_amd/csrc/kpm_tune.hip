@@ -88,14 +88,17 @@ static int tune_cache_store(const char* path, const TuneKey& k, const kpm_tune_t
   return KPM_OK;
 }
 
-// Rate (GB/s of algorithmic step traffic) of one plan run.
-static int timed_run(kpm_plan* P, void* stream, double* gbs) {
+// Recursion steps per millisecond of one plan run (the candidates run the same
+// workload; GB/s would not compare variants that move different bytes per
+// step), and the algorithmic GB/s of that run.
+static int timed_run(kpm_plan* P, void* stream, double* steps_per_ms, double* gbs) {
   int st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
   if (st != KPM_OK && st != KPM_E_SPECTRUM) return st;
   kpm_plan_info_t info;
   st = kpm_plan_info(P, &info);
   if (st != KPM_OK) return st;
-  *gbs = info.bytes_per_step * info.n_steps / (info.last_loop_ms * 1e-3) / 1e9;
+  *steps_per_ms = info.n_steps / info.last_loop_ms;
+  if (gbs) *gbs = info.bytes_per_step * info.n_steps / (info.last_loop_ms * 1e-3) / 1e9;
   return KPM_OK;
 }
 
@@ -137,7 +140,7 @@ static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
           }
           double rate = 0.0;
           st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
-          if (st == KPM_OK || st == KPM_E_SPECTRUM) st = timed_run(P, stream, &rate);
+          if (st == KPM_OK || st == KPM_E_SPECTRUM) st = timed_run(P, stream, &rate, nullptr);
           plan_free(P);
           delete P;
           if (st != KPM_OK && st != KPM_E_SPECTRUM) return st;
@@ -153,33 +156,34 @@ static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
   kpm_dos_params_t q2 = *p;
   q2.num_moments = 8 * probe_steps;
   // One plan alive at a time (the finalists may each need much of the HBM).
-  std::vector<std::vector<double>> rates(n_fin);
+  std::vector<std::vector<std::pair<double, double>>> rates(n_fin);   // (steps/ms, GB/s)
   for (int rep = 0; rep < 3; ++rep)
     for (int i = 0; i < n_fin; ++i) {
       kpm_plan* P = nullptr;
       int st = plan_create(lat, n_lat, &q2, &screened[i].second, &P);
       if (st != KPM_OK) return st;
-      double r = 0.0;
+      double r = 0.0, g = 0.0;
       st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
-      if (st == KPM_OK || st == KPM_E_SPECTRUM) st = timed_run(P, stream, &r);
+      if (st == KPM_OK || st == KPM_E_SPECTRUM) st = timed_run(P, stream, &r, &g);
       plan_free(P);
       delete P;
       if (st != KPM_OK && st != KPM_E_SPECTRUM) return st;
-      rates[i].push_back(r);
+      rates[i].push_back({r, g});
     }
   int bi = 0;
-  double bmed = -1.0;
+  double bmed = -1.0, bgbs = 0.0;
   for (int i = 0; i < n_fin; ++i) {
     std::sort(rates[i].begin(), rates[i].end());
-    const double med = rates[i][rates[i].size() / 2];
-    if (med > bmed) {
-      bmed = med;
+    const auto med = rates[i][rates[i].size() / 2];
+    if (med.first > bmed) {
+      bmed = med.first;
+      bgbs = med.second;
       bi = i;
     }
   }
   *best = screened[bi].second;
-  if (best_gbs) *best_gbs = bmed;
-  return tune_cache_store(cache_path, make_key(lat, n_lat, p), *best, bmed);
+  if (best_gbs) *best_gbs = bgbs;
+  return tune_cache_store(cache_path, make_key(lat, n_lat, p), *best, bgbs);
 }
 
 }  // namespace kpm
