@@ -101,6 +101,35 @@ def dos_moments(lat, par, lat_index: int = 0, model=None):
     return mu_r, mu_r.mean(axis=0), model
 
 
+def honeycomb_kspace_moments(L1: int, L2: int, t: float, e_min: float, e_max: float, M: int) -> np.ndarray:
+    """Exact mu_n = Tr T_n(H~)/N of the clean nearest-neighbour honeycomb torus.
+
+    The Bloch energies of the two-band model with the bonds A(n) - B(n + d),
+    d in {(0,0), (1,-1), (0,-1)}, are +-|t| |1 + exp(i(k1 - k2)) + exp(-i k2)|,
+    k_j = 2 pi m_j / L_j; the trace is the average of T_n over both bands
+    (eq. e4 with the rescaling of Sec. 2(a)), evaluated by the Chebyshev
+    recurrence on the k-grid.  A closed walk must take at least 2 min(L1, L2)
+    hops to wind around the torus, so these moments equal those of any larger
+    torus (and of the infinite lattice) for n < 2 min(L1, L2).
+    """
+    k1 = 2.0 * np.pi * np.arange(L1) / L1
+    k2 = 2.0 * np.pi * np.arange(L2) / L2
+    K1, K2 = np.meshgrid(k1, k2, indexing="ij")
+    e = np.abs(t) * np.abs(1.0 + np.exp(1j * (K1 - K2)) + np.exp(-1j * K2)).ravel()
+    d_plus, d_minus = (e_max + e_min) / 2.0, (e_max - e_min) / 2.0
+    mu = np.zeros(M)
+    for x in ((e - d_plus) / d_minus, (-e - d_plus) / d_minus):
+        t_prev = np.ones_like(x)
+        t_cur = x.copy()
+        mu[0] += 1.0
+        if M > 1:
+            mu[1] += t_cur.mean()
+        for n in range(2, M):
+            t_prev, t_cur = t_cur, 2.0 * x * t_cur - t_prev
+            mu[n] += t_cur.mean()
+    return mu / 2.0
+
+
 def jackson(M: int) -> np.ndarray:
     """Jackson kernel g_n, n = 0..M-1 (Weisse et al. 2006, the kernel the paper cites)."""
     n = np.arange(M, dtype=np.float64)

@@ -181,3 +181,23 @@ def test_delta_peak_is_resolved():
     sd = np.sqrt(np.sum(rho * (eps - a) ** 2) * de)
     ref = np.pi / M * np.sqrt(1 - a * a)
     assert 0.8 * ref < sd < 1.25 * ref
+
+
+def test_kspace_moments_pinned_to_exact_trace_and_walks():
+    """The k-space closed form equals the exact trace of the explicit Hamiltonian
+    (LDOS over all basis vectors) on a small torus, the walk-count moments, and
+    is independent of the torus size for n < 2 min(L1, L2)."""
+    lat = wl.Lattice(kind=wl.HONEYCOMB, L1=10, L2=12, t=-2.7, e_min=-8.5, e_max=8.5)
+    mu, _ = _exact_trace_moments(lat, 40)
+    ks = kpm.honeycomb_kspace_moments(10, 12, -2.7, -8.5, 8.5, 40)
+    assert np.max(np.abs(mu - ks)) < 1e-12
+    a = _walks()
+    x2 = (2.7 / 8.5) ** 2
+    assert abs(ks[2] - (2 * a[1] * x2 - 1)) < 1e-12
+    big = kpm.honeycomb_kspace_moments(40, 37, -2.7, -8.5, 8.5, 60)
+    small = kpm.honeycomb_kspace_moments(16, 15, -2.7, -8.5, 8.5, 60)
+    assert np.max(np.abs(big[:30] - small[:30])) < 1e-12      # n < 2 * 15
+    assert np.max(np.abs(big[30:] - small[30:])) > 1e-6       # the small torus winds beyond
+    # Asymmetric bounds shift the rescaled spectrum: mu_1 = -d_plus / d_minus.
+    sh = kpm.honeycomb_kspace_moments(8, 8, -2.7, -8.0, 9.0, 4)
+    assert abs(sh[1] - (-0.5 / 8.5)) < 1e-12
