@@ -16,7 +16,11 @@ Paper passages followed:
   e4/e7/delta_function_cheb_expansion.)
 * Sec. 2(a) KPM damping mu_n -> g_n mu_n with the Jackson kernel, which the
   paper cites (Weisse et al., Rev. Mod. Phys. 78, 275 (2006)) but does not
-  print:  g_n = [(M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1))]/(M+1).
+  print:  g_n = [(M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1))]/(M+1);
+  or with the Lorentz kernel the paper prints, sinh(lam (1 - n/M))/sinh(lam).
+* eqs. green_function_cheb_expansion(b): the CPGF expansion of the resolvent,
+  coefficients -2 sigma i exp(-sigma i n arccos(eps + i sigma eta)) /
+  sqrt(1 - (eps + i sigma eta)^2) times T_n(H~)/(1 + delta_n0).
 """
 from __future__ import annotations
 
@@ -135,6 +139,37 @@ def jackson(M: int) -> np.ndarray:
     n = np.arange(M, dtype=np.float64)
     q = np.pi / (M + 1)
     return ((M - n + 1) * np.cos(q * n) + np.sin(q * n) / np.tan(q)) / (M + 1)
+
+
+def lorentz(M: int, lam: float) -> np.ndarray:
+    """Lorentz kernel g_n = sinh(lam (1 - n/M)) / sinh(lam), n = 0..M-1 (Sec. 2(a),
+    KPM damping); a delta peak becomes a Lorentzian of width ~ lam/M."""
+    n = np.arange(M, dtype=np.float64)
+    return np.sinh(lam * (1.0 - n / M)) / np.sinh(lam)
+
+
+def cpgf_green(mu: np.ndarray, energies_ev: np.ndarray, e_min: float, e_max: float, eta_ev: float) -> np.ndarray:
+    """(1/N) Tr 1/(E - H + i eta) per eV from moments mu_n = Tr T_n(H~)/N: the CPGF
+    expansion of the retarded resolvent (eqs. green_function_cheb_expansion and
+    green_function_cheb_expansionb, sigma = +), with eps = (E - de+)/de- and the
+    broadening rescaled the same way, eta~ = eta / de-.  numpy's principal
+    branches of arccos and sqrt are those of the printed coefficients for
+    eta > 0 (the terms decay like exp(-n Im(-arccos z)))."""
+    mu = np.asarray(mu, dtype=np.float64)
+    d_plus, d_minus = (e_max + e_min) / 2.0, (e_max - e_min) / 2.0
+    z = (np.asarray(energies_ev, dtype=np.float64) - d_plus) / d_minus + 1j * (eta_ev / d_minus)
+    theta = np.arccos(z)
+    root = np.sqrt(1.0 - z * z)
+    out = np.zeros(z.shape, dtype=np.complex128)
+    for n in range(mu.size):
+        g_n = -2.0j * np.exp(-1j * n * theta) / root
+        out += g_n * mu[n] / (2.0 if n == 0 else 1.0)
+    return out / d_minus
+
+
+def cpgf_dos(mu: np.ndarray, energies_ev: np.ndarray, e_min: float, e_max: float, eta_ev: float) -> np.ndarray:
+    """rho(E) = -(1/pi) Im (1/N) Tr G^+(E), per eV per orbital (Lorentzian-broadened DOS)."""
+    return -np.imag(cpgf_green(mu, energies_ev, e_min, e_max, eta_ev)) / np.pi
 
 
 def chebyshev_t(n_max: int, x: np.ndarray) -> np.ndarray:

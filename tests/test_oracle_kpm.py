@@ -201,3 +201,46 @@ def test_kspace_moments_pinned_to_exact_trace_and_walks():
     # Asymmetric bounds shift the rescaled spectrum: mu_1 = -d_plus / d_minus.
     sh = kpm.honeycomb_kspace_moments(8, 8, -2.7, -8.0, 9.0, 4)
     assert abs(sh[1] - (-0.5 / 8.5)) < 1e-12
+
+
+def test_lorentz_kernel_properties_and_width():
+    """Lorentz kernel: g_0 = 1, strictly decreasing, positive; a delta peak at the
+    band centre becomes a near-Lorentzian of half width ~ lam/M."""
+    M, lam = 1000, 4.0
+    g = kpm.lorentz(M, lam)
+    assert g[0] == 1.0 and np.all(np.diff(g) < 0) and np.all(g > 0)
+    assert abs(g[-1] - np.sinh(lam / M) / np.sinh(lam)) < 1e-15
+    mu = kpm.chebyshev_t(M, np.array([0.0]))[:, 0]           # mu_n = T_n(0): a level at eps = 0
+    E = np.linspace(-0.05, 0.05, 20001)
+    rho = kpm.dos(mu, E, -1.0, 1.0, kernel=g)
+    half = E[rho >= rho.max() / 2]
+    hwhm = (half[-1] - half[0]) / 2
+    assert abs(hwhm / (lam / M) - 1) < 0.1
+
+
+def test_cpgf_single_level_is_lorentzian():
+    """The CPGF series of one level (mu_n = T_n(a)) sums to the broadened delta
+    eta / (pi ((eps - a)^2 + eta^2)); truncation error ~ |exp(-i arccos z)|^M."""
+    a, eta, M = 0.3, 0.01, 3000
+    mu = kpm.chebyshev_t(M, np.array([a]))[:, 0]
+    E = np.linspace(-1.5, 1.5, 601)                            # also outside the band
+    rho = kpm.cpgf_dos(mu, E, -1.0, 1.0, eta)
+    ref = eta / (np.pi * ((E - a) ** 2 + eta ** 2))
+    assert np.max(np.abs(rho - ref) / ref) < 1e-9
+
+
+def test_cpgf_green_matches_resolvent_trace():
+    """(1/N) Tr 1/(E - H + i eta) of a disordered, vacancy-diluted honeycomb torus
+    from dense eigenvalues, against the CPGF sum over its exact-trace moments."""
+    lat = wl.Lattice(kind=wl.HONEYCOMB, L1=6, L2=5, t=-2.7, anderson_w=1.5, vacancy_p=0.05, disorder_seed=3,
+                     e_min=-9.0, e_max=9.0)
+    m = lattice.build(lat)
+    lam = np.linalg.eigvalsh(m.H.toarray())
+    M, eta = 4000, 0.1
+    x = (lam - 0.0) / 9.0
+    mu = np.cos(np.arange(M)[:, None] * np.arccos(x)[None, :]).mean(axis=1)
+    E = np.linspace(-10.0, 10.0, 81)
+    G = kpm.cpgf_green(mu, E, -9.0, 9.0, eta)
+    ref = np.mean(1.0 / (E[:, None] - lam[None, :] + 1j * eta), axis=1)
+    assert np.max(np.abs(G - ref) / np.abs(ref)) < 1e-10
+    assert np.allclose(kpm.cpgf_dos(mu, E, -9.0, 9.0, eta), -ref.imag / np.pi, rtol=1e-10, atol=0)
