@@ -300,6 +300,21 @@ def main():
     plan.close()
 
     extra = {}
+    # Post-processing of the headline moments (device pointers, 1024 energies):
+    # Jackson and Lorentz KPM, and the CPGF resolvent at eta = 10 meV.
+    rec = {}
+    for name, fn in (("jackson", lambda: kpm.reconstruct_jackson(mean[0], E, lat.e_min, lat.e_max)),
+                     ("lorentz_lambda4", lambda: kpm.reconstruct_lorentz(mean[0], E, lat.e_min, lat.e_max, 4.0)),
+                     ("cpgf_eta10meV", lambda: kpm.reconstruct_cpgf(mean[0], E, lat.e_min, lat.e_max, 0.01,
+                                                                    green=True))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        rec[name + "_ms"] = (time.perf_counter() - t0) / 10 * 1e3
+    extra["reconstruction"] = {"energies": int(E.numel()), "moments": args.M, **rec}
     if not args.no_fp64:
         log("[bench] FP64 pass")
         lat64, par64 = wl.graphene_large(precision=wl.FP64, L=args.L, M=args.M, R=args.R)

@@ -199,6 +199,33 @@ int kpm_reconstruct_jackson(const double* mu, int32_t M, const double* energies_
                             double e_min, double e_max, double* rho, int32_t on_device,
                             void* hip_stream);
 
+/*
+ * The same KPM reconstruction with the Lorentz kernel the paper prints for
+ * damping Gibbs oscillations (Sec. 2(a)): g_n = sinh(lambda (1 - n/M)) /
+ * sinh(lambda), n = 0..M-1; a delta peak becomes a Lorentzian of half width
+ * ~ lambda/M in rescaled units.  Arguments as kpm_reconstruct_jackson;
+ * lambda > 0 (KPM_E_INVALID otherwise).
+ */
+int kpm_reconstruct_lorentz(const double* mu, int32_t M, const double* energies_ev, int32_t K,
+                            double e_min, double e_max, double lambda, double* rho, int32_t on_device,
+                            void* hip_stream);
+
+/*
+ * CPGF reconstruction (eqs. green_function_cheb_expansion and
+ * green_function_cheb_expansionb, retarded sector): the traced resolvent
+ *   G(E) = (1/N) Tr 1/(E - H + i eta) = (1/de-) sum_{n<M} g_n(z) mu_n / (1 + delta_n0),
+ *   g_n(z) = -2 i exp(-i n arccos z) / sqrt(1 - z^2),  z = (E - de+)/de- + i eta/de-,
+ * and rho(E) = -Im G(E) / pi (the DOS broadened by a Lorentzian of half width
+ * eta, per eV per orbital).  Defined for every E, inside or outside the
+ * spectrum bounds; the truncation error decays like exp(-M Im(-arccos z)),
+ * i.e. M ~ several de-/eta terms converge.  mu [M], energies_ev [K] (eV),
+ * rho [K], green [K][2] (re, im; may be NULL), all FP64, host or device
+ * pointers as on_device says.  eta_ev > 0 (KPM_E_INVALID otherwise).
+ */
+int kpm_reconstruct_cpgf(const double* mu, int32_t M, const double* energies_ev, int32_t K, double e_min,
+                         double e_max, double eta_ev, double* rho, double* green, int32_t on_device,
+                         void* hip_stream);
+
 /* Conductivity moment request (KITE Calculation.conductivity_dc/optical, direction = alpha beta). */
 typedef struct kpm_cond_params_t {
   int32_t num_moments;     /* M >= 2: Gamma is M x M */

@@ -1,11 +1,18 @@
-// Jackson-damped DOS reconstruction (paper eqs. e7 and
-// delta_function_cheb_expansion; Jackson kernel of Weisse et al. 2006, which
-// the paper cites for KPM damping).  FP64 throughout.
+// DOS reconstructions from Chebyshev moments, FP64 throughout.
 //
-//   rho(E) = [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n T_n(eps)] / (pi sqrt(1 - eps^2) de-)
+// KPM (paper eqs. e7 and delta_function_cheb_expansion) with a damping kernel:
+//   rho(E) = [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n T_n(eps)] / (pi sqrt(1 - eps^2) de-),
+// g_n the Jackson kernel (Weisse et al. 2006, which the paper cites) or the
+// Lorentz kernel the paper prints (Sec. 2(a)).  One workgroup stages
+// c_n = g_n mu_n (x2 for n >= 1) in LDS in chunks; each thread owns one energy
+// and runs the scalar Chebyshev recursion in eps.
 //
-// One workgroup stages c_n = g_n mu_n (x2 for n >= 1) in LDS in chunks; each
-// thread owns one energy and runs the scalar Chebyshev recursion in x.
+// CPGF (eqs. green_function_cheb_expansion(b)): the retarded resolvent
+//   (1/N) Tr 1/(E - H + i eta) = (1/de-) sum_n g_n(z) mu_n / (1 + delta_n0),
+//   g_n(z) = -2 i w^n / sqrt(1 - z^2),  z = eps + i eta/de-,  w = exp(-i arccos z).
+// w is the root of w^2 - 2 z w + 1 = 0 inside the unit circle (taken as the
+// reciprocal of the outer root, which has no cancellation), and with that
+// branch sqrt(1 - z^2) = i (w - z), so g_n = -2 w^n / (w - z).
 
 #include "kpm_internal.h"
 
@@ -14,13 +21,16 @@
 
 namespace kpm {
 
-__device__ inline double jackson_g(int n, int M) {
+enum { kKernelJackson = 0, kKernelLorentz = 1 };
+
+__device__ inline double damping(int kernel, int n, int M, double lam) {
+  if (kernel == kKernelLorentz) return sinh(lam * (1.0 - (double)n / M)) / sinh(lam);
   const double q = M_PI / (M + 1);
   return ((M - n + 1) * cos(q * n) + sin(q * n) / tan(q)) / (M + 1);
 }
 
-__global__ void jackson_dos_kernel(const double* mu, int M, const double* energies, int K, double e_min,
-                                   double e_max, double* rho) {
+__global__ void kernel_dos_kernel(const double* mu, int M, const double* energies, int K, double e_min,
+                                  double e_max, int kernel, double lam, double* rho) {
   __shared__ double coef[1024];
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const double de_p = 0.5 * (e_max + e_min), de_m = 0.5 * (e_max - e_min);
@@ -31,7 +41,7 @@ __global__ void jackson_dos_kernel(const double* mu, int M, const double* energi
     __syncthreads();
     for (int i = threadIdx.x; i < 1024 && base + i < M; i += blockDim.x) {
       const int n = base + i;
-      coef[i] = (n == 0 ? 1.0 : 2.0) * jackson_g(n, M) * mu[n];
+      coef[i] = (n == 0 ? 1.0 : 2.0) * damping(kernel, n, M, lam) * mu[n];
     }
     __syncthreads();
     const int cnt = min(1024, M - base);
@@ -49,6 +59,69 @@ __global__ void jackson_dos_kernel(const double* mu, int M, const double* energi
     }
   }
   if (k < K) rho[k] = inside ? acc / (M_PI * sqrt(1.0 - eps * eps) * de_m) : 0.0;
+}
+
+struct cplx {
+  double re, im;
+};
+__device__ inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm (scaled by the larger component of b).
+  if (fabs(b.re) >= fabs(b.im)) {
+    const double r = b.im / b.re, d = b.re + b.im * r;
+    return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  }
+  const double r = b.re / b.im, d = b.re * r + b.im;
+  return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+// Principal square root.
+__device__ inline cplx csqrt_p(cplx z) {
+  const double m = hypot(z.re, z.im);
+  if (m == 0.0) return {0.0, 0.0};
+  if (z.re >= 0.0) {
+    const double p = sqrt(0.5 * (m + z.re));
+    return {p, z.im / (2.0 * p)};
+  }
+  const double q = copysign(sqrt(0.5 * (m - z.re)), z.im);
+  return {z.im / (2.0 * q), q};
+}
+
+__global__ void cpgf_kernel(const double* mu, int M, const double* energies, int K, double e_min, double e_max,
+                            double eta_ev, double* rho, double* green) {
+  __shared__ double cm[1024];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const double de_p = 0.5 * (e_max + e_min), de_m = 0.5 * (e_max - e_min);
+  const cplx z = {(k < K) ? (energies[k] - de_p) / de_m : 0.0, eta_ev / de_m};
+  // Roots of w^2 - 2 z w + 1: z +- sqrt(z^2 - 1); the outer one has |.| > 1.
+  const cplx s = csqrt_p({z.re * z.re - z.im * z.im - 1.0, 2.0 * z.re * z.im});
+  const cplx wp = {z.re + s.re, z.im + s.im}, wm = {z.re - s.re, z.im - s.im};
+  const cplx outer = (hypot(wp.re, wp.im) >= hypot(wm.re, wm.im)) ? wp : wm;
+  const cplx w = cdiv({1.0, 0.0}, outer);
+  cplx pw = {1.0, 0.0};   // w^n
+  cplx acc = {0.0, 0.0};  // sum_n mu_n w^n / (1 + delta_n0)
+  for (int base = 0; base < M; base += 1024) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 1024 && base + i < M; i += blockDim.x) {
+      const int n = base + i;
+      cm[i] = (n == 0 ? 0.5 : 1.0) * mu[n];
+    }
+    __syncthreads();
+    const int cnt = min(1024, M - base);
+    for (int i = 0; i < cnt; ++i) {
+      acc.re += cm[i] * pw.re;
+      acc.im += cm[i] * pw.im;
+      pw = cmul(pw, w);
+    }
+  }
+  // G = -2 acc / ((w - z) de-).
+  const cplx g = cdiv({-2.0 * acc.re / de_m, -2.0 * acc.im / de_m}, {w.re - z.re, w.im - z.im});
+  if (k < K) {
+    rho[k] = -g.im / M_PI;
+    if (green) {
+      green[2 * k] = g.re;
+      green[2 * k + 1] = g.im;
+    }
+  }
 }
 
 // T=0 longitudinal conductivity from Gamma (Kubo-Greenwood limit of the
@@ -69,7 +142,7 @@ __global__ void sigma_kernel(const double* gamma, int M, const double* energies,
   }
   const double th = acos(eps);
   const double pref = 2.0 / (M_PI * sqrt(1.0 - eps * eps));
-  for (int n = threadIdx.x; n < M; n += blockDim.x) w[n] = jackson_g(n, M) * pref * cos(n * th);
+  for (int n = threadIdx.x; n < M; n += blockDim.x) w[n] = damping(kKernelJackson, n, M, 0.0) * pref * cos(n * th);
   __syncthreads();
   double acc = 0.0;
   for (int n = threadIdx.x; n < M; n += blockDim.x) {
@@ -127,11 +200,12 @@ extern "C" int kpm_reconstruct_sigma(const double* gamma, int32_t M, const doubl
   return KPM_OK;
 }
 
-extern "C" int kpm_reconstruct_jackson(const double* mu, int32_t M, const double* energies_ev, int32_t K,
-                                       double e_min, double e_max, double* rho, int32_t on_device,
-                                       void* hip_stream) {
-  using namespace kpm;
-  clear_error();
+namespace kpm {
+// Shared driver: stages host inputs, launches one of the DOS kernels, copies
+// the outputs back.  green (CPGF only) may be NULL.
+static int reconstruct(const char* name, int which, const double* mu, int32_t M, const double* energies_ev,
+                       int32_t K, double e_min, double e_max, double param, double* rho, double* green,
+                       int32_t on_device, void* hip_stream) {
   KPM_CHECK_ARG(mu && energies_ev && rho, "NULL argument");
   KPM_CHECK_ARG(M >= 1 && K >= 1, "need M >= 1 and K >= 1");
   KPM_CHECK_ARG(std::isfinite(e_min) && std::isfinite(e_max) && e_min < e_max, "need e_min < e_max");
@@ -139,26 +213,65 @@ extern "C" int kpm_reconstruct_jackson(const double* mu, int32_t M, const double
   const double* dmu = mu;
   const double* den = energies_ev;
   double* drho = rho;
+  double* dg = green;
   double* tmp = nullptr;
   if (!on_device) {
-    KPM_TRY_HIP(hipMalloc(&tmp, sizeof(double) * ((size_t)M + 2 * (size_t)K)));
+    KPM_TRY_HIP(hipMalloc(&tmp, sizeof(double) * ((size_t)M + 4 * (size_t)K)));
     KPM_TRY_HIP(hipMemcpyAsync(tmp, mu, sizeof(double) * M, hipMemcpyHostToDevice, s));
     KPM_TRY_HIP(hipMemcpyAsync(tmp + M, energies_ev, sizeof(double) * K, hipMemcpyHostToDevice, s));
     dmu = tmp;
     den = tmp + M;
     drho = tmp + M + K;
+    dg = green ? tmp + M + 2 * (size_t)K : nullptr;
   }
-  hipLaunchKernelGGL(jackson_dos_kernel, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, dmu, M, den, K, e_min,
-                     e_max, drho);
+  const dim3 grid((unsigned)ceil_div(K, 256)), block(256);
+  if (which == 2)
+    hipLaunchKernelGGL(cpgf_kernel, grid, block, 0, s, dmu, M, den, K, e_min, e_max, param, drho, dg);
+  else
+    hipLaunchKernelGGL(kernel_dos_kernel, grid, block, 0, s, dmu, M, den, K, e_min, e_max, which, param, drho);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && !on_device) {
     e = hipMemcpyAsync(rho, drho, sizeof(double) * K, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && green) e = hipMemcpyAsync(green, dg, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
   if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) {
-    set_error("kpm_reconstruct_jackson: %s", hipGetErrorString(e));
+    set_error("%s: %s", name, hipGetErrorString(e));
     return KPM_E_DEVICE;
   }
   return KPM_OK;
+}
+}  // namespace kpm
+
+extern "C" int kpm_reconstruct_jackson(const double* mu, int32_t M, const double* energies_ev, int32_t K,
+                                       double e_min, double e_max, double* rho, int32_t on_device,
+                                       void* hip_stream) {
+  kpm::clear_error();
+  return kpm::reconstruct("kpm_reconstruct_jackson", kpm::kKernelJackson, mu, M, energies_ev, K, e_min, e_max, 0.0,
+                          rho, nullptr, on_device, hip_stream);
+}
+
+extern "C" int kpm_reconstruct_lorentz(const double* mu, int32_t M, const double* energies_ev, int32_t K,
+                                       double e_min, double e_max, double lambda, double* rho, int32_t on_device,
+                                       void* hip_stream) {
+  kpm::clear_error();
+  if (!(std::isfinite(lambda) && lambda > 0.0)) {
+    kpm::set_error("kpm_reconstruct_lorentz: need lambda > 0");
+    return KPM_E_INVALID;
+  }
+  return kpm::reconstruct("kpm_reconstruct_lorentz", kpm::kKernelLorentz, mu, M, energies_ev, K, e_min, e_max, lambda,
+                          rho, nullptr, on_device, hip_stream);
+}
+
+extern "C" int kpm_reconstruct_cpgf(const double* mu, int32_t M, const double* energies_ev, int32_t K, double e_min,
+                                    double e_max, double eta_ev, double* rho, double* green, int32_t on_device,
+                                    void* hip_stream) {
+  kpm::clear_error();
+  if (!(std::isfinite(eta_ev) && eta_ev > 0.0)) {
+    kpm::set_error("kpm_reconstruct_cpgf: need eta > 0");
+    return KPM_E_INVALID;
+  }
+  return kpm::reconstruct("kpm_reconstruct_cpgf", 2, mu, M, energies_ev, K, e_min, e_max, eta_ev, rho, green,
+                          on_device, hip_stream);
 }

@@ -94,6 +94,10 @@ def _load():
         "kpm_plan_destroy": (ctypes.c_int, [_P]),
         "kpm_reconstruct_jackson": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
                                                    ctypes.c_double, _P, ctypes.c_int32, _P]),
+        "kpm_reconstruct_lorentz": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
+                                                   ctypes.c_double, ctypes.c_double, _P, ctypes.c_int32, _P]),
+        "kpm_reconstruct_cpgf": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_double, _P, _P, ctypes.c_int32, _P]),
         "kpm_moments_cond": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.POINTER(c_cond_params), _P,
                                             ctypes.c_int32, _P]),
         "kpm_reconstruct_sigma": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
@@ -279,6 +283,51 @@ def reconstruct_jackson(mu, energies, e_min: float, e_max: float, stream=None):
     _check(LIB.kpm_reconstruct_jackson(mu.data_ptr(), mu.numel(), en.data_ptr(), en.numel(), float(e_min),
                                        float(e_max), rho.data_ptr(), 1, _stream_handle(stream)))
     return rho
+
+
+def reconstruct_lorentz(mu, energies, e_min: float, e_max: float, lam: float, stream=None):
+    """kpm_reconstruct_lorentz on host numpy arrays or device torch tensors."""
+    if isinstance(mu, np.ndarray):
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        en = np.ascontiguousarray(energies, dtype=np.float64)
+        rho = np.zeros(en.shape)
+        _check(LIB.kpm_reconstruct_lorentz(mu.ctypes.data, mu.size, en.ctypes.data, en.size, float(e_min),
+                                           float(e_max), float(lam), rho.ctypes.data, 0, _stream_handle(stream)))
+        return rho
+    import torch
+    mu = mu.contiguous().to(torch.float64)
+    en = energies.contiguous().to(torch.float64)
+    rho = torch.zeros_like(en)
+    if stream is None:
+        stream = torch.cuda.current_stream(mu.device)
+    _check(LIB.kpm_reconstruct_lorentz(mu.data_ptr(), mu.numel(), en.data_ptr(), en.numel(), float(e_min),
+                                       float(e_max), float(lam), rho.data_ptr(), 1, _stream_handle(stream)))
+    return rho
+
+
+def reconstruct_cpgf(mu, energies, e_min: float, e_max: float, eta: float, green: bool = False, stream=None):
+    """kpm_reconstruct_cpgf: rho [K] (and the complex traced resolvent [K] if green)
+    on host numpy arrays or device torch tensors."""
+    if isinstance(mu, np.ndarray):
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        en = np.ascontiguousarray(energies, dtype=np.float64)
+        rho = np.zeros(en.shape)
+        g = np.zeros(en.shape + (2,)) if green else None
+        _check(LIB.kpm_reconstruct_cpgf(mu.ctypes.data, mu.size, en.ctypes.data, en.size, float(e_min),
+                                        float(e_max), float(eta), rho.ctypes.data, g.ctypes.data if green else None,
+                                        0, _stream_handle(stream)))
+        return (rho, g[..., 0] + 1j * g[..., 1]) if green else rho
+    import torch
+    mu = mu.contiguous().to(torch.float64)
+    en = energies.contiguous().to(torch.float64)
+    rho = torch.zeros_like(en)
+    g = torch.zeros(en.shape + (2,), dtype=torch.float64, device=en.device) if green else None
+    if stream is None:
+        stream = torch.cuda.current_stream(mu.device)
+    _check(LIB.kpm_reconstruct_cpgf(mu.data_ptr(), mu.numel(), en.data_ptr(), en.numel(), float(e_min),
+                                    float(e_max), float(eta), rho.data_ptr(), g.data_ptr() if green else None, 1,
+                                    _stream_handle(stream)))
+    return (rho, torch.view_as_complex(g)) if green else rho
 
 
 def bandwidth_probe(pattern: int, bytes_per_array: int, iters: int = 10, grid: int = 4096, block: int = 256,

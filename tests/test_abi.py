@@ -108,6 +108,11 @@ def test_argument_validation_without_device():
         kpm.reconstruct_jackson(np.zeros(0), np.zeros(4), -1.0, 1.0)
     with pytest.raises(kpm.KPMError):
         kpm.reconstruct_jackson(np.ones(4), np.zeros(4), 1.0, -1.0)
+    for bad in (0.0, -0.1):
+        with pytest.raises(kpm.KPMError):
+            kpm.reconstruct_cpgf(np.ones(4), np.zeros(4), -1.0, 1.0, bad)
+        with pytest.raises(kpm.KPMError):
+            kpm.reconstruct_lorentz(np.ones(4), np.zeros(4), -1.0, 1.0, bad)
     with pytest.raises(kpm.KPMError):
         kpm.bandwidth_probe(7, 1 << 20)
     with pytest.raises(kpm.KPMError):

@@ -331,3 +331,37 @@ def test_two_step_kernel_falls_back_where_ineligible(K):
         plan.close()
         mu_o, _ = oracle_moments(lat, par)
         assert np.max(np.abs(mu[0] - mu_o)) <= fp32_tol(16)
+
+
+def test_lorentz_and_cpgf_reconstruction(K):
+    """Lorentz-kernel KPM and CPGF (resolvent and DOS) from the GPU against the
+    oracle on the same moments, inside and outside the spectrum bounds, host and
+    device pointers; and a 20000-term CPGF series of one level against the exact
+    Lorentzian (truncation ~ exp(-M eta / sqrt(1 - eps^2)) ~ e^-40)."""
+    import torch
+    lat, par = wl.graphene_small()
+    _, mean_o = oracle_moments(lat, par)
+    E = np.concatenate([wl.energy_grid(-9.0, 9.0, 1024), [-12.0, -8.7, 8.9, 12.0]])
+    for lam in (1.0, 4.0):
+        ref = okpm.dos(mean_o, E, lat.e_min, lat.e_max, kernel=okpm.lorentz(mean_o.size, lam))
+        rho = K.reconstruct_lorentz(mean_o, E, lat.e_min, lat.e_max, lam)
+        assert np.max(np.abs(rho - ref)) <= 1e-12 * np.max(np.abs(ref))
+    for eta in (0.02, 0.3):
+        g_ref = okpm.cpgf_green(mean_o, E, lat.e_min, lat.e_max, eta)
+        rho, g = K.reconstruct_cpgf(mean_o, E, lat.e_min, lat.e_max, eta, green=True)
+        assert np.max(np.abs(g - g_ref)) <= 1e-11 * np.max(np.abs(g_ref))
+        assert np.max(np.abs(rho + g_ref.imag / np.pi)) <= 1e-11 * np.max(np.abs(g_ref))
+        rho_d, g_d = K.reconstruct_cpgf(torch.tensor(mean_o, device="cuda"), torch.tensor(E, device="cuda"),
+                                        lat.e_min, lat.e_max, eta, green=True)
+        assert np.array_equal(rho_d.cpu().numpy(), rho) and np.array_equal(g_d.cpu().numpy(), g)
+    a, eta, M = -0.4, 0.002, 20000
+    mu1 = okpm.chebyshev_t(M, np.array([a]))[:, 0]
+    e = np.linspace(-1.2, 1.2, 241)
+    rho1 = K.reconstruct_cpgf(mu1, e, -1.0, 1.0, eta)
+    lor = eta / (np.pi * ((e - a) ** 2 + eta ** 2))
+    assert np.max(np.abs(rho1 - lor) / lor) <= 1e-9
+    for bad in (0.0, -1.0, float("nan")):
+        with pytest.raises(K.KPMError):
+            K.reconstruct_cpgf(mean_o, E, lat.e_min, lat.e_max, bad)
+        with pytest.raises(K.KPMError):
+            K.reconstruct_lorentz(mean_o, E, lat.e_min, lat.e_max, bad)
