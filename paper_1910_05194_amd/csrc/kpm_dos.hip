@@ -29,6 +29,11 @@
 #ifndef KPM_STEP_NT
 #define KPM_STEP_NT 0
 #endif
+// Streaming (non-temporal) hints in the two-step kernel: bit 0 the two
+// output vectors, bit 1 the v_{n-1} loads.  Off by default (measured).
+#ifndef KPM_STEP2_NT
+#define KPM_STEP2_NT 0
+#endif
 
 #include <algorithm>
 #include <cmath>
@@ -843,7 +848,10 @@ __global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
       S.alive = true;
       if (act) {
         const int64_t site = ((int64_t)yy * L1 + n1) * NSUB + s;
-        if (A.read_w1) S.w = ld_pack(wb + site * Rp * 2 + coff);
+        if (A.read_w1) {
+          if constexpr ((KPM_STEP2_NT & 2) != 0) S.w = ld_pack_nt(wb + site * Rp * 2 + coff);
+          else S.w = ld_pack(wb + site * Rp * 2 + coff);
+        }
         if constexpr (ONSITE) S.ons = A.onsite[site_off + site];
         if constexpr (MASK) S.alive = A.mask[site_off + site] != 0;
       }
@@ -889,7 +897,10 @@ __global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
         P o;
         site_update2<T, KIND>(A.a1, A.b1, A.read_w1 != 0, hop, cur.ons, cur.alive, vo, cur.w, vn, o, own, vv1, wv1);
         r1(q, xl, s) = o;
-        if (own) st_pack(o1 + site * Rp * 2 + coff, o);
+        if (own) {
+          if constexpr ((KPM_STEP2_NT & 1) != 0) st_pack_nt(o1 + site * Rp * 2 + coff, o);
+          else st_pack(o1 + site * Rp * 2 + coff, o);
+        }
       }
       lds_barrier();
       if (A.two && inner && j >= 2) {
@@ -915,7 +926,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
         const P wo2 = r0(sm, xl + 1, s);
         P o;
         site_update2<T, KIND>((T)2, (T)1, true, hop, ons_prev, alive_prev, vo, wo2, vn, o, true, vv2, wv2);
-        st_pack(o2 + site * Rp * 2 + coff, o);
+        if constexpr ((KPM_STEP2_NT & 1) != 0) st_pack_nt(o2 + site * Rp * 2 + coff, o);
+        else st_pack(o2 + site * Rp * 2 + coff, o);
       }
       ons_prev = cur.ons;             // row y, for the next phase 2
       alive_prev = cur.alive;
