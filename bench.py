@@ -5,8 +5,9 @@ NN t = -2.7 eV, Anderson W = 1 eV, bounds +-8.5 eV, M = 2048 moments, R = 32
 random-phase complex64 vectors batched in one recursion, FP32 recursion with
 FP64 moment accumulation.  One bench "step" is one complete pass of the DOS
 path on that input: disorder/model build, start vectors, ceil(M/2) = 1024
-Chebyshev steps with fused moments (512 launches of the two-steps-per-sweep
-kernel, or 1024 single-step launches, replayed from a hipGraph), the moment
+Chebyshev steps with fused moments (ceil(1024 / KS) launches of a sweep
+kernel that does KS = 2..4 steps per launch, or 1024 single-step launches,
+replayed from a hipGraph), the moment
 reduction, and the Jackson DOS reconstruction on 1024 energies.  The kernel
 variant and launch shape come from the library's autotuner (run before the
 timed region).
@@ -288,9 +289,9 @@ def main():
     # Step kernel: algorithmic bytes per launch / average launch duration over
     # the timed region (hipEvents around the graph of step launches on the
     # run's stream; the graph also holds the few moment-reduction launches, so
-    # this is a lower bound on the step kernel's own rate).  The two-step
-    # kernel (variant 3) covers two recursion steps per launch.
-    steps_per_launch = 2 if info["kernel"] == 3 else 1
+    # this is a lower bound on the step kernel's own rate).  The sweep
+    # kernels (variants 3, 4, 5) cover 2, 3, 4 recursion steps per launch.
+    steps_per_launch = info["kernel"] - 1 if info["kernel"] >= 3 else 1
     n_launches = -(-info["n_steps"] // steps_per_launch)
     avg_launch_ms = float(np.mean(loop_ms)) / n_launches
     bytes_per_launch = info["bytes_per_step"] * info["n_steps"] / n_launches
@@ -380,7 +381,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(info, args),
                      "kernel": {1: "kpm::step_kernel", 2: "kpm::step_kernel_ring",
-                                3: "kpm::step2_kernel"}[info["kernel"]] + " (FP32, honeycomb, on-site array)",
+                                3: "kpm::sweep_kernel<KS=2>", 4: "kpm::sweep_kernel<KS=3>",
+                                5: "kpm::sweep_kernel<KS=4>"}[info["kernel"]] + " (FP32, honeycomb, on-site array)",
                      "steps_per_launch": steps_per_launch,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms},
         "cpu_baseline": cpu,

@@ -99,27 +99,34 @@ typedef struct kpm_dos_params_t {
 
 /* Optional launch shape of the Chebyshev step kernel (0 = library choice / autotune cache). */
 typedef struct kpm_tune_t {
-  int32_t block;           /* threads per workgroup (64..512, multiple of 64) */
+  int32_t block;           /* threads per workgroup (64..512, multiple of 64); 0 = 512 for the sweep kernels,
+                              256 otherwise */
   int32_t rows;            /* lattice rows (along a2) per tile */
   int32_t grid;            /* persistent workgroups (multiple of 8); 0 = one per tile */
   int32_t use_graph;       /* 1 = replay the step loop as a captured hipGraph (default), 0 = eager */
-  int32_t kernel;          /* 0 = default (3 where eligible, else 2), 1 = direct neighbour loads, 2 = LDS row
-                              ring, 3 = two steps per sweep (spinless lattices without Peierls phases and with
-                              room for four vectors; falls back to 2 otherwise) */
+  int32_t kernel;          /* 0 = default (4 where eligible, else 2), 1 = direct neighbour loads, 2 = LDS row
+                              ring, 3/4/5 = 2/3/4 steps per sweep (spinless lattices without Peierls phases
+                              and with room for four vectors; a sweep whose row rings do not fit in LDS takes
+                              one step fewer, down to 2) */
+  int32_t chunks;          /* 16-byte vector chunks per site that one tile covers (1..E, E = the site's R_padded
+                              complex values in 16-byte chunks); a tile then spans block / (sublattices * chunks)
+                              cell columns; 0 = library choice */
 } kpm_tune_t;
 
 typedef struct kpm_plan_info_t {
-  int32_t n_steps;               /* recursion steps per run (ceil(M/2)); variant 3 launches once per two */
+  int32_t n_steps;               /* recursion steps per run (ceil(M/2)); variants 3/4/5 launch once per 2/3/4 */
   int32_t n_tiles;               /* tiles in the work list */
   int32_t grid, block, rows, tile_cells_x;
   int32_t r_padded;              /* vectors per orbital as stored (R rounded up) */
-  int32_t kernel;                /* step kernel variant in use (1 direct, 2 LDS ring, 3 two steps per sweep) */
+  int32_t kernel;                /* step kernel variant in use (1 direct, 2 LDS ring, 3/4/5 = 2/3/4 steps per
+                                    sweep) */
   int64_t n_orbitals;            /* orbitals in the batch, vacancies included */
-  double bytes_per_step;         /* algorithmic HBM bytes per recursion step (variant 3: two vectors in and
-                                    two out per pair of steps) */
+  double bytes_per_step;         /* algorithmic HBM bytes per recursion step (variants 3/4/5: two vectors
+                                    and the site arrays in, two vectors out, per sweep of 2/3/4 steps) */
   double last_loop_ms;           /* step loop of the last run (hipEvents on the run's stream) */
   double last_run_ms;            /* whole last run (hipEvents) */
   int64_t n_active_total;        /* active orbitals summed over lattices (after the last run) */
+  int32_t tile_chunks;           /* 16-byte vector chunks per site a tile covers */
 } kpm_plan_info_t;
 
 typedef struct kpm_plan kpm_plan_t;
@@ -156,11 +163,11 @@ int kpm_moments_dos(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
 /*
  * Launch-shape autotuner (the analogue of the paper's user-tuned TILE size,
  * Sec. 3(b) and Table 1).  Runs the recursion for probe_steps steps with each
- * candidate (kernel variant 1/2/3 x block x rows x grid) on the given
+ * candidate (kernel variant 1..5 x block x rows x grid) on the given
  * workload, timed with hipEvents on hip_stream, re-times the three fastest on
  * 4 probe_steps steps (median of three rounds), and returns the one with the
  * shortest time per step in *best (and its algorithmic GB/s in *best_gbs, may
- * be NULL; variant 3 moves fewer bytes per step, so GB/s does not rank
+ * be NULL; the sweep variants move fewer bytes per step, so GB/s does not rank
  * variants).  If cache_path is non-NULL the
  * result is appended to that text file; kpm_plan_create reads the file named
  * by the environment variable KPM_TUNE_CACHE whenever it is called without a

@@ -29,10 +29,10 @@
 #ifndef KPM_STEP_NT
 #define KPM_STEP_NT 0
 #endif
-// Streaming (non-temporal) hints in the two-step kernel: bit 0 the two
+// Streaming (non-temporal) hints in the sweep kernels: bit 0 the two
 // output vectors, bit 1 the v_{n-1} loads.  Off by default (measured).
-#ifndef KPM_STEP2_NT
-#define KPM_STEP2_NT 0
+#ifndef KPM_SWEEP_NT
+#define KPM_SWEEP_NT 0
 #endif
 
 #include <algorithm>
@@ -684,40 +684,44 @@ __global__ void __launch_bounds__(kMaxStepBlock) step_kernel_ring(StepArgs<T> A)
 }
 
 // ---------------------------------------------------------------------------
-// Two Chebyshev steps per sweep (temporal blocking) for the spinless lattices
-// without Peierls phases:
-//     v_{n+1} = a1 H~ v_n - b1 v_{n-1},   v_{n+2} = 2 H~ v_{n+1} - v_n,
-// with the doubling dot products of both steps, from one pass over v_n and
-// v_{n-1}.  Per pair of steps HBM moves two vectors in and two out, instead of
-// three per step.
+// KS Chebyshev steps per sweep (temporal blocking) for the spinless lattices
+// without Peierls phases: level l = 1..KS of a sweep is v_{n+l},
+//     v_{n+1} = a1 H~ v_n - b1 v_{n-1},   v_{n+l} = 2 H~ v_{n+l-1} - v_{n+l-2},
+// with the doubling dot products of every step, from one pass over v_n and
+// v_{n-1}.  Only the last two levels go back to HBM (the next sweep starts
+// from them), so per KS steps HBM moves two vectors in and two out, instead
+// of three per step.
 //
-// A tile is a band of Tx - 2 interior cell columns and Ty rows of one
-// (lattice, r-group).  The workgroup's thread columns cover the interior plus
-// one column on each side, so that v_{n+1} is available on a one-cell halo
-// (recomputed by the neighbouring tiles too); v_n comes with one more halo
-// column on each side.  Rows are marched upwards: row y of v_n enters a
-// 4-slot LDS ring, v_{n+1}(y) goes to a 3-slot ring, and v_{n+2}(y - 1) is
-// formed from that ring.  Both outputs go to buffers that no tile reads in
-// the same sweep (neighbouring tiles still read v_n and v_{n-1} on halos).
-// two = 0 runs the first half only (an odd last step).
+// A tile is a band of Tx - 2 (KS - 1) interior cell columns and Ty rows of
+// one (lattice, r-group).  The workgroup's Tx thread columns cover the
+// interior plus KS - 1 columns on each side: level l is formed on thread
+// columns [l - 1, Tx - l] (each level needs one neighbour column more than
+// the next), so level KS covers the interior; v_n comes with one more halo
+// column per side.  Rows are marched upwards: at iteration j, row y0 + j of
+// v_n enters a 4-slot LDS ring and level l forms row y0 + j - l into a 3-slot
+// ring of its own (the last level only to HBM); KS barriers per row.  The
+// outputs go to buffers that no tile reads in the same sweep (neighbouring
+// tiles still read v_n and v_{n-1} on halos).  nlev < KS runs the first nlev
+// levels only (the last, short sweep of a recursion).
 // ---------------------------------------------------------------------------
+constexpr int kMaxSweep = 4;
+
 template <typename T>
-struct Step2Args {
+struct SweepArgs {
   const LatDev<T>* __restrict__ lats;
   const int4* __restrict__ tiles;   // (lattice, r-group, x0, y0), x0 the first interior column
   const int* __restrict__ slot_of;
   int n_tiles;
   const T* __restrict__ v;          // v_n
   const T* __restrict__ w;          // v_{n-1} (read when read_w1)
-  T* __restrict__ out1;             // v_{n+1}
-  T* __restrict__ out2;             // v_{n+2}
+  T* __restrict__ out_a;            // v_{n+nlev-1} (nlev >= 2)
+  T* __restrict__ out_b;            // v_{n+nlev}
   const T* __restrict__ onsite;
   const uint8_t* __restrict__ mask;
-  double* part1;                    // slot partials of step n
-  double* part2;                    // slot partials of step n + 1
+  double* part[kMaxSweep];          // slot partials of steps n .. n+nlev-1
   T a1, b1;
-  int read_w1, two;
-  int Tx, Ty, E, Ew, Rp;            // Tx = thread columns (interior + 2)
+  int read_w1, nlev;
+  int Tx, Ty, E, Ew, Rp;            // Tx = thread columns (interior + 2 (KS - 1))
 };
 
 // out = a (H~ v)_i - b w_i at one site (no Peierls phase, one spin), and the
@@ -755,13 +759,14 @@ __device__ inline void site_update2(T a, T b, bool read_w, T hop, T ons, bool al
   }
 }
 
-template <typename T, int KIND, bool ONSITE, bool MASK>
-__global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
+template <typename T, int KIND, bool ONSITE, bool MASK, int KS>
+__global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   using P = Pack<T>;
   constexpr int NC = P::NC;
   constexpr int NSUB = KindTraits<KIND>::NSUB;
   constexpr int NNB = KindTraits<KIND>::NNB;
   static_assert(KindTraits<KIND>::NSPIN == 1, "spinless lattices only");
+  static_assert(KS >= 2 && KS <= kMaxSweep, "2..kMaxSweep steps per sweep");
   extern __shared__ double lds[];
 
   const int tid = threadIdx.x;
@@ -773,14 +778,17 @@ __global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
   const int xl = grp / NSUB;
   const int Rp = A.Rp;
   const int Tx = A.Tx;
-  // v_n ring: [4 slots][Tx + 2 cells][sub][chunk]; v_{n+1} ring: [3][Tx][sub][chunk].
-  // The moment flush reuses the same LDS between tiles.
+  const int nlev = A.nlev;
+  // v_n ring: [4 slots][Tx + 2 cells][sub][chunk]; level l (1..KS-1) ring:
+  // [3 slots][Tx][sub][chunk].  The moment flush reuses the same LDS between tiles.
   P* ring0 = reinterpret_cast<P*>(lds);
   const int row0 = (Tx + 2) * NSUB * Ew;
-  P* ring1 = ring0 + 4 * row0;
-  const int row1 = Tx * NSUB * Ew;
+  P* ringl = ring0 + 4 * row0;
+  const int rowl = Tx * NSUB * Ew;
   auto r0 = [&](int slot, int cell, int sub) -> P& { return ring0[slot * row0 + (cell * NSUB + sub) * Ew + cl]; };
-  auto r1 = [&](int slot, int cell, int sub) -> P& { return ring1[slot * row1 + (cell * NSUB + sub) * Ew + cl]; };
+  auto rl = [&](int lev, int slot, int cell, int sub) -> P& {
+    return ringl[((lev - 1) * 3 + slot) * rowl + (cell * NSUB + sub) * Ew + cl];
+  };
 
   const int xcd = blockIdx.x & 7;
   const int jx = blockIdx.x >> 3;
@@ -788,9 +796,11 @@ __global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
   const int t_begin = (int)(((int64_t)xcd * A.n_tiles) >> 3);
   const int t_end = (int)(((int64_t)(xcd + 1) * A.n_tiles) >> 3);
 
-  double vv1[NC], wv1[NC], vv2[NC], wv2[NC];
+  double vv[KS][NC], wv[KS][NC];
 #pragma unroll
-  for (int j = 0; j < NC; ++j) vv1[j] = wv1[j] = vv2[j] = wv2[j] = 0.0;
+  for (int l = 0; l < KS; ++l)
+#pragma unroll
+    for (int j = 0; j < NC; ++j) vv[l][j] = wv[l][j] = 0.0;
 
   for (int ti = t_begin + jx; ti < t_end; ti += gx) {
     const int4 tl = A.tiles[ti];
@@ -799,19 +809,20 @@ __global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
     const int64_t site_off = Lg.site_off;
     const T hop = Lg.hop, ons_c = Lg.onsite_const;
     const int x0 = tl.z, y0 = tl.w;
-    const int n_in = min(Tx - 2, L1 - x0);       // interior columns of this tile
-    const int wcols = n_in + 2;                  // thread columns in use
-    const int xe = (x0 == 0) ? L1 - 1 : x0 - 1;  // column of thread column 0
+    const int n_in = min(Tx - 2 * (KS - 1), L1 - x0);   // interior columns of this tile
+    const int wcols = n_in + 2 * (KS - 1);              // thread columns in use
+    int xe = (x0 - (KS - 1)) % L1;                       // column of thread column 0
+    if (xe < 0) xe += L1;
     const int n1 = (xe + xl) % L1;
     const int c = tl.y * Ew + cl;
     const bool lane_ok = (grp < n_grp) && (c < A.E);
     const bool act = lane_ok && (xl < wcols);
-    const bool inner = act && (xl >= 1) && (xl <= n_in);
+    const bool inner = act && (xl >= KS - 1) && (xl <= wcols - KS);
     const int64_t coff = (int64_t)c * NC * 2;
     const T* __restrict__ vb = A.v + Lg.vec_off;
     const T* __restrict__ wb = A.w + Lg.vec_off;
-    T* __restrict__ o1 = A.out1 + Lg.vec_off;
-    T* __restrict__ o2 = A.out2 + Lg.vec_off;
+    T* __restrict__ oa = A.out_a + Lg.vec_off;
+    T* __restrict__ ob = A.out_b + Lg.vec_off;
     // Halo cells of v_n: left of thread column 0, right of thread column wcols - 1.
     const int hl = (xe == 0) ? L1 - 1 : xe - 1;
     const int hr = (xe + wcols) % L1;
@@ -821,9 +832,9 @@ __global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
       y %= L2;
       return y < 0 ? y + L2 : y;
     };
-    // Everything a row needs from HBM (v_n with halos for row y + 1, v_{n-1},
-    // on-site potential and vacancy flag for row y) is loaded into registers
-    // one iteration ahead, as one group: the phases themselves only touch LDS
+    // Everything a row needs from HBM (v_n with halos, v_{n-1}, on-site
+    // potential and vacancy flag of level 1's row) is loaded into registers
+    // one iteration ahead, as one group: the levels themselves only touch LDS
     // and store, so the in-order load counter never makes them wait for the
     // next row's loads.  Two register sets alternate (the loop is unrolled by
     // two), so no loaded value is copied after the next loads were issued.
@@ -849,109 +860,135 @@ __global__ void __launch_bounds__(kMaxStepBlock) step2_kernel(Step2Args<T> A) {
       if (act) {
         const int64_t site = ((int64_t)yy * L1 + n1) * NSUB + s;
         if (A.read_w1) {
-          if constexpr ((KPM_STEP2_NT & 2) != 0) S.w = ld_pack_nt(wb + site * Rp * 2 + coff);
+          if constexpr ((KPM_SWEEP_NT & 2) != 0) S.w = ld_pack_nt(wb + site * Rp * 2 + coff);
           else S.w = ld_pack(wb + site * Rp * 2 + coff);
         }
         if constexpr (ONSITE) S.ons = A.onsite[site_off + site];
         if constexpr (MASK) S.alive = A.mask[site_off + site] != 0;
       }
     };
+    auto put = [&](T* base, int64_t site, const P& o) {
+      if constexpr ((KPM_SWEEP_NT & 1) != 0) st_pack_nt(base + site * Rp * 2 + coff, o);
+      else st_pack(base + site * Rp * 2 + coff, o);
+    };
     const int ty = min(A.Ty, L2 - y0);
-    T ons_prev = ons_c;
-    bool alive_prev = true;
-    int q = 0;
-    // One row: v_{n+1}(y) on all thread columns, then v_{n+2}(y - 1) on the
-    // interior.  cur holds v_n row y + 1 and the site data of row y.
+    const int j_end = ty + KS;
+    // Site data of the rows the levels form now: level l uses entry l - 1
+    // (level l's row is level 1's row of l - 1 iterations ago).
+    T ons_h[KS];
+    bool alive_h[KS];
+#pragma unroll
+    for (int l = 0; l < KS; ++l) {
+      ons_h[l] = ons_c;
+      alive_h[l] = true;
+    }
+    // One iteration: cur holds v_n row y0 + j and the site data of row y0 + j - 1.
     auto row = [&](int j, const RowSet& cur, RowSet& nxt) {
-      const int y = y0 - 1 + j;
       // All of cur has arrived (vmcnt(0); expcnt and lgkmcnt left at their
       // maxima), so no later use of it waits for the loads issued below.
       __builtin_amdgcn_s_waitcnt(0x0F70);
-      store_row(cur, (j + 2) & 3);
+      store_row(cur, (j + KS) & 3);   // v_n row r sits in slot (r - (y0 - KS)) & 3
+#pragma unroll
+      for (int l = KS - 1; l > 0; --l) {
+        ons_h[l] = ons_h[l - 1];
+        alive_h[l] = alive_h[l - 1];
+      }
+      ons_h[0] = cur.ons;
+      alive_h[0] = cur.alive;
       __builtin_amdgcn_sched_barrier(0);
-      if (j + 1 < ty + 2) {
-        fetch_row(nxt, wrap(y + 2));
-        fetch_site(nxt, wrap(y + 1));
+      if (j + 1 < j_end) {
+        fetch_row(nxt, wrap(y0 + j + 1));
+        fetch_site(nxt, wrap(y0 + j));
       }
       lds_barrier();
-      const int sy = (j + 1) & 3, sm = j & 3, sp = (j + 2) & 3;
-      if (act) {
-        const int64_t site = ((int64_t)wrap(y) * L1 + n1) * NSUB + s;
-        P vn[NNB];
-        if constexpr (KIND == KPM_SQUARE) {
-          vn[0] = r0(sy, xl + 2, 0);
-          vn[1] = r0(sy, xl, 0);
-          vn[2] = r0(sp, xl + 1, 0);
-          vn[3] = r0(sm, xl + 1, 0);
-        } else if (s == 0) {
-          vn[0] = r0(sy, xl + 1, 1);
-          vn[1] = r0(sm, xl + 2, 1);
-          vn[2] = r0(sm, xl + 1, 1);
-        } else {
-          vn[0] = r0(sy, xl + 1, 0);
-          vn[1] = r0(sp, xl, 0);
-          vn[2] = r0(sp, xl + 1, 0);
-        }
-        const P vo = r0(sy, xl + 1, s);
-        const bool own = inner && (y >= y0) && (y < y0 + ty);
-        P o;
-        site_update2<T, KIND>(A.a1, A.b1, A.read_w1 != 0, hop, cur.ons, cur.alive, vo, cur.w, vn, o, own, vv1, wv1);
-        r1(q, xl, s) = o;
-        if (own) {
-          if constexpr ((KPM_STEP2_NT & 1) != 0) st_pack_nt(o1 + site * Rp * 2 + coff, o);
-          else st_pack(o1 + site * Rp * 2 + coff, o);
+      const int q = ((j % 3) + 3) % 3;   // ring slot of the rows formed at iteration j
+      const int qm1 = (q + 2) % 3, qm2 = (q + 1) % 3;
+      // Level 1 (row y0 + j - 1) from v_n rows y0 + j - 2 .. y0 + j.
+      {
+        const int y = y0 + j - 1;
+        if (act) {
+          const int sy = (j - 1 + KS) & 3, sm = (j - 2 + KS) & 3, sp = (j + KS) & 3;
+          const int64_t site = ((int64_t)wrap(y) * L1 + n1) * NSUB + s;
+          P vn[NNB];
+          if constexpr (KIND == KPM_SQUARE) {
+            vn[0] = r0(sy, xl + 2, 0);
+            vn[1] = r0(sy, xl, 0);
+            vn[2] = r0(sp, xl + 1, 0);
+            vn[3] = r0(sm, xl + 1, 0);
+          } else if (s == 0) {
+            vn[0] = r0(sy, xl + 1, 1);
+            vn[1] = r0(sm, xl + 2, 1);
+            vn[2] = r0(sm, xl + 1, 1);
+          } else {
+            vn[0] = r0(sy, xl + 1, 0);
+            vn[1] = r0(sp, xl, 0);
+            vn[2] = r0(sp, xl + 1, 0);
+          }
+          const P vo = r0(sy, xl + 1, s);
+          const bool own = inner && (y >= y0) && (y < y0 + ty);
+          P o;
+          site_update2<T, KIND>(A.a1, A.b1, A.read_w1 != 0, hop, ons_h[0], alive_h[0], vo, cur.w, vn, o, own,
+                                vv[0], wv[0]);
+          rl(1, q, xl, s) = o;
+          if (own && nlev <= 2) put(nlev == 1 ? ob : oa, site, o);
         }
       }
-      lds_barrier();
-      if (A.two && inner && j >= 2) {
-        // v_{n+2}(y - 1) from v_{n+1} rows y - 2, y - 1, y and v_n(y - 1).
-        const int qm = (q + 1) % 3, q0 = (q + 2) % 3, qp = q;
-        const int64_t site = ((int64_t)wrap(y - 1) * L1 + n1) * NSUB + s;
-        P vn[NNB];
-        if constexpr (KIND == KPM_SQUARE) {
-          vn[0] = r1(q0, xl + 1, 0);
-          vn[1] = r1(q0, xl - 1, 0);
-          vn[2] = r1(qp, xl, 0);
-          vn[3] = r1(qm, xl, 0);
-        } else if (s == 0) {
-          vn[0] = r1(q0, xl, 1);
-          vn[1] = r1(qm, xl + 1, 1);
-          vn[2] = r1(qm, xl, 1);
-        } else {
-          vn[0] = r1(q0, xl, 0);
-          vn[1] = r1(qp, xl - 1, 0);
-          vn[2] = r1(qp, xl, 0);
+#pragma unroll
+      for (int lev = 2; lev <= KS; ++lev) {
+        lds_barrier();
+        // Level lev (row y0 + j - lev) from level lev-1 rows y - 1 .. y + 1
+        // (formed at iterations j - 2 .. j) and w = level lev-2 at row y.
+        const int y = y0 + j - lev;
+        if (lev <= nlev && act && xl >= lev - 1 && xl <= wcols - lev && j >= 2 * lev - KS) {
+          const int64_t site = ((int64_t)wrap(y) * L1 + n1) * NSUB + s;
+          P vn[NNB];
+          if constexpr (KIND == KPM_SQUARE) {
+            vn[0] = rl(lev - 1, qm1, xl + 1, 0);
+            vn[1] = rl(lev - 1, qm1, xl - 1, 0);
+            vn[2] = rl(lev - 1, q, xl, 0);
+            vn[3] = rl(lev - 1, qm2, xl, 0);
+          } else if (s == 0) {
+            vn[0] = rl(lev - 1, qm1, xl, 1);
+            vn[1] = rl(lev - 1, qm2, xl + 1, 1);
+            vn[2] = rl(lev - 1, qm2, xl, 1);
+          } else {
+            vn[0] = rl(lev - 1, qm1, xl, 0);
+            vn[1] = rl(lev - 1, q, xl - 1, 0);
+            vn[2] = rl(lev - 1, q, xl, 0);
+          }
+          const P vo = rl(lev - 1, qm1, xl, s);
+          const P wo = (lev == 2) ? r0((j - 2 + KS) & 3, xl + 1, s) : rl(lev == 2 ? 1 : lev - 2, qm2, xl, s);
+          const bool own = inner && (y >= y0) && (y < y0 + ty);
+          P o;
+          site_update2<T, KIND>((T)2, (T)1, true, hop, ons_h[lev - 1], alive_h[lev - 1], vo, wo, vn, o, own,
+                                vv[lev - 1], wv[lev - 1]);
+          if (lev < KS) rl(lev, q, xl, s) = o;
+          if (own && lev >= nlev - 1) put(lev == nlev ? ob : oa, site, o);
         }
-        const P vo = r1(q0, xl, s);
-        const P wo2 = r0(sm, xl + 1, s);
-        P o;
-        site_update2<T, KIND>((T)2, (T)1, true, hop, ons_prev, alive_prev, vo, wo2, vn, o, true, vv2, wv2);
-        if constexpr ((KPM_STEP2_NT & 1) != 0) st_pack_nt(o2 + site * Rp * 2 + coff, o);
-        else st_pack(o2 + site * Rp * 2 + coff, o);
       }
-      ons_prev = cur.ons;             // row y, for the next phase 2
-      alive_prev = cur.alive;
-      q = (q == 2) ? 0 : q + 1;
     };
-    // v_n row r sits in slot (r - (y0 - 2)) & 3; v_{n+1} row y0 - 1 + j in slot j % 3.
-    fetch_row(sa, wrap(y0 - 2));
+    // Prologue: v_n rows y0 - KS and y0 - KS + 1 into slots 0 and 1; the
+    // first iteration's row and site data into registers.
+    const int j0 = 2 - KS;
+    fetch_row(sa, wrap(y0 - KS));
     store_row(sa, 0);
-    fetch_row(sa, wrap(y0 - 1));
+    fetch_row(sa, wrap(y0 - KS + 1));
     store_row(sa, 1);
-    fetch_row(sa, wrap(y0));
-    fetch_site(sa, wrap(y0 - 1));
-    int j = 0;
-    for (; j + 1 < ty + 2; j += 2) {
+    fetch_row(sa, wrap(y0 + j0));
+    fetch_site(sa, wrap(y0 + j0 - 1));
+    int j = j0;
+    for (; j + 1 < j_end; j += 2) {
       row(j, sa, sb);
       row(j + 1, sb, sa);
     }
-    if (j < ty + 2) row(j, sa, sb);
+    if (j < j_end) row(j, sa, sb);
     __syncthreads();   // the next tile (or the moment flush) reuses the LDS
     const int tn = ti + gx;
     const int slot = A.slot_of[ti];
     if (tn >= t_end || A.slot_of[tn] != slot) {
-      flush_slot<NC>(lds, A.part1, slot, tid, Ew, grp, n_grp, vv1, wv1);
-      if (A.two) flush_slot<NC>(lds, A.part2, slot, tid, Ew, grp, n_grp, vv2, wv2);
+#pragma unroll
+      for (int l = 0; l < KS; ++l)
+        if (l < nlev) flush_slot<NC>(lds, A.part[l], slot, tid, Ew, grp, n_grp, vv[l], wv[l]);
     }
   }
 }
@@ -1147,15 +1184,23 @@ static void* pick_step(int variant, bool onsite, bool mask, bool phase) {
   }
 }
 
+template <typename T, int KIND, int KS>
+static void* pick_sweep_ks(bool onsite, bool mask) {
+  if (onsite) return mask ? (void*)sweep_kernel<T, KIND, true, true, KS> : (void*)sweep_kernel<T, KIND, true, false, KS>;
+  return mask ? (void*)sweep_kernel<T, KIND, false, true, KS> : (void*)sweep_kernel<T, KIND, false, false, KS>;
+}
+
 template <typename T, int KIND>
-static void* pick_step2(bool onsite, bool mask) {
-  if (onsite) return mask ? (void*)step2_kernel<T, KIND, true, true> : (void*)step2_kernel<T, KIND, true, false>;
-  return mask ? (void*)step2_kernel<T, KIND, false, true> : (void*)step2_kernel<T, KIND, false, false>;
+static void* pick_sweep(int ks, bool onsite, bool mask) {
+  if (ks == 2) return pick_sweep_ks<T, KIND, 2>(onsite, mask);
+  if (ks == 3) return pick_sweep_ks<T, KIND, 3>(onsite, mask);
+  return pick_sweep_ks<T, KIND, 4>(onsite, mask);
 }
 
 template <typename T>
-static void* pick_step2_kind(int kind, bool onsite, bool mask) {
-  return kind == KPM_SQUARE ? pick_step2<T, KPM_SQUARE>(onsite, mask) : pick_step2<T, KPM_HONEYCOMB>(onsite, mask);
+static void* pick_sweep_kind(int kind, int ks, bool onsite, bool mask) {
+  return kind == KPM_SQUARE ? pick_sweep<T, KPM_SQUARE>(ks, onsite, mask)
+                            : pick_sweep<T, KPM_HONEYCOMB>(ks, onsite, mask);
 }
 
 template <typename T, bool VEL>
@@ -1280,7 +1325,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   // No launch shape given: use the autotune cache (KPM_TUNE_CACHE) if it has one.
   kpm_tune_t cached;
   if (lat != nullptr && n_lat >= 1 && p != nullptr &&
-      (!tune || (tune->block == 0 && tune->rows == 0 && tune->grid == 0 && tune->kernel == 0))) {
+      (!tune || (tune->block == 0 && tune->rows == 0 && tune->grid == 0 && tune->kernel == 0 && tune->chunks == 0))) {
     std::memset(&cached, 0, sizeof(cached));
     cached.use_graph = tune ? tune->use_graph : 1;
     if (tune_cache_lookup(lat, n_lat, p, &cached)) tune = &cached;
@@ -1368,7 +1413,8 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   }
 
   // Launch shape.
-  P->block = (tune && tune->block > 0) ? tune->block : 256;
+  const bool block_given = tune && tune->block > 0;
+  P->block = block_given ? tune->block : 256;
   P->Ty = (tune && tune->rows > 0) ? tune->rows : 64;
   P->use_graph = tune ? (tune->use_graph != 0) : true;
   if (P->block < 64 || P->block > kMaxStepBlock || (P->block % 64) != 0) {
@@ -1376,35 +1422,62 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     delete P;
     return KPM_E_INVALID;
   }
-  // Kernel variant: 3 = two steps per sweep (spinless lattices without
-  // Peierls phases, room for two more vectors), 2 = LDS row ring, 1 = direct
-  // loads.  The default is the fastest eligible one.
-  const int want = (tune && tune->kernel > 0) ? tune->kernel : 3;
-  if (want < 1 || want > 3) {
-    set_error("kernel must be 0 (default), 1, 2 or 3");
+  const int chunks = tune ? tune->chunks : 0;
+  if (chunks < 0 || chunks > P->block / P->n_sub) {
+    set_error("chunks must be in [0, block / sublattices]");
+    delete P;
+    return KPM_E_INVALID;
+  }
+  // Kernel variant: 3, 4, 5 = 2, 3, 4 steps per sweep (spinless lattices
+  // without Peierls phases, room for two more vectors), 2 = LDS row ring,
+  // 1 = direct loads.  The default (three steps per sweep where eligible)
+  // was the fastest on the graphene workloads in FP32 and FP64.
+  const int want = (tune && tune->kernel > 0) ? tune->kernel : 4;
+  if (want < 1 || want > 5) {
+    set_error("kernel must be 0 (default) or 1..5");
     delete P;
     return KPM_E_INVALID;
   }
   P->variant = want;
-  if (P->variant == 3) {
+  if (P->variant >= 3) {
     const double vec_b = (double)P->n_orb * P->Rp * 2 * P->tsize;
     size_t free_b = 0, total_b = 0;
     const bool room = hipMemGetInfo(&free_b, &total_b) == hipSuccess && (double)free_b > 4.0 * vec_b + 2.0e9;
     if (P->kind == KPM_HONEYCOMB_SPIN || P->has_phase || !room) P->variant = 2;
   }
-  if (P->variant == 3) {
-    // Chunks per r-group such that a tile has ~32 thread columns (30 interior).
-    P->Ew = (int)std::min<int64_t>(P->E, std::max(1, P->block / (P->n_sub * 32)));
-    P->Tx = P->block / (P->n_sub * P->Ew);
-    if (P->Tx < 3) P->variant = 2;
+  if (P->variant >= 3 && !block_given) P->block = kMaxStepBlock;
+  int lds_max = 65536;
+  {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      lds_max = v;
   }
-  if (P->variant != 3) {
-    P->Ew = (int)std::min<int64_t>(P->E, std::max(1, P->block / P->n_sub));
+  // Sweep kernels: by default a tile covers 8 chunks (128 contiguous bytes)
+  // of each site, and at least 4 KS thread columns (KS - 1 on each side are
+  // halo); the row rings must fit in LDS, otherwise fewer steps per sweep,
+  // down to the single-step ring.
+  while (P->variant >= 3) {
+    const int ks = P->variant - 1;
+    if (chunks > 0) {
+      P->Ew = (int)std::min<int64_t>(P->E, chunks);
+    } else {
+      P->Ew = (int)std::min<int64_t>(P->E, 8);
+      while (P->Ew > 1 && P->block / (P->n_sub * P->Ew) < 4 * ks) P->Ew >>= 1;
+    }
+    P->Tx = P->block / (P->n_sub * P->Ew);
+    const size_t rings = (4 * (size_t)(P->Tx + 2) + 3 * (size_t)(ks - 1) * P->Tx) * P->n_sub * P->Ew * 16;
+    if (P->Tx >= 2 * ks - 1 && rings <= (size_t)lds_max) break;
+    P->variant = (ks == 2) ? 2 : P->variant - 1;
+  }
+  P->sweep = (P->variant >= 3) ? P->variant - 1 : 1;
+  if (P->variant < 3) {
+    P->Ew = (int)std::min<int64_t>(P->E, chunks > 0 ? chunks : std::max(1, P->block / P->n_sub));
     P->Tx = std::max(1, P->block / (P->n_sub * P->Ew));
   }
   P->n_rg = (int)ceil_div(P->E, P->Ew);
-  // Cells a tile owns along n1 (the two-step kernel spends two thread columns on halos).
-  const int xstep = (P->variant == 3) ? P->Tx - 2 : P->Tx;
+  // Cells a tile owns along n1 (a sweep kernel spends KS - 1 thread columns per side on halos).
+  const int xstep = P->Tx - 2 * (P->sweep - 1);
   if (!(tune && tune->rows > 0)) {
     // Default rows per tile: the largest power of two <= 64 that still gives
     // at least 2048 tiles (8 per CU), so that small lattices fill the chip.
@@ -1479,15 +1552,17 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   const double part_step_bytes = (double)P->n_slots * Rw * 2 * 8;
   const double budget = 2.0e9;
   P->steps_per_chunk = (int)std::max<double>(1.0, std::min<double>(P->n_steps, std::floor(budget / part_step_bytes)));
-  // The two-step kernel writes the partials of a step pair into one chunk.
-  if (P->variant == 3) P->steps_per_chunk = std::max(2, P->steps_per_chunk & ~1);
+  // A sweep kernel writes the partials of its KS steps into one chunk.
+  if (P->sweep > 1)
+    P->steps_per_chunk = std::max(P->sweep, P->steps_per_chunk - P->steps_per_chunk % P->sweep);
 
   // Algorithmic bytes per step: read v_n and v_{n-1}, write v_{n+1}, per-site
-  // arrays; the two-step kernel reads two vectors and writes two per pair.
+  // arrays; a sweep kernel reads two vectors and the site arrays and writes
+  // two vectors per KS steps.
   const double site_arrays =
       (P->has_onsite ? (double)P->n_sites * P->tsize : 0.0) + (P->has_mask ? (double)P->n_sites : 0.0);
-  P->bytes_per_step = (P->variant == 3)
-                          ? 2.0 * (double)P->n_orb * P->Rp * 2 * P->tsize + 0.5 * site_arrays
+  P->bytes_per_step = (P->sweep > 1)
+                          ? (4.0 * (double)P->n_orb * P->Rp * 2 * P->tsize + site_arrays) / P->sweep
                           : 3.0 * (double)P->n_orb * P->Rp * 2 * P->tsize + site_arrays;
 
   // Device allocations.
@@ -1498,7 +1573,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   };
   A(&P->X, vec_bytes);
   A(&P->Y, vec_bytes);
-  if (P->variant == 3) {
+  if (P->sweep > 1) {
     A(&P->Z, vec_bytes);
     A(&P->W, vec_bytes);
   }
@@ -1581,20 +1656,20 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     return KPM_E_DEVICE;
   }
   // LDS: the ring variant needs 4 rows of (Tx + 2) cells (fall back to direct
-  // loads when that exceeds 64 KiB); the two-step kernel its two rings.
+  // loads when that exceeds 64 KiB); a sweep kernel its row rings.
   const size_t ring_bytes = (size_t)P->block * 2 * P->NC * sizeof(double) +
                             4 * (size_t)(P->Tx + 2) * P->n_sub * P->n_spin * P->Ew * 16;
   if (P->variant == 2 && ring_bytes > 65536) P->variant = 1;
-  if (P->variant == 3) {
-    // Two row rings; the moment flush reuses the same LDS between tiles.
-    const size_t rings = (4 * (size_t)(P->Tx + 2) + 3 * (size_t)P->Tx) * P->n_sub * P->Ew * 16;
+  if (P->sweep > 1) {
+    // v_n ring and one ring per inner level; the moment flush reuses the same LDS between tiles.
+    const size_t rings =
+        (4 * (size_t)(P->Tx + 2) + 3 * (size_t)(P->sweep - 1) * P->Tx) * P->n_sub * P->Ew * 16;
     P->lds_bytes = std::max(rings, (size_t)P->block * 2 * P->NC * sizeof(double));
+    P->sweep_fn = (P->prec == KPM_FP32) ? pick_sweep_kind<float>(P->kind, P->sweep, P->has_onsite, P->has_mask)
+                                        : pick_sweep_kind<double>(P->kind, P->sweep, P->has_onsite, P->has_mask);
   } else {
     P->lds_bytes = (P->variant == 2) ? ring_bytes : (size_t)P->block * 2 * P->NC * sizeof(double);
   }
-  if (P->variant == 3)
-    P->step2_fn = (P->prec == KPM_FP32) ? pick_step2_kind<float>(P->kind, P->has_onsite, P->has_mask)
-                                        : pick_step2_kind<double>(P->kind, P->has_onsite, P->has_mask);
   P->step_fn = (P->prec == KPM_FP32)
                    ? pick_step_kind<float, false>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase)
                    : pick_step_kind<double, false>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase);
@@ -1670,8 +1745,8 @@ static hipError_t launch_step_t(kpm_plan* P, hipStream_t s, const StepLaunch& L)
 }
 
 hipError_t plan_launch_step(kpm_plan* P, hipStream_t s, const StepLaunch& L) {
-  // Single steps need the single-step tile list (the two-step plan's tiles overlap).
-  if (P->variant == 3) return hipErrorInvalidValue;
+  // Single steps need the single-step tile list (a sweep plan's tiles overlap).
+  if (P->sweep > 1) return hipErrorInvalidValue;
   return P->prec == KPM_FP32 ? launch_step_t<float>(P, s, L) : launch_step_t<double>(P, s, L);
 }
 
@@ -1689,41 +1764,40 @@ int plan_set_vector_base(kpm_plan* P, int64_t r0) {
   return KPM_OK;
 }
 
-// The DOS recursion: v_0 = start, v_1 = H~ v_0, v_{k+1} = 2 H~ v_k - v_{k-1},
-// in place over two buffers, with the doubling dot products of every step.
+// One sweep: steps k .. k + nlev - 1 of the recursion from v = v_k and
+// w = v_{k-1}; out_a receives v_{k+nlev-1} (nlev >= 2), out_b v_{k+nlev}.
 template <typename T>
-static hipError_t launch_step2_t(kpm_plan* P, hipStream_t s, const void* v, const void* w, void* out1, void* out2,
-                                 int first, int two, double* part1, double* part2) {
-  Step2Args<T> a;
+static hipError_t launch_sweep_t(kpm_plan* P, hipStream_t s, const void* v, const void* w, void* out_a, void* out_b,
+                                 int first, int nlev, double* part0, int64_t part_stride) {
+  SweepArgs<T> a;
   a.lats = (const LatDev<T>*)P->latdev;
   a.tiles = P->tiles;
   a.slot_of = P->slot_of;
   a.n_tiles = P->n_tiles;
   a.v = (const T*)v;
   a.w = (const T*)(w ? w : v);
-  a.out1 = (T*)out1;
-  a.out2 = (T*)out2;
+  a.out_a = (T*)out_a;
+  a.out_b = (T*)out_b;
   a.onsite = (const T*)P->onsite;
   a.mask = P->mask;
-  a.part1 = part1;
-  a.part2 = part2;
+  for (int l = 0; l < kMaxSweep; ++l) a.part[l] = (l < nlev) ? part0 + l * part_stride : nullptr;
   a.a1 = first ? (T)1 : (T)2;
   a.b1 = first ? (T)0 : (T)1;
   a.read_w1 = first ? 0 : 1;
-  a.two = two;
+  a.nlev = nlev;
   a.Tx = P->Tx;
   a.Ty = P->Ty;
   a.E = P->E;
   a.Ew = P->Ew;
   a.Rp = P->Rp;
   void* args[] = {&a};
-  return hipLaunchKernel(P->step2_fn, dim3(P->grid), dim3(P->block), args, P->lds_bytes, s);
+  return hipLaunchKernel(P->sweep_fn, dim3(P->grid), dim3(P->block), args, P->lds_bytes, s);
 }
 
-// Two-step recursion: launches cover steps (k, k+1); the outputs go to the two
-// buffers the launch does not read (four vectors rotate), an odd last step
-// runs the first half alone.
-static hipError_t launch_loop2(kpm_plan* P, hipStream_t s) {
+// The DOS recursion with KS steps per launch: v_0 = start, v_1 = H~ v_0,
+// v_{k+1} = 2 H~ v_k - v_{k-1}.  A launch reads two buffers and writes the
+// other two (four vectors rotate); the last launch runs the remaining steps.
+static hipError_t launch_loop_sweep(kpm_plan* P, hipStream_t s) {
   const int Rw = P->Ew * P->NC;
   const int64_t part_stride = (int64_t)P->n_slots * Rw * 2;
   void* cur = P->X;    // v_k
@@ -1731,13 +1805,12 @@ static hipError_t launch_loop2(kpm_plan* P, hipStream_t s) {
   void* fa = P->Y;
   void* fb = P->Z;
   int chunk0 = 0;
-  for (int k = 0; k < P->n_steps; k += 2) {
-    const int two = (k + 1 < P->n_steps) ? 1 : 0;
-    double* p1 = P->part + (int64_t)(k - chunk0) * part_stride;
-    double* p2 = two ? p1 + part_stride : nullptr;
+  for (int k = 0; k < P->n_steps; k += P->sweep) {
+    const int nlev = std::min(P->sweep, P->n_steps - k);
+    double* p0 = P->part + (int64_t)(k - chunk0) * part_stride;
     hipError_t le = (P->prec == KPM_FP32)
-                        ? launch_step2_t<float>(P, s, cur, prev, fa, fb, k == 0 ? 1 : 0, two, p1, p2)
-                        : launch_step2_t<double>(P, s, cur, prev, fa, fb, k == 0 ? 1 : 0, two, p1, p2);
+                        ? launch_sweep_t<float>(P, s, cur, prev, fa, fb, k == 0 ? 1 : 0, nlev, p0, part_stride)
+                        : launch_sweep_t<double>(P, s, cur, prev, fa, fb, k == 0 ? 1 : 0, nlev, p0, part_stride);
     if (le != hipSuccess) return le;
     void* oc = cur;
     void* op = prev;
@@ -1745,7 +1818,7 @@ static hipError_t launch_loop2(kpm_plan* P, hipStream_t s) {
     prev = fa;
     fa = oc;
     fb = op;
-    const int last = k + two;
+    const int last = k + nlev - 1;
     if (last - chunk0 + 1 >= P->steps_per_chunk || last == P->n_steps - 1) {
       const int nsc = last - chunk0 + 1;
       hipLaunchKernelGGL(reduce_slots_kernel, dim3(nsc, P->n_lat * P->n_rg, (unsigned)ceil_div(2 * Rw, 64)),
@@ -1758,7 +1831,7 @@ static hipError_t launch_loop2(kpm_plan* P, hipStream_t s) {
 }
 
 static hipError_t launch_loop(kpm_plan* P, hipStream_t s) {
-  if (P->variant == 3) return launch_loop2(P, s);
+  if (P->sweep > 1) return launch_loop_sweep(P, s);
   const int Rw = P->Ew * P->NC;
   const int64_t part_stride = (int64_t)P->n_slots * Rw * 2;
   int chunk0 = 0;
@@ -1888,6 +1961,7 @@ int kpm_plan_info(kpm_plan_t* P, kpm_plan_info_t* info) {
   info->block = P->block;
   info->rows = P->Ty;
   info->tile_cells_x = P->Tx;
+  info->tile_chunks = P->Ew;
   info->r_padded = P->Rp;
   info->kernel = P->variant;
   info->n_orbitals = P->n_orb;

@@ -2,7 +2,8 @@
 //
 // The paper leaves the TILE size of its CPU blocking to the user, who must
 // tune it per machine (Sec. 3(b); Sec. 5, Table 1).  Here the analogous
-// choices are the kernel variant, workgroup size, rows per tile and the
+// choices are the kernel variant (one step or 2..4 steps per sweep),
+// workgroup size, rows per tile, the site chunks a tile covers and the
 // persistent grid; kpm_autotune measures each candidate on the real workload
 // (a short recursion of probe_steps steps, timed with hipEvents on the
 // caller's stream) and records the fastest in a plain-text cache keyed by
@@ -14,8 +15,7 @@
 #include "kpm_plan.h"
 
 #include <algorithm>
-#include <vector>
-
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -61,14 +61,15 @@ bool tune_cache_lookup(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_pa
   while (std::getline(f, line)) {
     if (line.empty() || line[0] == '#') continue;
     std::istringstream is(line);
-    int kind, prec, rp, lg, kern, block, rows, grid;
+    int kind, prec, rp, lg, kern, block, rows, grid, chunks;
     double gbs;
-    if (!(is >> kind >> prec >> rp >> lg >> kern >> block >> rows >> grid >> gbs)) continue;
+    if (!(is >> kind >> prec >> rp >> lg >> kern >> block >> rows >> grid >> chunks >> gbs)) continue;
     if (kind == k.kind && prec == k.prec && rp == k.rp && lg == k.log2n) {
       t->kernel = kern;
       t->block = block;
       t->rows = rows;
       t->grid = grid;
+      t->chunks = chunks;
       found = true;   // the last matching line wins
     }
   }
@@ -84,7 +85,7 @@ static int tune_cache_store(const char* path, const TuneKey& k, const kpm_tune_t
     return KPM_E_INVALID;
   }
   f << k.kind << ' ' << k.prec << ' ' << k.rp << ' ' << k.log2n << ' ' << t.kernel << ' ' << t.block << ' ' << t.rows
-    << ' ' << t.grid << ' ' << gbs << '\n';
+    << ' ' << t.grid << ' ' << t.chunks << ' ' << gbs << '\n';
   return KPM_OK;
 }
 
@@ -114,38 +115,51 @@ static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
   KPM_CHECK_ARG(probe_steps >= 2 && probe_steps <= 4096, "probe_steps must be in [2, 4096]");
   kpm_dos_params_t q = *p;
   q.num_moments = 2 * probe_steps;
-  const int kernels[3] = {1, 2, 3};
-  const int blocks[2] = {256, 512};
-  const int rows_c[3] = {32, 128, 512};
-  const int grids[2] = {1024, 2048};
+  // Candidates: the single-step kernels over workgroup size, rows per tile
+  // and persistent grid; the sweep kernels over workgroup size, rows per
+  // tile and the site chunks a tile covers (the library's choice, 4 and 16:
+  // wider and narrower tiles), duplicates of an already screened shape
+  // skipped.
+  struct Cand { int kernel, block, rows, grid, chunks; };
+  std::vector<Cand> cands;
+  for (int kv : {1, 2})
+    for (int b : {256, 512})
+      for (int r : {32, 128})
+        for (int g : {1024, 2048}) cands.push_back({kv, b, r, g, 0});
+  for (int kv : {3, 4, 5})
+    for (int b : {256, 512})
+      for (int r : {32, 128})
+        for (int c : {0, 4, 16}) cands.push_back({kv, b, r, 2048, c});
   std::vector<std::pair<double, kpm_tune_t>> screened;
-  for (int kv : kernels)
-    for (int b : blocks)
-      for (int r : rows_c)
-        for (int g : grids) {
-          kpm_tune_t t;
-          std::memset(&t, 0, sizeof(t));
-          t.kernel = kv;
-          t.block = b;
-          t.rows = r;
-          t.grid = g;
-          t.use_graph = 1;
-          kpm_plan* P = nullptr;
-          int st = plan_create(lat, n_lat, &q, &t, &P);
-          if (st != KPM_OK) return st;
-          if (P->variant != kv) {   // the ring did not fit in LDS: skip the duplicate
-            plan_free(P);
-            delete P;
-            continue;
-          }
-          double rate = 0.0;
-          st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
-          if (st == KPM_OK || st == KPM_E_SPECTRUM) st = timed_run(P, stream, &rate, nullptr);
-          plan_free(P);
-          delete P;
-          if (st != KPM_OK && st != KPM_E_SPECTRUM) return st;
-          screened.push_back({rate, t});
-        }
+  std::vector<std::array<int, 5>> seen;   // (variant, block, rows, grid, chunks in use)
+  for (const Cand& cd : cands) {
+    kpm_tune_t t;
+    std::memset(&t, 0, sizeof(t));
+    t.kernel = cd.kernel;
+    t.block = cd.block;
+    t.rows = cd.rows;
+    t.grid = cd.grid;
+    t.chunks = cd.chunks;
+    t.use_graph = 1;
+    kpm_plan* P = nullptr;
+    int st = plan_create(lat, n_lat, &q, &t, &P);
+    if (st != KPM_OK) return st;
+    const std::array<int, 5> shape = {P->variant, P->block, P->Ty, P->grid, P->Ew};
+    // Fell back (LDS, lattice kind) or same shape as an earlier candidate: skip.
+    if (P->variant != cd.kernel || std::find(seen.begin(), seen.end(), shape) != seen.end()) {
+      plan_free(P);
+      delete P;
+      continue;
+    }
+    seen.push_back(shape);
+    double rate = 0.0;
+    st = kpm_plan_run(P, nullptr, nullptr, 1, stream);
+    if (st == KPM_OK || st == KPM_E_SPECTRUM) st = timed_run(P, stream, &rate, nullptr);
+    plan_free(P);
+    delete P;
+    if (st != KPM_OK && st != KPM_E_SPECTRUM) return st;
+    screened.push_back({rate, t});
+  }
   if (screened.empty()) {
     set_error("autotune: no candidate launch shape");
     return KPM_E_INVALID;

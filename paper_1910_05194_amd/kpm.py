@@ -63,7 +63,7 @@ class c_cond_stats(ctypes.Structure):
 
 class c_tune(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("rows", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("kernel", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("kernel", ctypes.c_int32), ("chunks", ctypes.c_int32)]
 
 
 class c_plan_info(ctypes.Structure):
@@ -71,7 +71,7 @@ class c_plan_info(ctypes.Structure):
                 ("block", ctypes.c_int32), ("rows", ctypes.c_int32), ("tile_cells_x", ctypes.c_int32),
                 ("r_padded", ctypes.c_int32), ("kernel", ctypes.c_int32), ("n_orbitals", ctypes.c_int64), ("bytes_per_step", ctypes.c_double),
                 ("last_loop_ms", ctypes.c_double), ("last_run_ms", ctypes.c_double),
-                ("n_active_total", ctypes.c_int64)]
+                ("n_active_total", ctypes.c_int64), ("tile_chunks", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -211,13 +211,13 @@ class Plan:
     """kpm_plan_*: a reusable, graph-captured DOS/LDOS moment pipeline."""
 
     def __init__(self, lattices: Sequence, par, block: int = 0, rows: int = 0, grid: int = 0,
-                 use_graph: bool = True, kernel: int = 0):
+                 use_graph: bool = True, kernel: int = 0, chunks: int = 0):
         self.n_lat = len(lattices)
         self.R = _num_vectors(par)
         self.M = int(par.num_moments)
         lats = c_lattices(lattices)
         p, keep = c_params(par)
-        tune = c_tune(int(block), int(rows), int(grid), 1 if use_graph else 0, int(kernel))
+        tune = c_tune(int(block), int(rows), int(grid), 1 if use_graph else 0, int(kernel), int(chunks))
         h = _P()
         _check(LIB.kpm_plan_create(lats, self.n_lat, ctypes.byref(p), ctypes.byref(tune), ctypes.byref(h)))
         del keep
@@ -484,4 +484,5 @@ def autotune(lattices: Sequence, par, probe_steps: int = 16, cache_path: Optiona
                             None if cache_path is None else cache_path.encode(), ctypes.byref(best),
                             ctypes.byref(gbs), _stream_handle(stream)))
     del keep
-    return {"kernel": best.kernel, "block": best.block, "rows": best.rows, "grid": best.grid, "GBs": gbs.value}
+    return {"kernel": best.kernel, "block": best.block, "rows": best.rows, "grid": best.grid, "chunks": best.chunks,
+            "GBs": gbs.value}

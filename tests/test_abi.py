@@ -96,6 +96,10 @@ def test_argument_validation_without_device():
         with pytest.raises(kpm.KPMError) as e:
             kpm.Plan([lat], par, block=blk)
         assert e.value.code == kpm.KPM_E_INVALID
+    for ch in (-1, 129):   # more chunks than a 256-thread honeycomb tile has lanes per sublattice
+        with pytest.raises(kpm.KPMError) as e:
+            kpm.Plan([lat], par, block=256, chunks=ch)
+        assert e.value.code == kpm.KPM_E_INVALID and "chunks" in str(e.value)
     lat3, par3 = wl.rashba_flux(L=8, M=8, R=1)
     for p, msg in [(par3.replace(alpha=2), "alpha"), (par3.replace(gamma_mode=9), "gamma_mode")]:
         with pytest.raises(kpm.KPMError) as e:

@@ -238,14 +238,15 @@ def test_autotune_cache(K, tmp_path, monkeypatch):
     par = wl.DosParams(num_moments=64, num_random=4, vector_seed=1, precision=wl.FP32)
     cache = str(tmp_path / "tune.txt")
     best = K.autotune([lat], par, probe_steps=4, cache_path=cache)
-    assert best["kernel"] in (1, 2, 3) and best["block"] in (256, 512) and best["GBs"] > 0
+    assert best["kernel"] in (1, 2, 3, 4, 5) and best["block"] in (256, 512) and best["GBs"] > 0
     line = open(cache).read().strip().split()
-    assert [int(v) for v in line[4:8]] == [best["kernel"], best["block"], best["rows"], best["grid"]]
+    assert [int(v) for v in line[4:9]] == [best["kernel"], best["block"], best["rows"], best["grid"], best["chunks"]]
     monkeypatch.setenv("KPM_TUNE_CACHE", cache)
     plan = K.Plan([lat], par)
     info = plan.info()
     assert (info["kernel"], info["block"], info["rows"], info["grid"]) == \
         (best["kernel"], best["block"], best["rows"], best["grid"])
+    assert best["chunks"] == 0 or info["tile_chunks"] == best["chunks"]
     mu = np.zeros((1, 4, 64))
     plan.run(mu)
     plan.close()
@@ -253,7 +254,7 @@ def test_autotune_cache(K, tmp_path, monkeypatch):
     assert np.max(np.abs(mu[0] - mu_o)) <= fp32_tol(64)
 
 
-TWO_STEP = [
+SWEEP_LATS = [
     wl.Lattice(kind=wl.HONEYCOMB, L1=37, L2=23, t=-2.7, anderson_w=1.0, vacancy_p=0.03, disorder_seed=17,
                e_min=-9.0, e_max=8.7),
     wl.Lattice(kind=wl.HONEYCOMB, L1=64, L2=70, t=-2.7, anderson_w=0.7, disorder_seed=3),
@@ -265,14 +266,16 @@ TWO_STEP = [
 ]
 
 
-@pytest.mark.parametrize("lat", TWO_STEP, ids=lambda l: f"{wl.KIND_NAMES[l.kind]}{l.L1}x{l.L2}")
+@pytest.mark.parametrize("lat", SWEEP_LATS, ids=lambda l: f"{wl.KIND_NAMES[l.kind]}{l.L1}x{l.L2}")
 @pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
-def test_two_step_kernel_matches_single_step_and_oracle(K, lat, prec):
-    """The two-steps-per-sweep kernel (variant 3) against the single-step ring
-    kernel and the oracle: even and odd step counts (M = 2 is one step, M = 41
-    ends on a half sweep), tile shapes down to one row and one r-chunk, halo
-    columns that wrap onto the tile itself on tiny lattices."""
-    for M, R in ((2, 3), (8, 5), (41, 2)):
+@pytest.mark.parametrize("kernel", [3, 4, 5], ids=["ks2", "ks3", "ks4"])
+def test_sweep_kernel_matches_single_step_and_oracle(K, lat, prec, kernel):
+    """The multi-step sweep kernels (variants 3/4/5: 2/3/4 steps per launch)
+    against the single-step ring kernel and the oracle: step counts that end
+    on a full and on every kind of short last sweep (M = 2 is one step), tile
+    shapes down to one row and one r-chunk, halo columns that wrap onto the
+    tile itself on tiny lattices."""
+    for M, R in ((2, 3), (8, 5), (14, 2), (41, 2)):
         par = wl.DosParams(num_moments=M, num_random=R, vector_seed=8, precision=prec)
         ref = K.Plan([lat], par, kernel=2)
         mu_r = np.zeros((1, R, M))
@@ -281,8 +284,10 @@ def test_two_step_kernel_matches_single_step_and_oracle(K, lat, prec):
         mu_o, _ = oracle_moments(lat, par)
         tol = 1e-10 if prec == wl.FP64 else fp32_tol(max(M, 8))
         for tune in (dict(block=64, rows=1), dict(block=128, rows=3, grid=16), dict(block=512, rows=0)):
-            plan = K.Plan([lat], par, kernel=3, **tune)
-            assert plan.info()["kernel"] == 3
+            plan = K.Plan([lat], par, kernel=kernel, **tune)
+            # Wide tiles (few r-chunks) may not fit the deeper sweeps' rings in LDS.
+            used = plan.info()["kernel"]
+            assert used == kernel or (tune["block"] == 512 and 3 <= used < kernel), (used, tune)
             mu = np.zeros((1, R, M))
             plan.run(mu)
             plan.close()
@@ -291,28 +296,29 @@ def test_two_step_kernel_matches_single_step_and_oracle(K, lat, prec):
 
 
 @pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
-def test_two_step_uneven_batch_and_ldos(K, prec):
-    """Uneven lattices of both spinless kinds in one two-step plan, several
+@pytest.mark.parametrize("kernel", [3, 4, 5], ids=["ks2", "ks3", "ks4"])
+def test_sweep_uneven_batch_and_ldos(K, prec, kernel):
+    """Uneven lattices of both spinless kinds in one sweep plan, several
     r-groups per tile (R = 40), and LDOS start vectors."""
     lats = [wl.Lattice(kind=wl.HONEYCOMB, L1=L, L2=L2, t=-2.7, vacancy_p=0.01 * (i + 1), anderson_w=0.5,
                        disorder_seed=100 + i)
             for i, (L, L2) in enumerate([(8, 8), (33, 17), (2, 5), (64, 40), (91, 22)])]
     M, R = 30, 40
     par = wl.DosParams(num_moments=M, num_random=R, vector_seed=77, precision=prec)
-    plan = K.Plan(lats, par, kernel=3, block=256)
-    assert plan.info()["kernel"] == 3
+    plan = K.Plan(lats, par, kernel=kernel, block=256)
+    assert plan.info()["kernel"] == kernel
     mu = np.zeros((len(lats), R, M))
     plan.run(mu)
     plan.close()
     for i, lat in enumerate(lats):
         mu_o, _ = oracle_moments(lat, par, lat_index=i)
         assert np.max(np.abs(mu[i] - mu_o)) <= (1e-10 if prec == wl.FP64 else fp32_tol(M)), i
-    lat = TWO_STEP[4]
+    lat = SWEEP_LATS[4]
     from oracle import lattice as olat
     model = olat.build(lat)
     sites = [int(model.orb_index[i]) for i in (0, 3, 77, model.n_active - 1)]
     par = wl.DosParams(num_moments=24, start=wl.START_SITES, sites=sites, precision=prec)
-    plan = K.Plan([lat], par, kernel=3)
+    plan = K.Plan([lat], par, kernel=kernel)
     mu = np.zeros((1, len(sites), 24))
     plan.run(mu)
     plan.close()
@@ -320,11 +326,12 @@ def test_two_step_uneven_batch_and_ldos(K, prec):
     assert np.max(np.abs(mu[0] - mu_o)) <= (1e-10 if prec == wl.FP64 else fp32_tol(24))
 
 
-def test_two_step_kernel_falls_back_where_ineligible(K):
+@pytest.mark.parametrize("kernel", [3, 4, 5], ids=["ks2", "ks3", "ks4"])
+def test_sweep_kernel_falls_back_where_ineligible(K, kernel):
     """Spinful lattices and Peierls phases take the single-step ring kernel."""
     par = wl.DosParams(num_moments=16, num_random=2, vector_seed=3, precision=wl.FP32)
     for lat in (RAGGED[1], RAGGED[2]):
-        plan = K.Plan([lat], par, kernel=3)
+        plan = K.Plan([lat], par, kernel=kernel)
         assert plan.info()["kernel"] == 2
         mu = np.zeros((1, 2, 16))
         plan.run(mu)

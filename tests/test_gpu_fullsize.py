@@ -115,8 +115,8 @@ def test_uneven_batch_full_size(K):
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("prec", [wl.FP32, wl.FP64], ids=["fp32", "fp64"])
 def test_clean_graphene_4096_all_moments_vs_kspace(K, prec):
-    """All 2048 moments of clean graphene 4096^2 (R = 32, default plan: the
-    two-steps-per-sweep kernel) against the exact moments from the k-space
+    """All 2048 moments of clean graphene 4096^2 (R = 32, default plan: a
+    multi-step sweep kernel) against the exact moments from the k-space
     closed form (a 1024^2 k-grid is exact for n < 2048): the stochastic-trace
     mean lies within 6 sigma of the exact value for every n, sigma being the
     spread of the 32 per-vector moments / sqrt(32)."""
@@ -125,7 +125,7 @@ def test_clean_graphene_4096_all_moments_vs_kspace(K, prec):
     lat, par = wl.graphene_large(precision=prec, L=L, M=M, R=R)
     lat = lat.replace(anderson_w=0.0)
     plan = K.Plan([lat], par)
-    assert plan.info()["kernel"] == 3
+    assert plan.info()["kernel"] >= 3
     mu = torch.zeros((1, R, M), dtype=torch.float64, device="cuda")
     plan.run(mu)
     plan.close()
