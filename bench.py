@@ -210,7 +210,7 @@ def measured_traffic(info, args):
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    launch = [info["kernel"], info["block"], info["rows"], info["grid"]]
+    launch = [info["kernel"], info["block"], info["rows"], info["grid"], info["tile_chunks"]]
     sha = step_kernel_source_hash()
     for r in rec.get("records", []):
         if r.get("source_sha256") == sha and r.get("launch") == launch and r.get("workload") == [args.L, args.R]:
@@ -231,7 +231,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the library's default launch shape")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the recursion steps one by one instead of replaying a hipGraph (for profilers)")
-    ap.add_argument("--launch", default="", help="pin the FP32 launch shape: kernel,block,rows,grid (skips the autotuner)")
+    ap.add_argument("--launch", default="",
+                    help="pin the FP32 launch shape: kernel,block,rows,grid[,chunks] (skips the autotuner)")
     ap.add_argument("--legs", default="c1,c3,c4,c5", help="extra legs: c1,c3,c4,c5 (empty for none)")
     ap.add_argument("--mlp-train", type=int, default=4000,
                     help="training lattices (1024^2 cells each) of the learned-extrapolation leg")
@@ -256,11 +257,11 @@ def main():
     E = torch.tensor(wl.energy_grid(lat.e_min, lat.e_max, 1024), device=dev)
     tune = {}
     if args.launch:
-        tune = dict(zip(("kernel", "block", "rows", "grid"), (int(x) for x in args.launch.split(","))))
+        tune = dict(zip(("kernel", "block", "rows", "grid", "chunks"), (int(x) for x in args.launch.split(","))))
     elif not args.no_tune:
         log("[bench] autotune (FP32)")
         best = kpm.autotune([lat], par.replace(num_moments=32), probe_steps=16)
-        tune = {k: best[k] for k in ("kernel", "block", "rows", "grid")}
+        tune = {k: best[k] for k in ("kernel", "block", "rows", "grid", "chunks")}
         log(f"[bench] tuned: {best}")
     log(f"[bench] plan: graphene {args.L}x{args.L}, M={args.M}, R={args.R}, FP32, {tune}")
     plan = kpm.Plan([lat], par, use_graph=not args.no_graph, **tune)
@@ -322,7 +323,7 @@ def main():
         tune64 = {}
         if not args.no_tune:
             b64 = kpm.autotune([lat64], par64.replace(num_moments=32), probe_steps=16)
-            tune64 = {k: b64[k] for k in ("kernel", "block", "rows", "grid")}
+            tune64 = {k: b64[k] for k in ("kernel", "block", "rows", "grid", "chunks")}
         p64 = kpm.Plan([lat64], par64, **tune64)
         mu64 = torch.zeros_like(mu)
         mean64 = torch.zeros_like(mean)
@@ -375,7 +376,8 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"graphene honeycomb {args.L}x{args.L} + Anderson W=1 eV, M={args.M}, "
                                f"R={args.R} complex64, FP32 recursion / FP64 moments, Jackson 1024 E",
-                   "orbitals": N, "moments": args.M, "vectors": args.R, "launch": tune},
+                   "orbitals": N, "moments": args.M, "vectors": args.R,
+                   "launch": dict(tune, tile_chunks=info["tile_chunks"])},
         "step_rate": N * info["n_steps"] * args.R / dt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -384,7 +386,11 @@ def main():
                                 3: "kpm::sweep_kernel<KS=2>", 4: "kpm::sweep_kernel<KS=3>",
                                 5: "kpm::sweep_kernel<KS=4>"}[info["kernel"]] + " (FP32, honeycomb, on-site array)",
                      "steps_per_launch": steps_per_launch,
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms},
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
+                     # What a one-step-per-launch kernel (read v_n, v_(n-1) and the site
+                     # arrays, write v_(n+1)) would have to stream for the same step rate.
+                     "single_step_equivalent_GBs": (3.0 * N * args.R * 8 + N * 4) * info["n_steps"] / (
+                         float(np.mean(loop_ms)) * 1e-3) / 1e9},
         "cpu_baseline": cpu,
     }
     out.update(extra)

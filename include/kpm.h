@@ -104,7 +104,7 @@ typedef struct kpm_tune_t {
   int32_t rows;            /* lattice rows (along a2) per tile */
   int32_t grid;            /* persistent workgroups (multiple of 8); 0 = one per tile */
   int32_t use_graph;       /* 1 = replay the step loop as a captured hipGraph (default), 0 = eager */
-  int32_t kernel;          /* 0 = default (4 where eligible, else 2), 1 = direct neighbour loads, 2 = LDS row
+  int32_t kernel;          /* 0 = default (5 where eligible, else 2), 1 = direct neighbour loads, 2 = LDS row
                               ring, 3/4/5 = 2/3/4 steps per sweep (spinless lattices without Peierls phases
                               and with room for four vectors; a sweep whose row rings do not fit in LDS takes
                               one step fewer, down to 2) */

@@ -39,6 +39,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 namespace kpm {
@@ -767,6 +768,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   constexpr int NNB = KindTraits<KIND>::NNB;
   static_assert(KindTraits<KIND>::NSPIN == 1, "spinless lattices only");
   static_assert(KS >= 2 && KS <= kMaxSweep, "2..kMaxSweep steps per sweep");
+  constexpr int NH = 2 * KS - 1;   // site-data history: level l uses the entry 2 (l - 1) iterations old
   extern __shared__ double lds[];
 
   const int tid = threadIdx.x;
@@ -780,14 +782,14 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   const int Tx = A.Tx;
   const int nlev = A.nlev;
   // v_n ring: [4 slots][Tx + 2 cells][sub][chunk]; level l (1..KS-1) ring:
-  // [3 slots][Tx][sub][chunk].  The moment flush reuses the same LDS between tiles.
+  // [4 slots][Tx][sub][chunk].  The moment flush reuses the same LDS between tiles.
   P* ring0 = reinterpret_cast<P*>(lds);
   const int row0 = (Tx + 2) * NSUB * Ew;
   P* ringl = ring0 + 4 * row0;
   const int rowl = Tx * NSUB * Ew;
   auto r0 = [&](int slot, int cell, int sub) -> P& { return ring0[slot * row0 + (cell * NSUB + sub) * Ew + cl]; };
   auto rl = [&](int lev, int slot, int cell, int sub) -> P& {
-    return ringl[((lev - 1) * 3 + slot) * rowl + (cell * NSUB + sub) * Ew + cl];
+    return ringl[((lev - 1) * 4 + slot) * rowl + (cell * NSUB + sub) * Ew + cl];
   };
 
   const int xcd = blockIdx.x & 7;
@@ -836,23 +838,26 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     // potential and vacancy flag of level 1's row) is loaded into registers
     // one iteration ahead, as one group: the levels themselves only touch LDS
     // and store, so the in-order load counter never makes them wait for the
-    // next row's loads.  Two register sets alternate (the loop is unrolled by
-    // two), so no loaded value is copied after the next loads were issued.
+    // next row's loads.  Two register sets alternate.  A thread loads at most
+    // one halo cell (a sweep tile has at least three thread columns, and on
+    // the honeycomb lattice only sublattice 0 needs the left halo and only
+    // sublattice 1 the right one).
     struct RowSet {
-      P own, left, right, w;
+      P own, halo, w;
       T ons;
       bool alive;
     };
-    RowSet sa, sb;
+    RowSet set[2];
+    const bool load_halo = load_left || load_right;
+    const int halo_col = load_left ? hl : hr;
+    const int halo_cell = load_left ? 0 : wcols + 1;
     auto fetch_row = [&](RowSet& S, int yy) {
       if (act) S.own = ld_pack(vb + (((int64_t)yy * L1 + n1) * NSUB + s) * Rp * 2 + coff);
-      if (load_left) S.left = ld_pack(vb + (((int64_t)yy * L1 + hl) * NSUB + s) * Rp * 2 + coff);
-      if (load_right) S.right = ld_pack(vb + (((int64_t)yy * L1 + hr) * NSUB + s) * Rp * 2 + coff);
+      if (load_halo) S.halo = ld_pack(vb + (((int64_t)yy * L1 + halo_col) * NSUB + s) * Rp * 2 + coff);
     };
     auto store_row = [&](const RowSet& S, int slot) {
       if (act) r0(slot, xl + 1, s) = S.own;
-      if (load_left) r0(slot, 0, s) = S.left;
-      if (load_right) r0(slot, wcols + 1, s) = S.right;
+      if (load_halo) r0(slot, halo_cell, s) = S.halo;
     };
     auto fetch_site = [&](RowSet& S, int yy) {
       S.ons = ons_c;
@@ -872,116 +877,128 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       else st_pack(base + site * Rp * 2 + coff, o);
     };
     const int ty = min(A.Ty, L2 - y0);
-    const int j_end = ty + KS;
-    // Site data of the rows the levels form now: level l uses entry l - 1
-    // (level l's row is level 1's row of l - 1 iterations ago).
-    T ons_h[KS];
-    bool alive_h[KS];
+    // Level l forms row y0 + j - (2 l - 1) at iteration j: it reads rows of
+    // level l - 1 formed one, two and three iterations earlier, so the levels
+    // of one iteration are independent and one barrier per row suffices.
+    // Level l is active for j in [3 l - 1 - KS, ty + KS + l - 2].
+    const int j0 = 2 - KS;
+    const int j_last = ty + 2 * KS - 2;
+    // Site data of the rows the levels form, as a shift register.  The
+    // centre value and w of a level come from this thread's own cell of the
+    // LDS rings (no other thread writes that cell before the read).
+    T ons_h[NH];
+    bool alive_h[NH];
 #pragma unroll
-    for (int l = 0; l < KS; ++l) {
-      ons_h[l] = ons_c;
-      alive_h[l] = true;
+    for (int k = 0; k < NH; ++k) {
+      ons_h[k] = ons_c;
+      alive_h[k] = true;
     }
-    // One iteration: cur holds v_n row y0 + j and the site data of row y0 + j - 1.
-    auto row = [&](int j, const RowSet& cur, RowSet& nxt) {
+    // One iteration with phase p = (j - j0) mod 4: set[p & 1] holds v_n row
+    // y0 + j and the site data of row y0 + j - 1.  v_n row y0 + j sits in LDS
+    // slot (p + 2) & 3, the rows level l forms at iteration j in slot p.
+    auto row = [&](auto ph, int j) {
+      constexpr int p = decltype(ph)::value;
+      RowSet& cur = set[p & 1];
+      RowSet& nxt = set[(p + 1) & 1];
       // All of cur has arrived (vmcnt(0); expcnt and lgkmcnt left at their
       // maxima), so no later use of it waits for the loads issued below.
       __builtin_amdgcn_s_waitcnt(0x0F70);
-      store_row(cur, (j + KS) & 3);   // v_n row r sits in slot (r - (y0 - KS)) & 3
+      store_row(cur, (p + 2) & 3);
 #pragma unroll
-      for (int l = KS - 1; l > 0; --l) {
-        ons_h[l] = ons_h[l - 1];
-        alive_h[l] = alive_h[l - 1];
+      for (int k = NH - 1; k > 0; --k) {
+        ons_h[k] = ons_h[k - 1];
+        alive_h[k] = alive_h[k - 1];
       }
       ons_h[0] = cur.ons;
       alive_h[0] = cur.alive;
       __builtin_amdgcn_sched_barrier(0);
-      if (j + 1 < j_end) {
+      if (j + 1 <= ty + KS - 1) {
         fetch_row(nxt, wrap(y0 + j + 1));
         fetch_site(nxt, wrap(y0 + j));
       }
       lds_barrier();
-      const int q = ((j % 3) + 3) % 3;   // ring slot of the rows formed at iteration j
-      const int qm1 = (q + 2) % 3, qm2 = (q + 1) % 3;
+      // Levels from the deepest down: level l reads w from level l - 2's ring
+      // slot of four iterations back, the slot that level l - 2 refills now.
+#pragma unroll
+      for (int lev = KS; lev >= 2; --lev) {
+        const int y = y0 + j - (2 * lev - 1);
+        if (lev <= nlev && act && xl >= lev - 1 && xl <= wcols - lev && j >= 3 * lev - 1 - KS &&
+            j <= ty + KS + lev - 2) {
+          const int64_t site = ((int64_t)wrap(y) * L1 + n1) * NSUB + s;
+          constexpr int sp1 = (p + 3) & 3, s0 = (p + 2) & 3, sm1 = (p + 1) & 3;   // rows y + 1, y, y - 1
+          P vn[NNB];
+          if constexpr (KIND == KPM_SQUARE) {
+            vn[0] = rl(lev - 1, s0, xl + 1, 0);
+            vn[1] = rl(lev - 1, s0, xl - 1, 0);
+            vn[2] = rl(lev - 1, sp1, xl, 0);
+            vn[3] = rl(lev - 1, sm1, xl, 0);
+          } else if (s == 0) {
+            vn[0] = rl(lev - 1, s0, xl, 1);
+            vn[1] = rl(lev - 1, sm1, xl + 1, 1);
+            vn[2] = rl(lev - 1, sm1, xl, 1);
+          } else {
+            vn[0] = rl(lev - 1, s0, xl, 0);
+            vn[1] = rl(lev - 1, sp1, xl - 1, 0);
+            vn[2] = rl(lev - 1, sp1, xl, 0);
+          }
+          const P vo = rl(lev - 1, s0, xl, s);   // level lev-1, row y
+          // Level lev-2 at row y: v_n row y0 + j - 3 (its slot is refilled by
+          // the next iteration's row, from this same thread for its own cell),
+          // or level lev-2's output of four iterations back.
+          const P wo = (lev == 2) ? r0((p + 3) & 3, xl + 1, s) : rl(lev >= 3 ? lev - 2 : 1, p, xl, s);
+          const bool own = inner && (y >= y0) && (y < y0 + ty);
+          P o;
+          site_update2<T, KIND>((T)2, (T)1, true, hop, ons_h[2 * lev - 2], alive_h[2 * lev - 2], vo, wo, vn, o, own,
+                                vv[lev - 1], wv[lev - 1]);
+          if (lev < KS) rl(lev, p, xl, s) = o;
+          if (own && lev >= nlev - 1) put(lev == nlev ? ob : oa, site, o);
+        }
+      }
       // Level 1 (row y0 + j - 1) from v_n rows y0 + j - 2 .. y0 + j.
       {
         const int y = y0 + j - 1;
-        if (act) {
-          const int sy = (j - 1 + KS) & 3, sm = (j - 2 + KS) & 3, sp = (j + KS) & 3;
+        if (act && j <= ty + KS - 1) {
+          constexpr int sp1 = (p + 2) & 3, s0 = (p + 1) & 3, sm1 = p;   // v_n rows y + 1, y, y - 1
           const int64_t site = ((int64_t)wrap(y) * L1 + n1) * NSUB + s;
           P vn[NNB];
           if constexpr (KIND == KPM_SQUARE) {
-            vn[0] = r0(sy, xl + 2, 0);
-            vn[1] = r0(sy, xl, 0);
-            vn[2] = r0(sp, xl + 1, 0);
-            vn[3] = r0(sm, xl + 1, 0);
+            vn[0] = r0(s0, xl + 2, 0);
+            vn[1] = r0(s0, xl, 0);
+            vn[2] = r0(sp1, xl + 1, 0);
+            vn[3] = r0(sm1, xl + 1, 0);
           } else if (s == 0) {
-            vn[0] = r0(sy, xl + 1, 1);
-            vn[1] = r0(sm, xl + 2, 1);
-            vn[2] = r0(sm, xl + 1, 1);
+            vn[0] = r0(s0, xl + 1, 1);
+            vn[1] = r0(sm1, xl + 2, 1);
+            vn[2] = r0(sm1, xl + 1, 1);
           } else {
-            vn[0] = r0(sy, xl + 1, 0);
-            vn[1] = r0(sp, xl, 0);
-            vn[2] = r0(sp, xl + 1, 0);
+            vn[0] = r0(s0, xl + 1, 0);
+            vn[1] = r0(sp1, xl, 0);
+            vn[2] = r0(sp1, xl + 1, 0);
           }
-          const P vo = r0(sy, xl + 1, s);
+          const P vo = r0(s0, xl + 1, s);   // v_n row y
           const bool own = inner && (y >= y0) && (y < y0 + ty);
           P o;
           site_update2<T, KIND>(A.a1, A.b1, A.read_w1 != 0, hop, ons_h[0], alive_h[0], vo, cur.w, vn, o, own,
                                 vv[0], wv[0]);
-          rl(1, q, xl, s) = o;
+          rl(1, p, xl, s) = o;
           if (own && nlev <= 2) put(nlev == 1 ? ob : oa, site, o);
         }
       }
-#pragma unroll
-      for (int lev = 2; lev <= KS; ++lev) {
-        lds_barrier();
-        // Level lev (row y0 + j - lev) from level lev-1 rows y - 1 .. y + 1
-        // (formed at iterations j - 2 .. j) and w = level lev-2 at row y.
-        const int y = y0 + j - lev;
-        if (lev <= nlev && act && xl >= lev - 1 && xl <= wcols - lev && j >= 2 * lev - KS) {
-          const int64_t site = ((int64_t)wrap(y) * L1 + n1) * NSUB + s;
-          P vn[NNB];
-          if constexpr (KIND == KPM_SQUARE) {
-            vn[0] = rl(lev - 1, qm1, xl + 1, 0);
-            vn[1] = rl(lev - 1, qm1, xl - 1, 0);
-            vn[2] = rl(lev - 1, q, xl, 0);
-            vn[3] = rl(lev - 1, qm2, xl, 0);
-          } else if (s == 0) {
-            vn[0] = rl(lev - 1, qm1, xl, 1);
-            vn[1] = rl(lev - 1, qm2, xl + 1, 1);
-            vn[2] = rl(lev - 1, qm2, xl, 1);
-          } else {
-            vn[0] = rl(lev - 1, qm1, xl, 0);
-            vn[1] = rl(lev - 1, q, xl - 1, 0);
-            vn[2] = rl(lev - 1, q, xl, 0);
-          }
-          const P vo = rl(lev - 1, qm1, xl, s);
-          const P wo = (lev == 2) ? r0((j - 2 + KS) & 3, xl + 1, s) : rl(lev == 2 ? 1 : lev - 2, qm2, xl, s);
-          const bool own = inner && (y >= y0) && (y < y0 + ty);
-          P o;
-          site_update2<T, KIND>((T)2, (T)1, true, hop, ons_h[lev - 1], alive_h[lev - 1], vo, wo, vn, o, own,
-                                vv[lev - 1], wv[lev - 1]);
-          if (lev < KS) rl(lev, q, xl, s) = o;
-          if (own && lev >= nlev - 1) put(lev == nlev ? ob : oa, site, o);
-        }
-      }
     };
-    // Prologue: v_n rows y0 - KS and y0 - KS + 1 into slots 0 and 1; the
+    // Prologue: v_n rows y0 - KS and y0 - KS + 1 into slots 0 and 1, the
     // first iteration's row and site data into registers.
-    const int j0 = 2 - KS;
-    fetch_row(sa, wrap(y0 - KS));
-    store_row(sa, 0);
-    fetch_row(sa, wrap(y0 - KS + 1));
-    store_row(sa, 1);
-    fetch_row(sa, wrap(y0 + j0));
-    fetch_site(sa, wrap(y0 + j0 - 1));
-    int j = j0;
-    for (; j + 1 < j_end; j += 2) {
-      row(j, sa, sb);
-      row(j + 1, sb, sa);
+    fetch_row(set[0], wrap(y0 - KS));
+    store_row(set[0], 0);
+    fetch_row(set[0], wrap(y0 - KS + 1));
+    store_row(set[0], 1);
+    fetch_row(set[0], wrap(y0 + j0));
+    fetch_site(set[0], wrap(y0 + j0 - 1));
+    for (int j = j0; j <= j_last; j += 4) {
+      row(std::integral_constant<int, 0>{}, j);
+      row(std::integral_constant<int, 1>{}, j + 1);
+      row(std::integral_constant<int, 2>{}, j + 2);
+      row(std::integral_constant<int, 3>{}, j + 3);
     }
-    if (j < j_end) row(j, sa, sb);
     __syncthreads();   // the next tile (or the moment flush) reuses the LDS
     const int tn = ti + gx;
     const int slot = A.slot_of[ti];
@@ -1430,9 +1447,9 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   }
   // Kernel variant: 3, 4, 5 = 2, 3, 4 steps per sweep (spinless lattices
   // without Peierls phases, room for two more vectors), 2 = LDS row ring,
-  // 1 = direct loads.  The default (three steps per sweep where eligible)
+  // 1 = direct loads.  The default (four steps per sweep where eligible)
   // was the fastest on the graphene workloads in FP32 and FP64.
-  const int want = (tune && tune->kernel > 0) ? tune->kernel : 4;
+  const int want = (tune && tune->kernel > 0) ? tune->kernel : 5;
   if (want < 1 || want > 5) {
     set_error("kernel must be 0 (default) or 1..5");
     delete P;
@@ -1466,7 +1483,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
       while (P->Ew > 1 && P->block / (P->n_sub * P->Ew) < 4 * ks) P->Ew >>= 1;
     }
     P->Tx = P->block / (P->n_sub * P->Ew);
-    const size_t rings = (4 * (size_t)(P->Tx + 2) + 3 * (size_t)(ks - 1) * P->Tx) * P->n_sub * P->Ew * 16;
+    const size_t rings = (4 * (size_t)(P->Tx + 2) + 4 * (size_t)(ks - 1) * P->Tx) * P->n_sub * P->Ew * 16;
     if (P->Tx >= 2 * ks - 1 && rings <= (size_t)lds_max) break;
     P->variant = (ks == 2) ? 2 : P->variant - 1;
   }
@@ -1663,7 +1680,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   if (P->sweep > 1) {
     // v_n ring and one ring per inner level; the moment flush reuses the same LDS between tiles.
     const size_t rings =
-        (4 * (size_t)(P->Tx + 2) + 3 * (size_t)(P->sweep - 1) * P->Tx) * P->n_sub * P->Ew * 16;
+        (4 * (size_t)(P->Tx + 2) + 4 * (size_t)(P->sweep - 1) * P->Tx) * P->n_sub * P->Ew * 16;
     P->lds_bytes = std::max(rings, (size_t)P->block * 2 * P->NC * sizeof(double));
     P->sweep_fn = (P->prec == KPM_FP32) ? pick_sweep_kind<float>(P->kind, P->sweep, P->has_onsite, P->has_mask)
                                         : pick_sweep_kind<double>(P->kind, P->sweep, P->has_onsite, P->has_mask);
