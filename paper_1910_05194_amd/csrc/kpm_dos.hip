@@ -726,11 +726,13 @@ struct SweepArgs {
 };
 
 // out = a (H~ v)_i - b w_i at one site (no Peierls phase, one spin), and the
-// doubling dot products when acc.
+// doubling dot products <v|v>, <out|v> added to the partial sums pv, pw when
+// acc (a select, not a branch: the values of threads outside their level's
+// columns may be anything).
 template <typename T, int KIND>
-__device__ inline void site_update2(T a, T b, bool read_w, T hop, T ons, bool alive, const Pack<T>& vo,
-                                    const Pack<T>& wo, const Pack<T> (&vn)[KindTraits<KIND>::NNB], Pack<T>& out,
-                                    bool acc, double* vv, double* wv) {
+__device__ inline void sweep_site(T a, T b, bool read_w, T hop, T ons, bool alive, const Pack<T>& vo,
+                                  const Pack<T>& wo, const Pack<T> (&vn)[KindTraits<KIND>::NNB], Pack<T>& out,
+                                  bool acc, T* pv, T* pw) {
   constexpr int NC = Pack<T>::NC;
   constexpr int NNB = KindTraits<KIND>::NNB;
 #pragma unroll
@@ -752,11 +754,10 @@ __device__ inline void site_update2(T a, T b, bool read_w, T hop, T ons, bool al
     }
     out.v[2 * j] = orr;
     out.v[2 * j + 1] = oi;
-    if (acc) {
-      const double xr = (double)vo.v[2 * j], xi = (double)vo.v[2 * j + 1];
-      vv[j] += xr * xr + xi * xi;
-      wv[j] += (double)orr * xr + (double)oi * xi;
-    }
+    const T xr = vo.v[2 * j], xi = vo.v[2 * j + 1];
+    const T dv = xi * xi + xr * xr, dw = oi * xi + orr * xr;
+    pv[j] += acc ? dv : (T)0;
+    pw[j] += acc ? dw : (T)0;
   }
 }
 
@@ -781,12 +782,20 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   const int Rp = A.Rp;
   const int Tx = A.Tx;
   const int nlev = A.nlev;
-  // v_n ring: [4 slots][Tx + 2 cells][sub][chunk]; level l (1..KS-1) ring:
-  // [4 slots][Tx][sub][chunk].  The moment flush reuses the same LDS between tiles.
+  // v_n ring: [4 slots][Tx + 2 cells][sub][chunk] (cell = thread column + 1,
+  // halos in cells 0 and wcols + 1); level l (1..KS-1) ring: the same shape;
+  // one spare cell after the last ring.  The moment flush reuses the same LDS
+  // between tiles.
   P* ring0 = reinterpret_cast<P*>(lds);
   const int row0 = (Tx + 2) * NSUB * Ew;
   P* ringl = ring0 + 4 * row0;
-  const int rowl = Tx * NSUB * Ew;
+  const int rowl = row0;
+  // Every thread computes every level of every active iteration: no branch
+  // on its column.  Results of columns outside a level's range are garbage
+  // that no thread of the next level reads.  Threads beyond the last whole
+  // thread column (when Ew does not divide the workgroup) work on column Tx:
+  // they write only cell Tx + 1, which is never read.
+  const int xlc = (grp < n_grp) ? xl : Tx;
   auto r0 = [&](int slot, int cell, int sub) -> P& { return ring0[slot * row0 + (cell * NSUB + sub) * Ew + cl]; };
   auto rl = [&](int lev, int slot, int cell, int sub) -> P& {
     return ringl[((lev - 1) * 4 + slot) * rowl + (cell * NSUB + sub) * Ew + cl];
@@ -803,6 +812,10 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   for (int l = 0; l < KS; ++l)
 #pragma unroll
     for (int j = 0; j < NC; ++j) vv[l][j] = wv[l][j] = 0.0;
+  // Partial sums of the doubling dot products over one group of four rows,
+  // in the vectors' precision (FP32 vectors: a site's products and a
+  // four-row sum in FP32, then added to the FP64 sums).
+  T pv[KS][NC], pw[KS][NC];
 
   for (int ti = t_begin + jx; ti < t_end; ti += gx) {
     const int4 tl = A.tiles[ti];
@@ -830,9 +843,12 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     const int hr = (xe + wcols) % L1;
     const bool load_left = lane_ok && (xl == 0) && (KIND == KPM_SQUARE || s == 0);
     const bool load_right = lane_ok && (xl == wcols - 1) && (KIND == KPM_SQUARE || s == 1);
+    // Row index modulo L2 (uniform, and within a few periods of the range:
+    // no division).
     auto wrap = [&](int y) {
-      y %= L2;
-      return y < 0 ? y + L2 : y;
+      while (y < 0) y += L2;
+      while (y >= L2) y -= L2;
+      return y;
     };
     // Everything a row needs from HBM (v_n with halos, v_{n-1}, on-site
     // potential and vacancy flag of level 1's row) is loaded into registers
@@ -851,9 +867,20 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     const bool load_halo = load_left || load_right;
     const int halo_col = load_left ? hl : hr;
     const int halo_cell = load_left ? 0 : wcols + 1;
+    // Offsets within a lattice row (bytes for the vectors, sites for the site
+    // arrays): a row's base is the same for the whole workgroup, so an access
+    // adds one 32-bit per-thread offset to it (a row holds < 2^31 bytes).
+    const int64_t row_elems = (int64_t)L1 * NSUB * Rp * 2;
+    const int64_t row_sites = (int64_t)L1 * NSUB;
+    const uint32_t lane_b = (uint32_t)((((int64_t)n1 * NSUB + s) * Rp * 2 + coff) * (int64_t)sizeof(T));
+    const uint32_t halo_b = (uint32_t)((((int64_t)halo_col * NSUB + s) * Rp * 2 + coff) * (int64_t)sizeof(T));
+    const int lane_site = n1 * NSUB + s;
+    auto vrow = [&](const T* base, int yy, uint32_t off) {
+      return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base + (int64_t)yy * row_elems) + off);
+    };
     auto fetch_row = [&](RowSet& S, int yy) {
-      if (act) S.own = ld_pack(vb + (((int64_t)yy * L1 + n1) * NSUB + s) * Rp * 2 + coff);
-      if (load_halo) S.halo = ld_pack(vb + (((int64_t)yy * L1 + halo_col) * NSUB + s) * Rp * 2 + coff);
+      if (act) S.own = ld_pack(vrow(vb, yy, lane_b));
+      if (load_halo) S.halo = ld_pack(vrow(vb, yy, halo_b));
     };
     auto store_row = [&](const RowSet& S, int slot) {
       if (act) r0(slot, xl + 1, s) = S.own;
@@ -863,18 +890,19 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       S.ons = ons_c;
       S.alive = true;
       if (act) {
-        const int64_t site = ((int64_t)yy * L1 + n1) * NSUB + s;
         if (A.read_w1) {
-          if constexpr ((KPM_SWEEP_NT & 2) != 0) S.w = ld_pack_nt(wb + site * Rp * 2 + coff);
-          else S.w = ld_pack(wb + site * Rp * 2 + coff);
+          if constexpr ((KPM_SWEEP_NT & 2) != 0) S.w = ld_pack_nt(vrow(wb, yy, lane_b));
+          else S.w = ld_pack(vrow(wb, yy, lane_b));
         }
-        if constexpr (ONSITE) S.ons = A.onsite[site_off + site];
-        if constexpr (MASK) S.alive = A.mask[site_off + site] != 0;
+        const int64_t row_site = site_off + (int64_t)yy * row_sites;
+        if constexpr (ONSITE) S.ons = A.onsite[row_site + lane_site];
+        if constexpr (MASK) S.alive = A.mask[row_site + lane_site] != 0;
       }
     };
-    auto put = [&](T* base, int64_t site, const P& o) {
-      if constexpr ((KPM_SWEEP_NT & 1) != 0) st_pack_nt(base + site * Rp * 2 + coff, o);
-      else st_pack(base + site * Rp * 2 + coff, o);
+    auto put = [&](T* base, int yy, const P& o) {
+      T* q = const_cast<T*>(vrow(base, yy, lane_b));
+      if constexpr ((KPM_SWEEP_NT & 1) != 0) st_pack_nt(q, o);
+      else st_pack(q, o);
     };
     const int ty = min(A.Ty, L2 - y0);
     // Level l forms row y0 + j - (2 l - 1) at iteration j: it reads rows of
@@ -922,66 +950,67 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
 #pragma unroll
       for (int lev = KS; lev >= 2; --lev) {
         const int y = y0 + j - (2 * lev - 1);
-        if (lev <= nlev && act && xl >= lev - 1 && xl <= wcols - lev && j >= 3 * lev - 1 - KS &&
-            j <= ty + KS + lev - 2) {
-          const int64_t site = ((int64_t)wrap(y) * L1 + n1) * NSUB + s;
+        const int yw = wrap(y);
+        if (lev <= nlev && j >= 3 * lev - 1 - KS && j <= ty + KS + lev - 2) {
           constexpr int sp1 = (p + 3) & 3, s0 = (p + 2) & 3, sm1 = (p + 1) & 3;   // rows y + 1, y, y - 1
+          const int x = xlc + 1;   // this thread's cell
           P vn[NNB];
           if constexpr (KIND == KPM_SQUARE) {
-            vn[0] = rl(lev - 1, s0, xl + 1, 0);
-            vn[1] = rl(lev - 1, s0, xl - 1, 0);
-            vn[2] = rl(lev - 1, sp1, xl, 0);
-            vn[3] = rl(lev - 1, sm1, xl, 0);
+            vn[0] = rl(lev - 1, s0, x + 1, 0);
+            vn[1] = rl(lev - 1, s0, x - 1, 0);
+            vn[2] = rl(lev - 1, sp1, x, 0);
+            vn[3] = rl(lev - 1, sm1, x, 0);
           } else if (s == 0) {
-            vn[0] = rl(lev - 1, s0, xl, 1);
-            vn[1] = rl(lev - 1, sm1, xl + 1, 1);
-            vn[2] = rl(lev - 1, sm1, xl, 1);
+            vn[0] = rl(lev - 1, s0, x, 1);
+            vn[1] = rl(lev - 1, sm1, x + 1, 1);
+            vn[2] = rl(lev - 1, sm1, x, 1);
           } else {
-            vn[0] = rl(lev - 1, s0, xl, 0);
-            vn[1] = rl(lev - 1, sp1, xl - 1, 0);
-            vn[2] = rl(lev - 1, sp1, xl, 0);
+            vn[0] = rl(lev - 1, s0, x, 0);
+            vn[1] = rl(lev - 1, sp1, x - 1, 0);
+            vn[2] = rl(lev - 1, sp1, x, 0);
           }
-          const P vo = rl(lev - 1, s0, xl, s);   // level lev-1, row y
+          const P vo = rl(lev - 1, s0, x, s);   // level lev-1, row y
           // Level lev-2 at row y: v_n row y0 + j - 3 (its slot is refilled by
           // the next iteration's row, from this same thread for its own cell),
           // or level lev-2's output of four iterations back.
-          const P wo = (lev == 2) ? r0((p + 3) & 3, xl + 1, s) : rl(lev >= 3 ? lev - 2 : 1, p, xl, s);
+          const P wo = (lev == 2) ? r0((p + 3) & 3, x, s) : rl(lev >= 3 ? lev - 2 : 1, p, x, s);
           const bool own = inner && (y >= y0) && (y < y0 + ty);
           P o;
-          site_update2<T, KIND>((T)2, (T)1, true, hop, ons_h[2 * lev - 2], alive_h[2 * lev - 2], vo, wo, vn, o, own,
-                                vv[lev - 1], wv[lev - 1]);
-          if (lev < KS) rl(lev, p, xl, s) = o;
-          if (own && lev >= nlev - 1) put(lev == nlev ? ob : oa, site, o);
+          sweep_site<T, KIND>((T)2, (T)1, true, hop, ons_h[2 * lev - 2], alive_h[2 * lev - 2], vo, wo, vn, o, own,
+                              pv[lev - 1], pw[lev - 1]);
+          if (lev < KS) rl(lev, p, x, s) = o;
+          if (own && lev >= nlev - 1) put(lev == nlev ? ob : oa, yw, o);
         }
       }
       // Level 1 (row y0 + j - 1) from v_n rows y0 + j - 2 .. y0 + j.
       {
         const int y = y0 + j - 1;
-        if (act && j <= ty + KS - 1) {
+        const int yw = wrap(y);
+        if (j <= ty + KS - 1) {
           constexpr int sp1 = (p + 2) & 3, s0 = (p + 1) & 3, sm1 = p;   // v_n rows y + 1, y, y - 1
-          const int64_t site = ((int64_t)wrap(y) * L1 + n1) * NSUB + s;
+          const int x = xlc + 1;
           P vn[NNB];
           if constexpr (KIND == KPM_SQUARE) {
-            vn[0] = r0(s0, xl + 2, 0);
-            vn[1] = r0(s0, xl, 0);
-            vn[2] = r0(sp1, xl + 1, 0);
-            vn[3] = r0(sm1, xl + 1, 0);
+            vn[0] = r0(s0, x + 1, 0);
+            vn[1] = r0(s0, x - 1, 0);
+            vn[2] = r0(sp1, x, 0);
+            vn[3] = r0(sm1, x, 0);
           } else if (s == 0) {
-            vn[0] = r0(s0, xl + 1, 1);
-            vn[1] = r0(sm1, xl + 2, 1);
-            vn[2] = r0(sm1, xl + 1, 1);
+            vn[0] = r0(s0, x, 1);
+            vn[1] = r0(sm1, x + 1, 1);
+            vn[2] = r0(sm1, x, 1);
           } else {
-            vn[0] = r0(s0, xl + 1, 0);
-            vn[1] = r0(sp1, xl, 0);
-            vn[2] = r0(sp1, xl + 1, 0);
+            vn[0] = r0(s0, x, 0);
+            vn[1] = r0(sp1, x - 1, 0);
+            vn[2] = r0(sp1, x, 0);
           }
-          const P vo = r0(s0, xl + 1, s);   // v_n row y
+          const P vo = r0(s0, x, s);   // v_n row y
           const bool own = inner && (y >= y0) && (y < y0 + ty);
           P o;
-          site_update2<T, KIND>(A.a1, A.b1, A.read_w1 != 0, hop, ons_h[0], alive_h[0], vo, cur.w, vn, o, own,
-                                vv[0], wv[0]);
-          rl(1, p, xl, s) = o;
-          if (own && nlev <= 2) put(nlev == 1 ? ob : oa, site, o);
+          sweep_site<T, KIND>(A.a1, A.b1, A.read_w1 != 0, hop, ons_h[0], alive_h[0], vo, cur.w, vn, o, own, pv[0],
+                              pw[0]);
+          rl(1, p, x, s) = o;
+          if (own && nlev <= 2) put(nlev == 1 ? ob : oa, yw, o);
         }
       }
     };
@@ -994,10 +1023,21 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     fetch_row(set[0], wrap(y0 + j0));
     fetch_site(set[0], wrap(y0 + j0 - 1));
     for (int j = j0; j <= j_last; j += 4) {
+#pragma unroll
+      for (int l = 0; l < KS; ++l)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) pv[l][q] = pw[l][q] = (T)0;
       row(std::integral_constant<int, 0>{}, j);
       row(std::integral_constant<int, 1>{}, j + 1);
       row(std::integral_constant<int, 2>{}, j + 2);
       row(std::integral_constant<int, 3>{}, j + 3);
+#pragma unroll
+      for (int l = 0; l < KS; ++l)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+          vv[l][q] += (double)pv[l][q];
+          wv[l][q] += (double)pw[l][q];
+        }
     }
     __syncthreads();   // the next tile (or the moment flush) reuses the LDS
     const int tn = ti + gx;
@@ -1460,7 +1500,11 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     const double vec_b = (double)P->n_orb * P->Rp * 2 * P->tsize;
     size_t free_b = 0, total_b = 0;
     const bool room = hipMemGetInfo(&free_b, &total_b) == hipSuccess && (double)free_b > 4.0 * vec_b + 2.0e9;
-    if (P->kind == KPM_HONEYCOMB_SPIN || P->has_phase || !room) P->variant = 2;
+    // The sweep kernels address a lattice row with 32-bit offsets.
+    bool rows_fit = true;
+    for (int l = 0; l < n_lat; ++l)
+      rows_fit = rows_fit && (int64_t)lat[l].L1 * P->n_sub * P->Rp * 2 * (int64_t)P->tsize < (int64_t(1) << 31);
+    if (P->kind == KPM_HONEYCOMB_SPIN || P->has_phase || !room || !rows_fit) P->variant = 2;
   }
   if (P->variant >= 3 && !block_given) P->block = kMaxStepBlock;
   int lds_max = 65536;
@@ -1483,7 +1527,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
       while (P->Ew > 1 && P->block / (P->n_sub * P->Ew) < 4 * ks) P->Ew >>= 1;
     }
     P->Tx = P->block / (P->n_sub * P->Ew);
-    const size_t rings = (4 * (size_t)(P->Tx + 2) + 4 * (size_t)(ks - 1) * P->Tx) * P->n_sub * P->Ew * 16;
+    const size_t rings = (4 * (size_t)ks * (P->Tx + 2) + 1) * P->n_sub * P->Ew * 16;
     if (P->Tx >= 2 * ks - 1 && rings <= (size_t)lds_max) break;
     P->variant = (ks == 2) ? 2 : P->variant - 1;
   }
@@ -1679,8 +1723,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   if (P->variant == 2 && ring_bytes > 65536) P->variant = 1;
   if (P->sweep > 1) {
     // v_n ring and one ring per inner level; the moment flush reuses the same LDS between tiles.
-    const size_t rings =
-        (4 * (size_t)(P->Tx + 2) + 4 * (size_t)(P->sweep - 1) * P->Tx) * P->n_sub * P->Ew * 16;
+    const size_t rings = (4 * (size_t)P->sweep * (P->Tx + 2) + 1) * P->n_sub * P->Ew * 16;
     P->lds_bytes = std::max(rings, (size_t)P->block * 2 * P->NC * sizeof(double));
     P->sweep_fn = (P->prec == KPM_FP32) ? pick_sweep_kind<float>(P->kind, P->sweep, P->has_onsite, P->has_mask)
                                         : pick_sweep_kind<double>(P->kind, P->sweep, P->has_onsite, P->has_mask);
