@@ -84,6 +84,8 @@ typedef struct kpm_lattice_t {
   double vacancy_p;        /* 0 <= p < 1 */
   uint64_t disorder_seed;
   double e_min, e_max;     /* spectrum bounds used for the rescaling, eV, e_min < e_max */
+  double exchange;         /* Delta_ex, eV: + Delta_ex on spin up, - on spin down (eq. HQAHE; KPM_HONEYCOMB_SPIN
+                              only, else 0) */
 } kpm_lattice_t;
 
 /* DOS / LDOS moment request (KITE Calculation.dos / ldos). */

@@ -8,7 +8,8 @@ Paper passages followed:
 * Sec. 3(d) honeycomb listing: lattice vectors, sublattice positions and the
   three A-B hoppings with offsets (0,0), (1,-1), (0,-1).
 * Sec. 4, eq. HQAHE: hopping t, Rashba term (2i/3) lambda_R (s x d_ij)_z with
-  d_ij the unit vector from site j to site i, spin-independent disorder V.
+  d_ij the unit vector from site j to site i, exchange Delta_ex s_z (+ on spin
+  up, - on spin down), spin-independent disorder V.
 * Sec. 4 (magnetic field): Peierls substitution on a periodic lattice; the
   flux per cell must be commensurate with the torus (flux * L1 integer).
   The gauge is the Landau gauge A = phi (0, s1) in fractional coordinates, so a
@@ -121,6 +122,9 @@ def build(lat) -> Model:
             raise ValueError("flux * L1 must be an integer on a torus")
     if lat.rashba != 0.0 and kind != HONEYCOMB_SPIN:
         raise ValueError("Rashba coupling needs the spinful lattice")
+    exchange = getattr(lat, "exchange", 0.0)
+    if exchange != 0.0 and kind != HONEYCOMB_SPIN:
+        raise ValueError("the exchange field needs the spinful lattice")
     N = L1 * L2 * n_sub * n_spin
 
     n1, n2 = np.meshgrid(np.arange(L1), np.arange(L2), indexing="xy")
@@ -182,6 +186,9 @@ def build(lat) -> Model:
     V, site_active = disorder_arrays(lat)
     orb_site = np.arange(N) // n_spin
     diag = V[orb_site]
+    if n_spin == 2:
+        # s_z = +1 on spin up (orbital 2 site), -1 on spin down (2 site + 1).
+        diag = diag + exchange * (1.0 - 2.0 * (np.arange(N) % 2))
 
     H = sp.coo_matrix((np.concatenate([vals, diag.astype(complex)]),
                        (np.concatenate([rows, np.arange(N)]), np.concatenate([cols, np.arange(N)]))),

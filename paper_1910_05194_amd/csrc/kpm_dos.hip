@@ -96,6 +96,7 @@ struct LatDev {
   T hop;                // t/de-
   T blk[3][8];          // spin lattice: H_{A,B'} / de- for bond class k (2x2 complex, row-major), no phase
   T vc[2][2][4];        // velocity: (r_i - r_j)_dir * de- for [dir][sublattice of i][neighbour k]
+  T exch;               // spin lattice: Delta_ex / de- (+ on spin up, - on spin down)
 };
 
 template <typename T>
@@ -155,7 +156,7 @@ __device__ inline void cmul_acc(T& ore, T& oim, T are, T aim, T bre, T bim) {
 template <typename T, int KIND>
 struct LatRegs {
   int64_t site_off, vec_off, phase_off;
-  T onsite_const, hop;
+  T onsite_const, hop, exch;
   T blk[3][8];
   int L1, L2;
 };
@@ -169,6 +170,7 @@ __device__ inline void load_lat(const LatDev<T>& Lg, LatRegs<T, KIND>& L) {
   L.hop = Lg.hop;
   L.L1 = Lg.L1;
   L.L2 = Lg.L2;
+  L.exch = Lg.exch;
   if constexpr (KIND == KPM_HONEYCOMB_SPIN) {
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -221,7 +223,10 @@ __device__ inline void site_update(const StepArgs<T>& A, const LatRegs<T, KIND>&
   for (int sp = 0; sp < NSPIN; ++sp) {
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      T hr = ons * vo[sp].v[2 * j], hi = ons * vo[sp].v[2 * j + 1];
+      // On-site term; the spin lattice adds the exchange field +-Delta_ex.
+      T onsp = ons;
+      if constexpr (KIND == KPM_HONEYCOMB_SPIN) onsp = ons + (sp == 0 ? L.exch : -L.exch);
+      T hr = onsp * vo[sp].v[2 * j], hi = onsp * vo[sp].v[2 * j + 1];
       T gr = 0, gi = 0;   // velocity accumulator
 #pragma unroll
       for (int k = 0; k < NNB; ++k) {
@@ -1286,6 +1291,8 @@ static int validate_lattice(const kpm_lattice_t& L, int idx) {
   KPM_CHECK_ARG(L.vacancy_p >= 0.0 && L.vacancy_p < 1.0, "lattice %d: vacancy_p must be in [0, 1)", idx);
   KPM_CHECK_ARG(L.rashba == 0.0 || L.kind == KPM_HONEYCOMB_SPIN,
                 "lattice %d: Rashba coupling needs KPM_HONEYCOMB_SPIN", idx);
+  KPM_CHECK_ARG(std::isfinite(L.exchange) && (L.exchange == 0.0 || L.kind == KPM_HONEYCOMB_SPIN),
+                "lattice %d: the exchange field needs KPM_HONEYCOMB_SPIN", idx);
   if (L.flux != 0.0) {
     KPM_CHECK_ARG(L.kind != KPM_SQUARE, "lattice %d: flux on the square lattice is not supported", idx);
     const double q = L.flux * L.L1;
@@ -1312,6 +1319,7 @@ static void fill_latdev(kpm_plan* P, std::vector<LatDev<T>>& out) {
     d.phase_off = P->phase_off[l];
     d.onsite_const = (T)(-de_p / de_m);
     d.hop = (T)(L.t / de_m);
+    d.exch = (T)(L.exchange / de_m);
     // Velocity [r^dir, H]_ij = (r_i - r_j)_dir H_ij; the kernel applies it to the
     // rescaled hop terms, hence the factor de-.
     if (L.kind == KPM_SQUARE) {

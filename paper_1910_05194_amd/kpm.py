@@ -39,7 +39,8 @@ class c_lattice(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("L1", ctypes.c_int32), ("L2", ctypes.c_int32),
                 ("t", ctypes.c_double), ("rashba", ctypes.c_double), ("flux", ctypes.c_double),
                 ("anderson_w", ctypes.c_double), ("vacancy_p", ctypes.c_double),
-                ("disorder_seed", ctypes.c_uint64), ("e_min", ctypes.c_double), ("e_max", ctypes.c_double)]
+                ("disorder_seed", ctypes.c_uint64), ("e_min", ctypes.c_double), ("e_max", ctypes.c_double),
+                ("exchange", ctypes.c_double)]
 
 
 class c_dos_params(ctypes.Structure):
@@ -143,7 +144,7 @@ def c_lattices(lattices) -> ctypes.Array:
         arr[i] = c_lattice(int(L.kind), int(L.L1), int(L.L2), float(L.t), float(getattr(L, "rashba", 0.0)),
                            float(getattr(L, "flux", 0.0)), float(getattr(L, "anderson_w", 0.0)),
                            float(getattr(L, "vacancy_p", 0.0)), int(getattr(L, "disorder_seed", 0)) & (2**64 - 1),
-                           float(L.e_min), float(L.e_max))
+                           float(L.e_min), float(L.e_max), float(getattr(L, "exchange", 0.0)))
     return arr
 
 

@@ -82,6 +82,7 @@ class Lattice:
     disorder_seed: int = 0
     e_min: float = -8.5
     e_max: float = 8.5
+    exchange: float = 0.0      # Delta_ex s_z, eV (HONEYCOMB_SPIN only)
 
     @property
     def n_sub(self) -> int:
