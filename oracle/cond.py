@@ -92,3 +92,202 @@ def sigma_from_gamma(gamma: np.ndarray, energies_ev: np.ndarray, e_min: float, e
     s = np.einsum("nk,nm,mk->k", W, gamma.real, W)
     out[inside] = -2.0 * np.pi ** 2 * (n_orbitals / area_nm2) / de_m ** 2 * s
     return out
+
+
+# ---------------------------------------------------------------------------
+# Kubo-Bastin (Fermi sea) conductivity, in particular the Hall conductivity.
+#
+# Paper passages followed:
+# * eq. cond 1st order: first-order response with f(eps), the delta function
+#   and the retarded/advanced resolvents.  Its static limit is the Kubo-Bastin
+#   form (reading used, stated because the paper prints Lambda_nm(omega) with
+#   a 1/omega prefactor and leaves omega -> 0 to KITE-tools):
+#     sigma_ab(mu) = (i e^2 hbar / Omega) int d eps f(eps)
+#                    Tr[ v_a delta(eps-H) v_b dG^R/d eps - v_a dG^A/d eps v_b delta(eps-H) ],
+#   v = h~/(i hbar), h~ = [r, H]; T = 0, so f = theta(mu - eps).
+# * eq. delta_function_cheb_expansion (Delta_n) and eqs.
+#   green_function_cheb_expansion(b) (CPGF g_n^{R,A} at broadening eta) for
+#   the two factors, and eq. Gammanm for the trace: in rescaled units
+#     sigma_ab(mu)/(e^2/h) = Re{ -2 pi i (N/Omega)/de-^2 int_{-1}^{mu~} d eps
+#         sum_nm Gamma_nm [Delta_n(eps) g'^R_m(eps) - g'^A_n(eps) Delta_m(eps)] },
+#   g' = d g / d eps.  This is the Lambda_nm contraction of eq.
+#   conductivity_1st_order for a static field.
+# ---------------------------------------------------------------------------
+
+def _eigen(model):
+    E, U = np.linalg.eigh(model.H.toarray())
+    return E, U
+
+
+def gamma_nm_exact(model: lattice.Model, e_min: float, e_max: float, M: int, alpha: int, beta: int) -> np.ndarray:
+    """Gamma_nm (eq. Gammanm) as an exact trace, in the eigenbasis of H (dense):
+        Tr[h~^a T_n(H~) h~^b T_m(H~)] = sum_ab (h~^a)_ab T_n(e_b) (h~^b)_ba T_m(e_a),
+    divided by N (1+d_n0)(1+d_m0).  [M, M] complex."""
+    E, U = _eigen(model)
+    A = U.conj().T @ velocity(model, alpha).toarray() @ U
+    B = U.conj().T @ velocity(model, beta).toarray() @ U
+    d_plus, d_minus = (e_max + e_min) / 2.0, (e_max - e_min) / 2.0
+    T = kpm.chebyshev_t(M, (E - d_plus) / d_minus).T          # [state, n]
+    W = A * B.T                                                # W[a, b] = A_ab B_ba
+    G = T.T @ W.T @ T                                          # [n, m] = sum_ab T_n(e_b) W_ab T_m(e_a)
+    G = G / E.size
+    G[0, :] /= 2.0
+    G[:, 0] /= 2.0
+    return G
+
+
+def sigma_kubo_eigen(model: lattice.Model, mu_ev: float, alpha: int = 0, beta: int = 1) -> float:
+    """The Kubo-Bastin Fermi-sea conductivity at T = 0 and eta -> 0 in units of
+    e^2/h, summed over eigenstates (the definition, evaluated directly):
+        sigma_ab = Re{ (-2 pi i / Omega) sum_{E_a < mu <= E_b} [P_ab - P_ba] / (E_a - E_b)^2 },
+        P_ab = (h~^a)_ab (h~^b)_ba,  Omega = L1 L2 * cell area.
+    For a = x, b = y this is (4 pi/Omega) sum Im[(h~^x)_ab (h~^y)_ba]/(E_a - E_b)^2
+    (the diagonal terms of the Bastin integral cancel between its two parts)."""
+    E, U = _eigen(model)
+    A = U.conj().T @ velocity(model, alpha).toarray() @ U
+    B = U.conj().T @ velocity(model, beta).toarray() @ U
+    occ = np.nonzero(E < mu_ev)[0]
+    emp = np.nonzero(E >= mu_ev)[0]
+    P_ab = A[np.ix_(occ, emp)] * B[np.ix_(emp, occ)].T
+    P_ba = A[np.ix_(emp, occ)].T * B[np.ix_(occ, emp)]
+    den = (E[occ][:, None] - E[emp][None, :]) ** 2
+    n_cells = model.site_active.size // model.n_sub
+    omega = n_cells * model.cell_area
+    return float(np.real(-2j * np.pi / omega * np.sum((P_ab - P_ba) / den)))
+
+
+def cpgf_derivative(M: int, eps: np.ndarray, eta: float, sign: int) -> np.ndarray:
+    """d g_n^{sign,eta}(eps) / d eps for n < M (eq. green_function_cheb_expansionb,
+    rescaled units): with z = eps + i sign eta, theta = arccos z, s = sqrt(1 - z^2),
+        g_n = -2 sign i exp(-sign i n theta) / s,
+        g_n' = -2 sign i exp(-sign i n theta) [sign i n / s^2 + z / s^3]
+    (d theta/dz = -1/s, d(1/s)/dz = z/s^3).  [len(eps), M]."""
+    z = np.asarray(eps, dtype=np.float64) + 1j * sign * eta
+    theta = np.arccos(z)
+    s = np.sqrt(1.0 - z * z)
+    n = np.arange(M, dtype=np.float64)
+    e = np.exp(-sign * 1j * np.outer(theta, n))
+    return -2.0 * sign * 1j * e * (sign * 1j * n[None, :] / (s * s)[:, None] + (z / s ** 3)[:, None])
+
+
+def sigma_bastin(gamma: np.ndarray, energies_ev, e_min: float, e_max: float, eta_ev: float,
+                 orbitals_per_nm2: float, n_theta: int) -> np.ndarray:
+    """T = 0 Kubo-Bastin conductivity (e^2/h) at Fermi energies ``energies_ev`` from a
+    full [M, M] Gamma (formula in the block comment above).
+
+    The energy integral is taken in theta (eps = cos theta, so Delta_n d eps =
+    (2/pi) cos(n theta) d theta): midpoint rule on n_theta equal cells of
+    [0, pi], each cell weighted by the part of it inside [theta_mu, pi]."""
+    gamma = np.asarray(gamma, dtype=np.complex128)
+    M = gamma.shape[0]
+    d_plus, d_minus = (e_max + e_min) / 2.0, (e_max - e_min) / 2.0
+    eta = eta_ev / d_minus
+    h = np.pi / n_theta
+    th = (np.arange(n_theta) + 0.5) * h
+    eps = np.cos(th)
+    D = 2.0 * np.cos(np.outer(th, np.arange(M))) / np.pi       # Delta_n(eps) sin(theta), [q, n]
+    gR = cpgf_derivative(M, eps, eta, +1)                      # [q, m]
+    gA = cpgf_derivative(M, eps, eta, -1)                      # [q, n]
+    F = np.sum((D @ gamma) * gR, axis=1) - np.sum((gA @ gamma) * D, axis=1)
+    pref = -2j * np.pi * orbitals_per_nm2 / d_minus ** 2
+    out = []
+    for mu in np.atleast_1d(np.asarray(energies_ev, dtype=np.float64)):
+        mut = (mu - d_plus) / d_minus
+        if mut <= -1.0:
+            out.append(0.0)
+            continue
+        th_mu = 0.0 if mut >= 1.0 else float(np.arccos(mut))
+        lo = th - h / 2.0
+        w = np.clip(th + h / 2.0 - np.maximum(lo, th_mu), 0.0, h)   # covered length of each cell
+        out.append(float(np.real(pref * np.sum(F * w))))
+    return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# Clean periodic lattices in k space (independent of the real-space builder's
+# matrices; the same geometry and eq. HQAHE terms): Bloch Hamiltonian,
+# velocity i dH/dk, the Kubo sum on the k grid of an L1 x L2 torus, and the
+# Chern number of the occupied bands by the lattice link-variable method
+# (Fukui, Hatsugai and Suzuki, J. Phys. Soc. Jpn. 74, 1674 (2005)).
+# ---------------------------------------------------------------------------
+
+def bloch(lat, k, periodic_gauge: bool = False):
+    """(H(k), hx(k), hy(k)) of a clean honeycomb lattice (spinful or not): for a
+    bond from j (cell n + d) to i (cell n), H(k)[i, j] += h_ij exp(-i k.d_ij) with
+    d_ij = r_i - r_j, and h~^a(k) the same sum weighted by (d_ij)_a (= i dH/dk_a).
+    periodic_gauge drops the sublattice offsets from the phase (H(k + G) = H(k))."""
+    a1, a2, tau, bonds = lattice._geometry(lat.kind)
+    n_spin = 2 if lat.kind == lattice.HONEYCOMB_SPIN else 1
+    n = len(tau) * n_spin
+    H = np.zeros((n, n), dtype=complex)
+    hx = np.zeros((n, n), dtype=complex)
+    hy = np.zeros((n, n), dtype=complex)
+    sx = np.array([[0, 1], [1, 0]], dtype=complex)
+    sy = np.array([[0, -1j], [1j, 0]], dtype=complex)
+    for (si, sj, d1, d2) in bonds:
+        cell = d1 * a1 + d2 * a2
+        dvec = tau[si] - (cell + tau[sj])
+        ph = np.exp(-1j * np.dot(k, -cell if periodic_gauge else dvec))
+        dhat = dvec / np.linalg.norm(dvec)
+        for s in range(n_spin):
+            for s2 in range(n_spin):
+                hop = lat.t if s == s2 else 0.0
+                if n_spin == 2:
+                    hop = hop + (2j / 3.0) * lat.rashba * (sx[s, s2] * dhat[1] - sy[s, s2] * dhat[0])
+                i, j = si * n_spin + s, sj * n_spin + s2
+                for (Mx, w) in ((H, 1.0), (hx, dvec[0]), (hy, dvec[1])):
+                    Mx[i, j] += w * hop * ph
+                    Mx[j, i] += np.conj(w * hop * ph) * (1.0 if Mx is H else -1.0)
+    if n_spin == 2:
+        H += np.diag([lat.exchange if (q % 2) == 0 else -lat.exchange for q in range(n)])
+    return H, hx, hy
+
+
+def _recip(lat):
+    a1, a2, _, _ = lattice._geometry(lat.kind)
+    A = np.column_stack([a1, a2])
+    Bm = 2.0 * np.pi * np.linalg.inv(A).T
+    return Bm[:, 0], Bm[:, 1], abs(a1[0] * a2[1] - a1[1] * a2[0])
+
+
+def sigma_kubo_kgrid(lat, mu_ev: float, alpha: int = 0, beta: int = 1) -> float:
+    """sigma_ab of sigma_kubo_eigen for the clean L1 x L2 torus, summed over its
+    allowed wave vectors k = (m1 b1 / L1 + m2 b2 / L2) with the Bloch matrices."""
+    b1, b2, area = _recip(lat)
+    tot = 0.0 + 0.0j
+    for m1 in range(lat.L1):
+        for m2 in range(lat.L2):
+            k = m1 * b1 / lat.L1 + m2 * b2 / lat.L2
+            H, hx, hy = bloch(lat, k)
+            E, U = np.linalg.eigh(H)
+            A = U.conj().T @ (hx if alpha == 0 else hy) @ U
+            B = U.conj().T @ (hx if beta == 0 else hy) @ U
+            occ = np.nonzero(E < mu_ev)[0]
+            emp = np.nonzero(E >= mu_ev)[0]
+            P_ab = A[np.ix_(occ, emp)] * B[np.ix_(emp, occ)].T
+            P_ba = A[np.ix_(emp, occ)].T * B[np.ix_(occ, emp)]
+            tot += np.sum((P_ab - P_ba) / (E[occ][:, None] - E[emp][None, :]) ** 2)
+    return float(np.real(-2j * np.pi / (lat.L1 * lat.L2 * area) * tot))
+
+
+def chern_number(lat, n_occ: int, n_k: int) -> float:
+    """Chern number of the n_occ lowest bands on an n_k x n_k grid by the link
+    variables U_a(k) = det <u(k)|u(k + a)> (periodic gauge); the result is an
+    integer whenever the grid resolves the Berry curvature."""
+    b1, b2, _ = _recip(lat)
+    vecs = np.empty((n_k, n_k), dtype=object)
+    for i in range(n_k):
+        for j in range(n_k):
+            H, _, _ = bloch(lat, i * b1 / n_k + j * b2 / n_k, periodic_gauge=True)
+            vecs[i, j] = np.linalg.eigh(H)[1][:, :n_occ]
+    def link(u, v):
+        d = np.linalg.det(u.conj().T @ v)
+        return d / abs(d)
+    total = 0.0
+    for i in range(n_k):
+        for j in range(n_k):
+            ip, jp = (i + 1) % n_k, (j + 1) % n_k
+            f = link(vecs[i, j], vecs[ip, j]) * link(vecs[ip, j], vecs[ip, jp]) / (
+                link(vecs[i, jp], vecs[ip, jp]) * link(vecs[i, j], vecs[i, jp]))
+            total += np.angle(f)
+    return total / (2.0 * np.pi)

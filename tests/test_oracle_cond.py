@@ -112,3 +112,129 @@ def test_sigma_xx_equals_sigma_yy_on_c3_symmetric_torus():
     sy = cond.sigma_from_gamma(Gy, E, lat.e_min, lat.e_max, m.n_active, area)
     # The paper's a and a_cc differ from an exact regular hexagon by ~1e-5 relative.
     assert np.max(np.abs(sx - sy)) < 1e-4 * np.max(np.abs(sx))
+
+
+# --- Kubo-Bastin / Hall conductivity (eq. cond 1st order, static limit) -----
+
+T_HOP = -2.7
+
+
+def _qahe(L, W=0.0, seed=0, exchange=0.4 * abs(T_HOP), rashba=0.3 * abs(T_HOP)):
+    """The paper's QAHE model (eq. HQAHE, Fig. qahe): lambda_R = 0.3 t, Delta_ex = 0.4 t."""
+    return wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=L, L2=L, t=T_HOP, rashba=rashba, exchange=exchange,
+                      anderson_w=W, disorder_seed=seed, e_min=-10.0, e_max=10.0)
+
+
+def test_qahe_real_space_spectrum_equals_bloch_bands():
+    """The real-space builder (with the exchange term) and the k-space Bloch matrices
+    are separate code: on a clean 6 x 6 torus the eigenvalues must coincide."""
+    lat = _qahe(6)
+    m = lattice.build(lat)
+    e_real = np.sort(np.linalg.eigvalsh(m.H.toarray()))
+    b1, b2, _ = cond._recip(lat)
+    e_k = np.sort(np.concatenate([np.linalg.eigvalsh(cond.bloch(lat, i * b1 / 6 + j * b2 / 6)[0])
+                                  for i in range(6) for j in range(6)]))
+    assert np.max(np.abs(e_real - e_k)) < 1e-12
+
+
+@pytest.mark.parametrize("L", [6, 9])
+def test_kubo_real_space_equals_k_space(L):
+    """sigma_xy from the dense real-space eigenstates = the same Kubo sum over the
+    torus's Bloch states (independent matrices); L = 6, 9 give 0.614 and 1.633."""
+    lat = _qahe(L)
+    a = cond.sigma_kubo_eigen(lattice.build(lat), 0.0)
+    b = cond.sigma_kubo_kgrid(lat, 0.0)
+    assert abs(a - b) < 1e-10 * abs(b)
+    assert abs(a - {6: 0.6135722646, 9: 1.6330226427}[L]) < 1e-8
+
+
+def test_qahe_plateau_is_two_e2_over_h():
+    """The clean QAHE insulator has Chern number 2 (paper: sigma_xy = 2 e^2/h in the
+    gap).  The link-variable Chern number is an exact integer (+-2 by orientation),
+    and the Kubo sum on a 120 x 120 torus equals -C to 1e-6 at the gap centre and
+    off-centre inside the gap (E = +-0.3 eV; the gap is |E| < 0.62 eV)."""
+    lat = _qahe(6)
+    C = cond.chern_number(lat, 2, 24)
+    assert abs(C - round(C)) < 1e-9 and abs(round(C)) == 2
+    big = _qahe(120)
+    for mu in (0.0, 0.3, -0.3):
+        s = cond.sigma_kubo_kgrid(big, mu)
+        assert abs(s - (-round(C))) < 1e-6, (mu, s)
+
+
+def test_hall_vanishes_without_exchange_and_flips_with_it():
+    """Rashba alone keeps time reversal: sigma_xy = 0 (checked at E = 50 meV, off the
+    degenerate Dirac level of the gapless model).  Delta_ex -> -Delta_ex flips the
+    sign of sigma_xy."""
+    assert abs(cond.sigma_kubo_kgrid(_qahe(30, exchange=0.0), 0.05)) < 1e-12
+    s_p = cond.sigma_kubo_kgrid(_qahe(30), 0.0)
+    s_m = cond.sigma_kubo_kgrid(_qahe(30, exchange=-0.4 * abs(T_HOP)), 0.0)
+    assert abs(s_p + s_m) < 1e-10 and abs(s_p) > 1.9
+
+
+def test_gamma_exact_matches_dense_chebyshev_products():
+    """gamma_nm_exact (eigenbasis sum) against Tr[h~x T_n h~y T_m]/N/((1+d_n0)(1+d_m0))
+    with dense T_n(H~) matrices, on a disordered QAHE model with a vacancy."""
+    lat = _qahe(3, W=1.5, seed=3)
+    lat = lat.replace(vacancy_p=0.1, disorder_seed=5)
+    m = lattice.build(lat)
+    M = 9
+    G = cond.gamma_nm_exact(m, lat.e_min, lat.e_max, M, 0, 1)
+    Ht = kpm.rescale(m.H, lat.e_min, lat.e_max).toarray()
+    hx, hy = m.hx.toarray(), m.hy.toarray()
+    N = m.n_active
+    for n in range(M):
+        Tn = _cheb_dense(Ht, n)
+        for mm in range(M):
+            ref = np.trace(hx @ Tn @ hy @ _cheb_dense(Ht, mm)) / N / ((2 if n == 0 else 1) * (2 if mm == 0 else 1))
+            assert abs(G[n, mm] - ref) < 1e-11 * max(1.0, abs(ref)), (n, mm)
+
+
+def test_cpgf_derivative_matches_finite_differences():
+    """cpgf_derivative against a central difference of the printed coefficients
+    g_n = -2 s i exp(-s i n arccos z)/sqrt(1 - z^2), z = eps + i s eta."""
+    eps = np.array([-0.83, -0.2, 0.0, 0.37, 0.9])
+    eta, h, M = 0.01, 1e-6, 40
+    for sign in (1, -1):
+        def g(e):
+            z = e + 1j * sign * eta
+            n = np.arange(M)
+            return -2 * sign * 1j * np.exp(-sign * 1j * np.outer(np.arccos(z), n)) / np.sqrt(1 - z * z)[:, None]
+        fd = (g(eps + h) - g(eps - h)) / (2 * h)
+        an = cond.cpgf_derivative(M, eps, eta, sign)
+        assert np.max(np.abs(fd - an)) < 1e-6 * np.max(np.abs(an))
+
+
+def test_bastin_spectral_converges_to_eigenstate_kubo():
+    """The Gamma/Lambda route (sigma_bastin on the exact Gamma^xy, M = 4096,
+    eta = 50 meV) reproduces the eigenstate Kubo sum of the same 6 x 6 torus
+    (0.6136 e^2/h) to 1e-3; at M = 512 it is 2 % off (truncation)."""
+    lat = _qahe(6)
+    m = lattice.build(lat)
+    exact = cond.sigma_kubo_eigen(m, 0.0)
+    opn = m.n_active / (36 * m.cell_area)
+    G = cond.gamma_nm_exact(m, lat.e_min, lat.e_max, 4096, 0, 1)
+    s = cond.sigma_bastin(G, [0.0], lat.e_min, lat.e_max, 0.05, opn, 8192)[0]
+    assert abs(s - exact) < 1e-3 * abs(exact), (s, exact)
+    s512 = cond.sigma_bastin(G[:512, :512], [0.0], lat.e_min, lat.e_max, 0.05, opn, 1024)[0]
+    assert 0.005 < abs(s512 - exact) / abs(exact) < 0.05
+
+
+def test_bastin_both_directions_converge_on_a_disordered_model():
+    """Disordered 4 x 4 QAHE model (W = 1 eV), Gamma^yx = (Gamma^xy)^T exactly.  At
+    M = 4096, eta = 30 meV the spectral sigma_xy and sigma_yx match the eigenstate
+    Kubo sums (+-0.8173 e^2/h at three Fermi energies) to 0.5 %; the symmetric part
+    sigma_xy + sigma_yx, a truncation and broadening effect of the finite series
+    (4 % at M = 256), is below 1e-3."""
+    lat = _qahe(4, W=1.0, seed=9)
+    m = lattice.build(lat)
+    opn = m.n_active / (16 * m.cell_area)
+    E = [-0.4, 0.0, 0.25]
+    G = cond.gamma_nm_exact(m, lat.e_min, lat.e_max, 4096, 0, 1)
+    assert np.max(np.abs(cond.gamma_nm_exact(m, lat.e_min, lat.e_max, 64, 1, 0) - G[:64, :64].T)) < 1e-15
+    sxy = cond.sigma_bastin(G, E, lat.e_min, lat.e_max, 0.03, opn, 8192)
+    syx = cond.sigma_bastin(G.T.copy(), E, lat.e_min, lat.e_max, 0.03, opn, 8192)
+    exact = np.array([cond.sigma_kubo_eigen(m, e, 0, 1) for e in E])
+    assert np.max(np.abs(sxy - exact) / np.abs(exact)) < 5e-3, (sxy, exact)
+    assert np.max(np.abs(syx + exact) / np.abs(exact)) < 5e-3, (syx, exact)
+    assert np.max(np.abs(sxy + syx)) < 1e-3
