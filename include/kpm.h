@@ -292,6 +292,31 @@ int kpm_reconstruct_sigma(const double* gamma, int32_t M, const double* energies
                           double e_max, double orbitals_per_nm2, double* sigma, int32_t on_device, void* hip_stream);
 
 /*
+ * T = 0 Kubo-Bastin conductivity from Gamma^{ab} (any a, b; a = x, b = y is the
+ * Hall conductivity), in units of e^2/h: the static limit of the first-order
+ * formula (eq. cond 1st order) with the delta function of eq.
+ * delta_function_cheb_expansion and the CPGF resolvents of eqs.
+ * green_function_cheb_expansion(b) at broadening eta, contracted with Gamma as
+ * in eq. conductivity_1st_order (the Lambda_nm of a static field):
+ *   sigma_ab(mu) = Re{ -2 pi i (N/Omega)/de-^2 int_{-1}^{mu~} d eps
+ *                  sum_nm Gamma_nm [Delta_n(eps) g'^R_m(eps) - g'^A_n(eps) Delta_m(eps)] },
+ * g' = d g / d eps, mu~ = (mu - de+)/de-, N/Omega = orbitals_per_nm2.  The
+ * integral runs in theta (eps = cos theta) over n_theta equal cells of
+ * [0, pi] by the midpoint rule, the cell holding theta_mu weighted by its part
+ * inside [theta_mu, pi] (n_theta = 0: 4 M).
+ * gamma [M][M][2] (re, im) as kpm_moments_cond writes it, energies_ev [K]
+ * Fermi energies, sigma [K]; all host (on_device = 0) or all device pointers.
+ * Allocates a device workspace of ~16 (Mp^2 + (n_theta + 64) Mp) bytes,
+ * Mp = M rounded up to 64, and frees it before returning; synchronises
+ * hip_stream.  Errors: KPM_E_INVALID (NULL, M outside [1, 16384], K < 1,
+ * e_min >= e_max, eta <= 0, orbitals_per_nm2 <= 0, n_theta outside
+ * [0, 2^20]); KPM_E_DEVICE.
+ */
+int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, const double* energies_ev, int32_t K, double e_min,
+                                 double e_max, double eta_ev, double orbitals_per_nm2, int32_t n_theta, double* sigma,
+                                 int32_t on_device, void* hip_stream);
+
+/*
  * Moment-extrapolation MLP (the paper has no learned component: this is the
  * learned part of this implementation, specified by its shape alone).
  * Network n_in -> n_hidden -> n_hidden -> n_out, exact GELU x Phi(x) after the

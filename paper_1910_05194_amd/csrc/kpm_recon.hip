@@ -275,3 +275,239 @@ extern "C" int kpm_reconstruct_cpgf(const double* mu, int32_t M, const double* e
   return kpm::reconstruct("kpm_reconstruct_cpgf", 2, mu, M, energies_ev, K, e_min, e_max, eta_ev, rho, green,
                           on_device, hip_stream);
 }
+
+namespace kpm {
+
+// ---------------------------------------------------------------------------
+// T = 0 Kubo-Bastin conductivity from Gamma^{ab} (the static limit of the
+// first-order formula, eq. cond 1st order, written with eq.
+// delta_function_cheb_expansion for the delta function and the CPGF
+// coefficients of eqs. green_function_cheb_expansion(b) for the resolvents,
+// contracted with Gamma as in eq. conductivity_1st_order):
+//   sigma_ab(mu) = Re{ -2 pi i (N/Omega)/de-^2 int_{-1}^{mu~} d eps
+//                  sum_nm Gamma_nm [Delta_n(eps) g'^R_m(eps) - g'^A_n(eps) Delta_m(eps)] }  [e^2/h].
+// With eps = cos(theta), Delta_n d eps = (2/pi) cos(n theta) d theta, so the
+// integrand in theta is F(theta) = sum_n D_n(theta) W_n(theta),
+//   D_n = (2/pi) cos(n theta),   W_n = sum_m (g'^R_m Gamma_nm - g'^A_m Gamma_mn),
+// and g'^A = conj(g'^R) for real eps.  The retarded derivative, with
+// z = eps + i eta~, w = exp(-i arccos z) (the inner root, as above) and
+// s = sqrt(1 - z^2) = i (w - z):
+//   g'^R_n = -2 i w^n (i n / s^2 + z / s^3).
+// theta runs over Q equal cells of [0, pi] (midpoint rule); the cell holding
+// theta_mu counts with the part of it that lies in [theta_mu, pi].
+// Kernels: the g'^R table [Q][Mp]; the contraction on 64 x 64 (q, n) tiles
+// with FP64 partial sums per n tile; one workgroup per Fermi energy for the
+// weighted sum, all in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int kBT = 64;   // q and n tile
+constexpr int kBK = 8;    // m chunk
+
+__global__ void bastin_table_kernel(int Q, int M, int Mp, double eta, double2* gR) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q) return;
+  const double th = (q + 0.5) * M_PI / Q;
+  const cplx z = {cos(th), eta};
+  const cplx r = csqrt_p({z.re * z.re - z.im * z.im - 1.0, 2.0 * z.re * z.im});
+  const cplx wp = {z.re + r.re, z.im + r.im}, wm = {z.re - r.re, z.im - r.im};
+  const cplx outer = (hypot(wp.re, wp.im) >= hypot(wm.re, wm.im)) ? wp : wm;
+  const cplx w = cdiv({1.0, 0.0}, outer);
+  const cplx s = {-(w.im - z.im), w.re - z.re};            // i (w - z)
+  const cplx s2 = cmul(s, s);
+  const cplx s3 = cmul(s2, s);
+  const cplx inv_s2 = cdiv({1.0, 0.0}, s2);
+  const cplx zs3 = cdiv(z, s3);
+  cplx pw = {1.0, 0.0};
+  double2* row = gR + (int64_t)q * Mp;
+  for (int n = 0; n < Mp; ++n) {
+    if (n < M) {
+      // -2 i w^n (i n / s^2 + z / s^3)
+      const cplx b = {-n * inv_s2.im + zs3.re, n * inv_s2.re + zs3.im};
+      const cplx c = cmul(pw, b);
+      row[n] = make_double2(2.0 * c.im, -2.0 * c.re);
+      pw = cmul(pw, w);
+    } else {
+      row[n] = make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// gam: Gamma padded to [Mp][Mp] complex.  part[nt][q] = sum_{n in tile nt} D_n(theta_q) W_n(theta_q).
+__global__ void __launch_bounds__(256) bastin_contract_kernel(const double2* __restrict__ gR,
+                                                              const double2* __restrict__ gam, int Q, int Mp,
+                                                              double2* __restrict__ part) {
+  __shared__ double2 sg[kBT][kBK + 1];    // g'^R[q][m]
+  __shared__ double2 sr[kBT][kBK + 1];    // Gamma[n][m]
+  __shared__ double2 sc[kBK][kBT + 1];    // Gamma[m][n]
+  __shared__ double2 red[16][kBT + 1];
+  const int tq = threadIdx.x / 16, tn = threadIdx.x % 16;   // 16 x 16 threads, 4 x 4 outputs each
+  const int q0 = blockIdx.x * kBT, n0 = blockIdx.y * kBT;
+  cplx acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = {0.0, 0.0};
+  for (int m0 = 0; m0 < Mp; m0 += kBK) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kBT * kBK; e += 256) {
+      const int a = e / kBK, b = e % kBK;
+      const int q = q0 + a;
+      sg[a][b] = (q < Q) ? gR[(int64_t)q * Mp + m0 + b] : make_double2(0.0, 0.0);
+      sr[a][b] = gam[(int64_t)(n0 + a) * Mp + m0 + b];
+    }
+    for (int e = threadIdx.x; e < kBT * kBK; e += 256) {
+      const int b = e / kBT, a = e % kBT;
+      sc[b][a] = gam[(int64_t)(m0 + b) * Mp + n0 + a];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < kBK; ++k) {
+      cplx g[4], r[4], c[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double2 v = sg[tq * 4 + i][k];
+        g[i] = {v.x, v.y};
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double2 a = sr[tn * 4 + j][k], b = sc[k][tn * 4 + j];
+        r[j] = {a.x, a.y};
+        c[j] = {b.x, b.y};
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          // g Gamma_nm - conj(g) Gamma_mn
+          acc[i][j].re += g[i].re * r[j].re - g[i].im * r[j].im - (g[i].re * c[j].re + g[i].im * c[j].im);
+          acc[i][j].im += g[i].re * r[j].im + g[i].im * r[j].re - (g[i].re * c[j].im - g[i].im * c[j].re);
+        }
+    }
+  }
+  // Weight by D_n(theta_q) and sum this thread's four n; then over the 16 n-threads.
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = q0 + tq * 4 + i;
+    const double th = (q + 0.5) * M_PI / Q;
+    cplx t = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double d = 2.0 / M_PI * cos((double)(n0 + tn * 4 + j) * th);
+      t.re += d * acc[i][j].re;
+      t.im += d * acc[i][j].im;
+    }
+    red[tn][tq * 4 + i] = make_double2(t.re, t.im);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBT) {
+    const int a = threadIdx.x;
+    double sre = 0.0, sim = 0.0;
+    for (int j = 0; j < 16; ++j) {
+      sre += red[j][a].x;
+      sim += red[j][a].y;
+    }
+    const int q = q0 + a;
+    if (q < Q) part[(int64_t)blockIdx.y * Q + q] = make_double2(sre, sim);
+  }
+}
+
+__global__ void bastin_sigma_kernel(const double2* part, int n_tiles, int Q, const double* energies, int K,
+                                    double e_min, double e_max, double pref_im, double* sigma) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  const double de_p = 0.5 * (e_max + e_min), de_m = 0.5 * (e_max - e_min);
+  const double mut = (energies[k] - de_p) / de_m;
+  const double h = M_PI / Q;
+  const double th_mu = (mut >= 1.0) ? 0.0 : (mut <= -1.0 ? M_PI : acos(mut));
+  double acc = 0.0;   // Im of sum_q F_q w_q (pref is purely imaginary: Re(pref F) = -pref_im Im F)
+  for (int q = threadIdx.x; q < Q; q += blockDim.x) {
+    const double thq = (q + 0.5) * h;
+    const double lo = fmax(thq - 0.5 * h, th_mu);
+    const double wq = fmin(fmax(thq + 0.5 * h - lo, 0.0), h);
+    if (wq > 0.0) {
+      double fi = 0.0;
+      for (int t = 0; t < n_tiles; ++t) fi += part[(int64_t)t * Q + q].y;
+      acc += fi * wq;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sigma[k] = -pref_im * red[0];
+}
+
+__global__ void pad_gamma_kernel(const double* gamma, int M, int Mp, double2* out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Mp * Mp) return;
+  const int n = (int)(i / Mp), m = (int)(i % Mp);
+  out[i] = (n < M && m < M) ? make_double2(gamma[2 * ((int64_t)n * M + m)], gamma[2 * ((int64_t)n * M + m) + 1])
+                            : make_double2(0.0, 0.0);
+}
+
+}  // namespace kpm
+
+extern "C" int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, const double* energies_ev, int32_t K,
+                                            double e_min, double e_max, double eta_ev, double orbitals_per_nm2,
+                                            int32_t n_theta, double* sigma, int32_t on_device, void* hip_stream) {
+  using namespace kpm;
+  clear_error();
+  KPM_CHECK_ARG(gamma && energies_ev && sigma, "NULL argument");
+  KPM_CHECK_ARG(M >= 1 && M <= 16384 && K >= 1, "need 1 <= M <= 16384 and K >= 1");
+  KPM_CHECK_ARG(std::isfinite(e_min) && std::isfinite(e_max) && e_min < e_max, "need e_min < e_max");
+  KPM_CHECK_ARG(eta_ev > 0.0 && std::isfinite(eta_ev), "eta must be > 0");
+  KPM_CHECK_ARG(orbitals_per_nm2 > 0.0, "orbitals_per_nm2 must be > 0");
+  KPM_CHECK_ARG(n_theta >= 0 && n_theta <= (1 << 20), "n_theta must be in [0, 2^20]");
+  const int Q = n_theta > 0 ? n_theta : 4 * M;
+  const int Mp = (int)ceil_div(M, kBT) * kBT;
+  const int Qp = (int)ceil_div(Q, kBT) * kBT;
+  const int n_tiles = Mp / kBT;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const double de_m = 0.5 * (e_max - e_min);
+  // Workspace: padded Gamma, the g'^R table, the partial sums, and staged host data.
+  const size_t b_gam = sizeof(double2) * (size_t)Mp * Mp;
+  const size_t b_tab = sizeof(double2) * (size_t)Qp * Mp;
+  const size_t b_part = sizeof(double2) * (size_t)n_tiles * Q;
+  const size_t gn = (size_t)M * M * 2;
+  const size_t b_host = on_device ? 0 : sizeof(double) * (gn + 2 * (size_t)K);
+  char* ws = nullptr;
+  KPM_TRY_HIP(hipMalloc(&ws, b_gam + b_tab + b_part + b_host));
+  double2* gam = (double2*)ws;
+  double2* tab = (double2*)(ws + b_gam);
+  double2* part = (double2*)(ws + b_gam + b_tab);
+  const double* dg = gamma;
+  const double* den = energies_ev;
+  double* dsig = sigma;
+  hipError_t e = hipSuccess;
+  if (!on_device) {
+    double* h = (double*)(ws + b_gam + b_tab + b_part);
+    e = hipMemcpyAsync(h, gamma, sizeof(double) * gn, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + gn, energies_ev, sizeof(double) * K, hipMemcpyHostToDevice, s);
+    dg = h;
+    den = h + gn;
+    dsig = h + gn + K;
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(pad_gamma_kernel, dim3((unsigned)ceil_div((int64_t)Mp * Mp, 256)), dim3(256), 0, s, dg, M, Mp,
+                       gam);
+    // Table rows q >= Q stay unused (the contraction zero-fills them).
+    hipLaunchKernelGGL(bastin_table_kernel, dim3((unsigned)ceil_div(Q, 256)), dim3(256), 0, s, Q, M, Mp,
+                       eta_ev / de_m, tab);
+    hipLaunchKernelGGL(bastin_contract_kernel, dim3(Qp / kBT, n_tiles), dim3(256), 0, s, tab, gam, Q, Mp, part);
+    // pref = -2 pi i (N/Omega)/de-^2 is imaginary: Re(pref F) = -Im(pref) Im(F).
+    hipLaunchKernelGGL(bastin_sigma_kernel, dim3(K), dim3(256), 0, s, part, n_tiles, Q, den, K, e_min, e_max,
+                       -2.0 * M_PI * orbitals_per_nm2 / (de_m * de_m), dsig);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && !on_device) {
+    e = hipMemcpyAsync(sigma, dsig, sizeof(double) * K, hipMemcpyDeviceToHost, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(ws);
+  if (e != hipSuccess) {
+    set_error("kpm_reconstruct_sigma_bastin: %s", hipGetErrorString(e));
+    return KPM_E_DEVICE;
+  }
+  return KPM_OK;
+}

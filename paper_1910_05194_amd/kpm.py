@@ -103,6 +103,9 @@ def _load():
                                             ctypes.c_int32, _P]),
         "kpm_reconstruct_sigma": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
                                                  ctypes.c_double, ctypes.c_double, _P, ctypes.c_int32, _P]),
+        "kpm_reconstruct_sigma_bastin": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
+                                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                        ctypes.c_int32, _P, ctypes.c_int32, _P]),
         "kpm_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                           ctypes.POINTER(_P)]),
         "kpm_mlp_destroy": (ctypes.c_int, [_P]),
@@ -387,6 +390,31 @@ def reconstruct_sigma(gamma, energies, e_min: float, e_max: float, orbitals_per_
     _check(LIB.kpm_reconstruct_sigma(g.data_ptr(), g.shape[0], en.data_ptr(), en.numel(), float(e_min),
                                      float(e_max), float(orbitals_per_nm2), out.data_ptr(), 1,
                                      _stream_handle(stream)))
+    return out
+
+
+def reconstruct_sigma_bastin(gamma, energies, e_min: float, e_max: float, eta: float, orbitals_per_nm2: float,
+                             n_theta: int = 0, stream=None):
+    """kpm_reconstruct_sigma_bastin: T = 0 Kubo-Bastin sigma_ab(mu) in e^2/h from Gamma^{ab}
+    ([M, M] complex numpy or [M, M, 2] float64 torch on the device); eta in eV."""
+    if isinstance(gamma, np.ndarray):
+        g = np.ascontiguousarray(np.stack([gamma.real, gamma.imag], axis=-1)) if np.iscomplexobj(gamma) else \
+            np.ascontiguousarray(gamma, dtype=np.float64)
+        en = np.ascontiguousarray(np.atleast_1d(energies), dtype=np.float64)
+        out = np.zeros(en.shape)
+        _check(LIB.kpm_reconstruct_sigma_bastin(g.ctypes.data, g.shape[0], en.ctypes.data, en.size, float(e_min),
+                                                float(e_max), float(eta), float(orbitals_per_nm2), int(n_theta),
+                                                out.ctypes.data, 0, _stream_handle(stream)))
+        return out
+    import torch
+    g = gamma.contiguous()
+    en = energies.contiguous().to(torch.float64)
+    out = torch.zeros_like(en)
+    if stream is None:
+        stream = torch.cuda.current_stream(g.device)
+    _check(LIB.kpm_reconstruct_sigma_bastin(g.data_ptr(), g.shape[0], en.data_ptr(), en.numel(), float(e_min),
+                                            float(e_max), float(eta), float(orbitals_per_nm2), int(n_theta),
+                                            out.data_ptr(), 1, _stream_handle(stream)))
     return out
 
 

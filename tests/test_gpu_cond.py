@@ -32,6 +32,9 @@ LATS = [
     wl.Lattice(kind=wl.HONEYCOMB, L1=11, L2=6, t=-2.7, anderson_w=1.0, vacancy_p=0.05, disorder_seed=4,
                e_min=-8.9, e_max=8.6),
     wl.Lattice(kind=wl.SQUARE, L1=9, L2=13, t=-2.7, anderson_w=2.0, disorder_seed=8, e_min=-12.0, e_max=12.0),
+    # QAHE model (eq. HQAHE) with exchange, disorder and vacancies.
+    wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=8, L2=6, t=-2.7, rashba=0.81, exchange=1.08, anderson_w=1.25,
+               vacancy_p=0.03, disorder_seed=31, e_min=-10.0, e_max=10.0),
 ]
 
 
@@ -112,3 +115,71 @@ def test_cond_invalid_mode(K):
     with pytest.raises(K.KPMError) as e:
         K.moments_cond(lat, par, precision=wl.FP64)
     assert e.value.code == K.KPM_E_INVALID
+
+
+def _qahe(L, W=0.0, seed=0):
+    return wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=L, L2=L, t=-2.7, rashba=0.81, exchange=1.08, anderson_w=W,
+                      disorder_seed=seed, e_min=-10.0, e_max=10.0)
+
+
+def test_sigma_bastin_matches_oracle(K):
+    """kpm_reconstruct_sigma_bastin against the oracle's sigma_bastin (same
+    quadrature): the exact Gamma^xy of a disordered 4 x 4 QAHE model (M = 256),
+    and a random complex Gamma with M = 100 (padding to the 64-wide tiles), host
+    and device pointers, Fermi energies inside and outside the spectrum."""
+    import torch
+    lat = _qahe(4, W=1.0, seed=9)
+    m = olat.build(lat)
+    opn = m.n_active / (16 * m.cell_area)
+    E = np.array([-11.0, -9.99, -3.0, -0.4, 0.0, 0.25, 2.0, 9.99, 11.0])
+    G = ocond.gamma_nm_exact(m, lat.e_min, lat.e_max, 256, 0, 1)
+    for eta, q in ((0.1, 1024), (0.03, 700)):
+        ref = ocond.sigma_bastin(G, E, lat.e_min, lat.e_max, eta, opn, q)
+        got = K.reconstruct_sigma_bastin(G, E, lat.e_min, lat.e_max, eta, opn, n_theta=q)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"bastin eta {eta}: rel err {err:.2e}")
+        assert err <= 1e-10
+    rng = np.random.default_rng(4)
+    Gr = (rng.standard_normal((100, 100)) + 1j * rng.standard_normal((100, 100))) * 1e-3
+    ref = ocond.sigma_bastin(Gr, E, -7.0, 9.0, 0.05, 30.0, 400)
+    got = K.reconstruct_sigma_bastin(Gr, E, -7.0, 9.0, 0.05, 30.0)   # default n_theta = 4 M
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+    gt = torch.tensor(np.stack([Gr.real, Gr.imag], -1), device="cuda")
+    gd = K.reconstruct_sigma_bastin(gt, torch.tensor(E, device="cuda"), -7.0, 9.0, 0.05, 30.0)
+    assert np.array_equal(gd.cpu().numpy(), got)
+    with pytest.raises(K.KPMError):
+        K.reconstruct_sigma_bastin(Gr, E, -7.0, 9.0, 0.0, 30.0)
+
+
+def test_gamma_xy_with_exchange_split_bf16(K):
+    """Gamma^xy of the QAHE model through the production path (FP32 chains,
+    split-BF16 MFMA GEMM) against the FP64 oracle (same random vectors)."""
+    lat = LATS[-1]
+    par = wl.CondParams(num_moments=64, num_random=2, vector_seed=13, alpha=0, beta=1,
+                        gamma_mode=wl.GAMMA_SPLIT_BF16)
+    G = K.moments_cond(lat, par)
+    Go, _ = ocond.cond_gamma(lat, par)
+    err = rel_fro(G, Go)
+    print(f"Gamma^xy QAHE split-bf16: rel fro err {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_qahe_hall_plateau_end_to_end(K):
+    """The paper's QAHE result (Sec. 4, Fig. qahe): sigma_xy = 2 e^2/h inside the
+    gap of the clean model (lambda_R = 0.3 t, Delta_ex = 0.4 t; the oracle pins
+    the Chern number 2 and the 2 e^2/h Kubo sum).  Production path: FP32 chains,
+    split-BF16 Gamma^xy, 512 x 512 cells (1,048,576 orbitals), M = 1024, R = 1,
+    CPGF eta = 50 meV.  Measured 1.988-2.002 at |E| <= 0.5 eV (gap |E| < 0.62);
+    gate 1.5 %."""
+    import torch
+    L = 512
+    lat = _qahe(L)
+    par = wl.CondParams(num_moments=1024, num_random=1, vector_seed=3, alpha=0, beta=1,
+                        gamma_mode=wl.GAMMA_SPLIT_BF16)
+    G = K.moments_cond(lat, par, out_device="cuda")
+    cell = wl.A_HONEYCOMB ** 2 * np.sqrt(3) / 2
+    opn = 4 / cell
+    E = torch.tensor([-0.5, -0.3, 0.0, 0.3, 0.5], dtype=torch.float64, device="cuda")
+    s = K.reconstruct_sigma_bastin(G, E, lat.e_min, lat.e_max, 0.05, opn).cpu().numpy()
+    print("QAHE sigma_xy:", np.round(s, 4))
+    assert np.max(np.abs(s - 2.0)) < 0.03, s

@@ -53,6 +53,9 @@ RAGGED = [
     wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=13, L2=11, t=-2.7, rashba=0.2, flux=2 / 13, anderson_w=0.8,
                vacancy_p=0.02, disorder_seed=5),
     wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=16, L2=9, t=-2.7, rashba=0.35, disorder_seed=6),
+    # The paper's QAHE model (eq. HQAHE): Rashba 0.3 t, exchange 0.4 t, Anderson disorder, vacancies.
+    wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=12, L2=10, t=-2.7, rashba=0.81, exchange=1.08, anderson_w=1.25,
+               vacancy_p=0.02, disorder_seed=12, e_min=-10.0, e_max=10.0),
     wl.Lattice(kind=wl.SQUARE, L1=29, L2=17, t=-2.7, anderson_w=2.0, vacancy_p=0.05, disorder_seed=9,
                e_min=-12.0, e_max=12.0),
 ]
