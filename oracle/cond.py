@@ -291,3 +291,192 @@ def chern_number(lat, n_occ: int, n_k: int) -> float:
                 link(vecs[i, jp], vecs[ip, jp]) * link(vecs[i, j], vecs[i, jp]))
             total += np.angle(f)
     return total / (2.0 * np.pi)
+
+
+# ---------------------------------------------------------------------------
+# Optical conductivity sigma_ab(omega) at T = 0 (eq. cond 1st order with the
+# rank-1 and rank-2 Gamma of eq. Gammanm and the Lambda_n, Lambda_nm(omega)
+# that follow it, combined as in eq. conductivity_1st_order):
+#   sigma_ab(w)/(e^2/h) = (-2 pi i (N/Omega) / E_w) [ sum_n Gamma_n^{ab} L_n
+#                          + (1/de-) sum_nm Gamma_nm^{a,b} L_nm(w) ],
+#   L_n = int_{-1}^{mu~} d eps Delta_n(eps),
+#   L_nm(w) = int_{-1}^{mu~} d eps [g^R_n(eps + w~) Delta_m(eps) + Delta_n(eps) g^A_m(eps - w~)],
+# E_w = hbar omega in eV, w~ = E_w/de-, g^{R,A} the CPGF coefficients at
+# broadening eta (rescaled, hbar = 1), Gamma in eV nm^2 (rank 1) and eV^2 nm^2
+# (rank 2).  The energy integrals use the theta quadrature of sigma_bastin.
+# ---------------------------------------------------------------------------
+
+def velocity2(model: lattice.Model, a: int, b: int) -> sp.csr_matrix:
+    return model.h2[(min(a, b), max(a, b))]
+
+
+def gamma_n(Ht: sp.csr_matrix, h2: sp.csr_matrix, vectors: np.ndarray, M: int) -> np.ndarray:
+    """Rank-1 Gamma_n^{ab} averaged over the start vectors [R, N]:
+    (1/(R N)) sum_r <T_n(H~) r | h~^{ab} r> / (1 + d_n0)."""
+    R, N = vectors.shape
+    G = np.zeros(M, dtype=complex)
+    for r in range(R):
+        u = h2 @ vectors[r]
+        for n, vn in enumerate(kpm.chebyshev_vectors(Ht, vectors[r], M)):
+            G[n] += np.vdot(vn, u)
+    G /= R * N
+    G[0] /= 2.0
+    return G
+
+
+def cond_gamma1(lat, par, model=None):
+    """Gamma_n^{ab} for a lattice and CondParams-like ``par`` (random-phase vectors)."""
+    if model is None:
+        model = lattice.build(lat)
+    Ht = kpm.rescale(model.H, lat.e_min, lat.e_max)
+    vectors = kpm.random_phase_vectors(model, par.num_random, par.vector_seed, 0)
+    return gamma_n(Ht, velocity2(model, par.alpha, par.beta), vectors, par.num_moments), model
+
+
+def gamma_n_exact(model: lattice.Model, e_min: float, e_max: float, M: int, a: int, b: int) -> np.ndarray:
+    """Rank-1 Gamma_n^{ab} as an exact trace: sum_a (h~^{ab})_aa T_n(e_a) / (N (1 + d_n0))."""
+    E, U = _eigen(model)
+    C = np.real(np.einsum("ia,ij,ja->a", U.conj(), velocity2(model, a, b).toarray(), U))
+    d_plus, d_minus = (e_max + e_min) / 2.0, (e_max - e_min) / 2.0
+    G = kpm.chebyshev_t(M, (E - d_plus) / d_minus) @ C / E.size
+    G = G.astype(complex)
+    G[0] /= 2.0
+    return G
+
+
+def cpgf_coefficients(M: int, z: np.ndarray, sign: int) -> np.ndarray:
+    """g_n^{sign}(z) = -2 sign i exp(-sign i n arccos z) / sqrt(1 - z^2) for n < M (eq.
+    green_function_cheb_expansionb with z = eps + i sign eta; principal branches).
+    [len(z), M]."""
+    z = np.asarray(z, dtype=np.complex128)
+    theta = np.arccos(z)
+    s = np.sqrt(1.0 - z * z)
+    return -2.0 * sign * 1j * np.exp(-sign * 1j * np.outer(theta, np.arange(M))) / s[:, None]
+
+
+def sigma_optical(gamma_nm: np.ndarray, gamma_n: np.ndarray, omegas_ev, mu_ev: float, e_min: float, e_max: float,
+                  eta_ev: float, orbitals_per_nm2: float, n_theta: int) -> np.ndarray:
+    """Complex sigma_ab(omega) in e^2/h at T = 0 and Fermi energy mu (formula in the
+    block comment above).  Quadrature in theta as in sigma_bastin."""
+    gamma_nm = np.asarray(gamma_nm, dtype=np.complex128)
+    gamma_n = np.asarray(gamma_n, dtype=np.complex128)
+    M = gamma_nm.shape[0]
+    d_plus, d_minus = (e_max + e_min) / 2.0, (e_max - e_min) / 2.0
+    eta = eta_ev / d_minus
+    h = np.pi / n_theta
+    th = (np.arange(n_theta) + 0.5) * h
+    eps = np.cos(th)
+    D = 2.0 * np.cos(np.outer(th, np.arange(M))) / np.pi                   # [q, n]
+    mut = (mu_ev - d_plus) / d_minus
+    th_mu = 0.0 if mut >= 1.0 else (np.pi if mut <= -1.0 else float(np.arccos(mut)))
+    w = np.clip(th + h / 2.0 - np.maximum(th - h / 2.0, th_mu), 0.0, h)
+    lam_n = D.T @ w                                                         # Lambda_n
+    out = []
+    for Ew in np.atleast_1d(np.asarray(omegas_ev, dtype=np.float64)):
+        wt = Ew / d_minus
+        gR = cpgf_coefficients(M, eps + wt + 1j * eta, +1)                 # g^R_m(eps + w~)
+        gA = cpgf_coefficients(M, eps - wt - 1j * eta, -1)                 # g^A_m(eps - w~)
+        # sum_nm G_nm [gR_n D_m + D_n gA_m] = sum_n D_n sum_m (gA_m G_nm + gR_m G_mn)
+        F = np.sum(D * (gA @ gamma_nm.T + gR @ gamma_nm), axis=1)
+        para = np.sum(F * w) / d_minus
+        out.append(-2j * np.pi * orbitals_per_nm2 / Ew * (np.dot(gamma_n, lam_n) + para))
+    return np.array(out)
+
+
+def sigma_optical_eigen(model: lattice.Model, omegas_ev, mu_ev: float, eta_ev: float, a: int, b: int) -> np.ndarray:
+    """The same sigma_ab(omega) evaluated on the eigenstates (the definition with the
+    resolvents broadened by eta and the delta function exact):
+      (-2 pi i/(Omega E_w)) [ sum_a f_a C_aa + sum_ab A_ab B_ba ( f_a/(E_a - E_b + E_w + i eta)
+                                                             + f_b/(E_b - E_a - E_w - i eta) ) ],
+    A, B, C = h~^a, h~^b, h~^{ab} in the eigenbasis, f = theta(mu - E)."""
+    E, U = _eigen(model)
+    A = U.conj().T @ velocity(model, a).toarray() @ U
+    B = U.conj().T @ velocity(model, b).toarray() @ U
+    C = np.real(np.einsum("ia,ij,ja->a", U.conj(), velocity2(model, a, b).toarray(), U))
+    f = (E < mu_ev).astype(np.float64)
+    P = A * B.T
+    dE = E[:, None] - E[None, :]
+    n_cells = model.site_active.size // model.n_sub
+    omega = n_cells * model.cell_area
+    out = []
+    for Ew in np.atleast_1d(np.asarray(omegas_ev, dtype=np.float64)):
+        para = np.sum(P * (f[:, None] / (dE + Ew + 1j * eta_ev) + f[None, :] / (-dE - Ew - 1j * eta_ev)))
+        out.append(-2j * np.pi / (omega * Ew) * (np.dot(f, C) + para))
+    return np.array(out)
+
+
+def _bloch_many(lat, kpts: np.ndarray, a: int, b: int):
+    """H(k), h~^a(k), h~^b(k), h~^{ab}(k) for many wave vectors [Nk, 2] of a clean
+    honeycomb lattice (the bond sums of ``bloch`` and ``_bloch2``, vectorised over k)."""
+    a1, a2, tau, bonds = lattice._geometry(lat.kind)
+    n_spin = 2 if lat.kind == lattice.HONEYCOMB_SPIN else 1
+    n = len(tau) * n_spin
+    Nk = kpts.shape[0]
+    H, Ha, Hb, H2 = (np.zeros((Nk, n, n), dtype=complex) for _ in range(4))
+    sx = np.array([[0, 1], [1, 0]], dtype=complex)
+    sy = np.array([[0, -1j], [1j, 0]], dtype=complex)
+    for (si, sj, d1, d2) in bonds:
+        dvec = tau[si] - (d1 * a1 + d2 * a2 + tau[sj])
+        ph = np.exp(-1j * (kpts @ dvec))
+        dhat = dvec / np.linalg.norm(dvec)
+        for s in range(n_spin):
+            for s2 in range(n_spin):
+                hop = lat.t if s == s2 else 0.0
+                if n_spin == 2:
+                    hop = hop + (2j / 3.0) * lat.rashba * (sx[s, s2] * dhat[1] - sy[s, s2] * dhat[0])
+                i, j = si * n_spin + s, sj * n_spin + s2
+                for (Mx, w, sgn) in ((H, 1.0, 1.0), (Ha, dvec[a], -1.0), (Hb, dvec[b], -1.0),
+                                     (H2, dvec[a] * dvec[b], 1.0)):
+                    Mx[:, i, j] += w * hop * ph
+                    Mx[:, j, i] += sgn * np.conj(w * hop * ph)
+    if n_spin == 2:
+        H += np.diag([lat.exchange if (q % 2) == 0 else -lat.exchange for q in range(n)])[None]
+    return H, Ha, Hb, H2
+
+
+def sigma_optical_kgrid(lat, omegas_ev, mu_ev: float, eta_ev: float, a: int, b: int) -> np.ndarray:
+    """sigma_optical_eigen for the clean L1 x L2 torus from its Bloch states; the
+    second-order operator in k space is sum d^a d^b h exp(-i k.d) (= -d^2 H/dk_a dk_b)."""
+    b1, b2, area = _recip(lat)
+    Ews = np.atleast_1d(np.asarray(omegas_ev, dtype=np.float64))
+    tot = np.zeros(Ews.size, dtype=complex)
+    m1, m2 = np.meshgrid(np.arange(lat.L1), np.arange(lat.L2), indexing="ij")
+    kall = np.outer(m1.ravel() / lat.L1, b1) + np.outer(m2.ravel() / lat.L2, b2)
+    for c0 in range(0, kall.shape[0], 20000):
+        H, Ha, Hb, H2 = _bloch_many(lat, kall[c0:c0 + 20000], a, b)
+        E, U = np.linalg.eigh(H)
+        Uh = np.conj(np.swapaxes(U, 1, 2))
+        A = Uh @ Ha @ U
+        B = Uh @ Hb @ U
+        C = np.real(np.einsum("kia,kij,kja->ka", U.conj(), H2, U))
+        f = (E < mu_ev).astype(np.float64)
+        P = A * np.swapaxes(B, 1, 2)
+        dE = E[:, :, None] - E[:, None, :]
+        for i, Ew in enumerate(Ews):
+            tot[i] += np.sum(f * C) + np.sum(P * (f[:, :, None] / (dE + Ew + 1j * eta_ev)
+                                                   + f[:, None, :] / (-dE - Ew - 1j * eta_ev)))
+    return -2j * np.pi / (lat.L1 * lat.L2 * area * Ews) * tot
+
+
+def _bloch2(lat, k, a: int, b: int):
+    """k-space matrix of [r^a, [r^b, H]] for a clean honeycomb lattice (hopping terms only)."""
+    a1, a2, tau, bonds = lattice._geometry(lat.kind)
+    n_spin = 2 if lat.kind == lattice.HONEYCOMB_SPIN else 1
+    n = len(tau) * n_spin
+    Hm = np.zeros((n, n), dtype=complex)
+    sx = np.array([[0, 1], [1, 0]], dtype=complex)
+    sy = np.array([[0, -1j], [1j, 0]], dtype=complex)
+    for (si, sj, d1, d2) in bonds:
+        dvec = tau[si] - (d1 * a1 + d2 * a2 + tau[sj])
+        ph = np.exp(-1j * np.dot(k, dvec))
+        dhat = dvec / np.linalg.norm(dvec)
+        w = dvec[a] * dvec[b]
+        for s in range(n_spin):
+            for s2 in range(n_spin):
+                hop = lat.t if s == s2 else 0.0
+                if n_spin == 2:
+                    hop = hop + (2j / 3.0) * lat.rashba * (sx[s, s2] * dhat[1] - sy[s, s2] * dhat[0])
+                i, j = si * n_spin + s, sj * n_spin + s2
+                Hm[i, j] += w * hop * ph
+                Hm[j, i] += np.conj(w * hop * ph)
+    return Hm

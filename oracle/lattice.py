@@ -44,6 +44,7 @@ class Model:
     H: sp.csr_matrix          # physical Hamiltonian (eV), active orbitals only
     hx: sp.csr_matrix         # [x, H] (eV nm), same index space
     hy: sp.csr_matrix         # [y, H] (eV nm)
+    h2: dict                  # [a, [b, H]] (eV nm^2) for (a, b) in (0, 0), (0, 1), (1, 1)
     orb_index: np.ndarray     # global orbital index of each active orbital
     site_active: np.ndarray   # bool per site (cell*n_sub + s)
     onsite: np.ndarray        # V per site (eV), before removal
@@ -195,6 +196,9 @@ def build(lat) -> Model:
                       shape=(N, N)).tocsr()
     hx = sp.coo_matrix((dxs * vals, (rows, cols)), shape=(N, N)).tocsr()
     hy = sp.coo_matrix((dys * vals, (rows, cols)), shape=(N, N)).tocsr()
+    # Second-order operator [r^a, [r^b, H]]_ij = d^a_ij d^b_ij H_ij (eq. generalized velocity, n = 2).
+    dd = {(0, 0): dxs * dxs, (0, 1): dxs * dys, (1, 1): dys * dys}
+    h2 = {ab: sp.coo_matrix((w * vals, (rows, cols)), shape=(N, N)).tocsr() for ab, w in dd.items()}
 
     orb_active = site_active[orb_site]
     idx = np.nonzero(orb_active)[0]
@@ -202,8 +206,9 @@ def build(lat) -> Model:
         H = H[idx][:, idx].tocsr()
         hx = hx[idx][:, idx].tocsr()
         hy = hy[idx][:, idx].tocsr()
+        h2 = {ab: m[idx][:, idx].tocsr() for ab, m in h2.items()}
     cell_area = abs(a1[0] * a2[1] - a1[1] * a2[0])
-    return Model(H=H, hx=hx, hy=hy, orb_index=idx, site_active=site_active, onsite=V,
+    return Model(H=H, hx=hx, hy=hy, h2=h2, orb_index=idx, site_active=site_active, onsite=V,
                  n_sub=n_sub, n_spin=n_spin, cell_area=cell_area)
 
 

@@ -238,3 +238,76 @@ def test_bastin_both_directions_converge_on_a_disordered_model():
     assert np.max(np.abs(sxy - exact) / np.abs(exact)) < 5e-3, (sxy, exact)
     assert np.max(np.abs(syx + exact) / np.abs(exact)) < 5e-3, (syx, exact)
     assert np.max(np.abs(sxy + syx)) < 1e-3
+
+
+# --- Optical conductivity sigma_ab(omega) (eq. cond 1st order, rank-1 and rank-2 Gamma) ---
+
+def test_gamma1_exact_matches_trace_and_stochastic_basis():
+    """gamma_n_exact = Tr[h~^{ab} T_n(H~)]/(N(1+d_n0)) with dense T_n; the stochastic
+    gamma_n with the scaled basis vectors (so that <r|r> = N) gives the same trace;
+    h~^{ab} is Hermitian and Gamma_n^{ab} real; the n = 1 term of clean graphene
+    is the bond sum (1/N) sum_ij d^a_ij d^b_ij |H_ij|^2 / de-."""
+    lat = _qahe(3, W=1.5, seed=3).replace(vacancy_p=0.1, disorder_seed=5)
+    m = lattice.build(lat)
+    Ht = kpm.rescale(m.H, lat.e_min, lat.e_max)
+    N = m.n_active
+    vecs = np.sqrt(N) * np.eye(N, dtype=complex)
+    for ab in ((0, 0), (0, 1), (1, 1)):
+        h2 = cond.velocity2(m, *ab).toarray()
+        assert np.max(np.abs(h2 - h2.conj().T)) < 1e-14
+        G = cond.gamma_n_exact(m, lat.e_min, lat.e_max, 7, *ab)
+        Gs = cond.gamma_n(Ht, cond.velocity2(m, *ab), vecs, 7)
+        for n in range(7):
+            ref = np.trace(h2 @ _cheb_dense(Ht.toarray(), n)) / N / (2 if n == 0 else 1)
+            assert abs(G[n] - ref) < 1e-12 and abs(Gs[n] - ref) < 1e-12
+    g = wl.Lattice(kind=wl.HONEYCOMB, L1=6, L2=6, t=T_HOP)
+    mg = lattice.build(g)
+    de_m = 0.5 * (g.e_max - g.e_min)
+    G1 = cond.gamma_n_exact(mg, g.e_min, g.e_max, 3, 0, 0)
+    dx = np.abs(mg.hx.toarray() / np.where(mg.H.toarray() != 0, mg.H.toarray(), 1))
+    ref = np.sum(dx ** 2 * np.abs(mg.H.toarray()) ** 2) / mg.n_active / de_m
+    assert abs(G1[1].real - ref) < 1e-12 * ref and abs(G1[0]) < 1e-15
+
+
+def test_graphene_universal_optical_conductivity():
+    """Clean spinless graphene at mu = 0: Re sigma_xx(omega) -> pi/4 e^2/h (the
+    universal interband value e^2/(4 hbar) for spin and valley degeneracy 4,
+    halved without spin).  k-space sum on a 600^2 torus, eta = 50 meV: within
+    1 % at 0.5 eV, and the quadratic extrapolation from 0.5 and 1 eV to omega -> 0
+    within 0.5 %; sigma_xy = 0 (time reversal; checked at mu = 50 meV)."""
+    lat = wl.Lattice(kind=wl.HONEYCOMB, L1=600, L2=600, t=T_HOP, e_min=-9.0, e_max=9.0)
+    s = cond.sigma_optical_kgrid(lat, [0.5, 1.0], 0.0, 0.05, 0, 0).real / (np.pi / 4)
+    assert abs(s[0] - 1.0) < 0.01, s
+    s0 = s[0] - (s[1] - s[0]) / 3.0          # a + b w^2 through w = 0.5, 1
+    assert abs(s0 - 1.0) < 0.005, s0
+    # sigma_xy at mu = 50 meV (off the degenerate Dirac level, which a 60^2 grid contains).
+    assert np.max(np.abs(cond.sigma_optical_kgrid(wl.Lattice(kind=wl.HONEYCOMB, L1=60, L2=60, t=T_HOP),
+                                                  [0.5, 1.0], 0.05, 0.05, 0, 1))) < 1e-12
+
+
+def test_optical_real_space_equals_k_space():
+    """Eigenstate sigma_ab(omega) of the real-space torus = the Bloch-state sum (graphene
+    xx, QAHE xx and xy): independent matrices, 1e-12."""
+    for lat in (wl.Lattice(kind=wl.HONEYCOMB, L1=6, L2=6, t=T_HOP, e_min=-9, e_max=9), _qahe(4)):
+        m = lattice.build(lat)
+        for ab in ((0, 0), (0, 1)):
+            a = cond.sigma_optical_eigen(m, [0.5, 1.0, 2.5], 0.2, 0.1, *ab)
+            b = cond.sigma_optical_kgrid(lat, [0.5, 1.0, 2.5], 0.2, 0.1, *ab)
+            assert np.max(np.abs(a - b)) < 1e-12 * max(1.0, np.max(np.abs(a)))
+
+
+def test_optical_spectral_converges_to_eigenstate_definition():
+    """The Gamma/Lambda route (exact rank-1 and rank-2 Gamma, M = 2048) against the
+    eigenstate formula on the disordered 4 x 4 QAHE model at hbar omega = 0.3,
+    1, 2.5 eV, mu = 0.1 eV, eta = 0.1 eV: sigma_xy within 1 %, sigma_xx (M = 512)
+    within 1.5 %."""
+    lat = _qahe(4, W=1.0, seed=9)
+    m = lattice.build(lat)
+    opn = m.n_active / (16 * m.cell_area)
+    W = [0.3, 1.0, 2.5]
+    for ab, M, tol in (((0, 1), 2048, 0.01), ((0, 0), 512, 0.015)):
+        ex = cond.sigma_optical_eigen(m, W, 0.1, 0.1, *ab)
+        s = cond.sigma_optical(cond.gamma_nm_exact(m, lat.e_min, lat.e_max, M, *ab),
+                               cond.gamma_n_exact(m, lat.e_min, lat.e_max, M, *ab), W, 0.1, lat.e_min, lat.e_max,
+                               0.1, opn, 2 * M)
+        assert np.max(np.abs(s - ex) / np.abs(ex)) < tol, (ab, s, ex)
