@@ -265,6 +265,21 @@ typedef struct kpm_cond_params_t {
 int kpm_moments_cond(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma, int32_t out_on_device,
                      void* hip_stream);
 
+/*
+ * Rank-1 tensor (the Gamma_n^{ab} of the paper's Gamma family, eq. Gammanm and
+ * the examples after it) with the stochastic trace of Sec. 2(c):
+ *   Gamma_n^{ab} = 1/(R N) sum_r <T_n(H~) r | h~^{ab} r> / (1 + d_n0),
+ * h~^{ab} = [r^a, [r^b, H]] in eV nm^2 (Hermitian; bond vectors as for h~^a),
+ * |r> the random phases of kpm_moments_cond (same seed, same vectors).  Uses
+ * p->num_moments (>= 1), num_random, vector_seed, alpha, beta, precision;
+ * gamma_mode and max_batch are ignored (all vectors in one pass: three
+ * vectors of n_orbitals x R_padded complex values).  Output gamma1 [M][2]
+ * (re, im) FP64, host (out_on_device = 0) or device.  Errors: as
+ * kpm_moments_cond.
+ */
+int kpm_moments_gamma1(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma1, int32_t out_on_device,
+                       void* hip_stream);
+
 /* Timing and work of the last kpm_moments_cond call on the calling thread
  * (hipEvents on the call's stream). */
 typedef struct kpm_cond_stats_t {
@@ -306,7 +321,7 @@ int kpm_reconstruct_sigma(const double* gamma, int32_t M, const double* energies
  * inside [theta_mu, pi] (n_theta = 0: 4 M).
  * gamma [M][M][2] (re, im) as kpm_moments_cond writes it, energies_ev [K]
  * Fermi energies, sigma [K]; all host (on_device = 0) or all device pointers.
- * Allocates a device workspace of ~16 (Mp^2 + (n_theta + 64) Mp) bytes,
+ * Allocates a device workspace of ~16 (Mp^2 + 2 (n_theta + 64) Mp) bytes,
  * Mp = M rounded up to 64, and frees it before returning; synchronises
  * hip_stream.  Errors: KPM_E_INVALID (NULL, M outside [1, 16384], K < 1,
  * e_min >= e_max, eta <= 0, orbitals_per_nm2 <= 0, n_theta outside
@@ -315,6 +330,30 @@ int kpm_reconstruct_sigma(const double* gamma, int32_t M, const double* energies
 int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, const double* energies_ev, int32_t K, double e_min,
                                  double e_max, double eta_ev, double orbitals_per_nm2, int32_t n_theta, double* sigma,
                                  int32_t on_device, void* hip_stream);
+
+/*
+ * T = 0 optical conductivity sigma_ab(omega) in units of e^2/h at Fermi energy
+ * mu, from the rank-1 Gamma_n^{ab} (kpm_moments_gamma1) and the rank-2
+ * Gamma_nm^{a,b} (kpm_moments_cond) of the same lattice and directions
+ * (eq. conductivity_1st_order with the Lambda_n and Lambda_nm(omega) of the
+ * paper and f = theta(mu - eps)):
+ *   sigma(w) = (-2 pi i (N/Omega)/E_w) [ sum_n Gamma_n L_n + (1/de-) sum_nm Gamma_nm L_nm(w) ],
+ *   L_n = int_{-1}^{mu~} d eps Delta_n(eps),
+ *   L_nm(w) = int_{-1}^{mu~} d eps [g^R_n(eps + w~) Delta_m(eps) + Delta_n(eps) g^A_m(eps - w~)],
+ * E_w = hbar omega > 0 in eV (w~ = E_w/de-), g^{R,A} the CPGF coefficients at
+ * broadening eta; energy integrals as in kpm_reconstruct_sigma_bastin.
+ * gamma_nm [M][M][2], gamma_n [M][2], omegas_ev [K], sigma [K][2] (re, im);
+ * all host (on_device = 0) or all device pointers (the frequencies are copied
+ * to the host either way).  Work per frequency: two coefficient tables and
+ * one M x M x n_theta contraction.  Allocates and frees a device workspace;
+ * synchronises hip_stream.  Errors: KPM_E_INVALID (NULL, M outside
+ * [1, 16384], K outside [1, 65536], a frequency <= 0, e_min >= e_max,
+ * eta <= 0, orbitals_per_nm2 <= 0, n_theta outside [0, 2^20]); KPM_E_DEVICE.
+ */
+int kpm_reconstruct_sigma_optical(const double* gamma_nm, const double* gamma_n, int32_t M, const double* omegas_ev,
+                                  int32_t K, double mu_ev, double e_min, double e_max, double eta_ev,
+                                  double orbitals_per_nm2, int32_t n_theta, double* sigma, int32_t on_device,
+                                  void* hip_stream);
 
 /*
  * Moment-extrapolation MLP (the paper has no learned component: this is the

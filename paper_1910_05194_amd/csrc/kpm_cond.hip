@@ -248,7 +248,151 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   return st;
 }
 
+// Rank-1 tensor Gamma_n^{ab} = Tr[h~^{ab} T_n(H~)] / (N (1 + d_n0)) (paper eq.
+// Gammanm family, rank 1), h~^{ab} = [r^a, [r^b, H]] Hermitian, with the
+// stochastic trace: (1/(R N)) sum_r <T_n(H~) r | h~^{ab} r>.  u = h~^{ab} r comes
+// from one velocity-only launch of the step kernel (second-order weights);
+// the recursion then runs in place over two buffers and each step's dot
+// product <v_n | u> is summed per workgroup in FP64 and reduced in a fixed
+// order at the end.
+constexpr int kDotBlocks = 1024;
+
+template <typename T>
+__global__ void dot_partial_kernel(const T* __restrict__ v, const T* __restrict__ u, int64_t n_cplx,
+                                   double* __restrict__ part) {
+  __shared__ double sr[256], si[256];
+  double ar = 0.0, ai = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_cplx; i += (int64_t)gridDim.x * blockDim.x) {
+    const double vr = v[2 * i], vi = v[2 * i + 1], ur = u[2 * i], ui = u[2 * i + 1];
+    ar += vr * ur + vi * ui;   // conj(v) u
+    ai += vr * ui - vi * ur;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      sr[threadIdx.x] += sr[threadIdx.x + st];
+      si[threadIdx.x] += si[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sr[0];
+    part[2 * blockIdx.x + 1] = si[0];
+  }
+}
+
+__global__ void gamma1_finish_kernel(const double* part, int M, int R, const unsigned long long* active, double* out) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= M) return;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < kDotBlocks; ++b) {
+    re += part[((int64_t)n * kDotBlocks + b) * 2];
+    im += part[((int64_t)n * kDotBlocks + b) * 2 + 1];
+  }
+  const double sc = 1.0 / ((double)R * (double)active[0] * (n == 0 ? 2.0 : 1.0));
+  out[2 * n] = re * sc;
+  out[2 * n + 1] = im * sc;
+}
+
+static int gamma1_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* g1, int32_t on_dev,
+                      void* stream) {
+  KPM_CHECK_ARG(lat && p && g1, "NULL argument");
+  KPM_CHECK_ARG(p->num_moments >= 1, "num_moments must be >= 1");
+  KPM_CHECK_ARG(p->num_random >= 1, "num_random must be >= 1");
+  KPM_CHECK_ARG((p->alpha == 0 || p->alpha == 1) && (p->beta == 0 || p->beta == 1), "alpha, beta must be 0 (x) or 1 (y)");
+  KPM_CHECK_ARG(p->precision == KPM_FP32 || p->precision == KPM_FP64, "precision must be KPM_FP32 or KPM_FP64");
+  hipStream_t s = (hipStream_t)stream;
+  const int M = p->num_moments, R = p->num_random;
+  kpm_dos_params_t dp;
+  std::memset(&dp, 0, sizeof(dp));
+  dp.num_moments = std::max(2, M);
+  dp.num_random = R;
+  dp.vector_seed = p->vector_seed;
+  dp.precision = p->precision;
+  dp.start = KPM_START_RANDOM_PHASE;
+  kpm_tune_t tune;
+  std::memset(&tune, 0, sizeof(tune));
+  tune.use_graph = 0;
+  tune.kernel = 2;
+  kpm_plan* P = nullptr;
+  KPM_TRY(plan_create(lat, 1, &dp, &tune, &P));
+  const int64_t n_cplx = P->n_orb * P->Rp;
+  void* U = nullptr;
+  double *part = nullptr, *gdev = nullptr;
+  int st = KPM_OK;
+  hipError_t e = hipMalloc(&U, (size_t)n_cplx * 2 * P->tsize);
+  if (e == hipSuccess) e = hipMalloc(&part, (size_t)M * kDotBlocks * 2 * sizeof(double));
+  if (e == hipSuccess && !on_dev) e = hipMalloc(&gdev, (size_t)M * 2 * sizeof(double));
+  if (e == hipSuccess) st = plan_set_vector_base(P, 0);
+  if (e == hipSuccess && st == KPM_OK) e = plan_launch_prep(P, s);
+  auto dot = [&](const void* v, int n) {
+    if (P->prec == KPM_FP32)
+      hipLaunchKernelGGL(dot_partial_kernel<float>, dim3(kDotBlocks), dim3(256), 0, s, (const float*)v, (const float*)U,
+                         n_cplx, part + (int64_t)n * kDotBlocks * 2);
+    else
+      hipLaunchKernelGGL(dot_partial_kernel<double>, dim3(kDotBlocks), dim3(256), 0, s, (const double*)v,
+                         (const double*)U, n_cplx, part + (int64_t)n * kDotBlocks * 2);
+    return hipGetLastError();
+  };
+  if (e == hipSuccess && st == KPM_OK) {
+    // u = h~^{ab} xi (velocity-only launch: no output vector, no dots).
+    StepLaunch S;
+    S.v = P->X; S.out = P->Y; S.write_out = 0; S.read_w = 0; S.dots = 0; S.a = 0.0; S.b = 0.0;
+    S.velocity = true; S.vel = U; S.vdir = 2 + p->alpha + p->beta; S.vel_scale = 1.0;
+    e = plan_launch_step(P, s, S);
+  }
+  void* cur = P->X;
+  void* prev = P->Y;
+  for (int n = 0; n < M && e == hipSuccess && st == KPM_OK; ++n) {
+    if (n == 1) {
+      StepLaunch S;
+      S.v = P->X; S.out = P->Y; S.read_w = 0; S.a = 1.0; S.b = 0.0; S.dots = 0;
+      e = plan_launch_step(P, s, S);
+      cur = P->Y;
+      prev = P->X;
+    } else if (n >= 2) {
+      StepLaunch S;
+      S.v = cur; S.w = prev; S.out = prev; S.dots = 0;   // v_n over v_{n-2}, in place
+      e = plan_launch_step(P, s, S);
+      std::swap(cur, prev);
+    }
+    if (e == hipSuccess) e = dot(cur, n);
+  }
+  if (e == hipSuccess && st == KPM_OK) {
+    double* out = on_dev ? g1 : gdev;
+    hipLaunchKernelGGL(gamma1_finish_kernel, dim3((unsigned)ceil_div(M, 256)), dim3(256), 0, s, part, M, R, P->active,
+                       out);
+    e = hipGetLastError();
+    if (e == hipSuccess && !on_dev) e = hipMemcpyAsync(g1, gdev, (size_t)M * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  } else {
+    (void)hipStreamSynchronize(s);
+  }
+  if (e != hipSuccess && st == KPM_OK) {
+    set_error("kpm_moments_gamma1: %s", hipGetErrorString(e));
+    st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
+  }
+  for (void* ptr : {U, (void*)part, (void*)gdev})
+    if (ptr) (void)hipFree(ptr);
+  plan_free(P);
+  delete P;
+  return st;
+}
+
 }  // namespace kpm
+
+extern "C" int kpm_moments_gamma1(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma1,
+                                  int32_t out_on_device, void* hip_stream) {
+  try {
+    kpm::clear_error();
+    return kpm::gamma1_run(lat, p, gamma1, out_on_device, hip_stream);
+  } catch (...) {
+    kpm::set_error("internal error (exception) in kpm_moments_gamma1");
+    return KPM_E_DEVICE;
+  }
+}
 
 extern "C" int kpm_cond_last_stats(kpm_cond_stats_t* out) {
   if (!out) {

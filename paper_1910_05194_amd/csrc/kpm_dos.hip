@@ -95,7 +95,8 @@ struct LatDev {
   T onsite_const;       // -de+/de- (used when there is no per-site array)
   T hop;                // t/de-
   T blk[3][8];          // spin lattice: H_{A,B'} / de- for bond class k (2x2 complex, row-major), no phase
-  T vc[2][2][4];        // velocity: (r_i - r_j)_dir * de- for [dir][sublattice of i][neighbour k]
+  T vc[5][2][4];        // velocity weights for [dir][sublattice of i][neighbour k]: dir 0, 1 = x, y:
+                        // (r_i - r_j)_dir * de-; dir 2, 3, 4 = xx, xy, yy: the product of two components * de-
   T exch;               // spin lattice: Delta_ex / de- (+ on spin up, - on spin down)
 };
 
@@ -1322,18 +1323,30 @@ static void fill_latdev(kpm_plan* P, std::vector<LatDev<T>>& out) {
     d.exch = (T)(L.exchange / de_m);
     // Velocity [r^dir, H]_ij = (r_i - r_j)_dir H_ij; the kernel applies it to the
     // rescaled hop terms, hence the factor de-.
+    // The second-order operator [r^a, [r^b, H]]_ij = (r_i - r_j)_a (r_i - r_j)_b H_ij
+    // (eq. generalized velocity with two indices) uses the same stencil with
+    // the product of the two components (dir 2, 3, 4 = xx, xy, yy).
+    const int ab[3][2] = {{0, 0}, {0, 1}, {1, 1}};
     if (L.kind == KPM_SQUARE) {
       const double d_sq[4][2] = {{-kASq, 0.0}, {kASq, 0.0}, {0.0, -kASq}, {0.0, kASq}};
-      for (int dir = 0; dir < 2; ++dir)
-        for (int k = 0; k < 4; ++k) d.vc[dir][0][k] = (T)(d_sq[k][dir] * de_m);
+      for (int k = 0; k < 4; ++k) {
+        for (int dir = 0; dir < 2; ++dir) d.vc[dir][0][k] = (T)(d_sq[k][dir] * de_m);
+        for (int q = 0; q < 3; ++q) d.vc[2 + q][0][k] = (T)(d_sq[k][ab[q][0]] * d_sq[k][ab[q][1]] * de_m);
+      }
     } else {
-      for (int k = 0; k < 3; ++k)
+      for (int k = 0; k < 3; ++k) {
+        // d_k = r_A(n) - r_B(n + d_k): seen from A (+d_k) and from B (-d_k).
+        double dk[2];
         for (int dir = 0; dir < 2; ++dir) {
-          // d_k = r_A(n) - r_B(n + d_k): seen from A (+d_k) and from B (-d_k).
-          const double dk = g.tauA[dir] - (kBondD1[k] * g.a1[dir] + kBondD2[k] * g.a2[dir] + g.tauB[dir]);
-          d.vc[dir][0][k] = (T)(dk * de_m);
-          d.vc[dir][1][k] = (T)(-dk * de_m);
+          dk[dir] = g.tauA[dir] - (kBondD1[k] * g.a1[dir] + kBondD2[k] * g.a2[dir] + g.tauB[dir]);
+          d.vc[dir][0][k] = (T)(dk[dir] * de_m);
+          d.vc[dir][1][k] = (T)(-dk[dir] * de_m);
         }
+        for (int q = 0; q < 3; ++q) {
+          d.vc[2 + q][0][k] = (T)(dk[ab[q][0]] * dk[ab[q][1]] * de_m);
+          d.vc[2 + q][1][k] = d.vc[2 + q][0][k];
+        }
+      }
     }
     if (L.kind == KPM_HONEYCOMB_SPIN) {
       typedef std::complex<double> cd;

@@ -22,7 +22,8 @@ struct StepLaunch {
   int64_t blk_row = 0, blk_rows = 0;
   double a = 2.0, b = 1.0;     // v_{n+1} = a H~ v_n - b v_{n-1}
   double vel_scale = 1.0;
-  int read_w = 1, write_out = 1, dots = 1, vdir = 0;
+  int read_w = 1, write_out = 1, dots = 1;
+  int vdir = 0;                // velocity stencil: 0 x, 1 y ([r^a, H]); 2 xx, 3 xy, 4 yy ([r^a, [r^b, H]])
   double* part = nullptr;      // moment slots for this step (dots)
 };
 

@@ -17,6 +17,7 @@
 #include "kpm_internal.h"
 
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 namespace kpm {
@@ -295,35 +296,47 @@ namespace kpm {
 //   g'^R_n = -2 i w^n (i n / s^2 + z / s^3).
 // theta runs over Q equal cells of [0, pi] (midpoint rule); the cell holding
 // theta_mu counts with the part of it that lies in [theta_mu, pi].
-// Kernels: the g'^R table [Q][Mp]; the contraction on 64 x 64 (q, n) tiles
-// with FP64 partial sums per n tile; one workgroup per Fermi energy for the
-// weighted sum, all in a fixed order (deterministic).
+// Kernels: the g'^R and -g'^A tables [Q][Mp]; the contraction on 64 x 64
+// (q, n) tiles with FP64 partial sums per n tile; one workgroup per Fermi
+// energy for the weighted sum, all in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
 constexpr int kBT = 64;   // q and n tile
 constexpr int kBK = 8;    // m chunk
 
-__global__ void bastin_table_kernel(int Q, int M, int Mp, double eta, double2* gR) {
+// Table of CPGF coefficients at z_q = cos(theta_q) + shift + i eta (retarded
+// branch), for n < M (zero for M <= n < Mp): deriv = 0 gives g_n = -2 w^n/(w - z),
+// deriv = 1 gives d g_n/d eps; xform 0 stores the value, 1 its conjugate (the
+// advanced coefficient at the conjugate point), 2 minus its conjugate.
+__global__ void cpgf_table_kernel(int Q, int M, int Mp, double shift, double eta, int deriv, int xform,
+                                  double2* out) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= Q) return;
   const double th = (q + 0.5) * M_PI / Q;
-  const cplx z = {cos(th), eta};
+  const cplx z = {cos(th) + shift, eta};
   const cplx r = csqrt_p({z.re * z.re - z.im * z.im - 1.0, 2.0 * z.re * z.im});
   const cplx wp = {z.re + r.re, z.im + r.im}, wm = {z.re - r.re, z.im - r.im};
   const cplx outer = (hypot(wp.re, wp.im) >= hypot(wm.re, wm.im)) ? wp : wm;
   const cplx w = cdiv({1.0, 0.0}, outer);
-  const cplx s = {-(w.im - z.im), w.re - z.re};            // i (w - z)
+  const cplx s = {-(w.im - z.im), w.re - z.re};            // i (w - z) = sqrt(1 - z^2)
   const cplx s2 = cmul(s, s);
-  const cplx s3 = cmul(s2, s);
   const cplx inv_s2 = cdiv({1.0, 0.0}, s2);
-  const cplx zs3 = cdiv(z, s3);
+  const cplx zs3 = cdiv(z, cmul(s2, s));
+  const cplx m2_wz = cdiv({-2.0, 0.0}, {w.re - z.re, w.im - z.im});   // -2/(w - z)
   cplx pw = {1.0, 0.0};
-  double2* row = gR + (int64_t)q * Mp;
+  double2* row = out + (int64_t)q * Mp;
   for (int n = 0; n < Mp; ++n) {
     if (n < M) {
-      // -2 i w^n (i n / s^2 + z / s^3)
-      const cplx b = {-n * inv_s2.im + zs3.re, n * inv_s2.re + zs3.im};
-      const cplx c = cmul(pw, b);
-      row[n] = make_double2(2.0 * c.im, -2.0 * c.re);
+      cplx v;
+      if (deriv) {
+        // -2 i w^n (i n / s^2 + z / s^3)
+        const cplx c = cmul(pw, {-n * inv_s2.im + zs3.re, n * inv_s2.re + zs3.im});
+        v = {2.0 * c.im, -2.0 * c.re};
+      } else {
+        v = cmul(pw, m2_wz);
+      }
+      if (xform == 1) v.im = -v.im;
+      if (xform == 2) v.re = -v.re;
+      row[n] = make_double2(v.re, v.im);
       pw = cmul(pw, w);
     } else {
       row[n] = make_double2(0.0, 0.0);
@@ -331,11 +344,14 @@ __global__ void bastin_table_kernel(int Q, int M, int Mp, double eta, double2* g
   }
 }
 
-// gam: Gamma padded to [Mp][Mp] complex.  part[nt][q] = sum_{n in tile nt} D_n(theta_q) W_n(theta_q).
-__global__ void __launch_bounds__(256) bastin_contract_kernel(const double2* __restrict__ gR,
+// gam: Gamma padded to [Mp][Mp] complex.  W_n(theta_q) = sum_m (ta[q][m] Gamma_nm + tb[q][m] Gamma_mn);
+// part[nt][q] = sum_{n in tile nt} D_n(theta_q) W_n(theta_q).
+__global__ void __launch_bounds__(256) bastin_contract_kernel(const double2* __restrict__ ta,
+                                                              const double2* __restrict__ tb,
                                                               const double2* __restrict__ gam, int Q, int Mp,
                                                               double2* __restrict__ part) {
-  __shared__ double2 sg[kBT][kBK + 1];    // g'^R[q][m]
+  __shared__ double2 sa[kBT][kBK + 1];    // ta[q][m]
+  __shared__ double2 sb[kBT][kBK + 1];    // tb[q][m]
   __shared__ double2 sr[kBT][kBK + 1];    // Gamma[n][m]
   __shared__ double2 sc[kBK][kBT + 1];    // Gamma[m][n]
   __shared__ double2 red[16][kBT + 1];
@@ -351,7 +367,8 @@ __global__ void __launch_bounds__(256) bastin_contract_kernel(const double2* __r
     for (int e = threadIdx.x; e < kBT * kBK; e += 256) {
       const int a = e / kBK, b = e % kBK;
       const int q = q0 + a;
-      sg[a][b] = (q < Q) ? gR[(int64_t)q * Mp + m0 + b] : make_double2(0.0, 0.0);
+      sa[a][b] = (q < Q) ? ta[(int64_t)q * Mp + m0 + b] : make_double2(0.0, 0.0);
+      sb[a][b] = (q < Q) ? tb[(int64_t)q * Mp + m0 + b] : make_double2(0.0, 0.0);
       sr[a][b] = gam[(int64_t)(n0 + a) * Mp + m0 + b];
     }
     for (int e = threadIdx.x; e < kBT * kBK; e += 256) {
@@ -359,27 +376,27 @@ __global__ void __launch_bounds__(256) bastin_contract_kernel(const double2* __r
       sc[b][a] = gam[(int64_t)(m0 + b) * Mp + n0 + a];
     }
     __syncthreads();
-#pragma unroll 4
+#pragma unroll 2
     for (int k = 0; k < kBK; ++k) {
-      cplx g[4], r[4], c[4];
+      cplx ga[4], gb[4], r[4], c[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const double2 v = sg[tq * 4 + i][k];
-        g[i] = {v.x, v.y};
+        const double2 va = sa[tq * 4 + i][k], vb = sb[tq * 4 + i][k];
+        ga[i] = {va.x, va.y};
+        gb[i] = {vb.x, vb.y};
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const double2 a = sr[tn * 4 + j][k], b = sc[k][tn * 4 + j];
-        r[j] = {a.x, a.y};
-        c[j] = {b.x, b.y};
+        const double2 x = sr[tn * 4 + j][k], y = sc[k][tn * 4 + j];
+        r[j] = {x.x, x.y};
+        c[j] = {y.x, y.y};
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          // g Gamma_nm - conj(g) Gamma_mn
-          acc[i][j].re += g[i].re * r[j].re - g[i].im * r[j].im - (g[i].re * c[j].re + g[i].im * c[j].im);
-          acc[i][j].im += g[i].re * r[j].im + g[i].im * r[j].re - (g[i].re * c[j].im - g[i].im * c[j].re);
+          acc[i][j].re += ga[i].re * r[j].re - ga[i].im * r[j].im + gb[i].re * c[j].re - gb[i].im * c[j].im;
+          acc[i][j].im += ga[i].re * r[j].im + ga[i].im * r[j].re + gb[i].re * c[j].im + gb[i].im * c[j].re;
         }
     }
   }
@@ -467,7 +484,7 @@ extern "C" int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, cons
   const double de_m = 0.5 * (e_max - e_min);
   // Workspace: padded Gamma, the g'^R table, the partial sums, and staged host data.
   const size_t b_gam = sizeof(double2) * (size_t)Mp * Mp;
-  const size_t b_tab = sizeof(double2) * (size_t)Qp * Mp;
+  const size_t b_tab = 2 * sizeof(double2) * (size_t)Qp * Mp;
   const size_t b_part = sizeof(double2) * (size_t)n_tiles * Q;
   const size_t gn = (size_t)M * M * 2;
   const size_t b_host = on_device ? 0 : sizeof(double) * (gn + 2 * (size_t)K);
@@ -491,10 +508,14 @@ extern "C" int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, cons
   if (e == hipSuccess) {
     hipLaunchKernelGGL(pad_gamma_kernel, dim3((unsigned)ceil_div((int64_t)Mp * Mp, 256)), dim3(256), 0, s, dg, M, Mp,
                        gam);
-    // Table rows q >= Q stay unused (the contraction zero-fills them).
-    hipLaunchKernelGGL(bastin_table_kernel, dim3((unsigned)ceil_div(Q, 256)), dim3(256), 0, s, Q, M, Mp,
-                       eta_ev / de_m, tab);
-    hipLaunchKernelGGL(bastin_contract_kernel, dim3(Qp / kBT, n_tiles), dim3(256), 0, s, tab, gam, Q, Mp, part);
+    // Table rows q >= Q stay unused (the contraction zero-fills them).  ta = g'^R,
+    // tb = -g'^A = -conj(g'^R).
+    hipLaunchKernelGGL(cpgf_table_kernel, dim3((unsigned)ceil_div(Q, 256)), dim3(256), 0, s, Q, M, Mp, 0.0,
+                       eta_ev / de_m, 1, 0, tab);
+    hipLaunchKernelGGL(cpgf_table_kernel, dim3((unsigned)ceil_div(Q, 256)), dim3(256), 0, s, Q, M, Mp, 0.0,
+                       eta_ev / de_m, 1, 2, tab + (size_t)Qp * Mp);
+    hipLaunchKernelGGL(bastin_contract_kernel, dim3(Qp / kBT, n_tiles), dim3(256), 0, s, tab,
+                       tab + (size_t)Qp * Mp, gam, Q, Mp, part);
     // pref = -2 pi i (N/Omega)/de-^2 is imaginary: Re(pref F) = -Im(pref) Im(F).
     hipLaunchKernelGGL(bastin_sigma_kernel, dim3(K), dim3(256), 0, s, part, n_tiles, Q, den, K, e_min, e_max,
                        -2.0 * M_PI * orbitals_per_nm2 / (de_m * de_m), dsig);
@@ -507,6 +528,192 @@ extern "C" int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, cons
   (void)hipFree(ws);
   if (e != hipSuccess) {
     set_error("kpm_reconstruct_sigma_bastin: %s", hipGetErrorString(e));
+    return KPM_E_DEVICE;
+  }
+  return KPM_OK;
+}
+
+namespace kpm {
+
+// ---------------------------------------------------------------------------
+// Optical conductivity sigma_ab(omega) at T = 0 and Fermi energy mu (eq. cond
+// 1st order, rank-1 and rank-2 Gamma of eq. Gammanm, Lambda_n and
+// Lambda_nm(omega), combined as in eq. conductivity_1st_order):
+//   sigma(w)/(e^2/h) = (-2 pi i (N/Omega)/E_w) [ sum_n Gamma_n L_n + (1/de-) sum_nm Gamma_nm L_nm(w) ],
+//   L_n = int_{-1}^{mu~} Delta_n,  L_nm(w) = int_{-1}^{mu~} [g^R_n(eps + w~) Delta_m + Delta_n g^A_m(eps - w~)],
+// in theta with the quadrature of the Kubo-Bastin reconstruction.  The
+// rank-2 part is the same contraction with ta = g^A(eps - w~) and
+// tb = g^R(eps + w~): sum_n D_n sum_m (g^A_m Gamma_nm + g^R_m Gamma_mn).
+// ---------------------------------------------------------------------------
+__device__ inline double cell_weight(int q, int Q, double th_mu) {
+  const double h = M_PI / Q;
+  const double thq = (q + 0.5) * h;
+  const double lo = fmax(thq - 0.5 * h, th_mu);
+  return fmin(fmax(thq + 0.5 * h - lo, 0.0), h);
+}
+
+// out = sum_q w_q sum_n Gamma1_n D_n(theta_q) (one workgroup, fixed order).
+__global__ void optical_rank1_kernel(const double* g1, int M, int Q, double th_mu, double* out) {
+  __shared__ double sr[256], si[256];
+  double ar = 0.0, ai = 0.0;
+  for (int q = threadIdx.x; q < Q; q += blockDim.x) {
+    const double wq = cell_weight(q, Q, th_mu);
+    if (wq <= 0.0) continue;
+    const double th = (q + 0.5) * M_PI / Q;
+    double cr = 0.0, ci = 0.0;
+    for (int n = 0; n < M; ++n) {
+      const double d = 2.0 / M_PI * cos((double)n * th);
+      cr += d * g1[2 * n];
+      ci += d * g1[2 * n + 1];
+    }
+    ar += wq * cr;
+    ai += wq * ci;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      sr[threadIdx.x] += sr[threadIdx.x + st];
+      si[threadIdx.x] += si[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sr[0];
+    out[1] = si[0];
+  }
+}
+
+// para = sum_q w_q sum_t part[t][q] (one workgroup, fixed order).
+__global__ void optical_para_kernel(const double2* part, int n_tiles, int Q, double th_mu, double* para) {
+  __shared__ double sr[256], si[256];
+  double ar = 0.0, ai = 0.0;
+  for (int q = threadIdx.x; q < Q; q += blockDim.x) {
+    const double wq = cell_weight(q, Q, th_mu);
+    if (wq <= 0.0) continue;
+    double fr = 0.0, fi = 0.0;
+    for (int t = 0; t < n_tiles; ++t) {
+      fr += part[(int64_t)t * Q + q].x;
+      fi += part[(int64_t)t * Q + q].y;
+    }
+    ar += wq * fr;
+    ai += wq * fi;
+  }
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      sr[threadIdx.x] += sr[threadIdx.x + st];
+      si[threadIdx.x] += si[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    para[0] = sr[0];
+    para[1] = si[0];
+  }
+}
+
+// sigma[k] = -2 pi i (N/Omega)/E_k (lam + para_k / de-), stored (re, im).
+__global__ void optical_final_kernel(const double* para, const double* lam, const double* omegas, int K, double de_m,
+                                     double opn, double* sigma) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double xr = lam[0] + para[2 * k] / de_m, xi = lam[1] + para[2 * k + 1] / de_m;
+  const double c = 2.0 * M_PI * opn / omegas[k];
+  sigma[2 * k] = c * xi;        // -i (xr + i xi) = xi - i xr
+  sigma[2 * k + 1] = -c * xr;
+}
+
+}  // namespace kpm
+
+extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const double* gamma_n, int32_t M,
+                                             const double* omegas_ev, int32_t K, double mu_ev, double e_min,
+                                             double e_max, double eta_ev, double orbitals_per_nm2, int32_t n_theta,
+                                             double* sigma, int32_t on_device, void* hip_stream) {
+  using namespace kpm;
+  clear_error();
+  KPM_CHECK_ARG(gamma_nm && gamma_n && omegas_ev && sigma, "NULL argument");
+  KPM_CHECK_ARG(M >= 1 && M <= 16384 && K >= 1 && K <= 65536, "need 1 <= M <= 16384 and 1 <= K <= 65536");
+  KPM_CHECK_ARG(std::isfinite(e_min) && std::isfinite(e_max) && e_min < e_max, "need e_min < e_max");
+  KPM_CHECK_ARG(std::isfinite(mu_ev), "mu must be finite");
+  KPM_CHECK_ARG(eta_ev > 0.0 && std::isfinite(eta_ev), "eta must be > 0");
+  KPM_CHECK_ARG(orbitals_per_nm2 > 0.0, "orbitals_per_nm2 must be > 0");
+  KPM_CHECK_ARG(n_theta >= 0 && n_theta <= (1 << 20), "n_theta must be in [0, 2^20]");
+  hipStream_t s = (hipStream_t)hip_stream;
+  // The frequencies set the table shifts: they are needed on the host.
+  std::vector<double> om((size_t)K);
+  if (on_device) {
+    KPM_TRY_HIP(hipMemcpyAsync(om.data(), omegas_ev, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    KPM_TRY_HIP(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(om.data(), omegas_ev, sizeof(double) * K);
+  }
+  for (double w : om) KPM_CHECK_ARG(w > 0.0 && std::isfinite(w), "every frequency must be > 0 (hbar omega in eV)");
+  const int Q = n_theta > 0 ? n_theta : 4 * M;
+  const int Mp = (int)ceil_div(M, kBT) * kBT;
+  const int Qp = (int)ceil_div(Q, kBT) * kBT;
+  const int n_tiles = Mp / kBT;
+  const double de_p = 0.5 * (e_max + e_min), de_m = 0.5 * (e_max - e_min);
+  const double mut = (mu_ev - de_p) / de_m;
+  const double th_mu = mut >= 1.0 ? 0.0 : (mut <= -1.0 ? M_PI : std::acos(mut));
+  const size_t b_gam = sizeof(double2) * (size_t)Mp * Mp;
+  const size_t b_tab = 2 * sizeof(double2) * (size_t)Qp * Mp;
+  const size_t b_part = sizeof(double2) * (size_t)n_tiles * Q;
+  const size_t b_small = sizeof(double) * (2 * (size_t)K + 2);
+  const size_t gn = (size_t)M * M * 2;
+  const size_t b_host = on_device ? 0 : sizeof(double) * (gn + 2 * (size_t)M + (size_t)K + 2 * (size_t)K);
+  char* ws = nullptr;
+  KPM_TRY_HIP(hipMalloc(&ws, b_gam + b_tab + b_part + b_small + b_host));
+  double2* gam = (double2*)ws;
+  double2* ta = (double2*)(ws + b_gam);
+  double2* tb = ta + (size_t)Qp * Mp;
+  double2* part = (double2*)(ws + b_gam + b_tab);
+  double* para = (double*)(ws + b_gam + b_tab + b_part);
+  double* lam = para + 2 * (size_t)K;
+  const double* dgnm = gamma_nm;
+  const double* dgn = gamma_n;
+  const double* dom = omegas_ev;
+  double* dsig = sigma;
+  hipError_t e = hipSuccess;
+  if (!on_device) {
+    double* h = (double*)(ws + b_gam + b_tab + b_part + b_small);
+    e = hipMemcpyAsync(h, gamma_nm, sizeof(double) * gn, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + gn, gamma_n, sizeof(double) * 2 * M, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + gn + 2 * M, omegas_ev, sizeof(double) * K, hipMemcpyHostToDevice, s);
+    dgnm = h;
+    dgn = h + gn;
+    dom = h + gn + 2 * M;
+    dsig = h + gn + 2 * M + K;
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(pad_gamma_kernel, dim3((unsigned)ceil_div((int64_t)Mp * Mp, 256)), dim3(256), 0, s, dgnm, M,
+                       Mp, gam);
+    hipLaunchKernelGGL(optical_rank1_kernel, dim3(1), dim3(256), 0, s, dgn, M, Q, th_mu, lam);
+    const double eta = eta_ev / de_m;
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+      const double wt = om[k] / de_m;
+      hipLaunchKernelGGL(cpgf_table_kernel, dim3((unsigned)ceil_div(Q, 256)), dim3(256), 0, s, Q, M, Mp, -wt, eta, 0,
+                         1, ta);   // g^A(eps - w~) = conj(g^R(eps - w~ + i eta))
+      hipLaunchKernelGGL(cpgf_table_kernel, dim3((unsigned)ceil_div(Q, 256)), dim3(256), 0, s, Q, M, Mp, wt, eta, 0, 0,
+                         tb);   // g^R(eps + w~)
+      hipLaunchKernelGGL(bastin_contract_kernel, dim3(Qp / kBT, n_tiles), dim3(256), 0, s, ta, tb, gam, Q, Mp, part);
+      hipLaunchKernelGGL(optical_para_kernel, dim3(1), dim3(256), 0, s, part, n_tiles, Q, th_mu, para + 2 * k);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(optical_final_kernel, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, para, lam, dom, K,
+                         de_m, orbitals_per_nm2, dsig);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(sigma, dsig, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(ws);
+  if (e != hipSuccess) {
+    set_error("kpm_reconstruct_sigma_optical: %s", hipGetErrorString(e));
     return KPM_E_DEVICE;
   }
   return KPM_OK;

@@ -106,6 +106,10 @@ def _load():
         "kpm_reconstruct_sigma_bastin": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
                                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                                         ctypes.c_int32, _P, ctypes.c_int32, _P]),
+        "kpm_reconstruct_sigma_optical": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32,
+                                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P,
+                                                         ctypes.c_int32, _P]),
         "kpm_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                           ctypes.POINTER(_P)]),
         "kpm_mlp_destroy": (ctypes.c_int, [_P]),
@@ -117,6 +121,8 @@ def _load():
         "kpm_mlp_gradients": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P, _D, _P]),
         "kpm_mlp_fit_scaling": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P]),
         "kpm_cond_last_stats": (ctypes.c_int, [ctypes.POINTER(c_cond_stats)]),
+        "kpm_moments_gamma1": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.POINTER(c_cond_params), _P,
+                                              ctypes.c_int32, _P]),
         "kpm_autotune": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, ctypes.POINTER(c_dos_params),
                                         ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(c_tune), _D, _P]),
         "kpm_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -363,6 +369,24 @@ def moments_cond(lattice, par, precision: int = FP32, max_batch: int = 0, out_de
     return g
 
 
+def moments_gamma1(lattice, par, precision: int = FP32, out_device=None, stream=None):
+    """kpm_moments_gamma1: Gamma_n^{ab} as a complex array [M] (numpy) or a float64 [M, 2] torch tensor."""
+    lat = c_lattices([lattice])
+    p = c_cond_params(int(par.num_moments), int(par.num_random), int(par.vector_seed) & (2**64 - 1),
+                      int(par.alpha), int(par.beta), int(par.gamma_mode), int(precision), 0)
+    M = int(par.num_moments)
+    if out_device is None:
+        g = np.zeros((M, 2))
+        _check(LIB.kpm_moments_gamma1(lat, ctypes.byref(p), g.ctypes.data, 0, _stream_handle(stream)))
+        return g[:, 0] + 1j * g[:, 1]
+    import torch
+    g = torch.zeros((M, 2), dtype=torch.float64, device=out_device)
+    if stream is None:
+        stream = torch.cuda.current_stream(g.device)
+    _check(LIB.kpm_moments_gamma1(lat, ctypes.byref(p), g.data_ptr(), 1, _stream_handle(stream)))
+    return g
+
+
 def cond_last_stats() -> dict:
     """kpm_cond_last_stats of the calling thread."""
     st = c_cond_stats()
@@ -415,6 +439,34 @@ def reconstruct_sigma_bastin(gamma, energies, e_min: float, e_max: float, eta: f
     _check(LIB.kpm_reconstruct_sigma_bastin(g.data_ptr(), g.shape[0], en.data_ptr(), en.numel(), float(e_min),
                                             float(e_max), float(eta), float(orbitals_per_nm2), int(n_theta),
                                             out.data_ptr(), 1, _stream_handle(stream)))
+    return out
+
+
+def reconstruct_sigma_optical(gamma_nm, gamma_n, omegas, mu: float, e_min: float, e_max: float, eta: float,
+                              orbitals_per_nm2: float, n_theta: int = 0, stream=None):
+    """kpm_reconstruct_sigma_optical: complex sigma_ab(omega) in e^2/h (T = 0, Fermi energy mu in eV) from
+    the rank-2 and rank-1 Gamma (numpy complex [M, M] and [M], or float64 torch [M, M, 2] and [M, 2])."""
+    if isinstance(gamma_nm, np.ndarray):
+        g2 = np.ascontiguousarray(np.stack([gamma_nm.real, gamma_nm.imag], axis=-1), dtype=np.float64)
+        g1 = np.ascontiguousarray(np.stack([np.real(gamma_n), np.imag(gamma_n)], axis=-1), dtype=np.float64)
+        om = np.ascontiguousarray(np.atleast_1d(omegas), dtype=np.float64)
+        out = np.zeros((om.size, 2))
+        _check(LIB.kpm_reconstruct_sigma_optical(g2.ctypes.data, g1.ctypes.data, g2.shape[0], om.ctypes.data, om.size,
+                                                 float(mu), float(e_min), float(e_max), float(eta),
+                                                 float(orbitals_per_nm2), int(n_theta), out.ctypes.data, 0,
+                                                 _stream_handle(stream)))
+        return out[:, 0] + 1j * out[:, 1]
+    import torch
+    g2 = gamma_nm.contiguous()
+    g1 = gamma_n.contiguous()
+    om = omegas.contiguous().to(torch.float64)
+    out = torch.zeros((om.numel(), 2), dtype=torch.float64, device=g2.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(g2.device)
+    _check(LIB.kpm_reconstruct_sigma_optical(g2.data_ptr(), g1.data_ptr(), g2.shape[0], om.data_ptr(), om.numel(),
+                                             float(mu), float(e_min), float(e_max), float(eta),
+                                             float(orbitals_per_nm2), int(n_theta), out.data_ptr(), 1,
+                                             _stream_handle(stream)))
     return out
 
 
