@@ -480,3 +480,82 @@ def _bloch2(lat, k, a: int, b: int):
                 Hm[i, j] += w * hop * ph
                 Hm[j, i] += np.conj(w * hop * ph)
     return Hm
+
+
+# ---------------------------------------------------------------------------
+# Single-shot Fermi-surface DC conductivity (Sec. 3(b) large-scale section:
+# the 'single-shot' evaluation that avoids the double recursion of eq.
+# Gammanm).  Reading used: the T = 0 Kubo-Greenwood conductivity with the
+# Lorentzian-broadened delta function of the CPGF resolvent,
+#   sigma_ab(E)/(e^2/h) = -2 pi^2 (1/Omega) Tr[h~^a d_eta(E-H) h~^b d_eta(E-H)],
+#   d_eta(E-H) = -(1/pi) Im G^R(E + i eta) = (1/de-) sum_n c_n(E) T_n(H~)/(1+d_n0),
+#   c_n(E) = -Im g_n(z~)/pi (eq. green_function_cheb_expansionb, z~ = eps + i eta~),
+# with the stochastic trace: for each random vector r,
+#   a = d_eta h~^a r,  b = h~^b d_eta r,  Tr[...] ~ -(1/R) sum_r <a|b>
+# (h~^a is anti-Hermitian), i.e. two Chebyshev recursions per vector that
+# serve every energy (O(K M N) work for K energies).
+# ---------------------------------------------------------------------------
+
+def singleshot_coefficients(M: int, energies_ev, e_min: float, e_max: float, eta_ev: float) -> np.ndarray:
+    """c_n(E_k) / (de- (1 + d_n0)): the expansion of d_eta(E - H) in T_n(H~).  [K, M]."""
+    d_plus, d_minus = (e_max + e_min) / 2.0, (e_max - e_min) / 2.0
+    z = (np.atleast_1d(np.asarray(energies_ev, dtype=np.float64)) - d_plus) / d_minus + 1j * eta_ev / d_minus
+    c = -np.imag(cpgf_coefficients(M, z, +1)) / np.pi / d_minus
+    c[:, 0] /= 2.0
+    return c
+
+
+def sigma_singleshot(model: lattice.Model, e_min: float, e_max: float, energies_ev, eta_ev: float, M: int,
+                     vectors: np.ndarray, a: int = 0, b: int = 0) -> np.ndarray:
+    """Single-shot sigma_ab(E) in e^2/h with the given start vectors [R, N] (formula above)."""
+    Ht = kpm.rescale(model.H, e_min, e_max)
+    C = singleshot_coefficients(M, energies_ev, e_min, e_max, eta_ev)      # [K, M]
+    K = C.shape[0]
+    R = vectors.shape[0]
+    ha, hb = velocity(model, a), velocity(model, b)
+    acc = np.zeros(K)
+    for r in range(R):
+        xi = vectors[r]
+        A = np.zeros((K, xi.size), dtype=complex)
+        for n, vn in enumerate(kpm.chebyshev_vectors(Ht, ha @ xi, M)):
+            A += C[:, n][:, None] * vn[None, :]
+        Bd = np.zeros((K, xi.size), dtype=complex)
+        for n, vn in enumerate(kpm.chebyshev_vectors(Ht, xi, M)):
+            Bd += C[:, n][:, None] * vn[None, :]
+        for k in range(K):
+            acc[k] += np.real(np.vdot(A[k], hb @ Bd[k]))
+    n_cells = model.site_active.size // model.n_sub
+    return 2.0 * np.pi ** 2 / (n_cells * model.cell_area) * acc / R
+
+
+def sigma_kubo_greenwood_eigen(model: lattice.Model, energies_ev, eta_ev: float, a: int = 0, b: int = 0) -> np.ndarray:
+    """-2 pi^2 (1/Omega) sum_ab (h~^a)_ab d_eta(E - E_b) (h~^b)_ba d_eta(E - E_a) on the eigenstates,
+    d_eta(x) = eta / (pi (x^2 + eta^2)): the definition the single-shot series converges to."""
+    E, U = _eigen(model)
+    A = U.conj().T @ velocity(model, a).toarray() @ U
+    B = U.conj().T @ velocity(model, b).toarray() @ U
+    P = A * B.T
+    n_cells = model.site_active.size // model.n_sub
+    out = []
+    for e in np.atleast_1d(np.asarray(energies_ev, dtype=np.float64)):
+        dl = eta_ev / (np.pi * ((e - E) ** 2 + eta_ev ** 2))
+        out.append(float(np.real(-2.0 * np.pi ** 2 / (n_cells * model.cell_area) * np.sum(P * dl[None, :] * dl[:, None]))))
+    return np.array(out)
+
+
+def sigma_kubo_greenwood_kgrid(lat, energies_ev, eta_ev: float, a: int = 0, b: int = 0) -> np.ndarray:
+    """sigma_kubo_greenwood_eigen for the clean L1 x L2 torus from its Bloch states."""
+    b1, b2, area = _recip(lat)
+    m1, m2 = np.meshgrid(np.arange(lat.L1), np.arange(lat.L2), indexing="ij")
+    kall = np.outer(m1.ravel() / lat.L1, b1) + np.outer(m2.ravel() / lat.L2, b2)
+    Es = np.atleast_1d(np.asarray(energies_ev, dtype=np.float64))
+    tot = np.zeros(Es.size)
+    for c0 in range(0, kall.shape[0], 20000):
+        H, Ha, Hb, _ = _bloch_many(lat, kall[c0:c0 + 20000], a, b)
+        E, U = np.linalg.eigh(H)
+        Uh = np.conj(np.swapaxes(U, 1, 2))
+        P = (Uh @ Ha @ U) * np.swapaxes(Uh @ Hb @ U, 1, 2)
+        for i, e in enumerate(Es):
+            dl = eta_ev / (np.pi * ((e - E) ** 2 + eta_ev ** 2))
+            tot[i] += np.real(np.sum(P * dl[:, None, :] * dl[:, :, None]))
+    return -2.0 * np.pi ** 2 / (lat.L1 * lat.L2 * area) * tot

@@ -311,3 +311,55 @@ def test_optical_spectral_converges_to_eigenstate_definition():
                                cond.gamma_n_exact(m, lat.e_min, lat.e_max, M, *ab), W, 0.1, lat.e_min, lat.e_max,
                                0.1, opn, 2 * M)
         assert np.max(np.abs(s - ex) / np.abs(ex)) < tol, (ab, s, ex)
+
+
+# --- Single-shot Fermi-surface DC conductivity --------------------------------
+
+def test_singleshot_equals_gamma_contraction_for_the_same_vectors():
+    """With the same random vectors and M, the single-shot sums equal the rank-2
+    Gamma route with the weights c_n c_m (an algebraic identity: <a|b> =
+    -N de-^2 sum_nm c_n c_m Gamma_nm(1+d_n0)(1+d_m0)/de-^2 ...), here checked
+    numerically on a disordered QAHE model with a vacancy, xx and xy."""
+    lat = _qahe(3, W=1.5, seed=3).replace(vacancy_p=0.1, disorder_seed=5)
+    m = lattice.build(lat)
+    M, R = 24, 2
+    vecs = kpm.random_phase_vectors(m, R, 11, 0)
+    E = np.array([-2.0, 0.0, 0.7])
+    Ht = kpm.rescale(m.H, lat.e_min, lat.e_max)
+    C = cond.singleshot_coefficients(M, E, lat.e_min, lat.e_max, 0.2)     # includes 1/(de-(1+d_n0))
+    omega = 9 * m.cell_area
+    for ab in ((0, 0), (0, 1)):
+        ss = cond.sigma_singleshot(m, lat.e_min, lat.e_max, E, 0.2, M, vecs, *ab)
+        G = cond.gamma_nm(Ht, cond.velocity(m, ab[0]), cond.velocity(m, ab[1]), vecs, M)   # /(R N (1+d)(1+d))
+        w = C * np.where(np.arange(M) == 0, 2.0, 1.0)[None, :]                              # c_n / de-
+        via_g = -2 * np.pi ** 2 / omega * m.n_active * np.real(np.einsum("kn,nm,km->k", w, G, w))
+        assert np.max(np.abs(ss - via_g)) < 1e-10 * np.max(np.abs(ss)), (ab, ss, via_g)
+
+
+def test_singleshot_converges_to_lorentzian_kubo_greenwood():
+    """Exact trace (scaled basis vectors) at M = 2048, eta = 0.2 eV on the disordered
+    4 x 4 QAHE model: the single-shot series equals the eigenstate formula with
+    Lorentzian deltas to 1e-6 relative (the CPGF series of a Lorentzian converges
+    exponentially for eta > 0)."""
+    lat = _qahe(4, W=1.0, seed=9)
+    m = lattice.build(lat)
+    vecs = np.sqrt(m.n_active) * np.eye(m.n_active, dtype=complex)
+    E = np.array([-1.5, 0.1, 0.9])
+    ss = cond.sigma_singleshot(m, lat.e_min, lat.e_max, E, 0.2, 2048, vecs, 0, 0)
+    ex = cond.sigma_kubo_greenwood_eigen(m, E, 0.2)
+    assert np.max(np.abs(ss - ex) / np.abs(ex)) < 1e-6, (ss, ex)
+
+
+def test_kubo_greenwood_real_space_equals_k_space_and_graphene_minimum():
+    """Real-space eigenstate Kubo-Greenwood = Bloch-state sum (6 x 6 graphene); clean
+    spinless graphene at the Dirac point gives the universal minimum 2/pi e^2/h
+    (4 e^2/(pi h) with spin and valley), independent of eta: 600^2 grid, eta = 0.05
+    and 0.1 eV, within 0.3 %."""
+    lat = wl.Lattice(kind=wl.HONEYCOMB, L1=6, L2=6, t=T_HOP, e_min=-9, e_max=9)
+    a = cond.sigma_kubo_greenwood_eigen(lattice.build(lat), [0.3, 1.0], 0.2)
+    b = cond.sigma_kubo_greenwood_kgrid(lat, [0.3, 1.0], 0.2)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+    big = wl.Lattice(kind=wl.HONEYCOMB, L1=600, L2=600, t=T_HOP, e_min=-9, e_max=9)
+    for eta in (0.05, 0.1):
+        s0 = cond.sigma_kubo_greenwood_kgrid(big, [0.0], eta)[0]
+        assert abs(s0 - 2 / np.pi) < 0.003 * (2 / np.pi), (eta, s0)
