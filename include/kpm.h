@@ -280,6 +280,25 @@ int kpm_moments_cond(const kpm_lattice_t* lat, const kpm_cond_params_t* p, doubl
 int kpm_moments_gamma1(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma1, int32_t out_on_device,
                        void* hip_stream);
 
+/*
+ * Single-shot Fermi-surface DC conductivity (the paper's 'single-shot'
+ * algorithm, Sec. 3(b): no double recursion), T = 0, in units of e^2/h:
+ *   sigma_ab(E) = -2 pi^2 (1/Omega) Tr[h~^a d_eta(E-H) h~^b d_eta(E-H)],
+ *   d_eta(E - H) = -(1/pi) Im G^R(E + i eta) = sum_n c_n(E) T_n(H~),
+ *   c_n = -Im g_n(z~) / (pi de- (1 + d_n0))  (eq. green_function_cheb_expansionb),
+ * Omega = L1 L2 * cell area, with the stochastic trace over the random phases
+ * of kpm_moments_cond (same seed, same vectors): -(1/R) sum_r <a|b>,
+ * a = d_eta h~^a r, b = h~^b d_eta r.  Two Chebyshev recursions per vector of
+ * p->num_moments steps serve all K energies (2 K accumulator vectors; the
+ * energies are batched to fit the free device memory).  Uses num_moments
+ * (>= 2), num_random, vector_seed, alpha, beta, precision.  energies_ev [K]
+ * (1 <= K <= 4096), sigma [K]: both host (on_device = 0) or both device.
+ * Errors: as kpm_moments_cond; KPM_E_INVALID also for eta <= 0; KPM_E_NOMEM
+ * when not even one energy's accumulators fit.
+ */
+int kpm_sigma_singleshot(const kpm_lattice_t* lat, const kpm_cond_params_t* p, const double* energies_ev, int32_t K,
+                         double eta_ev, double* sigma, int32_t out_on_device, void* hip_stream);
+
 /* Timing and work of the last kpm_moments_cond call on the calling thread
  * (hipEvents on the call's stream). */
 typedef struct kpm_cond_stats_t {

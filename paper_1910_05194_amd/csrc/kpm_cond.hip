@@ -17,7 +17,10 @@
 #include "kpm_plan.h"
 
 #include <algorithm>
+#include <cmath>
+#include <complex>
 #include <cstring>
+#include <vector>
 
 namespace kpm {
 
@@ -381,7 +384,215 @@ static int gamma1_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, doub
   return st;
 }
 
+// ---------------------------------------------------------------------------
+// Single-shot Fermi-surface DC conductivity (the paper's 'single-shot'
+// algorithm, Sec. 3(b), which avoids the double recursion of eq. Gammanm):
+//   sigma_ab(E)/(e^2/h) = -2 pi^2 (1/Omega) Tr[h~^a d_eta(E-H) h~^b d_eta(E-H)],
+//   d_eta(E - H) = sum_n c_n(E) T_n(H~),  c_n = -Im g_n(z~)/(pi de- (1 + d_n0))
+// (CPGF coefficients of eq. green_function_cheb_expansionb at z~ = eps + i eta~),
+// with the stochastic trace -(1/R) sum_r <a|b>, a = d_eta h~^a r, b = h~^b d_eta r.
+// Two recursions per vector serve every energy: the accumulators
+// A_k = sum_n c_n(E_k) T_n(H~) h~^a r and B_k = sum_n c_n(E_k) T_n(H~) r are
+// updated after each step by one kernel that reads the new vector once.
+// Energies are processed in batches sized to the free device memory.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void accumulate_kernel(const T* __restrict__ v, T* __restrict__ acc, int64_t n_elems, int64_t stride,
+                                  const double* __restrict__ coef, int K) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_elems; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = (double)v[i];
+    for (int k = 0; k < K; ++k) acc[k * stride + i] = (T)((double)acc[k * stride + i] + coef[k] * x);
+  }
+}
+
+template <typename T>
+__global__ void zero_kernel(T* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (T)0;
+}
+
+__global__ void singleshot_finish_kernel(const double* part, int K, double scale, double* sigma) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double re = 0.0;
+  for (int b = 0; b < kDotBlocks; ++b) re += part[((int64_t)k * kDotBlocks + b) * 2];
+  sigma[k] = scale * re;
+}
+
+static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, const double* energies_ev, int32_t K,
+                          double eta_ev, double* sigma, int32_t on_dev, void* stream) {
+  KPM_CHECK_ARG(lat && p && energies_ev && sigma, "NULL argument");
+  KPM_CHECK_ARG(p->num_moments >= 2, "num_moments must be >= 2");
+  KPM_CHECK_ARG(p->num_random >= 1, "num_random must be >= 1");
+  KPM_CHECK_ARG(K >= 1 && K <= 4096, "need 1 <= K <= 4096 energies");
+  KPM_CHECK_ARG(eta_ev > 0.0 && std::isfinite(eta_ev), "eta must be > 0");
+  KPM_CHECK_ARG((p->alpha == 0 || p->alpha == 1) && (p->beta == 0 || p->beta == 1), "alpha, beta must be 0 (x) or 1 (y)");
+  KPM_CHECK_ARG(p->precision == KPM_FP32 || p->precision == KPM_FP64, "precision must be KPM_FP32 or KPM_FP64");
+  hipStream_t s = (hipStream_t)stream;
+  const int M = p->num_moments, R = p->num_random;
+  std::vector<double> en((size_t)K);
+  if (on_dev) {
+    KPM_TRY_HIP(hipMemcpyAsync(en.data(), energies_ev, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    KPM_TRY_HIP(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(en.data(), energies_ev, sizeof(double) * K);
+  }
+  // Coefficients c_n(E_k) (host, FP64): g_n(z) = -2i w^n / sqrt(1 - z^2), w = exp(-i arccos z)
+  // the root of w^2 - 2 z w + 1 inside the unit circle, sqrt(1 - z^2) = i (w - z).
+  const double de_p = 0.5 * (lat->e_max + lat->e_min), de_m = 0.5 * (lat->e_max - lat->e_min);
+  std::vector<double> coef((size_t)K * M);
+  for (int k = 0; k < K; ++k) {
+    typedef std::complex<double> cd;
+    const cd z((en[k] - de_p) / de_m, eta_ev / de_m);
+    const cd r = std::sqrt(z * z - 1.0);
+    const cd outer = std::abs(z + r) >= std::abs(z - r) ? z + r : z - r;
+    const cd w = 1.0 / outer;
+    const cd pre = -2.0 / (w - z);   // g_n = pre w^n
+    cd pw(1.0, 0.0);
+    for (int n = 0; n < M; ++n) {
+      coef[(size_t)n * K + k] = -std::imag(pre * pw) / (M_PI * de_m) / (n == 0 ? 2.0 : 1.0);
+      pw *= w;
+    }
+  }
+  kpm_dos_params_t dp;
+  std::memset(&dp, 0, sizeof(dp));
+  dp.num_moments = M;
+  dp.num_random = R;
+  dp.vector_seed = p->vector_seed;
+  dp.precision = p->precision;
+  dp.start = KPM_START_RANDOM_PHASE;
+  kpm_tune_t tune;
+  std::memset(&tune, 0, sizeof(tune));
+  tune.use_graph = 0;
+  tune.kernel = 2;
+  kpm_plan* P = nullptr;
+  KPM_TRY(plan_create(lat, 1, &dp, &tune, &P));
+  const int64_t n_elems = P->n_orb * P->Rp * 2;
+  const size_t vec_b = (size_t)n_elems * P->tsize;
+  size_t free_b = 0, total_b = 0;
+  int st = KPM_OK;
+  hipError_t e = hipMemGetInfo(&free_b, &total_b);
+  // Energies per batch: 2 accumulators each, plus the start copy and a scratch vector.
+  int kb = (int)std::min<double>(K, std::floor((0.85 * (double)free_b - 2.0 * vec_b - 1.0e9) / (2.0 * vec_b)));
+  if (e == hipSuccess && kb < 1) {
+    set_error("not enough device memory for the single-shot accumulators (%.1f GB per energy)", 2.0 * vec_b / 1e9);
+    plan_free(P);
+    delete P;
+    return KPM_E_NOMEM;
+  }
+  void *V0 = nullptr, *Sc = nullptr, *acc = nullptr;
+  double *dcoef = nullptr, *part = nullptr, *dsig = nullptr;
+  if (e == hipSuccess) e = hipMalloc(&V0, vec_b);
+  if (e == hipSuccess) e = hipMalloc(&Sc, vec_b);
+  if (e == hipSuccess) e = hipMalloc(&acc, 2 * vec_b * (size_t)kb);
+  if (e == hipSuccess) e = hipMalloc(&dcoef, sizeof(double) * coef.size());
+  if (e == hipSuccess) e = hipMalloc(&part, sizeof(double) * 2 * kDotBlocks * (size_t)K);
+  if (e == hipSuccess) e = hipMalloc(&dsig, sizeof(double) * K);
+  if (e == hipSuccess) e = hipMemcpyAsync(dcoef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) st = plan_set_vector_base(P, 0);
+  const bool f32 = P->prec == KPM_FP32;
+  const dim3 eg(2048), eb(256);
+  // acc_k += c_n(E_k0 + k) v over kk energies (coefficients of step n at coef + n K + k0).
+  auto accumulate = [&](const void* v, void* A, int n, int k0, int kk) {
+    if (f32)
+      hipLaunchKernelGGL(accumulate_kernel<float>, eg, eb, 0, s, (const float*)v, (float*)A, n_elems, n_elems,
+                         dcoef + (size_t)n * K + k0, kk);
+    else
+      hipLaunchKernelGGL(accumulate_kernel<double>, eg, eb, 0, s, (const double*)v, (double*)A, n_elems, n_elems,
+                         dcoef + (size_t)n * K + k0, kk);
+    return hipGetLastError();
+  };
+  // One recursion from x0 (overwritten), accumulating every step into A.
+  auto chain = [&](void* x0, void* A, int k0, int kk) {
+    hipError_t er = accumulate(x0, A, 0, k0, kk);
+    void* cur = x0;
+    void* prev = Sc;
+    for (int n = 1; n < M && er == hipSuccess; ++n) {
+      StepLaunch S;
+      S.dots = 0;
+      if (n == 1) {
+        S.v = x0; S.out = Sc; S.read_w = 0; S.a = 1.0; S.b = 0.0;
+        er = plan_launch_step(P, s, S);
+        cur = Sc;
+        prev = x0;
+      } else {
+        S.v = cur; S.w = prev; S.out = prev;
+        er = plan_launch_step(P, s, S);
+        std::swap(cur, prev);
+      }
+      if (er == hipSuccess) er = accumulate(cur, A, n, k0, kk);
+    }
+    return er;
+  };
+  for (int k0 = 0; k0 < K && e == hipSuccess && st == KPM_OK; k0 += kb) {
+    const int kk = std::min(kb, K - k0);
+    char* Ab = (char*)acc;
+    char* Bb = (char*)acc + vec_b * (size_t)kb;
+    if (f32)
+      hipLaunchKernelGGL(zero_kernel<float>, eg, eb, 0, s, (float*)acc, 2 * n_elems * (int64_t)kb);
+    else
+      hipLaunchKernelGGL(zero_kernel<double>, eg, eb, 0, s, (double*)acc, 2 * n_elems * (int64_t)kb);
+    // r into X; x0 = h~^a r into V0 (velocity-only launch).
+    e = plan_launch_prep(P, s);
+    if (e == hipSuccess) {
+      StepLaunch S;
+      S.v = P->X; S.out = P->Y; S.write_out = 0; S.read_w = 0; S.dots = 0; S.a = 0.0; S.b = 0.0;
+      S.velocity = true; S.vel = V0; S.vdir = p->alpha; S.vel_scale = 1.0;
+      e = plan_launch_step(P, s, S);
+    }
+    if (e == hipSuccess) e = chain(V0, Ab, k0, kk);     // A_k = d_eta(E_k) h~^a r
+    if (e == hipSuccess) e = chain(P->X, Bb, k0, kk);   // B_k = d_eta(E_k) r
+    for (int k = 0; k < kk && e == hipSuccess; ++k) {
+      // b_k = h~^b B_k into the scratch vector, then <A_k | b_k>.
+      StepLaunch S;
+      S.v = Bb + vec_b * (size_t)k; S.out = P->Y; S.write_out = 0; S.read_w = 0; S.dots = 0; S.a = 0.0; S.b = 0.0;
+      S.velocity = true; S.vel = Sc; S.vdir = p->beta; S.vel_scale = 1.0;
+      e = plan_launch_step(P, s, S);
+      if (e != hipSuccess) break;
+      double* pk = part + (size_t)(k0 + k) * kDotBlocks * 2;
+      if (f32)
+        hipLaunchKernelGGL(dot_partial_kernel<float>, dim3(kDotBlocks), dim3(256), 0, s,
+                           (const float*)(Ab + vec_b * (size_t)k), (const float*)Sc, n_elems / 2, pk);
+      else
+        hipLaunchKernelGGL(dot_partial_kernel<double>, dim3(kDotBlocks), dim3(256), 0, s,
+                           (const double*)(Ab + vec_b * (size_t)k), (const double*)Sc, n_elems / 2, pk);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess && st == KPM_OK) {
+    const double omega = (double)lat->L1 * lat->L2 * cell_area_nm2(lat->kind);
+    double* out = on_dev ? sigma : dsig;
+    hipLaunchKernelGGL(singleshot_finish_kernel, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, part, K,
+                       2.0 * M_PI * M_PI / (omega * R), out);
+    e = hipGetLastError();
+    if (e == hipSuccess && !on_dev) e = hipMemcpyAsync(sigma, dsig, sizeof(double) * K, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  } else {
+    (void)hipStreamSynchronize(s);
+  }
+  if (e != hipSuccess && st == KPM_OK) {
+    set_error("kpm_sigma_singleshot: %s", hipGetErrorString(e));
+    st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
+  }
+  for (void* ptr : {V0, Sc, acc, (void*)dcoef, (void*)part, (void*)dsig})
+    if (ptr) (void)hipFree(ptr);
+  plan_free(P);
+  delete P;
+  return st;
+}
+
 }  // namespace kpm
+
+extern "C" int kpm_sigma_singleshot(const kpm_lattice_t* lat, const kpm_cond_params_t* p, const double* energies_ev,
+                                    int32_t K, double eta_ev, double* sigma, int32_t on_device, void* hip_stream) {
+  try {
+    kpm::clear_error();
+    return kpm::singleshot_run(lat, p, energies_ev, K, eta_ev, sigma, on_device, hip_stream);
+  } catch (...) {
+    kpm::set_error("internal error (exception) in kpm_sigma_singleshot");
+    return KPM_E_DEVICE;
+  }
+}
 
 extern "C" int kpm_moments_gamma1(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double* gamma1,
                                   int32_t out_on_device, void* hip_stream) {

@@ -69,6 +69,11 @@ struct Geometry {
   double fA[2], fB[2];   // fractional coordinates of the sublattice positions
 };
 
+// Area of one unit cell (nm^2): a^2 sqrt(3)/2 (honeycomb), a^2 (square).
+double cell_area_nm2(int kind) {
+  return kind == KPM_SQUARE ? kASq * kASq : kAHc * kAHc * std::sqrt(3.0) / 2.0;
+}
+
 static Geometry honeycomb_geometry() {
   Geometry g;
   g.a1[0] = kAHc; g.a1[1] = 0.0;

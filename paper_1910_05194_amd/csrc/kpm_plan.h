@@ -34,6 +34,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
                 kpm_plan** out);
 void plan_free(kpm_plan* P);
 bool tune_cache_lookup(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, kpm_tune_t* t);
+double cell_area_nm2(int kind);
 }  // namespace kpm
 
 struct kpm_plan {

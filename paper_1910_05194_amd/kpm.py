@@ -123,6 +123,8 @@ def _load():
         "kpm_cond_last_stats": (ctypes.c_int, [ctypes.POINTER(c_cond_stats)]),
         "kpm_moments_gamma1": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.POINTER(c_cond_params), _P,
                                               ctypes.c_int32, _P]),
+        "kpm_sigma_singleshot": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.POINTER(c_cond_params), _P,
+                                                ctypes.c_int32, ctypes.c_double, _P, ctypes.c_int32, _P]),
         "kpm_autotune": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, ctypes.POINTER(c_dos_params),
                                         ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(c_tune), _D, _P]),
         "kpm_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -385,6 +387,28 @@ def moments_gamma1(lattice, par, precision: int = FP32, out_device=None, stream=
         stream = torch.cuda.current_stream(g.device)
     _check(LIB.kpm_moments_gamma1(lat, ctypes.byref(p), g.data_ptr(), 1, _stream_handle(stream)))
     return g
+
+
+def sigma_singleshot(lattice, par, energies, eta: float, precision: int = FP32, stream=None):
+    """kpm_sigma_singleshot: sigma_ab(E) in e^2/h (T = 0, CPGF broadening eta in eV) for
+    energies as a numpy array (host result) or a float64 torch tensor (device result)."""
+    lat = c_lattices([lattice])
+    p = c_cond_params(int(par.num_moments), int(par.num_random), int(par.vector_seed) & (2**64 - 1),
+                      int(par.alpha), int(par.beta), int(par.gamma_mode), int(precision), 0)
+    if isinstance(energies, np.ndarray) or not hasattr(energies, "data_ptr"):
+        en = np.ascontiguousarray(np.atleast_1d(energies), dtype=np.float64)
+        out = np.zeros(en.shape)
+        _check(LIB.kpm_sigma_singleshot(lat, ctypes.byref(p), en.ctypes.data, en.size, float(eta), out.ctypes.data, 0,
+                                        _stream_handle(stream)))
+        return out
+    import torch
+    en = energies.contiguous().to(torch.float64)
+    out = torch.zeros_like(en)
+    if stream is None:
+        stream = torch.cuda.current_stream(en.device)
+    _check(LIB.kpm_sigma_singleshot(lat, ctypes.byref(p), en.data_ptr(), en.numel(), float(eta), out.data_ptr(), 1,
+                                    _stream_handle(stream)))
+    return out
 
 
 def cond_last_stats() -> dict:

@@ -249,3 +249,39 @@ def test_graphene_optical_conductivity_end_to_end(K):
     ratio = s[:, 0] / (np.pi / 4)
     print("graphene Re sigma_xx / (pi/4):", np.round(ratio, 4), "Im:", np.round(s[:, 1], 4))
     assert np.max(np.abs(ratio - np.array([1.0172, 1.0375, 1.0681]))) < 0.025, ratio
+
+
+@pytest.mark.parametrize("lat", [LATS[0], LATS[1], LATS[3]], ids=["spin-flux", "honeycomb", "qahe"])
+@pytest.mark.parametrize("ab", [(0, 0), (0, 1)])
+def test_singleshot_parity(K, lat, ab):
+    """kpm_sigma_singleshot against the oracle's single-shot sums with the same
+    random vectors (M = 40, R = 2, 5 energies): FP64 1e-10 relative to the largest
+    value, FP32 2e-5; device pointers give the same values."""
+    import torch
+    M, R = 40, 2
+    par = wl.CondParams(num_moments=M, num_random=R, vector_seed=23, alpha=ab[0], beta=ab[1])
+    m = olat.build(lat)
+    from oracle import kpm as okpm
+    vecs = okpm.random_phase_vectors(m, R, par.vector_seed, 0)
+    E = np.array([lat.e_min * 0.6, -0.8, 0.0, 0.45, lat.e_max * 0.5])
+    ref = ocond.sigma_singleshot(m, lat.e_min, lat.e_max, E, 0.15, M, vecs, *ab)
+    scale = np.max(np.abs(ref))
+    s64 = K.sigma_singleshot(lat, par, E, 0.15, precision=wl.FP64)
+    assert np.max(np.abs(s64 - ref)) <= 1e-10 * scale, (s64, ref)
+    s32 = K.sigma_singleshot(lat, par, E, 0.15, precision=wl.FP32)
+    assert np.max(np.abs(s32 - ref)) <= 2e-5 * scale, (s32, ref)
+    sd = K.sigma_singleshot(lat, par, torch.tensor(E, device="cuda"), 0.15, precision=wl.FP64).cpu().numpy()
+    assert np.array_equal(sd, s64)
+
+
+def test_graphene_minimum_conductivity_singleshot(K):
+    """Clean spinless graphene 1024 x 1024, single-shot on the GPU (FP32, M = 1024,
+    R = 4, eta = 0.1 eV): sigma_xx(0) = 2/pi e^2/h (the universal minimum, pinned in
+    the oracle), and the oracle's k-space values 1.2007 and 2.5937 e^2/h at 0.2 and
+    0.5 eV; gate 4 % (stochastic trace)."""
+    lat = wl.Lattice(kind=wl.HONEYCOMB, L1=1024, L2=1024, t=-2.7, e_min=-9.0, e_max=9.0)
+    par = wl.CondParams(num_moments=1024, num_random=4, vector_seed=6, alpha=0, beta=0)
+    s = K.sigma_singleshot(lat, par, np.array([0.0, 0.2, 0.5]), 0.1)
+    ref = np.array([2 / np.pi, 1.2007, 2.5937])
+    print("graphene single-shot sigma_xx:", np.round(s, 4), "ref", np.round(ref, 4))
+    assert np.max(np.abs(s - ref) / ref) < 0.04, s
