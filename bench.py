@@ -19,9 +19,12 @@ Further legs (each reported in its own JSON object): the same pass in FP64
 Gamma_nm conductivity workload (spinful Rashba + flux 1024^2, 512 x 512,
 R = 8, split-BF16 MFMA), the batched uneven workload (64 vacancy lattices
 256^2..2048^2, M = 1024, R = 4), the learned moment extrapolation (training
-and evaluation), and the CPU oracle on a bounded sample.
+and evaluation), the QAHE Hall plateau (Kubo-Bastin, 512^2, M = 1024), the
+optical and single-shot conductivities of clean graphene 1024^2, and the CPU
+oracle on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--legs c1,c3,c4,c5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                      [--legs c1,c3,c4,c5,hall,optical,singleshot]
 """
 from __future__ import annotations
 
@@ -103,6 +106,62 @@ def leg_gamma(kpm, wl, np):
             "gemm_useful_TFLOPs": st["gemm_useful_flops"] / (st["gemm_ms"] * 1e-3) / 1e12,
             "mfma_utilisation_bf16": gemm_tf / BF16_PEAK_TFLOPS, "batches": st["n_batches"],
             "gamma_00": [G[0, 0].real, G[0, 0].imag], "sigma_xx_e2h": dict(zip(map(float, E), map(float, sig)))}
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def leg_hall(kpm, wl, np):
+    """QAHE Hall conductivity: Gamma^xy on 512^2 spinful cells (M = 1024, R = 1) and the
+    T = 0 Kubo-Bastin reconstruction at 5 Fermi energies in the gap (plateau 2 e^2/h)."""
+    import torch
+    lat, par = wl.qahe()
+    opn = 4 / (wl.A_HONEYCOMB ** 2 * np.sqrt(3) / 2)
+    G, dt_g = _timed(lambda: kpm.moments_cond(lat, par, out_device="cuda"))
+    st = kpm.cond_last_stats()
+    E = torch.tensor([-0.5, -0.3, 0.0, 0.3, 0.5], dtype=torch.float64, device="cuda")
+    s, dt_r = _timed(lambda: kpm.reconstruct_sigma_bastin(G, E, lat.e_min, lat.e_max, 0.05, opn))
+    s = s.cpu().numpy()
+    return {"workload": "QAHE spinful honeycomb 512^2 (lambda_R = 0.3|t|, Delta_ex = 0.4|t|), Gamma^xy M=1024, R=1, "
+                        "split-BF16; T=0 Kubo-Bastin at eta = 50 meV",
+            "gamma_s": dt_g, "chain_ms": st["chain_ms"], "gemm_ms": st["gemm_ms"], "reconstruct_s": dt_r,
+            "sigma_xy_e2h": dict(zip(map(float, E.cpu().numpy()), map(float, s))),
+            "max_dev_from_2": float(np.max(np.abs(s - 2.0)))}
+
+
+def leg_optical(kpm, wl, np):
+    """Optical sigma_xx(omega) of clean graphene 1024^2 (rank-2 and rank-1 Gamma, M = 1024,
+    R = 4) against the universal pi/4 e^2/h (spinless)."""
+    import torch
+    lat, par = wl.graphene_clean()
+    opn = 2 / (wl.A_HONEYCOMB ** 2 * np.sqrt(3) / 2)
+    G2, dt2 = _timed(lambda: kpm.moments_cond(lat, par, out_device="cuda"))
+    G1, dt1 = _timed(lambda: kpm.moments_gamma1(lat, par, out_device="cuda"))
+    W = torch.tensor([0.5, 1.0, 1.5, 2.0], dtype=torch.float64, device="cuda")
+    s, dtr = _timed(lambda: kpm.reconstruct_sigma_optical(G2, G1, W, 0.0, lat.e_min, lat.e_max, 0.1, opn))
+    s = s.cpu().numpy()
+    return {"workload": "clean spinless graphene 1024^2, Gamma^xx M=1024 + Gamma_n^xx, R=4, eta = 0.1 eV, mu = 0",
+            "gamma2_s": dt2, "gamma1_s": dt1, "reconstruct_s": dtr,
+            "re_sigma_over_pi4": dict(zip(map(float, W.cpu().numpy()), map(float, s[:, 0] / (np.pi / 4)))),
+            "kspace_reference_over_pi4": {0.5: 1.0054, 1.0: 1.0172, 1.5: 1.0375, 2.0: 1.0681}}
+
+
+def leg_singleshot(kpm, wl, np):
+    """Single-shot Fermi-surface sigma_xx(E) of clean graphene 1024^2 (M = 1024, R = 4,
+    eta = 0.1 eV, 16 energies): O(K M N) instead of the O(M^2 N) Gamma route."""
+    lat, par = wl.graphene_clean()
+    E = np.linspace(-1.5, 1.5, 16)
+    E[np.argmin(np.abs(E))] = 0.0
+    s, dt = _timed(lambda: kpm.sigma_singleshot(lat, par, E, 0.1))
+    return {"workload": "clean spinless graphene 1024^2, single-shot sigma_xx, M=1024, R=4, eta = 0.1 eV, 16 energies",
+            "s": dt, "sigma_xx_e2h": dict(zip(map(float, E), map(float, s))),
+            "sigma_at_dirac_over_2_over_pi": float(s[np.argmin(np.abs(E))] / (2 / np.pi))}
 
 
 def leg_batch(kpm, wl, np):
@@ -233,7 +292,8 @@ def main():
                     help="launch the recursion steps one by one instead of replaying a hipGraph (for profilers)")
     ap.add_argument("--launch", default="",
                     help="pin the FP32 launch shape: kernel,block,rows,grid[,chunks] (skips the autotuner)")
-    ap.add_argument("--legs", default="c1,c3,c4,c5", help="extra legs: c1,c3,c4,c5 (empty for none)")
+    ap.add_argument("--legs", default="c1,c3,c4,c5,hall,optical,singleshot",
+                    help="extra legs: c1,c3,c4,c5,hall,optical,singleshot (empty for none)")
     ap.add_argument("--mlp-train", type=int, default=4000,
                     help="training lattices (1024^2 cells each) of the learned-extrapolation leg")
     ap.add_argument("--copy-probe", action="store_true",
@@ -354,11 +414,13 @@ def main():
         r = kpm.bandwidth_probe(0, 4 << 30, iters=5)
         extra["copy_probe"] = {"kernel": "kpm::probe_copy", "bytes_moved": r["bytes"], "ms": r["ms"], "GBs": r["GBs"]}
 
-    for name, fn in (("c1", leg_small), ("c3", leg_gamma), ("c4", leg_batch), ("c5", leg_mlp)):
+    for name, fn in (("c1", leg_small), ("c3", leg_gamma), ("c4", leg_batch), ("c5", leg_mlp), ("hall", leg_hall),
+                     ("optical", leg_optical), ("singleshot", leg_singleshot)):
         if name in legs:
             log(f"[bench] leg {name}")
             kw = {"n_train": args.mlp_train} if name == "c5" else {}
-            extra[{"c1": "small_fp64", "c3": "gamma", "c4": "uneven_batch", "c5": "mlp_extrapolation"}[name]] = \
+            extra[{"c1": "small_fp64", "c3": "gamma", "c4": "uneven_batch", "c5": "mlp_extrapolation",
+                   "hall": "qahe_hall", "optical": "graphene_optical", "singleshot": "graphene_singleshot"}[name]] = \
                 fn(kpm, wl, np, **kw)
 
     cpu = None

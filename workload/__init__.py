@@ -192,6 +192,22 @@ def rashba_flux(L: int = 1024, M: int = 512, R: int = 8, gamma_mode: int = GAMMA
     return lat, par
 
 
+def qahe(L: int = 512, M: int = 1024, R: int = 1) -> tuple:
+    """The paper's QAHE model (eq. HQAHE, Fig. qahe): spinful honeycomb, t = -2.7 eV,
+    lambda_R = 0.3 |t|, Delta_ex = 0.4 |t|, clean, bounds +-10 eV; Gamma^xy split-BF16."""
+    lat = Lattice(kind=HONEYCOMB_SPIN, L1=L, L2=L, t=-2.7, rashba=0.81, exchange=1.08,
+                  disorder_seed=DISORDER_SEED, e_min=-10.0, e_max=10.0)
+    par = CondParams(num_moments=M, num_random=R, vector_seed=3, alpha=0, beta=1, gamma_mode=GAMMA_SPLIT_BF16)
+    return lat, par
+
+
+def graphene_clean(L: int = 1024, M: int = 1024, R: int = 4) -> tuple:
+    """Clean spinless graphene, t = -2.7 eV, bounds +-9 eV; xx response, split-BF16 Gamma."""
+    lat = Lattice(kind=HONEYCOMB, L1=L, L2=L, t=-2.7, disorder_seed=DISORDER_SEED, e_min=-9.0, e_max=9.0)
+    par = CondParams(num_moments=M, num_random=R, vector_seed=4, alpha=0, beta=0, gamma_mode=GAMMA_SPLIT_BF16)
+    return lat, par
+
+
 def uneven_batch(n_lat: int = 64, lo: int = 256, hi: int = 2048, M: int = 1024, R: int = 4,
                  vacancy_p: float = 0.005, size_seed: int = 4) -> tuple:
     """n_lat graphene lattices with L_i ~ U{lo..hi} (square L_i x L_i), vacancies only."""
