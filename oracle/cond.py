@@ -104,15 +104,49 @@ def sigma_from_gamma(gamma: np.ndarray, energies_ev: np.ndarray, e_min: float, e
 #   a 1/omega prefactor and leaves omega -> 0 to KITE-tools):
 #     sigma_ab(mu) = (i e^2 hbar / Omega) int d eps f(eps)
 #                    Tr[ v_a delta(eps-H) v_b dG^R/d eps - v_a dG^A/d eps v_b delta(eps-H) ],
-#   v = h~/(i hbar), h~ = [r, H]; T = 0, so f = theta(mu - eps).
+#   v = h~/(i hbar), h~ = [r, H]; f the Fermi function at chemical potential
+#   mu and temperature T (f = theta(mu - eps) at T = 0).
 # * eq. delta_function_cheb_expansion (Delta_n) and eqs.
 #   green_function_cheb_expansion(b) (CPGF g_n^{R,A} at broadening eta) for
 #   the two factors, and eq. Gammanm for the trace: in rescaled units
-#     sigma_ab(mu)/(e^2/h) = Re{ -2 pi i (N/Omega)/de-^2 int_{-1}^{mu~} d eps
+#     sigma_ab(mu)/(e^2/h) = Re{ -2 pi i (N/Omega)/de-^2 int_{-1}^{1} d eps f(eps)
 #         sum_nm Gamma_nm [Delta_n(eps) g'^R_m(eps) - g'^A_n(eps) Delta_m(eps)] },
 #   g' = d g / d eps.  This is the Lambda_nm contraction of eq.
 #   conductivity_1st_order for a static field.
+# * The energy integrals with f (here and in the optical conductivity) run in
+#   theta, eps = cos theta, over Q equal cells of [0, pi]: the integrand apart
+#   from f at each cell's midpoint, times the cell's occupation weight
+#   int_cell f(cos theta) d theta.  At T = 0 that weight is the covered length
+#   of the cell inside [theta_mu, pi]; at T > 0 it is a midpoint sum over
+#   FERMI_SUB equal sub-cells (reading used: the paper gives no quadrature).
 # ---------------------------------------------------------------------------
+
+FERMI_SUB = 32
+
+
+def fermi(eps_ev, mu_ev: float, kT_ev: float) -> np.ndarray:
+    """Fermi-Dirac occupation 1/(1 + exp((eps - mu)/kT)) (kT in eV; kT = 0: the
+    step theta(mu - eps), 1/2 at eps = mu)."""
+    e = np.asarray(eps_ev, dtype=np.float64)
+    if kT_ev == 0.0:
+        return np.where(e < mu_ev, 1.0, np.where(e > mu_ev, 0.0, 0.5))
+    x = (e - mu_ev) / kT_ev
+    ex = np.exp(-np.abs(x))
+    return np.where(x > 0, ex / (1.0 + ex), 1.0 / (1.0 + ex))
+
+
+def occupation_weights(n_theta: int, mu_ev: float, kT_ev: float, e_min: float, e_max: float) -> np.ndarray:
+    """int_cell f(cos theta) d theta for the n_theta equal theta-cells of [0, pi]
+    (energies rescaled with the spectrum bounds), per the reading above."""
+    d_plus, d_minus = (e_max + e_min) / 2.0, (e_max - e_min) / 2.0
+    h = np.pi / n_theta
+    th = (np.arange(n_theta) + 0.5) * h
+    if kT_ev == 0.0:
+        mut = (mu_ev - d_plus) / d_minus
+        th_mu = 0.0 if mut >= 1.0 else (np.pi if mut <= -1.0 else float(np.arccos(mut)))
+        return np.clip(th + h / 2.0 - np.maximum(th - h / 2.0, th_mu), 0.0, h)
+    sub = th[:, None] - h / 2.0 + (np.arange(FERMI_SUB)[None, :] + 0.5) * (h / FERMI_SUB)
+    return fermi(d_plus + d_minus * np.cos(sub), mu_ev, kT_ev).sum(axis=1) * (h / FERMI_SUB)
 
 def _eigen(model):
     E, U = np.linalg.eigh(model.H.toarray())
@@ -136,24 +170,45 @@ def gamma_nm_exact(model: lattice.Model, e_min: float, e_max: float, M: int, alp
     return G
 
 
-def sigma_kubo_eigen(model: lattice.Model, mu_ev: float, alpha: int = 0, beta: int = 1) -> float:
-    """The Kubo-Bastin Fermi-sea conductivity at T = 0 and eta -> 0 in units of
-    e^2/h, summed over eigenstates (the definition, evaluated directly):
-        sigma_ab = Re{ (-2 pi i / Omega) sum_{E_a < mu <= E_b} [P_ab - P_ba] / (E_a - E_b)^2 },
-        P_ab = (h~^a)_ab (h~^b)_ba,  Omega = L1 L2 * cell area.
-    For a = x, b = y this is (4 pi/Omega) sum Im[(h~^x)_ab (h~^y)_ba]/(E_a - E_b)^2
-    (the diagonal terms of the Bastin integral cancel between its two parts)."""
+def sigma_kubo_eigen(model: lattice.Model, mu_ev: float, alpha: int = 0, beta: int = 1, kT_ev: float = 0.0) -> float:
+    """The Kubo-Bastin Fermi-sea conductivity at eta -> 0 in units of e^2/h,
+    summed over eigenstates (the definition, evaluated directly):
+        sigma_ab = Re{ (-2 pi i / Omega) sum_{a, b: E_a != E_b} f_a [P_ab - P_ba] / (E_a - E_b)^2 },
+        P_ab = (h~^a)_ab (h~^b)_ba,  Omega = L1 L2 * cell area,  f = fermi(E, mu, kT).
+    Pairs of occupied states cancel, so at T = 0 the sum runs over E_a < mu <= E_b.
+    For a = x, b = y this is (4 pi/Omega) sum f_a Im[(h~^x)_ab (h~^y)_ba]/(E_a - E_b)^2
+    (the diagonal terms of the Bastin integral cancel between its two parts; the
+    Fermi-surface terms it adds at finite eta vanish with eta for a != b)."""
     E, U = _eigen(model)
     A = U.conj().T @ velocity(model, alpha).toarray() @ U
     B = U.conj().T @ velocity(model, beta).toarray() @ U
-    occ = np.nonzero(E < mu_ev)[0]
-    emp = np.nonzero(E >= mu_ev)[0]
-    P_ab = A[np.ix_(occ, emp)] * B[np.ix_(emp, occ)].T
-    P_ba = A[np.ix_(emp, occ)].T * B[np.ix_(occ, emp)]
-    den = (E[occ][:, None] - E[emp][None, :]) ** 2
+    f = (E < mu_ev).astype(np.float64) if kT_ev == 0.0 else fermi(E, mu_ev, kT_ev)
+    P = A * B.T                                   # P_ab = A_ab B_ba
+    dE = E[:, None] - E[None, :]
+    off = np.abs(dE) > 1e-9 * max(1.0, float(np.max(np.abs(E))))
+    den = np.where(off, dE, 1.0) ** 2
     n_cells = model.site_active.size // model.n_sub
     omega = n_cells * model.cell_area
-    return float(np.real(-2j * np.pi / omega * np.sum((P_ab - P_ba) / den)))
+    return float(np.real(-2j * np.pi / omega * np.sum(np.where(off, f[:, None] * (P - P.T) / den, 0.0))))
+
+
+def sigma_bastin_eigen(model: lattice.Model, mu_ev: float, eta_ev: float, alpha: int = 0, beta: int = 1,
+                       kT_ev: float = 0.0) -> float:
+    """The Kubo-Bastin formula of the block comment above at finite broadening eta
+    and temperature, evaluated on the eigenstates (what the Gamma/Lambda route
+    tends to as M grows): the delta function picks E_b (first term) or E_a (second),
+    and the derivative of the broadened resolvent is -1/(eps - E + i eta)^2, so
+        sigma_ab = Re{ (-2 pi i / Omega) sum_ab P_ab (f_a - f_b) / (E_a - E_b - i eta)^2 },
+    P_ab = (h~^a)_ab (h~^b)_ba, f = fermi(E, mu, kT).  eta -> 0 gives sigma_kubo_eigen."""
+    E, U = _eigen(model)
+    A = U.conj().T @ velocity(model, alpha).toarray() @ U
+    B = U.conj().T @ velocity(model, beta).toarray() @ U
+    f = fermi(E, mu_ev, kT_ev)
+    P = A * B.T
+    den = (E[:, None] - E[None, :] - 1j * eta_ev) ** 2
+    n_cells = model.site_active.size // model.n_sub
+    omega = n_cells * model.cell_area
+    return float(np.real(-2j * np.pi / omega * np.sum(P * (f[:, None] - f[None, :]) / den)))
 
 
 def cpgf_derivative(M: int, eps: np.ndarray, eta: float, sign: int) -> np.ndarray:
@@ -171,13 +226,14 @@ def cpgf_derivative(M: int, eps: np.ndarray, eta: float, sign: int) -> np.ndarra
 
 
 def sigma_bastin(gamma: np.ndarray, energies_ev, e_min: float, e_max: float, eta_ev: float,
-                 orbitals_per_nm2: float, n_theta: int) -> np.ndarray:
-    """T = 0 Kubo-Bastin conductivity (e^2/h) at Fermi energies ``energies_ev`` from a
-    full [M, M] Gamma (formula in the block comment above).
+                 orbitals_per_nm2: float, n_theta: int, kT_ev: float = 0.0) -> np.ndarray:
+    """Kubo-Bastin conductivity (e^2/h) at chemical potentials ``energies_ev`` and
+    temperature kT_ev (eV) from a full [M, M] Gamma (formula in the block comment
+    above).
 
     The energy integral is taken in theta (eps = cos theta, so Delta_n d eps =
-    (2/pi) cos(n theta) d theta): midpoint rule on n_theta equal cells of
-    [0, pi], each cell weighted by the part of it inside [theta_mu, pi]."""
+    (2/pi) cos(n theta) d theta): the integrand at the midpoints of n_theta equal
+    cells of [0, pi] times each cell's occupation weight."""
     gamma = np.asarray(gamma, dtype=np.complex128)
     M = gamma.shape[0]
     d_plus, d_minus = (e_max + e_min) / 2.0, (e_max - e_min) / 2.0
@@ -192,13 +248,7 @@ def sigma_bastin(gamma: np.ndarray, energies_ev, e_min: float, e_max: float, eta
     pref = -2j * np.pi * orbitals_per_nm2 / d_minus ** 2
     out = []
     for mu in np.atleast_1d(np.asarray(energies_ev, dtype=np.float64)):
-        mut = (mu - d_plus) / d_minus
-        if mut <= -1.0:
-            out.append(0.0)
-            continue
-        th_mu = 0.0 if mut >= 1.0 else float(np.arccos(mut))
-        lo = th - h / 2.0
-        w = np.clip(th + h / 2.0 - np.maximum(lo, th_mu), 0.0, h)   # covered length of each cell
+        w = occupation_weights(n_theta, mu, kT_ev, e_min, e_max)
         out.append(float(np.real(pref * np.sum(F * w))))
     return np.array(out)
 
@@ -294,14 +344,14 @@ def chern_number(lat, n_occ: int, n_k: int) -> float:
 
 
 # ---------------------------------------------------------------------------
-# Optical conductivity sigma_ab(omega) at T = 0 (eq. cond 1st order with the
+# Optical conductivity sigma_ab(omega) (eq. cond 1st order with the
 # rank-1 and rank-2 Gamma of eq. Gammanm and the Lambda_n, Lambda_nm(omega)
 # that follow it, combined as in eq. conductivity_1st_order):
 #   sigma_ab(w)/(e^2/h) = (-2 pi i (N/Omega) / E_w) [ sum_n Gamma_n^{ab} L_n
 #                          + (1/de-) sum_nm Gamma_nm^{a,b} L_nm(w) ],
-#   L_n = int_{-1}^{mu~} d eps Delta_n(eps),
-#   L_nm(w) = int_{-1}^{mu~} d eps [g^R_n(eps + w~) Delta_m(eps) + Delta_n(eps) g^A_m(eps - w~)],
-# E_w = hbar omega in eV, w~ = E_w/de-, g^{R,A} the CPGF coefficients at
+#   L_n = int_{-1}^{1} d eps f(eps) Delta_n(eps),
+#   L_nm(w) = int_{-1}^{1} d eps f(eps) [g^R_n(eps + w~) Delta_m(eps) + Delta_n(eps) g^A_m(eps - w~)],
+# f the Fermi function at chemical potential mu and temperature T, E_w = hbar omega in eV, w~ = E_w/de-, g^{R,A} the CPGF coefficients at
 # broadening eta (rescaled, hbar = 1), Gamma in eV nm^2 (rank 1) and eV^2 nm^2
 # (rank 2).  The energy integrals use the theta quadrature of sigma_bastin.
 # ---------------------------------------------------------------------------
@@ -355,9 +405,9 @@ def cpgf_coefficients(M: int, z: np.ndarray, sign: int) -> np.ndarray:
 
 
 def sigma_optical(gamma_nm: np.ndarray, gamma_n: np.ndarray, omegas_ev, mu_ev: float, e_min: float, e_max: float,
-                  eta_ev: float, orbitals_per_nm2: float, n_theta: int) -> np.ndarray:
-    """Complex sigma_ab(omega) in e^2/h at T = 0 and Fermi energy mu (formula in the
-    block comment above).  Quadrature in theta as in sigma_bastin."""
+                  eta_ev: float, orbitals_per_nm2: float, n_theta: int, kT_ev: float = 0.0) -> np.ndarray:
+    """Complex sigma_ab(omega) in e^2/h at chemical potential mu and temperature kT_ev
+    (formula in the block comment above).  Quadrature in theta as in sigma_bastin."""
     gamma_nm = np.asarray(gamma_nm, dtype=np.complex128)
     gamma_n = np.asarray(gamma_n, dtype=np.complex128)
     M = gamma_nm.shape[0]
@@ -367,9 +417,7 @@ def sigma_optical(gamma_nm: np.ndarray, gamma_n: np.ndarray, omegas_ev, mu_ev: f
     th = (np.arange(n_theta) + 0.5) * h
     eps = np.cos(th)
     D = 2.0 * np.cos(np.outer(th, np.arange(M))) / np.pi                   # [q, n]
-    mut = (mu_ev - d_plus) / d_minus
-    th_mu = 0.0 if mut >= 1.0 else (np.pi if mut <= -1.0 else float(np.arccos(mut)))
-    w = np.clip(th + h / 2.0 - np.maximum(th - h / 2.0, th_mu), 0.0, h)
+    w = occupation_weights(n_theta, mu_ev, kT_ev, e_min, e_max)
     lam_n = D.T @ w                                                         # Lambda_n
     out = []
     for Ew in np.atleast_1d(np.asarray(omegas_ev, dtype=np.float64)):
@@ -383,17 +431,18 @@ def sigma_optical(gamma_nm: np.ndarray, gamma_n: np.ndarray, omegas_ev, mu_ev: f
     return np.array(out)
 
 
-def sigma_optical_eigen(model: lattice.Model, omegas_ev, mu_ev: float, eta_ev: float, a: int, b: int) -> np.ndarray:
+def sigma_optical_eigen(model: lattice.Model, omegas_ev, mu_ev: float, eta_ev: float, a: int, b: int,
+                        kT_ev: float = 0.0) -> np.ndarray:
     """The same sigma_ab(omega) evaluated on the eigenstates (the definition with the
     resolvents broadened by eta and the delta function exact):
       (-2 pi i/(Omega E_w)) [ sum_a f_a C_aa + sum_ab A_ab B_ba ( f_a/(E_a - E_b + E_w + i eta)
                                                              + f_b/(E_b - E_a - E_w - i eta) ) ],
-    A, B, C = h~^a, h~^b, h~^{ab} in the eigenbasis, f = theta(mu - E)."""
+    A, B, C = h~^a, h~^b, h~^{ab} in the eigenbasis, f = fermi(E, mu, kT) (theta(mu - E) at T = 0)."""
     E, U = _eigen(model)
     A = U.conj().T @ velocity(model, a).toarray() @ U
     B = U.conj().T @ velocity(model, b).toarray() @ U
     C = np.real(np.einsum("ia,ij,ja->a", U.conj(), velocity2(model, a, b).toarray(), U))
-    f = (E < mu_ev).astype(np.float64)
+    f = (E < mu_ev).astype(np.float64) if kT_ev == 0.0 else fermi(E, mu_ev, kT_ev)
     P = A * B.T
     dE = E[:, None] - E[None, :]
     n_cells = model.site_active.size // model.n_sub

@@ -240,6 +240,78 @@ def test_bastin_both_directions_converge_on_a_disordered_model():
     assert np.max(np.abs(sxy + syx)) < 1e-3
 
 
+# --- Finite temperature: the Fermi function f of eq. cond 1st order and of Lambda_n, Lambda_nm ---
+
+def test_fermi_function_and_cell_weights():
+    """fermi: f(mu) = 1/2, f(mu + x) + f(mu - x) = 1, no overflow far from mu, the step at
+    kT = 0.  occupation_weights: adaptive quadrature of f(cos theta) over each cell (kT > 0;
+    within the sub-cell midpoint rule's error, < 2e-5 of a cell on these 0.12 eV cells),
+    the covered lengths of [theta_mu, pi] at kT = 0, and kT -> 0 tending
+    to those within a sub-cell."""
+    from scipy import integrate
+    x = np.array([0.0, 0.013, 0.2, 3.0])
+    f_p, f_m = cond.fermi(0.3 + x, 0.3, 0.05), cond.fermi(0.3 - x, 0.3, 0.05)
+    assert f_p[0] == 0.5 and np.max(np.abs(f_p + f_m - 1.0)) < 1e-15
+    assert np.all(np.diff(f_p) < 0) and f_p[-1] < 1e-25
+    with np.errstate(over="raise"):
+        assert cond.fermi(np.array([-1e4, 1e4]), 0.0, 1e-3).tolist() == [1.0, 0.0]
+    assert cond.fermi(np.array([-0.1, 0.0, 0.1]), 0.0, 0.0).tolist() == [1.0, 0.5, 0.0]
+    Q, h = 256, np.pi / 256
+    for mu, kT in ((0.3, 0.1), (-4.0, 0.5), (9.5, 0.2)):
+        w = cond.occupation_weights(Q, mu, kT, -10.0, 10.0)
+        ref = [integrate.quad(lambda th: cond.fermi(10.0 * np.cos(th), mu, kT), q * h, (q + 1) * h,
+                              epsabs=1e-15, epsrel=1e-12)[0] for q in range(Q)]
+        assert np.max(np.abs(w - ref)) < 2e-5 * h, (mu, kT)
+    for mu in (-10.5, -3.3, 0.0, 7.1, 10.5):
+        w0 = cond.occupation_weights(Q, mu, 0.0, -10.0, 10.0)
+        # Covered length of each cell inside {theta : 10 cos(theta) < mu}, by brute force.
+        fine = (np.arange(Q * 2000) + 0.5) * (h / 2000)
+        ref = (10.0 * np.cos(fine) < mu).reshape(Q, 2000).sum(axis=1) * (h / 2000)
+        assert np.max(np.abs(w0 - ref)) <= h / 2000, mu
+        w1 = cond.occupation_weights(Q, mu, 1e-9, -10.0, 10.0)
+        assert np.max(np.abs(w1 - w0)) <= h / cond.FERMI_SUB, mu
+
+
+def test_bastin_finite_T_is_the_fermi_smearing_of_T0():
+    """Integrating the f-weighted energy integral by parts gives
+    sigma(mu, T) = int dE sigma(E, 0) (-df/dE), and this holds cell by cell for the
+    theta quadrature (up to its sub-cell rule): the T > 0 path against Simpson's rule
+    over the separate T = 0 path (disordered 4 x 4 QAHE model, M = 256).  Below a
+    cell's width (kT = 20 meV) the sub-cell rule limits the agreement to 5e-4."""
+    from scipy import integrate
+    lat = _qahe(4, W=1.0, seed=9)
+    m = lattice.build(lat)
+    opn = m.n_active / (16 * m.cell_area)
+    G = cond.gamma_nm_exact(m, lat.e_min, lat.e_max, 256, 0, 1)
+    for kT, mu, tol in ((0.1, 0.3, 1e-6), (0.3, 2.0, 1e-4), (0.02, -1.1, 5e-4)):
+        Eg = np.linspace(mu - 25 * kT, mu + 25 * kT, 20001)
+        s0 = cond.sigma_bastin(G, Eg, lat.e_min, lat.e_max, 0.1, opn, 512)
+        x = (Eg - mu) / kT
+        smeared = integrate.simpson(s0 / (kT * (2.0 + np.exp(x) + np.exp(-x))), x=Eg)
+        sT = cond.sigma_bastin(G, [mu], lat.e_min, lat.e_max, 0.1, opn, 512, kT_ev=kT)[0]
+        assert abs(sT - smeared) < tol * abs(smeared), (kT, mu, sT, smeared)
+
+
+def test_bastin_finite_T_converges_to_eigenstate_bastin():
+    """The eigenstate Kubo-Bastin sum at finite eta tends to the eta -> 0 Kubo sum
+    (1e-7, at T = 0 and kT = 0.1 eV); the Gamma/Lambda route (exact Gamma^xy, M = 4096,
+    eta = 30 meV) matches it at kT = 0.05 and 0.2 eV to 1e-4 on the disordered 4 x 4
+    QAHE model, where the finite-T values differ from T = 0 by up to 2.3x."""
+    lat = _qahe(4, W=1.0, seed=9)
+    m = lattice.build(lat)
+    opn = m.n_active / (16 * m.cell_area)
+    E = [-0.4, 0.0, 0.25]
+    for kT in (0.0, 0.1):
+        for e in E:
+            a, b = cond.sigma_bastin_eigen(m, e, 1e-9, 0, 1, kT), cond.sigma_kubo_eigen(m, e, 0, 1, kT)
+            assert abs(a - b) < 1e-7 * abs(b), (kT, e, a, b)
+    G = cond.gamma_nm_exact(m, lat.e_min, lat.e_max, 4096, 0, 1)
+    for kT in (0.05, 0.2):
+        s = cond.sigma_bastin(G, E, lat.e_min, lat.e_max, 0.03, opn, 8192, kT_ev=kT)
+        ex = np.array([cond.sigma_bastin_eigen(m, e, 0.03, 0, 1, kT) for e in E])
+        assert np.max(np.abs(s - ex) / np.abs(ex)) < 1e-4, (kT, s, ex)
+
+
 # --- Optical conductivity sigma_ab(omega) (eq. cond 1st order, rank-1 and rank-2 Gamma) ---
 
 def test_gamma1_exact_matches_trace_and_stochastic_basis():
@@ -311,6 +383,25 @@ def test_optical_spectral_converges_to_eigenstate_definition():
                                cond.gamma_n_exact(m, lat.e_min, lat.e_max, M, *ab), W, 0.1, lat.e_min, lat.e_max,
                                0.1, opn, 2 * M)
         assert np.max(np.abs(s - ex) / np.abs(ex)) < tol, (ab, s, ex)
+
+
+def test_optical_finite_T_converges_to_eigenstate_definition():
+    """The optical route with the Fermi function (kT = 0.1 and 0.4 eV, mu = 0.1 eV)
+    against the eigenstate formula with the same occupations: sigma_xx (M = 512) within
+    2e-3, sigma_xy (M = 1024) within 1e-4; at kT = 0.4 eV both differ from T = 0 by 7-30 %."""
+    lat = _qahe(4, W=1.0, seed=9)
+    m = lattice.build(lat)
+    opn = m.n_active / (16 * m.cell_area)
+    W = [0.3, 1.0, 2.5]
+    for ab, M, tol in (((0, 0), 512, 2e-3), ((0, 1), 1024, 1e-4)):
+        G2 = cond.gamma_nm_exact(m, lat.e_min, lat.e_max, M, *ab)
+        G1 = cond.gamma_n_exact(m, lat.e_min, lat.e_max, M, *ab)
+        for kT in (0.1, 0.4):
+            ex = cond.sigma_optical_eigen(m, W, 0.1, 0.1, *ab, kT_ev=kT)
+            s = cond.sigma_optical(G2, G1, W, 0.1, lat.e_min, lat.e_max, 0.1, opn, 2 * M, kT_ev=kT)
+            assert np.max(np.abs(s - ex) / np.abs(ex)) < tol, (ab, kT, s, ex)
+        ex0 = cond.sigma_optical_eigen(m, W, 0.1, 0.1, *ab)
+        assert np.min(np.abs(ex - ex0) / np.abs(ex0)) > 0.05
 
 
 # --- Single-shot Fermi-surface DC conductivity --------------------------------
