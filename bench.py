@@ -351,7 +351,7 @@ def main():
     # the timed region (hipEvents around the graph of step launches on the
     # run's stream; the graph also holds the few moment-reduction launches, so
     # this is a lower bound on the step kernel's own rate).  The sweep
-    # kernels (variants 3, 4, 5) cover 2, 3, 4 recursion steps per launch.
+    # kernels (variants 3..6) cover 2..5 recursion steps per launch.
     steps_per_launch = info["kernel"] - 1 if info["kernel"] >= 3 else 1
     n_launches = -(-info["n_steps"] // steps_per_launch)
     avg_launch_ms = float(np.mean(loop_ms)) / n_launches

@@ -101,30 +101,30 @@ typedef struct kpm_dos_params_t {
 
 /* Optional launch shape of the Chebyshev step kernel (0 = library choice / autotune cache). */
 typedef struct kpm_tune_t {
-  int32_t block;           /* threads per workgroup (64..512, multiple of 64); 0 = 512 for the sweep kernels,
-                              256 otherwise */
+  int32_t block;           /* threads per workgroup (64..512, multiple of 64); 0 = 512 for the sweep kernels
+                              (less where their row rings would not fit in LDS), 256 otherwise */
   int32_t rows;            /* lattice rows (along a2) per tile */
   int32_t grid;            /* persistent workgroups (multiple of 8); 0 = one per tile */
   int32_t use_graph;       /* 1 = replay the step loop as a captured hipGraph (default), 0 = eager */
   int32_t kernel;          /* 0 = default (5 where eligible, else 2), 1 = direct neighbour loads, 2 = LDS row
-                              ring, 3/4/5 = 2/3/4 steps per sweep (spinless lattices without Peierls phases
-                              and with room for four vectors; a sweep whose row rings do not fit in LDS takes
-                              one step fewer, down to 2) */
+                              ring, 3/4/5/6 = 2/3/4/5 steps per sweep (spinless lattices without Peierls
+                              phases and with room for four vectors; a sweep whose row rings do not fit in LDS
+                              takes one step fewer, down to 2) */
   int32_t chunks;          /* 16-byte vector chunks per site that one tile covers (1..E, E = the site's R_padded
                               complex values in 16-byte chunks); a tile then spans block / (sublattices * chunks)
                               cell columns; 0 = library choice */
 } kpm_tune_t;
 
 typedef struct kpm_plan_info_t {
-  int32_t n_steps;               /* recursion steps per run (ceil(M/2)); variants 3/4/5 launch once per 2/3/4 */
+  int32_t n_steps;               /* recursion steps per run (ceil(M/2)); variants 3..6 launch once per 2..5 */
   int32_t n_tiles;               /* tiles in the work list */
   int32_t grid, block, rows, tile_cells_x;
   int32_t r_padded;              /* vectors per orbital as stored (R rounded up) */
-  int32_t kernel;                /* step kernel variant in use (1 direct, 2 LDS ring, 3/4/5 = 2/3/4 steps per
+  int32_t kernel;                /* step kernel variant in use (1 direct, 2 LDS ring, 3..6 = 2..5 steps per
                                     sweep) */
   int64_t n_orbitals;            /* orbitals in the batch, vacancies included */
-  double bytes_per_step;         /* algorithmic HBM bytes per recursion step (variants 3/4/5: two vectors
-                                    and the site arrays in, two vectors out, per sweep of 2/3/4 steps) */
+  double bytes_per_step;         /* algorithmic HBM bytes per recursion step (variants 3..6: two vectors
+                                    and the site arrays in, two vectors out, per sweep of 2..5 steps) */
   double last_loop_ms;           /* step loop of the last run (hipEvents on the run's stream) */
   double last_run_ms;            /* whole last run (hipEvents) */
   int64_t n_active_total;        /* active orbitals summed over lattices (after the last run) */
@@ -165,7 +165,7 @@ int kpm_moments_dos(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
 /*
  * Launch-shape autotuner (the analogue of the paper's user-tuned TILE size,
  * Sec. 3(b) and Table 1).  Runs the recursion for probe_steps steps with each
- * candidate (kernel variant 1..5 x block x rows x grid) on the given
+ * candidate (kernel variant 1..6 x block x rows x grid x chunks) on the given
  * workload, timed with hipEvents on hip_stream, re-times the three fastest on
  * 4 probe_steps steps (median of three rounds), and returns the one with the
  * shortest time per step in *best (and its algorithmic GB/s in *best_gbs, may
@@ -326,51 +326,57 @@ int kpm_reconstruct_sigma(const double* gamma, int32_t M, const double* energies
                           double e_max, double orbitals_per_nm2, double* sigma, int32_t on_device, void* hip_stream);
 
 /*
- * T = 0 Kubo-Bastin conductivity from Gamma^{ab} (any a, b; a = x, b = y is the
- * Hall conductivity), in units of e^2/h: the static limit of the first-order
- * formula (eq. cond 1st order) with the delta function of eq.
+ * Kubo-Bastin conductivity from Gamma^{ab} (any a, b; a = x, b = y is the
+ * Hall conductivity) at chemical potential mu and temperature T, in units of
+ * e^2/h: the static limit of the first-order formula (eq. cond 1st order,
+ * with its Fermi function f) with the delta function of eq.
  * delta_function_cheb_expansion and the CPGF resolvents of eqs.
  * green_function_cheb_expansion(b) at broadening eta, contracted with Gamma as
  * in eq. conductivity_1st_order (the Lambda_nm of a static field):
- *   sigma_ab(mu) = Re{ -2 pi i (N/Omega)/de-^2 int_{-1}^{mu~} d eps
+ *   sigma_ab(mu) = Re{ -2 pi i (N/Omega)/de-^2 int_{-1}^{1} d eps f(eps)
  *                  sum_nm Gamma_nm [Delta_n(eps) g'^R_m(eps) - g'^A_n(eps) Delta_m(eps)] },
- * g' = d g / d eps, mu~ = (mu - de+)/de-, N/Omega = orbitals_per_nm2.  The
- * integral runs in theta (eps = cos theta) over n_theta equal cells of
- * [0, pi] by the midpoint rule, the cell holding theta_mu weighted by its part
- * inside [theta_mu, pi] (n_theta = 0: 4 M).
+ * g' = d g / d eps, f = 1/(1 + exp((E - mu)/kT)), N/Omega = orbitals_per_nm2.
+ * The integral runs in theta (eps = cos theta) over n_theta equal cells of
+ * [0, pi] (n_theta = 0: 4 M): the integrand apart from f at each cell's
+ * midpoint times int_cell f(cos theta) d theta, which at kT_ev = 0 is the
+ * length of the cell inside [theta_mu, pi] (mu~ = (mu - de+)/de- = cos
+ * theta_mu) and at kT_ev > 0 a midpoint sum over 32 sub-cells (the cells
+ * should then be narrower than a few kT).
  * gamma [M][M][2] (re, im) as kpm_moments_cond writes it, energies_ev [K]
  * Fermi energies, sigma [K]; all host (on_device = 0) or all device pointers.
  * Allocates a device workspace of ~16 (Mp^2 + 2 (n_theta + 64) Mp) bytes,
  * Mp = M rounded up to 64, and frees it before returning; synchronises
  * hip_stream.  Errors: KPM_E_INVALID (NULL, M outside [1, 16384], K < 1,
- * e_min >= e_max, eta <= 0, orbitals_per_nm2 <= 0, n_theta outside
+ * e_min >= e_max, eta <= 0, kT < 0, orbitals_per_nm2 <= 0, n_theta outside
  * [0, 2^20]); KPM_E_DEVICE.
  */
 int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, const double* energies_ev, int32_t K, double e_min,
-                                 double e_max, double eta_ev, double orbitals_per_nm2, int32_t n_theta, double* sigma,
-                                 int32_t on_device, void* hip_stream);
+                                 double e_max, double eta_ev, double kT_ev, double orbitals_per_nm2, int32_t n_theta,
+                                 double* sigma, int32_t on_device, void* hip_stream);
 
 /*
- * T = 0 optical conductivity sigma_ab(omega) in units of e^2/h at Fermi energy
- * mu, from the rank-1 Gamma_n^{ab} (kpm_moments_gamma1) and the rank-2
- * Gamma_nm^{a,b} (kpm_moments_cond) of the same lattice and directions
- * (eq. conductivity_1st_order with the Lambda_n and Lambda_nm(omega) of the
- * paper and f = theta(mu - eps)):
+ * Optical conductivity sigma_ab(omega) in units of e^2/h at chemical potential
+ * mu and temperature T (kT_ev, 0 allowed), from the rank-1 Gamma_n^{ab}
+ * (kpm_moments_gamma1) and the rank-2 Gamma_nm^{a,b} (kpm_moments_cond) of
+ * the same lattice and directions (eq. conductivity_1st_order with the
+ * Lambda_n and Lambda_nm(omega) of the paper and the Fermi function f):
  *   sigma(w) = (-2 pi i (N/Omega)/E_w) [ sum_n Gamma_n L_n + (1/de-) sum_nm Gamma_nm L_nm(w) ],
- *   L_n = int_{-1}^{mu~} d eps Delta_n(eps),
- *   L_nm(w) = int_{-1}^{mu~} d eps [g^R_n(eps + w~) Delta_m(eps) + Delta_n(eps) g^A_m(eps - w~)],
+ *   L_n = int d eps f(eps) Delta_n(eps),
+ *   L_nm(w) = int d eps f(eps) [g^R_n(eps + w~) Delta_m(eps) + Delta_n(eps) g^A_m(eps - w~)],
  * E_w = hbar omega > 0 in eV (w~ = E_w/de-), g^{R,A} the CPGF coefficients at
- * broadening eta; energy integrals as in kpm_reconstruct_sigma_bastin.
+ * broadening eta; energy integrals and occupation weights as in
+ * kpm_reconstruct_sigma_bastin.
  * gamma_nm [M][M][2], gamma_n [M][2], omegas_ev [K], sigma [K][2] (re, im);
  * all host (on_device = 0) or all device pointers (the frequencies are copied
  * to the host either way).  Work per frequency: two coefficient tables and
  * one M x M x n_theta contraction.  Allocates and frees a device workspace;
  * synchronises hip_stream.  Errors: KPM_E_INVALID (NULL, M outside
  * [1, 16384], K outside [1, 65536], a frequency <= 0, e_min >= e_max,
- * eta <= 0, orbitals_per_nm2 <= 0, n_theta outside [0, 2^20]); KPM_E_DEVICE.
+ * eta <= 0, kT < 0, orbitals_per_nm2 <= 0, n_theta outside [0, 2^20]);
+ * KPM_E_DEVICE.
  */
 int kpm_reconstruct_sigma_optical(const double* gamma_nm, const double* gamma_n, int32_t M, const double* omegas_ev,
-                                  int32_t K, double mu_ev, double e_min, double e_max, double eta_ev,
+                                  int32_t K, double mu_ev, double e_min, double e_max, double eta_ev, double kT_ev,
                                   double orbitals_per_nm2, int32_t n_theta, double* sigma, int32_t on_device,
                                   void* hip_stream);
 

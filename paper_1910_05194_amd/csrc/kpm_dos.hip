@@ -716,7 +716,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) step_kernel_ring(StepArgs<T> A)
 // tiles still read v_n and v_{n-1} on halos).  nlev < KS runs the first nlev
 // levels only (the last, short sweep of a recursion).
 // ---------------------------------------------------------------------------
-constexpr int kMaxSweep = 4;
+constexpr int kMaxSweep = 5;
 
 template <typename T>
 struct SweepArgs {
@@ -1262,7 +1262,8 @@ template <typename T, int KIND>
 static void* pick_sweep(int ks, bool onsite, bool mask) {
   if (ks == 2) return pick_sweep_ks<T, KIND, 2>(onsite, mask);
   if (ks == 3) return pick_sweep_ks<T, KIND, 3>(onsite, mask);
-  return pick_sweep_ks<T, KIND, 4>(onsite, mask);
+  if (ks == 4) return pick_sweep_ks<T, KIND, 4>(onsite, mask);
+  return pick_sweep_ks<T, KIND, 5>(onsite, mask);
 }
 
 template <typename T>
@@ -1511,13 +1512,13 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     delete P;
     return KPM_E_INVALID;
   }
-  // Kernel variant: 3, 4, 5 = 2, 3, 4 steps per sweep (spinless lattices
+  // Kernel variant: 3..6 = 2..5 steps per sweep (spinless lattices
   // without Peierls phases, room for two more vectors), 2 = LDS row ring,
   // 1 = direct loads.  The default (four steps per sweep where eligible)
   // was the fastest on the graphene workloads in FP32 and FP64.
   const int want = (tune && tune->kernel > 0) ? tune->kernel : 5;
-  if (want < 1 || want > 5) {
-    set_error("kernel must be 0 (default) or 1..5");
+  if (want < 1 || want > 6) {
+    set_error("kernel must be 0 (default) or 1..6");
     delete P;
     return KPM_E_INVALID;
   }
@@ -1542,8 +1543,9 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   }
   // Sweep kernels: by default a tile covers 8 chunks (128 contiguous bytes)
   // of each site, and at least 4 KS thread columns (KS - 1 on each side are
-  // halo); the row rings must fit in LDS, otherwise fewer steps per sweep,
-  // down to the single-step ring.
+  // halo); the row rings must fit in LDS, otherwise (with the workgroup
+  // size left to the library) a smaller workgroup, down to 4 KS thread
+  // columns, and then fewer steps per sweep, down to the single-step ring.
   while (P->variant >= 3) {
     const int ks = P->variant - 1;
     if (chunks > 0) {
@@ -1555,6 +1557,10 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     P->Tx = P->block / (P->n_sub * P->Ew);
     const size_t rings = (4 * (size_t)ks * (P->Tx + 2) + 1) * P->n_sub * P->Ew * 16;
     if (P->Tx >= 2 * ks - 1 && rings <= (size_t)lds_max) break;
+    if (!block_given && chunks == 0 && P->block - 64 >= 4 * ks * P->n_sub * P->Ew) {
+      P->block -= 64;
+      continue;
+    }
     P->variant = (ks == 2) ? 2 : P->variant - 1;
   }
   P->sweep = (P->variant >= 3) ? P->variant - 1 : 1;

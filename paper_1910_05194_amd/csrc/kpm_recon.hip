@@ -280,13 +280,14 @@ extern "C" int kpm_reconstruct_cpgf(const double* mu, int32_t M, const double* e
 namespace kpm {
 
 // ---------------------------------------------------------------------------
-// T = 0 Kubo-Bastin conductivity from Gamma^{ab} (the static limit of the
+// Kubo-Bastin conductivity from Gamma^{ab} (the static limit of the
 // first-order formula, eq. cond 1st order, written with eq.
 // delta_function_cheb_expansion for the delta function and the CPGF
 // coefficients of eqs. green_function_cheb_expansion(b) for the resolvents,
 // contracted with Gamma as in eq. conductivity_1st_order):
-//   sigma_ab(mu) = Re{ -2 pi i (N/Omega)/de-^2 int_{-1}^{mu~} d eps
-//                  sum_nm Gamma_nm [Delta_n(eps) g'^R_m(eps) - g'^A_n(eps) Delta_m(eps)] }  [e^2/h].
+//   sigma_ab(mu) = Re{ -2 pi i (N/Omega)/de-^2 int_{-1}^{1} d eps f(eps)
+//                  sum_nm Gamma_nm [Delta_n(eps) g'^R_m(eps) - g'^A_n(eps) Delta_m(eps)] }  [e^2/h],
+// f the Fermi function at chemical potential mu and temperature T.
 // With eps = cos(theta), Delta_n d eps = (2/pi) cos(n theta) d theta, so the
 // integrand in theta is F(theta) = sum_n D_n(theta) W_n(theta),
 //   D_n = (2/pi) cos(n theta),   W_n = sum_m (g'^R_m Gamma_nm - g'^A_m Gamma_mn),
@@ -294,8 +295,9 @@ namespace kpm {
 // z = eps + i eta~, w = exp(-i arccos z) (the inner root, as above) and
 // s = sqrt(1 - z^2) = i (w - z):
 //   g'^R_n = -2 i w^n (i n / s^2 + z / s^3).
-// theta runs over Q equal cells of [0, pi] (midpoint rule); the cell holding
-// theta_mu counts with the part of it that lies in [theta_mu, pi].
+// theta runs over Q equal cells of [0, pi]: the integrand apart from f at each
+// cell's midpoint, times the cell's occupation weight int_cell f(cos theta)
+// d theta (occ_weight).
 // Kernels: the g'^R and -g'^A tables [Q][Mp]; the contraction on 64 x 64
 // (q, n) tiles with FP64 partial sums per n tile; one workgroup per Fermi
 // energy for the weighted sum, all in a fixed order (deterministic).
@@ -427,19 +429,38 @@ __global__ void __launch_bounds__(256) bastin_contract_kernel(const double2* __r
   }
 }
 
+// Occupation weight of theta-cell q of Q: int_cell f(cos theta) d theta, f the
+// Fermi function 1/(1 + exp((eps - mu~)/kT~)) in rescaled energies.  kT~ = 0:
+// the length of the cell inside [theta_mu, pi] (theta_mu = arccos mu~, 0 or pi
+// outside the spectrum); kT~ > 0: midpoint sum over kFermiSub equal sub-cells.
+constexpr int kFermiSub = 32;
+
+__device__ inline double occ_weight(int q, int Q, double mut, double kTt) {
+  const double h = M_PI / Q;
+  const double lo = q * h;
+  if (kTt == 0.0) {
+    const double th_mu = (mut >= 1.0) ? 0.0 : (mut <= -1.0 ? M_PI : acos(mut));
+    return fmin(fmax(lo + h - fmax(lo, th_mu), 0.0), h);
+  }
+  const double hs = h / kFermiSub;
+  double acc = 0.0;
+  for (int j = 0; j < kFermiSub; ++j) {
+    const double x = (cos(lo + (j + 0.5) * hs) - mut) / kTt;
+    const double ex = exp(-fabs(x));   // no overflow on either side of mu
+    acc += (x > 0.0) ? ex / (1.0 + ex) : 1.0 / (1.0 + ex);
+  }
+  return acc * hs;
+}
+
 __global__ void bastin_sigma_kernel(const double2* part, int n_tiles, int Q, const double* energies, int K,
-                                    double e_min, double e_max, double pref_im, double* sigma) {
+                                    double e_min, double e_max, double kTt, double pref_im, double* sigma) {
   __shared__ double red[256];
   const int k = blockIdx.x;
   const double de_p = 0.5 * (e_max + e_min), de_m = 0.5 * (e_max - e_min);
   const double mut = (energies[k] - de_p) / de_m;
-  const double h = M_PI / Q;
-  const double th_mu = (mut >= 1.0) ? 0.0 : (mut <= -1.0 ? M_PI : acos(mut));
   double acc = 0.0;   // Im of sum_q F_q w_q (pref is purely imaginary: Re(pref F) = -pref_im Im F)
   for (int q = threadIdx.x; q < Q; q += blockDim.x) {
-    const double thq = (q + 0.5) * h;
-    const double lo = fmax(thq - 0.5 * h, th_mu);
-    const double wq = fmin(fmax(thq + 0.5 * h - lo, 0.0), h);
+    const double wq = occ_weight(q, Q, mut, kTt);
     if (wq > 0.0) {
       double fi = 0.0;
       for (int t = 0; t < n_tiles; ++t) fi += part[(int64_t)t * Q + q].y;
@@ -466,14 +487,16 @@ __global__ void pad_gamma_kernel(const double* gamma, int M, int Mp, double2* ou
 }  // namespace kpm
 
 extern "C" int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, const double* energies_ev, int32_t K,
-                                            double e_min, double e_max, double eta_ev, double orbitals_per_nm2,
-                                            int32_t n_theta, double* sigma, int32_t on_device, void* hip_stream) {
+                                            double e_min, double e_max, double eta_ev, double kT_ev,
+                                            double orbitals_per_nm2, int32_t n_theta, double* sigma,
+                                            int32_t on_device, void* hip_stream) {
   using namespace kpm;
   clear_error();
   KPM_CHECK_ARG(gamma && energies_ev && sigma, "NULL argument");
   KPM_CHECK_ARG(M >= 1 && M <= 16384 && K >= 1, "need 1 <= M <= 16384 and K >= 1");
   KPM_CHECK_ARG(std::isfinite(e_min) && std::isfinite(e_max) && e_min < e_max, "need e_min < e_max");
   KPM_CHECK_ARG(eta_ev > 0.0 && std::isfinite(eta_ev), "eta must be > 0");
+  KPM_CHECK_ARG(kT_ev >= 0.0 && std::isfinite(kT_ev), "kT must be >= 0");
   KPM_CHECK_ARG(orbitals_per_nm2 > 0.0, "orbitals_per_nm2 must be > 0");
   KPM_CHECK_ARG(n_theta >= 0 && n_theta <= (1 << 20), "n_theta must be in [0, 2^20]");
   const int Q = n_theta > 0 ? n_theta : 4 * M;
@@ -518,7 +541,7 @@ extern "C" int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, cons
                        tab + (size_t)Qp * Mp, gam, Q, Mp, part);
     // pref = -2 pi i (N/Omega)/de-^2 is imaginary: Re(pref F) = -Im(pref) Im(F).
     hipLaunchKernelGGL(bastin_sigma_kernel, dim3(K), dim3(256), 0, s, part, n_tiles, Q, den, K, e_min, e_max,
-                       -2.0 * M_PI * orbitals_per_nm2 / (de_m * de_m), dsig);
+                       kT_ev / de_m, -2.0 * M_PI * orbitals_per_nm2 / (de_m * de_m), dsig);
     e = hipGetLastError();
   }
   if (e == hipSuccess && !on_device) {
@@ -536,28 +559,22 @@ extern "C" int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, cons
 namespace kpm {
 
 // ---------------------------------------------------------------------------
-// Optical conductivity sigma_ab(omega) at T = 0 and Fermi energy mu (eq. cond
-// 1st order, rank-1 and rank-2 Gamma of eq. Gammanm, Lambda_n and
-// Lambda_nm(omega), combined as in eq. conductivity_1st_order):
+// Optical conductivity sigma_ab(omega) at chemical potential mu and
+// temperature T (eq. cond 1st order, rank-1 and rank-2 Gamma of eq. Gammanm,
+// Lambda_n and Lambda_nm(omega), combined as in eq. conductivity_1st_order):
 //   sigma(w)/(e^2/h) = (-2 pi i (N/Omega)/E_w) [ sum_n Gamma_n L_n + (1/de-) sum_nm Gamma_nm L_nm(w) ],
-//   L_n = int_{-1}^{mu~} Delta_n,  L_nm(w) = int_{-1}^{mu~} [g^R_n(eps + w~) Delta_m + Delta_n g^A_m(eps - w~)],
-// in theta with the quadrature of the Kubo-Bastin reconstruction.  The
+//   L_n = int f Delta_n,  L_nm(w) = int f [g^R_n(eps + w~) Delta_m + Delta_n g^A_m(eps - w~)],
+// in theta with the quadrature and occupation weights of the Kubo-Bastin
+// reconstruction.  The
 // rank-2 part is the same contraction with ta = g^A(eps - w~) and
 // tb = g^R(eps + w~): sum_n D_n sum_m (g^A_m Gamma_nm + g^R_m Gamma_mn).
 // ---------------------------------------------------------------------------
-__device__ inline double cell_weight(int q, int Q, double th_mu) {
-  const double h = M_PI / Q;
-  const double thq = (q + 0.5) * h;
-  const double lo = fmax(thq - 0.5 * h, th_mu);
-  return fmin(fmax(thq + 0.5 * h - lo, 0.0), h);
-}
-
 // out = sum_q w_q sum_n Gamma1_n D_n(theta_q) (one workgroup, fixed order).
-__global__ void optical_rank1_kernel(const double* g1, int M, int Q, double th_mu, double* out) {
+__global__ void optical_rank1_kernel(const double* g1, int M, int Q, double mut, double kTt, double* out) {
   __shared__ double sr[256], si[256];
   double ar = 0.0, ai = 0.0;
   for (int q = threadIdx.x; q < Q; q += blockDim.x) {
-    const double wq = cell_weight(q, Q, th_mu);
+    const double wq = occ_weight(q, Q, mut, kTt);
     if (wq <= 0.0) continue;
     const double th = (q + 0.5) * M_PI / Q;
     double cr = 0.0, ci = 0.0;
@@ -586,11 +603,11 @@ __global__ void optical_rank1_kernel(const double* g1, int M, int Q, double th_m
 }
 
 // para = sum_q w_q sum_t part[t][q] (one workgroup, fixed order).
-__global__ void optical_para_kernel(const double2* part, int n_tiles, int Q, double th_mu, double* para) {
+__global__ void optical_para_kernel(const double2* part, int n_tiles, int Q, double mut, double kTt, double* para) {
   __shared__ double sr[256], si[256];
   double ar = 0.0, ai = 0.0;
   for (int q = threadIdx.x; q < Q; q += blockDim.x) {
-    const double wq = cell_weight(q, Q, th_mu);
+    const double wq = occ_weight(q, Q, mut, kTt);
     if (wq <= 0.0) continue;
     double fr = 0.0, fi = 0.0;
     for (int t = 0; t < n_tiles; ++t) {
@@ -631,8 +648,8 @@ __global__ void optical_final_kernel(const double* para, const double* lam, cons
 
 extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const double* gamma_n, int32_t M,
                                              const double* omegas_ev, int32_t K, double mu_ev, double e_min,
-                                             double e_max, double eta_ev, double orbitals_per_nm2, int32_t n_theta,
-                                             double* sigma, int32_t on_device, void* hip_stream) {
+                                             double e_max, double eta_ev, double kT_ev, double orbitals_per_nm2,
+                                             int32_t n_theta, double* sigma, int32_t on_device, void* hip_stream) {
   using namespace kpm;
   clear_error();
   KPM_CHECK_ARG(gamma_nm && gamma_n && omegas_ev && sigma, "NULL argument");
@@ -640,6 +657,7 @@ extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const doubl
   KPM_CHECK_ARG(std::isfinite(e_min) && std::isfinite(e_max) && e_min < e_max, "need e_min < e_max");
   KPM_CHECK_ARG(std::isfinite(mu_ev), "mu must be finite");
   KPM_CHECK_ARG(eta_ev > 0.0 && std::isfinite(eta_ev), "eta must be > 0");
+  KPM_CHECK_ARG(kT_ev >= 0.0 && std::isfinite(kT_ev), "kT must be >= 0");
   KPM_CHECK_ARG(orbitals_per_nm2 > 0.0, "orbitals_per_nm2 must be > 0");
   KPM_CHECK_ARG(n_theta >= 0 && n_theta <= (1 << 20), "n_theta must be in [0, 2^20]");
   hipStream_t s = (hipStream_t)hip_stream;
@@ -658,7 +676,7 @@ extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const doubl
   const int n_tiles = Mp / kBT;
   const double de_p = 0.5 * (e_max + e_min), de_m = 0.5 * (e_max - e_min);
   const double mut = (mu_ev - de_p) / de_m;
-  const double th_mu = mut >= 1.0 ? 0.0 : (mut <= -1.0 ? M_PI : std::acos(mut));
+  const double kTt = kT_ev / de_m;
   const size_t b_gam = sizeof(double2) * (size_t)Mp * Mp;
   const size_t b_tab = 2 * sizeof(double2) * (size_t)Qp * Mp;
   const size_t b_part = sizeof(double2) * (size_t)n_tiles * Q;
@@ -691,7 +709,7 @@ extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const doubl
   if (e == hipSuccess) {
     hipLaunchKernelGGL(pad_gamma_kernel, dim3((unsigned)ceil_div((int64_t)Mp * Mp, 256)), dim3(256), 0, s, dgnm, M,
                        Mp, gam);
-    hipLaunchKernelGGL(optical_rank1_kernel, dim3(1), dim3(256), 0, s, dgn, M, Q, th_mu, lam);
+    hipLaunchKernelGGL(optical_rank1_kernel, dim3(1), dim3(256), 0, s, dgn, M, Q, mut, kTt, lam);
     const double eta = eta_ev / de_m;
     for (int k = 0; k < K && e == hipSuccess; ++k) {
       const double wt = om[k] / de_m;
@@ -700,7 +718,8 @@ extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const doubl
       hipLaunchKernelGGL(cpgf_table_kernel, dim3((unsigned)ceil_div(Q, 256)), dim3(256), 0, s, Q, M, Mp, wt, eta, 0, 0,
                          tb);   // g^R(eps + w~)
       hipLaunchKernelGGL(bastin_contract_kernel, dim3(Qp / kBT, n_tiles), dim3(256), 0, s, ta, tb, gam, Q, Mp, part);
-      hipLaunchKernelGGL(optical_para_kernel, dim3(1), dim3(256), 0, s, part, n_tiles, Q, th_mu, para + 2 * k);
+      hipLaunchKernelGGL(optical_para_kernel, dim3(1), dim3(256), 0, s, part, n_tiles, Q, mut, kTt,
+                         para + 2 * k);
       e = hipGetLastError();
     }
     if (e == hipSuccess) {

@@ -2,7 +2,7 @@
 //
 // The paper leaves the TILE size of its CPU blocking to the user, who must
 // tune it per machine (Sec. 3(b); Sec. 5, Table 1).  Here the analogous
-// choices are the kernel variant (one step or 2..4 steps per sweep),
+// choices are the kernel variant (one step or 2..5 steps per sweep),
 // workgroup size, rows per tile, the site chunks a tile covers and the
 // persistent grid; kpm_autotune measures each candidate on the real workload
 // (a short recursion of probe_steps steps, timed with hipEvents on the
@@ -118,18 +118,21 @@ static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
   // Candidates: the single-step kernels over workgroup size, rows per tile
   // and persistent grid; the sweep kernels over workgroup size, rows per
   // tile and the site chunks a tile covers (the library's choice, 4 and 16:
-  // wider and narrower tiles), duplicates of an already screened shape
-  // skipped.
+  // wider and narrower tiles; 448 threads is the largest workgroup whose
+  // five-step rings fit in LDS at the library's chunks), duplicates of an
+  // already screened shape and shapes that fell back to fewer steps skipped.
   struct Cand { int kernel, block, rows, grid, chunks; };
   std::vector<Cand> cands;
   for (int kv : {1, 2})
     for (int b : {256, 512})
       for (int r : {32, 128})
         for (int g : {1024, 2048}) cands.push_back({kv, b, r, g, 0});
-  for (int kv : {3, 4, 5})
-    for (int b : {256, 512})
+  for (int kv : {3, 4, 5, 6})
+    for (int b : {256, 448, 512}) {
+      if (b == 448 && kv != 6) continue;
       for (int r : {32, 128})
         for (int c : {0, 4, 16}) cands.push_back({kv, b, r, 2048, c});
+    }
   std::vector<std::pair<double, kpm_tune_t>> screened;
   std::vector<std::array<int, 5>> seen;   // (variant, block, rows, grid, chunks in use)
   for (const Cand& cd : cands) {

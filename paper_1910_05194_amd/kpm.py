@@ -105,11 +105,11 @@ def _load():
                                                  ctypes.c_double, ctypes.c_double, _P, ctypes.c_int32, _P]),
         "kpm_reconstruct_sigma_bastin": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_double,
                                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                                        ctypes.c_int32, _P, ctypes.c_int32, _P]),
+                                                        ctypes.c_double, ctypes.c_int32, _P, ctypes.c_int32, _P]),
         "kpm_reconstruct_sigma_optical": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, ctypes.c_int32,
                                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P,
-                                                         ctypes.c_int32, _P]),
+                                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                                         ctypes.c_int32, _P, ctypes.c_int32, _P]),
         "kpm_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                           ctypes.POINTER(_P)]),
         "kpm_mlp_destroy": (ctypes.c_int, [_P]),
@@ -442,17 +442,18 @@ def reconstruct_sigma(gamma, energies, e_min: float, e_max: float, orbitals_per_
 
 
 def reconstruct_sigma_bastin(gamma, energies, e_min: float, e_max: float, eta: float, orbitals_per_nm2: float,
-                             n_theta: int = 0, stream=None):
-    """kpm_reconstruct_sigma_bastin: T = 0 Kubo-Bastin sigma_ab(mu) in e^2/h from Gamma^{ab}
-    ([M, M] complex numpy or [M, M, 2] float64 torch on the device); eta in eV."""
+                             n_theta: int = 0, stream=None, kT: float = 0.0):
+    """kpm_reconstruct_sigma_bastin: Kubo-Bastin sigma_ab(mu) in e^2/h from Gamma^{ab}
+    ([M, M] complex numpy or [M, M, 2] float64 torch on the device) at chemical potentials
+    ``energies`` and temperature kT; eta and kT in eV."""
     if isinstance(gamma, np.ndarray):
         g = np.ascontiguousarray(np.stack([gamma.real, gamma.imag], axis=-1)) if np.iscomplexobj(gamma) else \
             np.ascontiguousarray(gamma, dtype=np.float64)
         en = np.ascontiguousarray(np.atleast_1d(energies), dtype=np.float64)
         out = np.zeros(en.shape)
         _check(LIB.kpm_reconstruct_sigma_bastin(g.ctypes.data, g.shape[0], en.ctypes.data, en.size, float(e_min),
-                                                float(e_max), float(eta), float(orbitals_per_nm2), int(n_theta),
-                                                out.ctypes.data, 0, _stream_handle(stream)))
+                                                float(e_max), float(eta), float(kT), float(orbitals_per_nm2),
+                                                int(n_theta), out.ctypes.data, 0, _stream_handle(stream)))
         return out
     import torch
     g = gamma.contiguous()
@@ -461,22 +462,23 @@ def reconstruct_sigma_bastin(gamma, energies, e_min: float, e_max: float, eta: f
     if stream is None:
         stream = torch.cuda.current_stream(g.device)
     _check(LIB.kpm_reconstruct_sigma_bastin(g.data_ptr(), g.shape[0], en.data_ptr(), en.numel(), float(e_min),
-                                            float(e_max), float(eta), float(orbitals_per_nm2), int(n_theta),
-                                            out.data_ptr(), 1, _stream_handle(stream)))
+                                            float(e_max), float(eta), float(kT), float(orbitals_per_nm2),
+                                            int(n_theta), out.data_ptr(), 1, _stream_handle(stream)))
     return out
 
 
 def reconstruct_sigma_optical(gamma_nm, gamma_n, omegas, mu: float, e_min: float, e_max: float, eta: float,
-                              orbitals_per_nm2: float, n_theta: int = 0, stream=None):
-    """kpm_reconstruct_sigma_optical: complex sigma_ab(omega) in e^2/h (T = 0, Fermi energy mu in eV) from
-    the rank-2 and rank-1 Gamma (numpy complex [M, M] and [M], or float64 torch [M, M, 2] and [M, 2])."""
+                              orbitals_per_nm2: float, n_theta: int = 0, stream=None, kT: float = 0.0):
+    """kpm_reconstruct_sigma_optical: complex sigma_ab(omega) in e^2/h (chemical potential mu and
+    temperature kT in eV) from the rank-2 and rank-1 Gamma (numpy complex [M, M] and [M], or float64
+    torch [M, M, 2] and [M, 2])."""
     if isinstance(gamma_nm, np.ndarray):
         g2 = np.ascontiguousarray(np.stack([gamma_nm.real, gamma_nm.imag], axis=-1), dtype=np.float64)
         g1 = np.ascontiguousarray(np.stack([np.real(gamma_n), np.imag(gamma_n)], axis=-1), dtype=np.float64)
         om = np.ascontiguousarray(np.atleast_1d(omegas), dtype=np.float64)
         out = np.zeros((om.size, 2))
         _check(LIB.kpm_reconstruct_sigma_optical(g2.ctypes.data, g1.ctypes.data, g2.shape[0], om.ctypes.data, om.size,
-                                                 float(mu), float(e_min), float(e_max), float(eta),
+                                                 float(mu), float(e_min), float(e_max), float(eta), float(kT),
                                                  float(orbitals_per_nm2), int(n_theta), out.ctypes.data, 0,
                                                  _stream_handle(stream)))
         return out[:, 0] + 1j * out[:, 1]
@@ -488,7 +490,7 @@ def reconstruct_sigma_optical(gamma_nm, gamma_n, omegas, mu: float, e_min: float
     if stream is None:
         stream = torch.cuda.current_stream(g2.device)
     _check(LIB.kpm_reconstruct_sigma_optical(g2.data_ptr(), g1.data_ptr(), g2.shape[0], om.data_ptr(), om.numel(),
-                                             float(mu), float(e_min), float(e_max), float(eta),
+                                             float(mu), float(e_min), float(e_max), float(eta), float(kT),
                                              float(orbitals_per_nm2), int(n_theta), out.data_ptr(), 1,
                                              _stream_handle(stream)))
     return out

@@ -124,9 +124,10 @@ def _qahe(L, W=0.0, seed=0):
 
 def test_sigma_bastin_matches_oracle(K):
     """kpm_reconstruct_sigma_bastin against the oracle's sigma_bastin (same
-    quadrature): the exact Gamma^xy of a disordered 4 x 4 QAHE model (M = 256),
-    and a random complex Gamma with M = 100 (padding to the 64-wide tiles), host
-    and device pointers, Fermi energies inside and outside the spectrum."""
+    quadrature): the exact Gamma^xy of a disordered 4 x 4 QAHE model (M = 256) at
+    T = 0 and kT = 5, 50, 300 meV, and a random complex Gamma with M = 100 (padding
+    to the 64-wide tiles), host and device pointers, chemical potentials inside and
+    outside the spectrum."""
     import torch
     lat = _qahe(4, W=1.0, seed=9)
     m = olat.build(lat)
@@ -139,6 +140,12 @@ def test_sigma_bastin_matches_oracle(K):
         err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
         print(f"bastin eta {eta}: rel err {err:.2e}")
         assert err <= 1e-10
+    for kT in (0.005, 0.05, 0.3):
+        ref = ocond.sigma_bastin(G, E, lat.e_min, lat.e_max, 0.05, opn, 1024, kT_ev=kT)
+        got = K.reconstruct_sigma_bastin(G, E, lat.e_min, lat.e_max, 0.05, opn, n_theta=1024, kT=kT)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"bastin kT {kT}: rel err {err:.2e}")
+        assert err <= 1e-10
     rng = np.random.default_rng(4)
     Gr = (rng.standard_normal((100, 100)) + 1j * rng.standard_normal((100, 100))) * 1e-3
     ref = ocond.sigma_bastin(Gr, E, -7.0, 9.0, 0.05, 30.0, 400)
@@ -149,6 +156,8 @@ def test_sigma_bastin_matches_oracle(K):
     assert np.array_equal(gd.cpu().numpy(), got)
     with pytest.raises(K.KPMError):
         K.reconstruct_sigma_bastin(Gr, E, -7.0, 9.0, 0.0, 30.0)
+    with pytest.raises(K.KPMError):
+        K.reconstruct_sigma_bastin(Gr, E, -7.0, 9.0, 0.05, 30.0, kT=-0.01)
 
 
 def test_gamma_xy_with_exchange_split_bf16(K):
@@ -170,7 +179,8 @@ def test_qahe_hall_plateau_end_to_end(K):
     the Chern number 2 and the 2 e^2/h Kubo sum).  Production path: FP32 chains,
     split-BF16 Gamma^xy, 512 x 512 cells (1,048,576 orbitals), M = 1024, R = 1,
     CPGF eta = 50 meV.  Measured 1.988-2.002 at |E| <= 0.5 eV (gap |E| < 0.62);
-    gate 1.5 %."""
+    gate 1.5 %.  At room temperature (kT = 25.9 meV, far below the half-gap) the
+    plateau holds at |mu| <= 0.3 eV to the same gate."""
     import torch
     L = 512
     lat = _qahe(L)
@@ -183,6 +193,9 @@ def test_qahe_hall_plateau_end_to_end(K):
     s = K.reconstruct_sigma_bastin(G, E, lat.e_min, lat.e_max, 0.05, opn).cpu().numpy()
     print("QAHE sigma_xy:", np.round(s, 4))
     assert np.max(np.abs(s - 2.0)) < 0.03, s
+    sT = K.reconstruct_sigma_bastin(G, E[1:4], lat.e_min, lat.e_max, 0.05, opn, kT=0.0259).cpu().numpy()
+    print("QAHE sigma_xy at kT = 25.9 meV:", np.round(sT, 4))
+    assert np.max(np.abs(sT - 2.0)) < 0.03, sT
 
 
 @pytest.mark.parametrize("lat", [LATS[0], LATS[1], LATS[3]], ids=["spin-flux", "honeycomb", "qahe"])
@@ -205,7 +218,8 @@ def test_gamma1_parity(K, lat, ab):
 def test_sigma_optical_matches_oracle(K):
     """kpm_reconstruct_sigma_optical against the oracle's sigma_optical (same
     quadrature) on the exact Gammas of the disordered 4 x 4 QAHE model (M = 200,
-    padding to 256), xx and xy, several frequencies; host and device pointers."""
+    padding to 256), xx and xy, several frequencies, T = 0 and kT = 0.2 eV; host
+    and device pointers."""
     import torch
     lat = _qahe(4, W=1.0, seed=9)
     m = olat.build(lat)
@@ -218,6 +232,11 @@ def test_sigma_optical_matches_oracle(K):
         got = K.reconstruct_sigma_optical(G2, G1, W, 0.1, lat.e_min, lat.e_max, 0.1, opn, n_theta=900)
         err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
         print(f"optical {ab}: rel err {err:.2e}")
+        assert err <= 1e-10
+        ref = ocond.sigma_optical(G2, G1, W, 0.1, lat.e_min, lat.e_max, 0.1, opn, 900, kT_ev=0.2)
+        gT = K.reconstruct_sigma_optical(G2, G1, W, 0.1, lat.e_min, lat.e_max, 0.1, opn, n_theta=900, kT=0.2)
+        err = np.max(np.abs(gT - ref)) / np.max(np.abs(ref))
+        print(f"optical {ab} kT 0.2: rel err {err:.2e}")
         assert err <= 1e-10
     g2t = torch.tensor(np.stack([G2.real, G2.imag], -1), device="cuda")
     g1t = torch.tensor(np.stack([G1.real, G1.imag], -1), device="cuda")

@@ -241,7 +241,7 @@ def test_autotune_cache(K, tmp_path, monkeypatch):
     par = wl.DosParams(num_moments=64, num_random=4, vector_seed=1, precision=wl.FP32)
     cache = str(tmp_path / "tune.txt")
     best = K.autotune([lat], par, probe_steps=4, cache_path=cache)
-    assert best["kernel"] in (1, 2, 3, 4, 5) and best["block"] in (256, 512) and best["GBs"] > 0
+    assert best["kernel"] in (1, 2, 3, 4, 5, 6) and best["block"] in (256, 448, 512) and best["GBs"] > 0
     line = open(cache).read().strip().split()
     assert [int(v) for v in line[4:9]] == [best["kernel"], best["block"], best["rows"], best["grid"], best["chunks"]]
     monkeypatch.setenv("KPM_TUNE_CACHE", cache)
@@ -271,9 +271,9 @@ SWEEP_LATS = [
 
 @pytest.mark.parametrize("lat", SWEEP_LATS, ids=lambda l: f"{wl.KIND_NAMES[l.kind]}{l.L1}x{l.L2}")
 @pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("kernel", [3, 4, 5], ids=["ks2", "ks3", "ks4"])
+@pytest.mark.parametrize("kernel", [3, 4, 5, 6], ids=["ks2", "ks3", "ks4", "ks5"])
 def test_sweep_kernel_matches_single_step_and_oracle(K, lat, prec, kernel):
-    """The multi-step sweep kernels (variants 3/4/5: 2/3/4 steps per launch)
+    """The multi-step sweep kernels (variants 3..6: 2..5 steps per launch)
     against the single-step ring kernel and the oracle: step counts that end
     on a full and on every kind of short last sweep (M = 2 is one step), tile
     shapes down to one row and one r-chunk, halo columns that wrap onto the
@@ -299,7 +299,7 @@ def test_sweep_kernel_matches_single_step_and_oracle(K, lat, prec, kernel):
 
 
 @pytest.mark.parametrize("prec", [wl.FP64, wl.FP32], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("kernel", [3, 4, 5], ids=["ks2", "ks3", "ks4"])
+@pytest.mark.parametrize("kernel", [3, 4, 5, 6], ids=["ks2", "ks3", "ks4", "ks5"])
 def test_sweep_uneven_batch_and_ldos(K, prec, kernel):
     """Uneven lattices of both spinless kinds in one sweep plan, several
     r-groups per tile (R = 40), and LDOS start vectors."""
@@ -329,7 +329,7 @@ def test_sweep_uneven_batch_and_ldos(K, prec, kernel):
     assert np.max(np.abs(mu[0] - mu_o)) <= (1e-10 if prec == wl.FP64 else fp32_tol(24))
 
 
-@pytest.mark.parametrize("kernel", [3, 4, 5], ids=["ks2", "ks3", "ks4"])
+@pytest.mark.parametrize("kernel", [3, 4, 5, 6], ids=["ks2", "ks3", "ks4", "ks5"])
 def test_sweep_kernel_falls_back_where_ineligible(K, kernel):
     """Spinful lattices and Peierls phases take the single-step ring kernel."""
     par = wl.DosParams(num_moments=16, num_random=2, vector_seed=3, precision=wl.FP32)
