@@ -6,7 +6,7 @@ random-phase complex64 vectors batched in one recursion, FP32 recursion with
 FP64 moment accumulation.  One bench "step" is one complete pass of the DOS
 path on that input: disorder/model build, start vectors, ceil(M/2) = 1024
 Chebyshev steps with fused moments (ceil(1024 / KS) launches of a sweep
-kernel that does KS = 2..4 steps per launch, or 1024 single-step launches,
+kernel that does KS = 2..5 steps per launch, or 1024 single-step launches,
 replayed from a hipGraph), the moment
 reduction, and the Jackson DOS reconstruction on 1024 energies.  The kernel
 variant and launch shape come from the library's autotuner (run before the
@@ -119,7 +119,8 @@ def _timed(fn):
 
 def leg_hall(kpm, wl, np):
     """QAHE Hall conductivity: Gamma^xy on 512^2 spinful cells (M = 1024, R = 1) and the
-    T = 0 Kubo-Bastin reconstruction at 5 Fermi energies in the gap (plateau 2 e^2/h)."""
+    Kubo-Bastin reconstruction at 5 chemical potentials in the gap (plateau 2 e^2/h), at
+    T = 0 and at room temperature (kT = 25.9 meV)."""
     import torch
     lat, par = wl.qahe()
     opn = 4 / (wl.A_HONEYCOMB ** 2 * np.sqrt(3) / 2)
@@ -128,11 +129,15 @@ def leg_hall(kpm, wl, np):
     E = torch.tensor([-0.5, -0.3, 0.0, 0.3, 0.5], dtype=torch.float64, device="cuda")
     s, dt_r = _timed(lambda: kpm.reconstruct_sigma_bastin(G, E, lat.e_min, lat.e_max, 0.05, opn))
     s = s.cpu().numpy()
+    sT, dt_rT = _timed(lambda: kpm.reconstruct_sigma_bastin(G, E, lat.e_min, lat.e_max, 0.05, opn, kT=0.0259))
+    sT = sT.cpu().numpy()
     return {"workload": "QAHE spinful honeycomb 512^2 (lambda_R = 0.3|t|, Delta_ex = 0.4|t|), Gamma^xy M=1024, R=1, "
-                        "split-BF16; T=0 Kubo-Bastin at eta = 50 meV",
+                        "split-BF16; Kubo-Bastin at eta = 50 meV, T = 0 and kT = 25.9 meV",
             "gamma_s": dt_g, "chain_ms": st["chain_ms"], "gemm_ms": st["gemm_ms"], "reconstruct_s": dt_r,
             "sigma_xy_e2h": dict(zip(map(float, E.cpu().numpy()), map(float, s))),
-            "max_dev_from_2": float(np.max(np.abs(s - 2.0)))}
+            "max_dev_from_2": float(np.max(np.abs(s - 2.0))),
+            "sigma_xy_e2h_kT_25.9meV": dict(zip(map(float, E.cpu().numpy()), map(float, sT))),
+            "reconstruct_kT_s": dt_rT}
 
 
 def leg_optical(kpm, wl, np):
@@ -444,9 +449,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(info, args),
-                     "kernel": {1: "kpm::step_kernel", 2: "kpm::step_kernel_ring",
-                                3: "kpm::sweep_kernel<KS=2>", 4: "kpm::sweep_kernel<KS=3>",
-                                5: "kpm::sweep_kernel<KS=4>"}[info["kernel"]] + " (FP32, honeycomb, on-site array)",
+                     "kernel": ({1: "kpm::step_kernel", 2: "kpm::step_kernel_ring"}.get(info["kernel"])
+                                or f"kpm::sweep_kernel<KS={info['kernel'] - 1}>") + " (FP32, honeycomb, on-site array)",
                      "steps_per_launch": steps_per_launch,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_launch_ms,
                      # What a one-step-per-launch kernel (read v_n, v_(n-1) and the site
