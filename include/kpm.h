@@ -289,12 +289,15 @@ int kpm_moments_gamma1(const kpm_lattice_t* lat, const kpm_cond_params_t* p, dou
  * Omega = L1 L2 * cell area, with the stochastic trace over the random phases
  * of kpm_moments_cond (same seed, same vectors): -(1/R) sum_r <a|b>,
  * a = d_eta h~^a r, b = h~^b d_eta r.  Two Chebyshev recursions per vector of
- * p->num_moments steps serve all K energies (2 K accumulator vectors; the
- * energies are batched to fit the free device memory).  Uses num_moments
- * (>= 2), num_random, vector_seed, alpha, beta, precision.  energies_ev [K]
- * (1 <= K <= 4096), sigma [K]: both host (on_device = 0) or both device.
- * Errors: as kpm_moments_cond; KPM_E_INVALID also for eta <= 0; KPM_E_NOMEM
- * when not even one energy's accumulators fit.
+ * p->num_moments steps serve all K energies: each writes its vectors into a
+ * history of B (3..64) vectors, flushed every B steps into 2 K accumulator
+ * vectors (B and the energies per batch fitted to the free device memory;
+ * workspace B + 2 kb + 2 vectors of n_orbitals x R_padded complex values).
+ * Uses num_moments (>= 2), num_random, vector_seed, alpha, beta, precision.
+ * energies_ev [K] (1 <= K <= 4096), sigma [K]: both host (on_device = 0) or
+ * both device.  Errors: as kpm_moments_cond; KPM_E_INVALID also for eta <= 0;
+ * KPM_E_NOMEM when not even a 3-vector history and one energy's accumulators
+ * fit.
  */
 int kpm_sigma_singleshot(const kpm_lattice_t* lat, const kpm_cond_params_t* p, const double* energies_ev, int32_t K,
                          double eta_ev, double* sigma, int32_t out_on_device, void* hip_stream);

@@ -392,16 +392,41 @@ static int gamma1_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, doub
 // (CPGF coefficients of eq. green_function_cheb_expansionb at z~ = eps + i eta~),
 // with the stochastic trace -(1/R) sum_r <a|b>, a = d_eta h~^a r, b = h~^b d_eta r.
 // Two recursions per vector serve every energy: the accumulators
-// A_k = sum_n c_n(E_k) T_n(H~) h~^a r and B_k = sum_n c_n(E_k) T_n(H~) r are
-// updated after each step by one kernel that reads the new vector once.
-// Energies are processed in batches sized to the free device memory.
+// A_k = sum_n c_n(E_k) T_n(H~) h~^a r and B_k = sum_n c_n(E_k) T_n(H~) r.
+// Each recursion writes T_n x into slot n mod B of a history of B vectors;
+// every B steps one pass reads the B vectors once and adds their weighted sum
+// to each accumulator (read and written once per B steps instead of once per
+// step: per step 1 + 2 K / B vectors move instead of 2 K).  B (<= 64) and the
+// energies per batch are sized to the free device memory.
 // ---------------------------------------------------------------------------
+constexpr int kMaxHist = 64;    // history vectors per flush
+constexpr int kAccGroup = 16;   // energies per flush pass (FP64 sums in registers)
+
 template <typename T>
-__global__ void accumulate_kernel(const T* __restrict__ v, T* __restrict__ acc, int64_t n_elems, int64_t stride,
-                                  const double* __restrict__ coef, int K) {
+struct HistPtrs {
+  const T* v[kMaxHist];
+};
+
+// acc_k[i] += sum_{b < nb} coef[b ldc + k] v_b[i] for k < kk <= kAccGroup; the
+// coefficient rows hold kAccGroup valid entries (zero padded).  One element per
+// thread, its kAccGroup sums in FP64, the accumulator rounded once per flush.
+template <typename T>
+__global__ void accumulate_block_kernel(HistPtrs<T> H, int nb, int64_t n_elems, T* __restrict__ acc, int64_t stride,
+                                        const double* __restrict__ coef, int ldc, int kk) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_elems; i += (int64_t)gridDim.x * blockDim.x) {
-    const double x = (double)v[i];
-    for (int k = 0; k < K; ++k) acc[k * stride + i] = (T)((double)acc[k * stride + i] + coef[k] * x);
+    double a[kAccGroup];
+#pragma unroll
+    for (int k = 0; k < kAccGroup; ++k) a[k] = 0.0;
+#pragma unroll 4
+    for (int b = 0; b < nb; ++b) {
+      const double x = (double)H.v[b][i];
+      const double* c = coef + (int64_t)b * ldc;
+#pragma unroll
+      for (int k = 0; k < kAccGroup; ++k) a[k] += c[k] * x;
+    }
+#pragma unroll
+    for (int k = 0; k < kAccGroup; ++k)
+      if (k < kk) acc[k * stride + i] = (T)((double)acc[k * stride + i] + a[k]);
   }
 }
 
@@ -440,7 +465,11 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
   // Coefficients c_n(E_k) (host, FP64): g_n(z) = -2i w^n / sqrt(1 - z^2), w = exp(-i arccos z)
   // the root of w^2 - 2 z w + 1 inside the unit circle, sqrt(1 - z^2) = i (w - z).
   const double de_p = 0.5 * (lat->e_max + lat->e_min), de_m = 0.5 * (lat->e_max - lat->e_min);
-  std::vector<double> coef((size_t)K * M);
+  // [n][Kp], Kp = K rounded up to kAccGroup, zero padded, plus kAccGroup zeros at
+  // the end: a flush pass reads kAccGroup entries of a row from any energy
+  // offset (a batch need not start at a multiple of kAccGroup), and uses kk.
+  const int Kp = (int)ceil_div(K, kAccGroup) * kAccGroup;
+  std::vector<double> coef((size_t)Kp * M + kAccGroup, 0.0);
   for (int k = 0; k < K; ++k) {
     typedef std::complex<double> cd;
     const cd z((en[k] - de_p) / de_m, eta_ev / de_m);
@@ -450,7 +479,7 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
     const cd pre = -2.0 / (w - z);   // g_n = pre w^n
     cd pw(1.0, 0.0);
     for (int n = 0; n < M; ++n) {
-      coef[(size_t)n * K + k] = -std::imag(pre * pw) / (M_PI * de_m) / (n == 0 ? 2.0 : 1.0);
+      coef[(size_t)n * Kp + k] = -std::imag(pre * pw) / (M_PI * de_m) / (n == 0 ? 2.0 : 1.0);
       pw *= w;
     }
   }
@@ -472,19 +501,25 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
   size_t free_b = 0, total_b = 0;
   int st = KPM_OK;
   hipError_t e = hipMemGetInfo(&free_b, &total_b);
-  // Energies per batch: 2 accumulators each, plus the start copy and a scratch vector.
-  int kb = (int)std::min<double>(K, std::floor((0.85 * (double)free_b - 2.0 * vec_b - 1.0e9) / (2.0 * vec_b)));
+  // Room in vectors besides the start copy and a scratch vector: the history
+  // takes up to a third of it (3 <= B <= 64, no more than M), each energy of a
+  // batch two accumulators.
+  const double room = std::floor((0.85 * (double)free_b - 2.0 * vec_b - 1.0e9) / (double)vec_b);
+  const int B = (int)std::max(3.0, std::min<double>(std::min(kMaxHist, M), std::floor(room / 3.0)));
+  const int kb = (int)std::min<double>(K, std::floor((room - B) / 2.0));
   if (e == hipSuccess && kb < 1) {
-    set_error("not enough device memory for the single-shot accumulators (%.1f GB per energy)", 2.0 * vec_b / 1e9);
+    set_error("not enough device memory for the single-shot history and accumulators (%.1f GB per vector, %d + 2 "
+              "needed)", vec_b / 1e9, B);
     plan_free(P);
     delete P;
     return KPM_E_NOMEM;
   }
-  void *V0 = nullptr, *Sc = nullptr, *acc = nullptr;
+  void *V0 = nullptr, *Sc = nullptr, *acc = nullptr, *hist = nullptr;
   double *dcoef = nullptr, *part = nullptr, *dsig = nullptr;
   if (e == hipSuccess) e = hipMalloc(&V0, vec_b);
   if (e == hipSuccess) e = hipMalloc(&Sc, vec_b);
   if (e == hipSuccess) e = hipMalloc(&acc, 2 * vec_b * (size_t)kb);
+  if (e == hipSuccess) e = hipMalloc(&hist, vec_b * (size_t)B);
   if (e == hipSuccess) e = hipMalloc(&dcoef, sizeof(double) * coef.size());
   if (e == hipSuccess) e = hipMalloc(&part, sizeof(double) * 2 * kDotBlocks * (size_t)K);
   if (e == hipSuccess) e = hipMalloc(&dsig, sizeof(double) * K);
@@ -492,36 +527,52 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
   if (e == hipSuccess) st = plan_set_vector_base(P, 0);
   const bool f32 = P->prec == KPM_FP32;
   const dim3 eg(2048), eb(256);
-  // acc_k += c_n(E_k0 + k) v over kk energies (coefficients of step n at coef + n K + k0).
-  auto accumulate = [&](const void* v, void* A, int n, int k0, int kk) {
-    if (f32)
-      hipLaunchKernelGGL(accumulate_kernel<float>, eg, eb, 0, s, (const float*)v, (float*)A, n_elems, n_elems,
-                         dcoef + (size_t)n * K + k0, kk);
-    else
-      hipLaunchKernelGGL(accumulate_kernel<double>, eg, eb, 0, s, (const double*)v, (double*)A, n_elems, n_elems,
-                         dcoef + (size_t)n * K + k0, kk);
-    return hipGetLastError();
+  // T_n x0: x0 itself for n = 0, history slot n mod B otherwise.
+  auto hvec = [&](void* x0, int n) -> void* { return n == 0 ? x0 : (char*)hist + vec_b * (size_t)(n % B); };
+  // Accumulators k0 .. k0 + kk - 1 (at A) += sum over steps n0 .. n0 + nb - 1 of c_n(E_k) T_n x0.
+  auto flush = [&](void* x0, void* A, int n0, int nb, int k0, int kk) {
+    hipError_t er = hipSuccess;
+    for (int g = 0; g < kk && er == hipSuccess; g += kAccGroup) {
+      const int kg = std::min(kAccGroup, kk - g);
+      const double* c = dcoef + (size_t)n0 * Kp + k0 + g;
+      char* Ag = (char*)A + vec_b * (size_t)g;
+      if (f32) {
+        HistPtrs<float> H;
+        for (int b = 0; b < nb; ++b) H.v[b] = (const float*)hvec(x0, n0 + b);
+        hipLaunchKernelGGL(accumulate_block_kernel<float>, eg, eb, 0, s, H, nb, n_elems, (float*)Ag, n_elems, c, Kp,
+                           kg);
+      } else {
+        HistPtrs<double> H;
+        for (int b = 0; b < nb; ++b) H.v[b] = (const double*)hvec(x0, n0 + b);
+        hipLaunchKernelGGL(accumulate_block_kernel<double>, eg, eb, 0, s, H, nb, n_elems, (double*)Ag, n_elems, c,
+                           Kp, kg);
+      }
+      er = hipGetLastError();
+    }
+    return er;
   };
-  // One recursion from x0 (overwritten), accumulating every step into A.
+  // One recursion from x0 into the history, flushed every B steps (a slot is
+  // rewritten only after its vector has been flushed).
   auto chain = [&](void* x0, void* A, int k0, int kk) {
-    hipError_t er = accumulate(x0, A, 0, k0, kk);
-    void* cur = x0;
-    void* prev = Sc;
+    hipError_t er = hipSuccess;
+    int n0 = 0;   // first step not yet flushed
     for (int n = 1; n < M && er == hipSuccess; ++n) {
       StepLaunch S;
       S.dots = 0;
+      S.v = hvec(x0, n - 1);
+      S.out = hvec(x0, n);
       if (n == 1) {
-        S.v = x0; S.out = Sc; S.read_w = 0; S.a = 1.0; S.b = 0.0;
-        er = plan_launch_step(P, s, S);
-        cur = Sc;
-        prev = x0;
+        S.read_w = 0; S.a = 1.0; S.b = 0.0;
       } else {
-        S.v = cur; S.w = prev; S.out = prev;
-        er = plan_launch_step(P, s, S);
-        std::swap(cur, prev);
+        S.w = hvec(x0, n - 2);
       }
-      if (er == hipSuccess) er = accumulate(cur, A, n, k0, kk);
+      er = plan_launch_step(P, s, S);
+      if (er == hipSuccess && n + 1 - n0 == B) {
+        er = flush(x0, A, n0, B, k0, kk);
+        n0 = n + 1;
+      }
     }
+    if (er == hipSuccess && n0 < M) er = flush(x0, A, n0, M - n0, k0, kk);
     return er;
   };
   for (int k0 = 0; k0 < K && e == hipSuccess && st == KPM_OK; k0 += kb) {
@@ -574,7 +625,7 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
     set_error("kpm_sigma_singleshot: %s", hipGetErrorString(e));
     st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
   }
-  for (void* ptr : {V0, Sc, acc, (void*)dcoef, (void*)part, (void*)dsig})
+  for (void* ptr : {V0, Sc, acc, hist, (void*)dcoef, (void*)part, (void*)dsig})
     if (ptr) (void)hipFree(ptr);
   plan_free(P);
   delete P;

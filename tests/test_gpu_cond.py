@@ -293,6 +293,25 @@ def test_singleshot_parity(K, lat, ab):
     assert np.array_equal(sd, s64)
 
 
+def test_singleshot_history_flushes_and_energy_groups(K):
+    """M = 150 (two full 64-vector history flushes and a partial one) and 21 energies
+    (two flush passes of up to 16) against the oracle's single-shot sums: FP64 1e-10,
+    FP32 2e-5 relative to the largest value."""
+    lat = LATS[3]
+    M, R = 150, 2
+    par = wl.CondParams(num_moments=M, num_random=R, vector_seed=29, alpha=0, beta=1)
+    m = olat.build(lat)
+    from oracle import kpm as okpm
+    vecs = okpm.random_phase_vectors(m, R, par.vector_seed, 0)
+    E = np.linspace(lat.e_min * 0.7, lat.e_max * 0.7, 21)
+    ref = ocond.sigma_singleshot(m, lat.e_min, lat.e_max, E, 0.12, M, vecs, 0, 1)
+    scale = np.max(np.abs(ref))
+    s64 = K.sigma_singleshot(lat, par, E, 0.12, precision=wl.FP64)
+    assert np.max(np.abs(s64 - ref)) <= 1e-10 * scale, (s64, ref)
+    s32 = K.sigma_singleshot(lat, par, E, 0.12, precision=wl.FP32)
+    assert np.max(np.abs(s32 - ref)) <= 2e-5 * scale, (s32, ref)
+
+
 def test_graphene_minimum_conductivity_singleshot(K):
     """Clean spinless graphene 1024 x 1024, single-shot on the GPU (FP32, M = 1024,
     R = 4, eta = 0.1 eV): sigma_xx(0) = 2/pi e^2/h (the universal minimum, pinned in
