@@ -15,6 +15,9 @@ computes, written from the paper (KITE, arXiv:1910.05194):
 * ``cond``    velocity operator [r^a, H] (eq. generalized velocity), the rank-2
               Gamma tensor (eq. Gammanm) by plain inner products, and the
               T=0 longitudinal conductivity from Gamma.
+* ``evolve``  wave-packet time evolution: the Chebyshev-Bessel expansion of
+              exp(-i H dt / hbar) (Sec. 4), the Gaussian packet and its spin
+              and position observables.
 * ``mlp``     FP64 forward/backward/Adam of the moment-extrapolation MLP.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of

@@ -55,6 +55,11 @@ class c_cond_params(ctypes.Structure):
                 ("gamma_mode", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
 
 
+class c_evolve_params(ctypes.Structure):
+    _fields_ = [("num_moments", ctypes.c_int32), ("num_points", ctypes.c_int32), ("num_packets", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("dt_fs", ctypes.c_double)]
+
+
 class c_cond_stats(ctypes.Structure):
     _fields_ = [("n_batches", ctypes.c_int32), ("vectors_per_batch", ctypes.c_int32), ("chain_ms", ctypes.c_double),
                 ("gemm_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("chain_bytes", ctypes.c_double),
@@ -125,6 +130,10 @@ def _load():
                                               ctypes.c_int32, _P]),
         "kpm_sigma_singleshot": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.POINTER(c_cond_params), _P,
                                                 ctypes.c_int32, ctypes.c_double, _P, ctypes.c_int32, _P]),
+        "kpm_wavepacket_gaussian": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, _P, _P, ctypes.c_double,
+                                                   _P, _P, ctypes.c_int32, _P]),
+        "kpm_time_evolve": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.POINTER(c_evolve_params), _P, _P,
+                                           ctypes.c_int32, _P]),
         "kpm_autotune": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, ctypes.POINTER(c_dos_params),
                                         ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(c_tune), _D, _P]),
         "kpm_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -409,6 +418,58 @@ def sigma_singleshot(lattice, par, energies, eta: float, precision: int = FP32, 
     _check(LIB.kpm_sigma_singleshot(lat, ctypes.byref(p), en.data_ptr(), en.numel(), float(eta), out.data_ptr(), 1,
                                     _stream_handle(stream)))
     return out
+
+
+def wavepacket_gaussian(lattice, k_vectors, spinors, width_nm: float, center_cells, out_device=None, stream=None):
+    """kpm_wavepacket_gaussian: the normalised Gaussian packet as complex numpy [n_orbitals]
+    (host) or float64 torch [n_orbitals, 2] on ``out_device``.  k_vectors [n_k, 2] (1/nm),
+    spinors [n_k, orbitals per cell] complex, center_cells (c1, c2)."""
+    lat = c_lattices([lattice])
+    kv = np.ascontiguousarray(np.atleast_2d(k_vectors), dtype=np.float64)
+    sp = np.atleast_2d(np.asarray(spinors, dtype=np.complex128))
+    spr = np.ascontiguousarray(np.stack([sp.real, sp.imag], axis=-1))
+    cc = np.ascontiguousarray(center_cells, dtype=np.float64)
+    n = int(lattice.L1) * int(lattice.L2) * {0: 2, 1: 4, 2: 1}.get(int(lattice.kind), 2)
+    if out_device is None:
+        out = np.zeros((n, 2))
+        _check(LIB.kpm_wavepacket_gaussian(lat, kv.shape[0], kv.ctypes.data, spr.ctypes.data, float(width_nm),
+                                           cc.ctypes.data, out.ctypes.data, 0, _stream_handle(stream)))
+        return out[:, 0] + 1j * out[:, 1]
+    import torch
+    out = torch.zeros((n, 2), dtype=torch.float64, device=out_device)
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    _check(LIB.kpm_wavepacket_gaussian(lat, kv.shape[0], kv.ctypes.data, spr.ctypes.data, float(width_nm),
+                                       cc.ctypes.data, out.data_ptr(), 1, _stream_handle(stream)))
+    return out
+
+
+def time_evolve(lattice, psi0, dt_fs: float, num_moments: int, num_points: int, precision: int = FP32, stream=None):
+    """kpm_time_evolve: (psi at t = (num_points - 1) dt, observables [num_points, R, 8]).
+    psi0: complex numpy [R, n_orbitals] or [n_orbitals] (host results), or float64 torch
+    [R, n_orbitals, 2] on the device (device results, psi0 left unchanged)."""
+    lat = c_lattices([lattice])
+    if isinstance(psi0, np.ndarray):
+        p0 = np.atleast_2d(np.asarray(psi0, dtype=np.complex128))
+        R = p0.shape[0]
+        buf = np.ascontiguousarray(np.stack([p0.real, p0.imag], axis=-1))
+        obs = np.zeros((int(num_points), R, 8))
+        par = c_evolve_params(int(num_moments), int(num_points), R, int(precision), float(dt_fs))
+        _check(LIB.kpm_time_evolve(lat, ctypes.byref(par), buf.ctypes.data, obs.ctypes.data, 0,
+                                   _stream_handle(stream)))
+        out = buf[..., 0] + 1j * buf[..., 1]
+        return (out[0] if np.ndim(psi0) == 1 else out), obs
+    import torch
+    buf = psi0.detach().to(torch.float64).contiguous().clone()
+    if buf.dim() == 2:
+        buf = buf.unsqueeze(0)
+    R = buf.shape[0]
+    obs = torch.zeros((int(num_points), R, 8), dtype=torch.float64, device=buf.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(buf.device)
+    par = c_evolve_params(int(num_moments), int(num_points), R, int(precision), float(dt_fs))
+    _check(LIB.kpm_time_evolve(lat, ctypes.byref(par), buf.data_ptr(), obs.data_ptr(), 1, _stream_handle(stream)))
+    return buf, obs
 
 
 def cond_last_stats() -> dict:
