@@ -169,6 +169,38 @@ def leg_singleshot(kpm, wl, np):
             "sigma_at_dirac_over_2_over_pi": float(s[np.argmin(np.abs(E))] / (2 / np.pi))}
 
 
+def leg_wavepacket(kpm, wl, np):
+    """The paper's spin-dynamics example at its size: 7168^2 spinful cells (205.5M
+    orbitals), Rashba 10 meV, Anderson 1.5 eV; two FP32 packets (spin along z and x)
+    evolved by 10 time steps of 2 fs with M = 70 Chebyshev terms each."""
+    import torch
+    torch.cuda.empty_cache()   # the evolution's history is sized to the free device memory
+    cfg = wl.spin_wavepacket()
+    lat = cfg["lattice"]
+    psi0, dt_b = _timed(lambda: torch.stack([kpm.wavepacket_gaussian(lat, cfg["k"], sp, cfg["width_nm"], cfg["center"],
+                                                                     out_device="cuda") for sp in cfg["spinors"]]))
+    n_pts = 11
+    (psi, obs), dt_e = _timed(lambda: kpm.time_evolve(lat, psi0, cfg["dt_fs"], cfg["num_moments"], n_pts,
+                                                      precision=wl.FP32))
+    del psi, psi0
+    obs = obs.cpu().numpy()
+    n_orb = lat.L1 * lat.L2 * 4
+    M = cfg["num_moments"]
+    # Bytes per time step: M - 1 recursion steps (v_n with neighbours, v_(n-1), v_(n+1), the
+    # site arrays) and the history flushes (M vectors read, psi(t + dt) written).
+    vec = n_orb * 2 * 8
+    step_bytes = (M - 1) * (3 * vec + n_orb // 2 * 5) + (M + 1) * vec
+    t = np.arange(n_pts) * cfg["dt_fs"]
+    return {"workload": "spinful honeycomb 7168^2 (205.5M orbitals), t = -2.507 eV, Rashba 10 meV, Anderson 1.5 eV; "
+                        "2 Gaussian packets (110 nm, K + 0.1 eV) FP32, 10 steps of 2 fs, M = 70",
+            "build_s": dt_b, "evolve_s": dt_e,
+            "orbital_step_updates_per_s": n_orb * 2 * (M - 1) * (n_pts - 1) / dt_e,
+            "algorithmic_GBs": step_bytes * (n_pts - 1) / dt_e / 1e9,
+            "t_fs": t.tolist(), "norm_drift": float(np.max(np.abs(obs[:, :, 0] - 1.0))),
+            "Sz_packet_z": obs[:, 0, 7].round(6).tolist(), "Sx_packet_x": obs[:, 1, 5].round(6).tolist(),
+            "msd_x_nm2_packet_z": (obs[:, 0, 3] - obs[:, 0, 1] ** 2).round(3).tolist()}
+
+
 def leg_batch(kpm, wl, np):
     """64 uneven vacancy lattices in one persistent kernel per step (hipGraph)."""
     import torch
@@ -297,7 +329,7 @@ def main():
                     help="launch the recursion steps one by one instead of replaying a hipGraph (for profilers)")
     ap.add_argument("--launch", default="",
                     help="pin the FP32 launch shape: kernel,block,rows,grid[,chunks] (skips the autotuner)")
-    ap.add_argument("--legs", default="c1,c3,c4,c5,hall,optical,singleshot",
+    ap.add_argument("--legs", default="c1,c3,c4,c5,hall,optical,singleshot,wavepacket",
                     help="extra legs: c1,c3,c4,c5,hall,optical,singleshot (empty for none)")
     ap.add_argument("--mlp-train", type=int, default=4000,
                     help="training lattices (1024^2 cells each) of the learned-extrapolation leg")
@@ -420,12 +452,13 @@ def main():
         extra["copy_probe"] = {"kernel": "kpm::probe_copy", "bytes_moved": r["bytes"], "ms": r["ms"], "GBs": r["GBs"]}
 
     for name, fn in (("c1", leg_small), ("c3", leg_gamma), ("c4", leg_batch), ("c5", leg_mlp), ("hall", leg_hall),
-                     ("optical", leg_optical), ("singleshot", leg_singleshot)):
+                     ("optical", leg_optical), ("singleshot", leg_singleshot), ("wavepacket", leg_wavepacket)):
         if name in legs:
             log(f"[bench] leg {name}")
             kw = {"n_train": args.mlp_train} if name == "c5" else {}
             extra[{"c1": "small_fp64", "c3": "gamma", "c4": "uneven_batch", "c5": "mlp_extrapolation",
-                   "hall": "qahe_hall", "optical": "graphene_optical", "singleshot": "graphene_singleshot"}[name]] = \
+                   "hall": "qahe_hall", "optical": "graphene_optical", "singleshot": "graphene_singleshot",
+                   "wavepacket": "spin_wavepacket"}[name]] = \
                 fn(kpm, wl, np, **kw)
 
     cpu = None

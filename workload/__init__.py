@@ -201,6 +201,23 @@ def qahe(L: int = 512, M: int = 1024, R: int = 1) -> tuple:
     return lat, par
 
 
+def spin_wavepacket(L: int = 7168) -> dict:
+    """The paper's spin-dynamics example (Sec. 4, Fig. spinpress(a)): spinful honeycomb
+    L x L cells, t = -2.507 eV, lambda_R = 10 meV, Anderson W = 1.5 eV, bounds +-8.5 eV;
+    2 fs time steps with M = 70 terms; a Gaussian packet of width 110 nm at the centre,
+    momentum K + q with hbar v_F q = E_F = 0.1 eV (v_F from the hopping), polarised along
+    z (first packet) and along x (second)."""
+    lat = Lattice(kind=HONEYCOMB_SPIN, L1=L, L2=L, t=-2.507, rashba=0.010, anderson_w=1.5,
+                  disorder_seed=DISORDER_SEED, e_min=-8.5, e_max=8.5)
+    hbar_vf = 1.5 * 2.507 * ACC_HONEYCOMB                      # eV nm
+    k = [4.0 * 3.141592653589793 / (3.0 * A_HONEYCOMB) + 0.1 / hbar_vf, 0.0]
+    s = 0.5 ** 0.5
+    sz = [s, 0.0, s, 0.0]                                       # A up, A down, B up, B down
+    sx = [0.5, 0.5, 0.5, 0.5]
+    return {"lattice": lat, "k": [k], "spinors": [[sz], [sx]], "width_nm": 110.0, "center": [L / 2, L / 2],
+            "dt_fs": 2.0, "num_moments": 70}
+
+
 def graphene_clean(L: int = 1024, M: int = 1024, R: int = 4) -> tuple:
     """Clean spinless graphene, t = -2.7 eV, bounds +-9 eV; xx response, split-BF16 Gamma."""
     lat = Lattice(kind=HONEYCOMB, L1=L, L2=L, t=-2.7, disorder_seed=DISORDER_SEED, e_min=-9.0, e_max=9.0)
