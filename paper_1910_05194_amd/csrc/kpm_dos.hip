@@ -710,11 +710,12 @@ __global__ void __launch_bounds__(kMaxStepBlock) step_kernel_ring(StepArgs<T> A)
 // columns [l - 1, Tx - l] (each level needs one neighbour column more than
 // the next), so level KS covers the interior; v_n comes with one more halo
 // column per side.  Rows are marched upwards: at iteration j, row y0 + j of
-// v_n enters a 4-slot LDS ring and level l forms row y0 + j - l into a 3-slot
-// ring of its own (the last level only to HBM); KS barriers per row.  The
-// outputs go to buffers that no tile reads in the same sweep (neighbouring
-// tiles still read v_n and v_{n-1} on halos).  nlev < KS runs the first nlev
-// levels only (the last, short sweep of a recursion).
+// v_n enters a 4-slot LDS ring and level l forms row y0 + j - (2 l - 1) into
+// a 4-slot ring of its own (the last level only to HBM), so that the levels of
+// one iteration read only rows formed in earlier iterations: one barrier per
+// row.  The outputs go to buffers that no tile reads in the same sweep
+// (neighbouring tiles still read v_n and v_{n-1} on halos).  nlev < KS runs the
+// first nlev levels only (the last, short sweep of a recursion).
 // ---------------------------------------------------------------------------
 constexpr int kMaxSweep = 5;
 

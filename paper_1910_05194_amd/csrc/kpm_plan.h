@@ -51,7 +51,7 @@ struct kpm_plan {
   // device memory
   void* X = nullptr;
   void* Y = nullptr;
-  void* Z = nullptr;           // two more vectors for the multi-step sweep kernels (variants 3-5)
+  void* Z = nullptr;           // two more vectors for the multi-step sweep kernels (variants 3-6)
   void* W = nullptr;
   void* onsite = nullptr;
   uint8_t* mask = nullptr;
@@ -72,8 +72,8 @@ struct kpm_plan {
   double* mean_dev = nullptr;
   void* step_fn = nullptr;
   void* step_fn_vel = nullptr;
-  void* sweep_fn = nullptr;    // multi-step sweep kernel (variants 3-5)
-  int variant = 2;             // 1 = direct-load step kernel, 2 = LDS row ring, 3/4/5 = 2/3/4 steps per sweep
+  void* sweep_fn = nullptr;    // multi-step sweep kernel (variants 3-6)
+  int variant = 2;             // 1 = direct-load step kernel, 2 = LDS row ring, 3..6 = 2..5 steps per sweep
   int sweep = 1;               // Chebyshev steps per launch (variant - 1 for the sweep kernels, else 1)
   size_t lds_bytes = 0;
   int64_t r_base = 0;          // global index of the plan's first random vector
