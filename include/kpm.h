@@ -426,7 +426,7 @@ int kpm_wavepacket_gaussian(const kpm_lattice_t* lat, int32_t n_k, const double*
  * the packet stays away from the periodic seam).  psi [R][n_orbitals][2] FP64:
  * on entry the states at t = 0, on return at t = (num_points - 1) dt;
  * observables [num_points][R][8] FP64; both host (on_device = 0) or both
- * device.  Workspace: the plan's two vectors and a history of up to 64 vectors
+ * device.  Workspace: the plan's two vectors and a history of up to 32 vectors
  * of n_orbitals x R_padded complex values (fewer if memory is short).
  * Synchronises hip_stream.  Errors: KPM_E_INVALID (NULL, parameters outside
  * their ranges, invalid lattice); KPM_E_NOMEM (not even a 3-vector history
@@ -434,6 +434,18 @@ int kpm_wavepacket_gaussian(const kpm_lattice_t* lat, int32_t n_k, const double*
  */
 int kpm_time_evolve(const kpm_lattice_t* lat, const kpm_evolve_params_t* p, double* psi, double* observables,
                     int32_t on_device, void* hip_stream);
+
+/* Timing and work of the last kpm_time_evolve call on the calling thread. */
+typedef struct kpm_evolve_stats_t {
+  int32_t history;            /* vectors in the history (flush every this many Chebyshev terms) */
+  int32_t time_steps;         /* num_points - 1 */
+  double loop_ms;             /* the time-step loop with its observables (hipEvents on the call's stream;
+                                 excludes workspace allocation, model build and the copies in and out) */
+  double bytes;               /* algorithmic HBM bytes of the loop: per recursion step v_n, v_(n-1),
+                                 v_(n+1) and the per-site arrays; per flush the history vectors read
+                                 and psi(t + dt) written (and read after the first flush) */
+} kpm_evolve_stats_t;
+int kpm_evolve_last_stats(kpm_evolve_stats_t* stats);
 
 /*
  * Moment-extrapolation MLP (the paper has no learned component: this is the

@@ -10,10 +10,11 @@
 //
 // One time step runs the M - 1 recursion steps T_{n+1} = 2 H~ T_n - T_{n-1} of
 // the plan's single-step kernel from psi(t), writing T_n psi into slot n mod B
-// of a history of B (<= 64) vectors; every B steps one pass folds the history
-// into psi(t + dt) with the complex coefficients (per step 1 + 1/B vectors of
-// traffic besides the recursion's three, instead of three for a per-step
-// update).
+// of a history of B (<= 32) vectors; every B steps one pass folds the history
+// into psi(t + dt) with the complex coefficients (per step about 1 + 2/B
+// vectors of traffic besides the recursion's three, instead of three for a
+// per-step update; 32 keeps the footprint at a third of what 64 would take for
+// under 1 % more traffic).
 //
 // The Gaussian packet psi(0, r) = exp(-|r - r_c|^2/(2 sigma^2)) sum_j
 // exp(i k_j.r) spinor_j (the printed exponent is garbled; sigma is read as the
@@ -37,8 +38,10 @@ constexpr double kHbarEvFs = 6.62607015e-34 / (2.0 * 3.14159265358979323846 * 1.
 // Lattice constants of the model build (Sec. 3(d) listing): honeycomb a and
 // a_cc, square a.
 constexpr double kEvA = 0.24595, kEvAcc = 0.142;
-constexpr int kEvoHist = 64;      // history vectors per flush
+constexpr int kEvoHist = 32;      // history vectors per flush
 constexpr int kObsBlocks = 512;   // partial sums per packet in the observables reduction
+
+static thread_local kpm_evolve_stats_t g_evo_stats;
 
 struct CellGeom {
   double a1x, a1y, a2x, a2y;
@@ -359,7 +362,17 @@ static hipError_t evolve_loop(kpm_plan* P, const kpm_evolve_params_t* p, const C
     hipLaunchKernelGGL(evolve_flush_kernel<T>, fg, fb, 0, s, H, nb, n_cplx, dcoef + n0, first, (T*)nxt);
     return hipGetLastError();
   };
-  hipError_t e = observe(0);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipError_t e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  if (e == hipSuccess) e = hipEventRecord(ev0, s);
+  if (e == hipSuccess) e = observe(0);
+  // Algorithmic bytes: a recursion step reads v_n (neighbours from cache) and
+  // v_(n-1), writes v_(n+1), reads the per-site arrays; a flush reads its
+  // history vectors and writes psi(t + dt) (reading it too after the first).
+  const double site_b = (double)n_sites * ((P->has_onsite ? (double)sizeof(T) : 0.0) + (P->has_mask ? 1.0 : 0.0));
+  const int n_flush = (M + B - 1) / B;
+  const double step_b = (double)(M - 1) * (3.0 * (double)vec_b + site_b) + ((double)M + 2.0 * n_flush - 1.0) * (double)vec_b;
   for (int k = 1; k < p->num_points && e == hipSuccess; ++k) {
     int n0 = 0, first = 1;
     for (int n = 1; n < M && e == hipSuccess; ++n) {
@@ -383,6 +396,16 @@ static hipError_t evolve_loop(kpm_plan* P, const kpm_evolve_params_t* p, const C
     std::swap(psi, nxt);
     if (e == hipSuccess) e = observe(k);
   }
+  if (e == hipSuccess) e = hipEventRecord(ev1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  g_evo_stats.history = B;
+  g_evo_stats.time_steps = p->num_points - 1;
+  g_evo_stats.loop_ms = ms;
+  g_evo_stats.bytes = step_b * (p->num_points - 1);
   // The final state ends in X (copied out by the caller).
   if (e == hipSuccess && psi != P->X) e = hipMemcpyAsync(P->X, psi, vec_b, hipMemcpyDeviceToDevice, s);
   return e;
@@ -397,6 +420,7 @@ static int evolve_run(const kpm_lattice_t* lat, const kpm_evolve_params_t* p, do
   KPM_CHECK_ARG(p->precision == KPM_FP32 || p->precision == KPM_FP64, "precision must be KPM_FP32 or KPM_FP64");
   KPM_CHECK_ARG(std::isfinite(p->dt_fs) && p->dt_fs != 0.0, "dt must be finite and nonzero");
   hipStream_t s = (hipStream_t)stream;
+  std::memset(&g_evo_stats, 0, sizeof(g_evo_stats));
   const int M = p->num_moments, R = p->num_packets;
   // Coefficients phase (2 - d_n0) (-i)^n J_n(x), x = de- dt/hbar (J_n(-x) = (-1)^n J_n(x)).
   const double de_p = 0.5 * (lat->e_max + lat->e_min), de_m = 0.5 * (lat->e_max - lat->e_min);
@@ -419,7 +443,7 @@ static int evolve_run(const kpm_lattice_t* lat, const kpm_evolve_params_t* p, do
   const size_t vec_b = (size_t)n_orb * P->Rp * 2 * P->tsize;
   size_t free_b = 0, total_b = 0;
   hipError_t e = hipMemGetInfo(&free_b, &total_b);
-  // History: up to 64 vectors (no more than M), in the free memory.
+  // History: up to 32 vectors (no more than M), in the free memory.
   const double room = std::floor((0.85 * (double)free_b - 1.0e9) / (double)vec_b);
   const int B = (int)std::min<double>(std::min(kEvoHist, std::max(3, M)), room);
   if (e == hipSuccess && B < 3) {
@@ -489,6 +513,12 @@ extern "C" int kpm_wavepacket_gaussian(const kpm_lattice_t* lat, int32_t n_k, co
     kpm::set_error("internal error (exception) in kpm_wavepacket_gaussian");
     return KPM_E_DEVICE;
   }
+}
+
+extern "C" int kpm_evolve_last_stats(kpm_evolve_stats_t* stats) {
+  if (!stats) return KPM_E_INVALID;
+  *stats = kpm::g_evo_stats;
+  return KPM_OK;
 }
 
 extern "C" int kpm_time_evolve(const kpm_lattice_t* lat, const kpm_evolve_params_t* p, double* psi,

@@ -60,6 +60,11 @@ class c_evolve_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("dt_fs", ctypes.c_double)]
 
 
+class c_evolve_stats(ctypes.Structure):
+    _fields_ = [("history", ctypes.c_int32), ("time_steps", ctypes.c_int32), ("loop_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 class c_cond_stats(ctypes.Structure):
     _fields_ = [("n_batches", ctypes.c_int32), ("vectors_per_batch", ctypes.c_int32), ("chain_ms", ctypes.c_double),
                 ("gemm_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("chain_bytes", ctypes.c_double),
@@ -134,6 +139,7 @@ def _load():
                                                    _P, _P, ctypes.c_int32, _P]),
         "kpm_time_evolve": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.POINTER(c_evolve_params), _P, _P,
                                            ctypes.c_int32, _P]),
+        "kpm_evolve_last_stats": (ctypes.c_int, [ctypes.POINTER(c_evolve_stats)]),
         "kpm_autotune": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, ctypes.POINTER(c_dos_params),
                                         ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(c_tune), _D, _P]),
         "kpm_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -470,6 +476,13 @@ def time_evolve(lattice, psi0, dt_fs: float, num_moments: int, num_points: int, 
     par = c_evolve_params(int(num_moments), int(num_points), R, int(precision), float(dt_fs))
     _check(LIB.kpm_time_evolve(lat, ctypes.byref(par), buf.data_ptr(), obs.data_ptr(), 1, _stream_handle(stream)))
     return buf, obs
+
+
+def evolve_last_stats() -> dict:
+    """kpm_evolve_last_stats of the calling thread."""
+    st = c_evolve_stats()
+    _check(LIB.kpm_evolve_last_stats(ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in c_evolve_stats._fields_}
 
 
 def cond_last_stats() -> dict:

@@ -120,6 +120,12 @@ def test_exchange_precession_and_norm_at_size(K):
     sp = np.array([1, 1, 1, 1]) / 2.0
     psi0 = K.wavepacket_gaussian(lat, [[2.0, 0.5]], [sp], 12.0, [256, 256], out_device="cuda")
     _, obs = K.time_evolve(lat, psi0.unsqueeze(0), 2.0, 60, 16, precision=wl.FP32)
+    st = K.evolve_last_stats()
+    # 60 terms: flushes of 32 and 28 history vectors; FP32 packs of 2 complex (R = 1 padded to 2).
+    vec = lat.L1 * lat.L2 * 4 * 2 * 8
+    site = lat.L1 * lat.L2 * 2 * (4 + 1)
+    assert st["history"] == 32 and st["time_steps"] == 15 and st["loop_ms"] > 0
+    assert st["bytes"] == pytest.approx(15 * (59 * (3 * vec + site) + (60 + 2 * 2 - 1) * vec), rel=1e-12)
     obs = obs.cpu().numpy()[:, 0, :]
     t = np.arange(16) * 2.0
     w = 2 * delta / oev.HBAR_EV_FS
