@@ -334,7 +334,8 @@ def main():
     ap.add_argument("--mlp-train", type=int, default=4000,
                     help="training lattices (1024^2 cells each) of the learned-extrapolation leg")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also time a plain 4 GiB device copy (HBM ceiling; counter calibration)")
+                    help="time the plain 4 GiB device copy (the default; kept for the recorded profiling commands)")
+    ap.add_argument("--no-copy-probe", action="store_true", help="skip the plain device copy (HBM ceiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the multi-GPU sharding of the recursion is not implemented.",
@@ -444,12 +445,14 @@ def main():
         extra["max_abs_dmu_fp32_vs_fp64"] = dmu
         p64.close()
 
-    if args.copy_probe:
+    copy_gbs = None
+    if not args.no_copy_probe:
         # The library's plain copy kernel (kpm::probe_copy) over 4 GiB arrays:
         # the HBM ceiling of a streaming pattern and the calibration of the
         # FETCH_SIZE / WRITE_SIZE counters (4 GiB read and 4 GiB written per launch).
         r = kpm.bandwidth_probe(0, 4 << 30, iters=5)
         extra["copy_probe"] = {"kernel": "kpm::probe_copy", "bytes_moved": r["bytes"], "ms": r["ms"], "GBs": r["GBs"]}
+        copy_gbs = r["GBs"]
 
     for name, fn in (("c1", leg_small), ("c3", leg_gamma), ("c4", leg_batch), ("c5", leg_mlp), ("hall", leg_hall),
                      ("optical", leg_optical), ("singleshot", leg_singleshot), ("wavepacket", leg_wavepacket)):
@@ -466,6 +469,7 @@ def main():
         log("[bench] cpu baseline (oracle)")
         cpu = cpu_baseline(lat, par)
 
+    traffic = measured_traffic(info, args)
     out = {
         "metric": "orbital*moment*vector updates/s (FP32 recursion, FP64 moments) and DOS error vs FP64",
         "value": value,
@@ -481,7 +485,7 @@ def main():
         "step_rate": N * info["n_steps"] * args.R / dt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(info, args),
+                     "traffic": traffic,
                      "kernel": ({1: "kpm::step_kernel", 2: "kpm::step_kernel_ring"}.get(info["kernel"])
                                 or f"kpm::sweep_kernel<KS={info['kernel'] - 1}>") + " (FP32, honeycomb, on-site array)",
                      "steps_per_launch": steps_per_launch,
@@ -489,7 +493,13 @@ def main():
                      # What a one-step-per-launch kernel (read v_n, v_(n-1) and the site
                      # arrays, write v_(n+1)) would have to stream for the same step rate.
                      "single_step_equivalent_GBs": (3.0 * N * args.R * 8 + N * 4) * info["n_steps"] / (
-                         float(np.mean(loop_ms)) * 1e-3) / 1e9},
+                         float(np.mean(loop_ms)) * 1e-3) / 1e9,
+                     # The measured ceiling of a plain streaming copy on this device, and the
+                     # step kernel's hardware bytes (the counter record) per launch time against it.
+                     "copy_ceiling_GBs": copy_gbs,
+                     "hw_GBs": (traffic / (avg_launch_ms * 1e-3) / 1e9) if traffic else None,
+                     "hw_frac_of_copy": (traffic / (avg_launch_ms * 1e-3) / 1e9 / copy_gbs)
+                     if (traffic and copy_gbs) else None},
         "cpu_baseline": cpu,
     }
     out.update(extra)
