@@ -59,9 +59,16 @@ def cpu_baseline(lat_full, par_full):
         okpm.dos_moments(lat, par)
         dt = time.perf_counter() - t0
     n = lat.n_orbitals
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n * M * R / dt, "unit": "orbital*moment*vector updates/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle (scipy CSR, FP64, one thread) on the headline model at 1024x1024 cells, R=1, "
-                      f"M={M}, model build included: {dt:.2f} s"}
+                      f"M={M}, model build included: {dt:.2f} s",
+            "host_cpu": model, "host_threads": os.cpu_count()}
 
 
 def leg_small(kpm, wl, np):

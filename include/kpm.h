@@ -424,7 +424,8 @@ int kpm_wavepacket_gaussian(const kpm_lattice_t* lat, int32_t n_k, const double*
  * <sigma_z>] (nm, nm^2, hbar/2; all but the norm divided by it; spin zero on
  * spinless lattices; positions as in kpm_wavepacket_gaussian, meaningful while
  * the packet stays away from the periodic seam).  psi [R][n_orbitals][2] FP64:
- * on entry the states at t = 0, on return at t = (num_points - 1) dt;
+ * on entry the states at t = 0 (entries on vacant orbitals are ignored: the
+ * model has no such states), on return at t = (num_points - 1) dt;
  * observables [num_points][R][8] FP64; both host (on_device = 0) or both
  * device.  Workspace: the plan's two vectors and a history of up to 32 vectors
  * of n_orbitals x R_padded complex values (fewer if memory is short).

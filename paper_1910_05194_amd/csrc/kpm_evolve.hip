@@ -135,15 +135,17 @@ __global__ void evo_scale_kernel(double* psi, int64_t n, double f) {
   if (i < n) psi[i] *= f;
 }
 
-// Plan layout [orbital][Rp] complex (T) <-> caller layout [R][n_orb] complex (FP64).
+// Plan layout [orbital][Rp] complex (T) <-> caller layout [R][n_orb] complex (FP64);
+// the copy in zeroes vacant orbitals (the model has no such states).
 template <typename T>
-__global__ void evolve_copy_in_kernel(const double* __restrict__ src, int64_t n_orb, int R, int Rp, T* __restrict__ dst) {
+__global__ void evolve_copy_in_kernel(const double* __restrict__ src, int64_t n_orb, int R, int Rp, int n_spin,
+                                      const uint8_t* __restrict__ mask, T* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_orb * Rp) return;
   const int64_t o = i / Rp;
   const int r = (int)(i - o * Rp);
   double re = 0.0, im = 0.0;
-  if (r < R) {
+  if (r < R && (!mask || mask[o / n_spin])) {
     re = src[2 * ((int64_t)r * n_orb + o)];
     im = src[2 * ((int64_t)r * n_orb + o) + 1];
   }
@@ -469,14 +471,16 @@ static int evolve_run(const kpm_lattice_t* lat, const kpm_evolve_params_t* p, do
   if (e == hipSuccess) {
     const unsigned gi = (unsigned)ceil_div(n_orb * P->Rp, 256), go = (unsigned)ceil_div(n_orb * R, 256);
     if (f32) {
-      hipLaunchKernelGGL(evolve_copy_in_kernel<float>, dim3(gi), dim3(256), 0, s, sp, n_orb, R, P->Rp, (float*)P->X);
+      hipLaunchKernelGGL(evolve_copy_in_kernel<float>, dim3(gi), dim3(256), 0, s, sp, n_orb, R, P->Rp, g.n_spin,
+                         (const uint8_t*)P->mask, (float*)P->X);
       e = hipGetLastError();
       if (e == hipSuccess) e = evolve_loop<float>(P, p, g, dcoef, B, hist, part, so, s);
       if (e == hipSuccess)
         hipLaunchKernelGGL(evolve_copy_out_kernel<float>, dim3(go), dim3(256), 0, s, (const float*)P->X, n_orb, R,
                            P->Rp, sp);
     } else {
-      hipLaunchKernelGGL(evolve_copy_in_kernel<double>, dim3(gi), dim3(256), 0, s, sp, n_orb, R, P->Rp, (double*)P->X);
+      hipLaunchKernelGGL(evolve_copy_in_kernel<double>, dim3(gi), dim3(256), 0, s, sp, n_orb, R, P->Rp, g.n_spin,
+                         (const uint8_t*)P->mask, (double*)P->X);
       e = hipGetLastError();
       if (e == hipSuccess) e = evolve_loop<double>(P, p, g, dcoef, B, hist, part, so, s);
       if (e == hipSuccess)

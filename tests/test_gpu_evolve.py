@@ -85,8 +85,9 @@ def test_time_evolution_matches_oracle(K, lat):
 
 
 def test_device_pointers_and_arguments(K):
-    """Device inputs give the host path's values bit for bit; M < 2, dt = 0 and a
-    spinless lattice's spin components (zero) are handled."""
+    """Device inputs give the host path's values bit for bit; amplitude on vacant
+    orbitals is ignored; M < 2, dt = 0 and a spinless lattice's spin components (zero)
+    are handled."""
     import torch
     lat = LATS[0]
     m = olat.build(lat)
@@ -98,6 +99,13 @@ def test_device_pointers_and_arguments(K):
     d_psi = d_psi.cpu().numpy()[0]
     assert np.array_equal(d_psi[:, 0] + 1j * d_psi[:, 1], h_psi)
     assert np.array_equal(d_obs.cpu().numpy()[:, 0, :], h_obs[:, 0, :])
+    # Amplitude on vacant orbitals is ignored: bit-identical results.
+    vac = np.setdiff1d(np.arange(psi0.size), m.orb_index)
+    assert vac.size > 0
+    bad = psi0.copy()
+    bad[vac] = 0.3 - 0.7j
+    b_psi, b_obs = K.time_evolve(lat, bad, 0.8, 60, 3, precision=wl.FP64)
+    assert np.array_equal(b_psi, h_psi) and np.array_equal(b_obs, h_obs)
     with pytest.raises(K.KPMError):
         K.time_evolve(lat, psi0, 0.8, 1, 3)
     with pytest.raises(K.KPMError):
