@@ -107,8 +107,8 @@ typedef struct kpm_tune_t {
   int32_t grid;            /* persistent workgroups (multiple of 8); 0 = one per tile */
   int32_t use_graph;       /* 1 = replay the step loop as a captured hipGraph (default), 0 = eager */
   int32_t kernel;          /* 0 = default (5 where eligible, else 2), 1 = direct neighbour loads, 2 = LDS row
-                              ring, 3/4/5/6 = 2/3/4/5 steps per sweep (spinless lattices without Peierls
-                              phases and with room for four vectors; a sweep whose row rings do not fit in LDS
+                              ring, 3/4/5/6 = 2/3/4/5 steps per sweep (spinless lattices, Peierls phases
+                              included, with room for four vectors; a sweep whose row rings do not fit in LDS
                               takes one step fewer, down to 2) */
   int32_t chunks;          /* 16-byte vector chunks per site that one tile covers (1..E, E = the site's R_padded
                               complex values in 16-byte chunks); a tile then spans block / (sublattices * chunks)

@@ -697,7 +697,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) step_kernel_ring(StepArgs<T> A)
 
 // ---------------------------------------------------------------------------
 // KS Chebyshev steps per sweep (temporal blocking) for the spinless lattices
-// without Peierls phases: level l = 1..KS of a sweep is v_{n+l},
+// (with or without Peierls phases): level l = 1..KS of a sweep is v_{n+l},
 //     v_{n+1} = a1 H~ v_n - b1 v_{n-1},   v_{n+l} = 2 H~ v_{n+l-1} - v_{n+l-2},
 // with the doubling dot products of every step, from one pass over v_n and
 // v_{n-1}.  Only the last two levels go back to HBM (the next sweep starts
@@ -731,20 +731,22 @@ struct SweepArgs {
   T* __restrict__ out_b;            // v_{n+nlev}
   const T* __restrict__ onsite;
   const uint8_t* __restrict__ mask;
+  const T* __restrict__ phase;      // Peierls table [L1][3] complex per lattice (PHASE)
   double* part[kMaxSweep];          // slot partials of steps n .. n+nlev-1
   T a1, b1;
   int read_w1, nlev;
   int Tx, Ty, E, Ew, Rp;            // Tx = thread columns (interior + 2 (KS - 1))
 };
 
-// out = a (H~ v)_i - b w_i at one site (no Peierls phase, one spin), and the
-// doubling dot products <v|v>, <out|v> added to the partial sums pv, pw when
-// acc (a select, not a branch: the values of threads outside their level's
-// columns may be anything).
-template <typename T, int KIND>
-__device__ inline void sweep_site(T a, T b, bool read_w, T hop, T ons, bool alive, const Pack<T>& vo,
-                                  const Pack<T>& wo, const Pack<T> (&vn)[KindTraits<KIND>::NNB], Pack<T>& out,
-                                  bool acc, T* pv, T* pw) {
+// out = a (H~ v)_i - b w_i at one site (one spin), and the doubling dot
+// products <v|v>, <out|v> added to the partial sums pv, pw when acc (a select,
+// not a branch: the values of threads outside their level's columns may be
+// anything).  With PHASE the neighbour k enters with the complex coefficient
+// (hre[k], him[k]) = hop exp(i theta_k) of the site's column, else with hop.
+template <typename T, int KIND, bool PHASE>
+__device__ inline void sweep_site(T a, T b, bool read_w, T hop, const T* hre, const T* him, T ons, bool alive,
+                                  const Pack<T>& vo, const Pack<T>& wo, const Pack<T> (&vn)[KindTraits<KIND>::NNB],
+                                  Pack<T>& out, bool acc, T* pv, T* pw) {
   constexpr int NC = Pack<T>::NC;
   constexpr int NNB = KindTraits<KIND>::NNB;
 #pragma unroll
@@ -752,8 +754,12 @@ __device__ inline void sweep_site(T a, T b, bool read_w, T hop, T ons, bool aliv
     T hr = ons * vo.v[2 * j], hi = ons * vo.v[2 * j + 1];
 #pragma unroll
     for (int k = 0; k < NNB; ++k) {
-      hr += hop * vn[k].v[2 * j];
-      hi += hop * vn[k].v[2 * j + 1];
+      if constexpr (PHASE) {
+        cmul_acc(hr, hi, hre[k], him[k], vn[k].v[2 * j], vn[k].v[2 * j + 1]);
+      } else {
+        hr += hop * vn[k].v[2 * j];
+        hi += hop * vn[k].v[2 * j + 1];
+      }
     }
     T orr = a * hr, oi = a * hi;
     if (read_w) {
@@ -773,13 +779,14 @@ __device__ inline void sweep_site(T a, T b, bool read_w, T hop, T ons, bool aliv
   }
 }
 
-template <typename T, int KIND, bool ONSITE, bool MASK, int KS>
+template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE, int KS>
 __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   using P = Pack<T>;
   constexpr int NC = P::NC;
   constexpr int NSUB = KindTraits<KIND>::NSUB;
   constexpr int NNB = KindTraits<KIND>::NNB;
   static_assert(KindTraits<KIND>::NSPIN == 1, "spinless lattices only");
+  static_assert(!PHASE || KIND == KPM_HONEYCOMB, "Peierls phases on the honeycomb lattice only");
   static_assert(KS >= 2 && KS <= kMaxSweep, "2..kMaxSweep steps per sweep");
   constexpr int NH = 2 * KS - 1;   // site-data history: level l uses the entry 2 (l - 1) iterations old
   extern __shared__ double lds[];
@@ -841,6 +848,20 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     int xe = (x0 - (KS - 1)) % L1;                       // column of thread column 0
     if (xe < 0) xe += L1;
     const int n1 = (xe + xl) % L1;
+    // Hopping coefficients of this thread's column (Peierls phases depend on n1
+    // only; the table is indexed by the A site's cell: a B site's bond class 1
+    // goes to the A site of column n1 - 1, and the B side takes the conjugate).
+    T hre[3], him[3];
+    if constexpr (PHASE) {
+      const int n1m = (n1 == 0) ? L1 - 1 : n1 - 1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int na = (s == 0 || k != 1) ? n1 : n1m;
+        const T* ph = A.phase + 2 * (Lg.phase_off + (int64_t)na * 3 + k);
+        hre[k] = hop * ph[0];
+        him[k] = (s == 0) ? hop * ph[1] : -hop * ph[1];
+      }
+    }
     const int c = tl.y * Ew + cl;
     const bool lane_ok = (grp < n_grp) && (c < A.E);
     const bool act = lane_ok && (xl < wcols);
@@ -988,7 +1009,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
           const P wo = (lev == 2) ? r0((p + 3) & 3, x, s) : rl(lev >= 3 ? lev - 2 : 1, p, x, s);
           const bool own = inner && (y >= y0) && (y < y0 + ty);
           P o;
-          sweep_site<T, KIND>((T)2, (T)1, true, hop, ons_h[2 * lev - 2], alive_h[2 * lev - 2], vo, wo, vn, o, own,
+          sweep_site<T, KIND, PHASE>((T)2, (T)1, true, hop, hre, him, ons_h[2 * lev - 2], alive_h[2 * lev - 2], vo, wo,
+                                     vn, o, own,
                               pv[lev - 1], pw[lev - 1]);
           if (lev < KS) rl(lev, p, x, s) = o;
           if (own && lev >= nlev - 1) put(lev == nlev ? ob : oa, yw, o);
@@ -1019,7 +1041,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
           const P vo = r0(s0, x, s);   // v_n row y
           const bool own = inner && (y >= y0) && (y < y0 + ty);
           P o;
-          sweep_site<T, KIND>(A.a1, A.b1, A.read_w1 != 0, hop, ons_h[0], alive_h[0], vo, cur.w, vn, o, own, pv[0],
+          sweep_site<T, KIND, PHASE>(A.a1, A.b1, A.read_w1 != 0, hop, hre, him, ons_h[0], alive_h[0], vo, cur.w, vn, o,
+                                     own, pv[0],
                               pw[0]);
           rl(1, p, x, s) = o;
           if (own && nlev <= 2) put(nlev == 1 ? ob : oa, yw, o);
@@ -1253,24 +1276,27 @@ static void* pick_step(int variant, bool onsite, bool mask, bool phase) {
   }
 }
 
-template <typename T, int KIND, int KS>
+template <typename T, int KIND, bool PHASE, int KS>
 static void* pick_sweep_ks(bool onsite, bool mask) {
-  if (onsite) return mask ? (void*)sweep_kernel<T, KIND, true, true, KS> : (void*)sweep_kernel<T, KIND, true, false, KS>;
-  return mask ? (void*)sweep_kernel<T, KIND, false, true, KS> : (void*)sweep_kernel<T, KIND, false, false, KS>;
+  if (onsite)
+    return mask ? (void*)sweep_kernel<T, KIND, true, true, PHASE, KS> : (void*)sweep_kernel<T, KIND, true, false, PHASE, KS>;
+  return mask ? (void*)sweep_kernel<T, KIND, false, true, PHASE, KS> : (void*)sweep_kernel<T, KIND, false, false, PHASE, KS>;
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, bool PHASE>
 static void* pick_sweep(int ks, bool onsite, bool mask) {
-  if (ks == 2) return pick_sweep_ks<T, KIND, 2>(onsite, mask);
-  if (ks == 3) return pick_sweep_ks<T, KIND, 3>(onsite, mask);
-  if (ks == 4) return pick_sweep_ks<T, KIND, 4>(onsite, mask);
-  return pick_sweep_ks<T, KIND, 5>(onsite, mask);
+  if (ks == 2) return pick_sweep_ks<T, KIND, PHASE, 2>(onsite, mask);
+  if (ks == 3) return pick_sweep_ks<T, KIND, PHASE, 3>(onsite, mask);
+  if (ks == 4) return pick_sweep_ks<T, KIND, PHASE, 4>(onsite, mask);
+  return pick_sweep_ks<T, KIND, PHASE, 5>(onsite, mask);
 }
 
+// The square lattice has no Peierls table.
 template <typename T>
-static void* pick_sweep_kind(int kind, int ks, bool onsite, bool mask) {
-  return kind == KPM_SQUARE ? pick_sweep<T, KPM_SQUARE>(ks, onsite, mask)
-                            : pick_sweep<T, KPM_HONEYCOMB>(ks, onsite, mask);
+static void* pick_sweep_kind(int kind, int ks, bool onsite, bool mask, bool phase) {
+  if (kind == KPM_SQUARE) return pick_sweep<T, KPM_SQUARE, false>(ks, onsite, mask);
+  return phase ? pick_sweep<T, KPM_HONEYCOMB, true>(ks, onsite, mask)
+               : pick_sweep<T, KPM_HONEYCOMB, false>(ks, onsite, mask);
 }
 
 template <typename T, bool VEL>
@@ -1513,7 +1539,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     delete P;
     return KPM_E_INVALID;
   }
-  // Kernel variant: 3..6 = 2..5 steps per sweep (spinless lattices
+  // Kernel variant: 3..6 = 2..5 steps per sweep (spinless lattices, with or
   // without Peierls phases, room for two more vectors), 2 = LDS row ring,
   // 1 = direct loads.  The default (four steps per sweep where eligible)
   // was the fastest on the graphene workloads in FP32 and FP64.
@@ -1532,7 +1558,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     bool rows_fit = true;
     for (int l = 0; l < n_lat; ++l)
       rows_fit = rows_fit && (int64_t)lat[l].L1 * P->n_sub * P->Rp * 2 * (int64_t)P->tsize < (int64_t(1) << 31);
-    if (P->kind == KPM_HONEYCOMB_SPIN || P->has_phase || !room || !rows_fit) P->variant = 2;
+    if (P->kind == KPM_HONEYCOMB_SPIN || !room || !rows_fit) P->variant = 2;
   }
   if (P->variant >= 3 && !block_given) P->block = kMaxStepBlock;
   int lds_max = 65536;
@@ -1758,8 +1784,9 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     // v_n ring and one ring per inner level; the moment flush reuses the same LDS between tiles.
     const size_t rings = (4 * (size_t)P->sweep * (P->Tx + 2) + 1) * P->n_sub * P->Ew * 16;
     P->lds_bytes = std::max(rings, (size_t)P->block * 2 * P->NC * sizeof(double));
-    P->sweep_fn = (P->prec == KPM_FP32) ? pick_sweep_kind<float>(P->kind, P->sweep, P->has_onsite, P->has_mask)
-                                        : pick_sweep_kind<double>(P->kind, P->sweep, P->has_onsite, P->has_mask);
+    P->sweep_fn = (P->prec == KPM_FP32)
+                      ? pick_sweep_kind<float>(P->kind, P->sweep, P->has_onsite, P->has_mask, P->has_phase)
+                      : pick_sweep_kind<double>(P->kind, P->sweep, P->has_onsite, P->has_mask, P->has_phase);
   } else {
     P->lds_bytes = (P->variant == 2) ? ring_bytes : (size_t)P->block * 2 * P->NC * sizeof(double);
   }
@@ -1873,6 +1900,7 @@ static hipError_t launch_sweep_t(kpm_plan* P, hipStream_t s, const void* v, cons
   a.out_b = (T*)out_b;
   a.onsite = (const T*)P->onsite;
   a.mask = P->mask;
+  a.phase = (const T*)P->phase;
   for (int l = 0; l < kMaxSweep; ++l) a.part[l] = (l < nlev) ? part0 + l * part_stride : nullptr;
   a.a1 = first ? (T)1 : (T)2;
   a.b1 = first ? (T)0 : (T)1;

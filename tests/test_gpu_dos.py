@@ -266,6 +266,9 @@ SWEEP_LATS = [
     wl.Lattice(kind=wl.SQUARE, L1=29, L2=17, t=-2.7, anderson_w=2.0, vacancy_p=0.05, disorder_seed=9,
                e_min=-12.0, e_max=12.0),
     wl.Lattice(kind=wl.SQUARE, L1=5, L2=3, t=-2.7, disorder_seed=2, e_min=-11.0, e_max=11.0),
+    # Peierls phases (flux per cell 3/19 and 1/4): tile columns wrap across the gauge's seam.
+    wl.Lattice(kind=wl.HONEYCOMB, L1=19, L2=29, t=-2.7, flux=3 / 19, anderson_w=0.5, disorder_seed=2),
+    wl.Lattice(kind=wl.HONEYCOMB, L1=4, L2=5, t=-2.7, flux=0.25, anderson_w=0.6, vacancy_p=0.05, disorder_seed=8),
 ]
 
 
@@ -277,7 +280,7 @@ def test_sweep_kernel_matches_single_step_and_oracle(K, lat, prec, kernel):
     against the single-step ring kernel and the oracle: step counts that end
     on a full and on every kind of short last sweep (M = 2 is one step), tile
     shapes down to one row and one r-chunk, halo columns that wrap onto the
-    tile itself on tiny lattices."""
+    tile itself on tiny lattices, Peierls phases."""
     for M, R in ((2, 3), (8, 5), (14, 2), (41, 2)):
         par = wl.DosParams(num_moments=M, num_random=R, vector_seed=8, precision=prec)
         ref = K.Plan([lat], par, kernel=2)
@@ -331,9 +334,9 @@ def test_sweep_uneven_batch_and_ldos(K, prec, kernel):
 
 @pytest.mark.parametrize("kernel", [3, 4, 5, 6], ids=["ks2", "ks3", "ks4", "ks5"])
 def test_sweep_kernel_falls_back_where_ineligible(K, kernel):
-    """Spinful lattices and Peierls phases take the single-step ring kernel."""
+    """Spinful lattices (with or without Peierls phases) take the single-step ring kernel."""
     par = wl.DosParams(num_moments=16, num_random=2, vector_seed=3, precision=wl.FP32)
-    for lat in (RAGGED[1], RAGGED[2]):
+    for lat in (RAGGED[2], RAGGED[3]):
         plan = K.Plan([lat], par, kernel=kernel)
         assert plan.info()["kernel"] == 2
         mu = np.zeros((1, 2, 16))
