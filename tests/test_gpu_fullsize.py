@@ -1,5 +1,7 @@
 """Full-size parity on sampled outputs, in the launch configuration bench.py times.
 
+* graphene 4096^2 + Anderson in a uniform field (flux 1/4096): the sweep with
+  Peierls phases against the FP64 single-step kernel and the oracle (n < 8).
 * graphene 4096^2 + Anderson, M=2048, R=32: FP32 (default plan, as benchmarked)
   and FP64; the oracle computes moments n < 12 of vectors r = 0 and r = 31 on
   the full 33.5M-orbital lattice; all 2048 moments are checked for the
@@ -74,6 +76,34 @@ def test_graphene_4096_full_size(K):
         print(f"r={r}: fp64 {e64:.2e}, fp32 {e32:.2e} vs oracle (n < {nmax})")
         assert e64 <= 1e-10
         assert e32 <= 4 * (nmax / 2) * 3e-7
+
+
+@pytest.mark.timeout(900)
+def test_graphene_4096_with_field_full_size(K):
+    """Graphene 4096^2 + Anderson in a uniform field (flux 1/4096 per cell, Peierls
+    phases): the default FP32 plan (four-step sweep with phases) against the FP64
+    single-step ring kernel and, for n < 8 of vector 0, the oracle."""
+    import torch
+    L, M, R = 4096, 64, 2
+    lat, par = wl.graphene_large(precision=wl.FP32, L=L, M=M, R=R)
+    lat = lat.replace(flux=1.0 / L)
+    plan = K.Plan([lat], par)
+    assert plan.info()["kernel"] == 5
+    mu32 = torch.zeros((1, R, M), dtype=torch.float64, device="cuda")
+    plan.run(mu32)
+    plan.close()
+    par64 = par.replace(precision=wl.FP64)
+    plan = K.Plan([lat], par64, kernel=2)
+    mu64 = torch.zeros((1, R, M), dtype=torch.float64, device="cuda")
+    plan.run(mu64)
+    plan.close()
+    mu32, mu64 = mu32.cpu().numpy()[0], mu64.cpu().numpy()[0]
+    d = np.max(np.abs(mu32 - mu64))
+    print(f"field, full size: max |mu_sweep_fp32 - mu_ring_fp64| = {d:.3e}")
+    assert d <= 4 * (M / 2) * 3e-7
+    nmax = 8
+    ref = _oracle_prefix(lat, par64, [0], nmax)
+    assert np.max(np.abs(mu64[0, :nmax] - ref[0])) <= 1e-10
 
 
 @pytest.mark.timeout(900)
