@@ -12,9 +12,12 @@ computes, written from the paper (KITE, arXiv:1910.05194):
               recursion (eq. e6), stochastic-trace moments computed directly
               as <r|T_n(H)|r> (Sec. 2(c)), the Jackson kernel and the DOS
               reconstruction (eqs. e7, delta_function_cheb_expansion).
-* ``cond``    velocity operator [r^a, H] (eq. generalized velocity), the rank-2
-              Gamma tensor (eq. Gammanm) by plain inner products, and the
-              T=0 longitudinal conductivity from Gamma.
+* ``cond``    velocity operators [r^a, H] and [r^a, [r^b, H]] (eq. generalized
+              velocity), the rank-2 and rank-1 Gamma tensors (eq. Gammanm) by
+              plain inner products, the T = 0 longitudinal conductivity from
+              Gamma, the Kubo-Bastin DC and optical conductivities with the
+              Fermi function (eqs. cond 1st order, conductivity_1st_order), the
+              single-shot conductivity, and eigenstate / k-space references.
 * ``evolve``  wave-packet time evolution: the Chebyshev-Bessel expansion of
               exp(-i H dt / hbar) (Sec. 4), the Gaussian packet and its spin
               and position observables.

@@ -1,6 +1,10 @@
-"""Rank-2 conductivity moments Gamma_nm and the T=0 longitudinal conductivity (FP64).
+"""Conductivity (FP64): the rank-2 and rank-1 Gamma moments, the T = 0 longitudinal
+(Kubo-Greenwood) conductivity, the Kubo-Bastin DC (Hall) and optical conductivities
+at any temperature, the single-shot Fermi-surface conductivity, and their
+eigenstate and k-space references.
 
-Test infrastructure only (see the package docstring).
+Test infrastructure only (see the package docstring).  The sections below cite
+the passages each part follows.
 
 Paper passages followed:
 * eq. generalized velocity and the definition that follows it: the operator
