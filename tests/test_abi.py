@@ -41,6 +41,8 @@ STRUCTS = {
     "kpm_plan_info_t": "c_plan_info",
     "kpm_cond_params_t": "c_cond_params",
     "kpm_cond_stats_t": "c_cond_stats",
+    "kpm_evolve_params_t": "c_evolve_params",
+    "kpm_evolve_stats_t": "c_evolve_stats",
 }
 
 
