@@ -123,4 +123,19 @@ def test_argument_validation_without_device():
         kpm.bandwidth_probe(7, 1 << 20)
     with pytest.raises(kpm.KPMError):
         kpm.MLP(0, 16, 16)
+    psi = np.zeros((1, lat.n_orbitals), dtype=np.complex128)
+    for args, msg in (((1.0, 1, 3), "num_moments"), ((0.0, 40, 3), "dt"), ((1.0, 40, 0), "num_points")):
+        with pytest.raises(kpm.KPMError) as e:
+            kpm.time_evolve(lat, psi, *args)
+        assert e.value.code == kpm.KPM_E_INVALID and msg in str(e.value), str(e.value)
+    with pytest.raises(kpm.KPMError) as e:
+        kpm.wavepacket_gaussian(lat, [[0.0, 0.0]], [[1.0, 1.0]], -1.0, [0, 0])
+    assert "width" in str(e.value)
+    G = np.zeros((8, 8), dtype=np.complex128)
+    with pytest.raises(kpm.KPMError) as e:
+        kpm.reconstruct_sigma_bastin(G, np.zeros(2), -1.0, 1.0, 0.1, 1.0, kT=-0.01)
+    assert "kT" in str(e.value)
+    with pytest.raises(kpm.KPMError) as e:
+        kpm.reconstruct_sigma_optical(G, np.zeros(8), np.array([0.5]), 0.0, -1.0, 1.0, 0.1, 1.0, kT=-0.01)
+    assert "kT" in str(e.value)
     assert kpm.last_error() != ""
