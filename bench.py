@@ -297,7 +297,7 @@ def step_kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1910_05194_amd", "csrc")
-    for f in ("kpm_dos.hip", "kpm_plan.h", "kpm_internal.h"):
+    for f in ("kpm_dos.hip", "kpm_plan.h", "kpm_internal.h", "kpm_geometry.h"):
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -21,6 +21,7 @@
 // workgroup in LDS and across workgroups by a fixed-order tree: results are
 // bitwise reproducible.
 
+#include "kpm_geometry.h"
 #include "kpm_internal.h"
 #include "kpm_plan.h"
 
@@ -57,9 +58,8 @@ void set_error(const char* fmt, ...) {
 void clear_error() { g_err.clear(); }
 
 // ---------------------------------------------------------------------------
-// Geometry (paper Sec. 3(d) listing): honeycomb a = 0.24595 nm, a_cc = 0.142 nm.
+// Geometry (paper Sec. 3(d) listing; the constants are in kpm_geometry.h).
 // ---------------------------------------------------------------------------
-constexpr double kAHc = 0.24595, kAccHc = 0.142, kASq = 0.24595;
 // Honeycomb bond classes: A(n) - B(n + d_k).
 constexpr int kBondD1[3] = {0, 1, 0};
 constexpr int kBondD2[3] = {0, -1, -1};

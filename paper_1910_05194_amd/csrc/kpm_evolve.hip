@@ -22,6 +22,7 @@
 // and normalised.  Observables per time point and packet: the norm, <x>, <y>,
 // <x^2>, <y^2> (nm, nm^2) and <sigma_x,y,z> (hbar/2), divided by the norm;
 // FP64 sums in a fixed order.
+#include "kpm_geometry.h"
 #include "kpm_internal.h"
 #include "kpm_plan.h"
 
@@ -35,9 +36,6 @@ namespace kpm {
 
 // hbar in eV fs from the exact SI constants h and e.
 constexpr double kHbarEvFs = 6.62607015e-34 / (2.0 * 3.14159265358979323846 * 1.602176634e-19) * 1e15;
-// Lattice constants of the model build (Sec. 3(d) listing): honeycomb a and
-// a_cc, square a.
-constexpr double kEvA = 0.24595, kEvAcc = 0.142;
 constexpr int kEvoHist = 32;      // history vectors per flush
 constexpr int kObsBlocks = 512;   // partial sums per packet in the observables reduction
 
@@ -55,13 +53,13 @@ static CellGeom cell_geom(const kpm_lattice_t& L) {
   g.L2 = L.L2;
   g.tx[0] = g.tx[1] = g.ty[0] = g.ty[1] = 0.0;
   if (L.kind == KPM_SQUARE) {
-    g.a1x = kEvA; g.a1y = 0.0; g.a2x = 0.0; g.a2y = kEvA;
+    g.a1x = kASq; g.a1y = 0.0; g.a2x = 0.0; g.a2y = kASq;
     g.n_sub = 1;
     g.n_spin = 1;
   } else {
-    g.a1x = kEvA; g.a1y = 0.0; g.a2x = 0.5 * kEvA; g.a2y = 0.5 * std::sqrt(3.0) * kEvA;
-    g.ty[0] = -0.5 * kEvAcc;
-    g.ty[1] = 0.5 * kEvAcc;
+    g.a1x = kAHc; g.a1y = 0.0; g.a2x = 0.5 * kAHc; g.a2y = 0.5 * std::sqrt(3.0) * kAHc;
+    g.ty[0] = -0.5 * kAccHc;
+    g.ty[1] = 0.5 * kAccHc;
     g.n_sub = 2;
     g.n_spin = L.kind == KPM_HONEYCOMB_SPIN ? 2 : 1;
   }
