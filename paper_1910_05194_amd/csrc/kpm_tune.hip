@@ -120,8 +120,8 @@ static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
   // tile and the site chunks a tile covers (the library's choice, 4 and 16:
   // wider and narrower tiles; 448 threads is the largest workgroup whose
   // five-step rings fit in LDS at the library's chunks).  256-row bands
-  // re-read half the halo rows of 128-row ones; they run on a 1024-workgroup
-  // grid so that each workgroup still takes several tiles.  Duplicates of an
+  // (library chunks only) re-read half the halo rows of 128-row ones; they run
+  // on a 1024-workgroup grid so that each workgroup still takes several tiles.  Duplicates of an
   // already screened shape and shapes that fell back to fewer steps are
   // skipped.
   struct Cand { int kernel, block, rows, grid, chunks; };
@@ -134,7 +134,8 @@ static int autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
     for (int b : {256, 448, 512}) {
       if (b == 448 && kv != 6) continue;
       for (int r : {32, 128, 256})
-        for (int c : {0, 4, 16}) cands.push_back({kv, b, r, r >= 256 ? 1024 : 2048, c});
+        for (int c : {0, 4, 16})
+          if (r < 256 || c == 0) cands.push_back({kv, b, r, r >= 256 ? 1024 : 2048, c});
     }
   std::vector<std::pair<double, kpm_tune_t>> screened;
   std::vector<std::array<int, 5>> seen;   // (variant, block, rows, grid, chunks in use)
