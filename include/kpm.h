@@ -103,7 +103,8 @@ typedef struct kpm_dos_params_t {
 typedef struct kpm_tune_t {
   int32_t block;           /* threads per workgroup (64..512, multiple of 64); 0 = 512 for the sweep kernels
                               (less where their row rings would not fit in LDS), 256 otherwise */
-  int32_t rows;            /* lattice rows (along a2) per tile */
+  int32_t rows;            /* lattice rows (along a2) per tile; 0 = the largest power of two <= 128 (sweep
+                              kernels) or <= 64 (single-step) that leaves >= 2048 tiles */
   int32_t grid;            /* persistent workgroups (multiple of 8); 0 = one per tile */
   int32_t use_graph;       /* 1 = replay the step loop as a captured hipGraph (default), 0 = eager */
   int32_t kernel;          /* 0 = default (5 where eligible, else 2), 1 = direct neighbour loads, 2 = LDS row

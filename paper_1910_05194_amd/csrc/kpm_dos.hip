@@ -1599,18 +1599,16 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   // Cells a tile owns along n1 (a sweep kernel spends KS - 1 thread columns per side on halos).
   const int xstep = P->Tx - 2 * (P->sweep - 1);
   if (!(tune && tune->rows > 0)) {
-    // Default rows per tile: the largest power of two <= 64 that still gives
-    // at least 2048 tiles (8 per CU), so that small lattices fill the chip.
-    int64_t cols = 0;
-    for (int l = 0; l < n_lat; ++l) cols += ceil_div(lat[l].L1, xstep) * P->n_rg;
-    int ty = 64;
+    // Default rows per tile: the largest power of two <= 64 (128 for the sweep
+    // kernels, whose bands re-read 2 KS halo rows) that still gives at least
+    // 2048 tiles (8 per CU), so that small lattices fill the chip.
+    int ty = P->variant >= 3 ? 128 : 64;
     while (ty > 1) {
       int64_t nt = 0;
       for (int l = 0; l < n_lat; ++l) nt += ceil_div(lat[l].L1, xstep) * P->n_rg * ceil_div(lat[l].L2, ty);
       if (nt >= 2048) break;
       ty >>= 1;
     }
-    (void)cols;
     P->Ty = ty;
   }
 
