@@ -163,8 +163,7 @@ def leg_optical(kpm, wl, np):
     s = s.cpu().numpy()
     return {"workload": "clean spinless graphene 1024^2, Gamma^xx M=1024 + Gamma_n^xx, R=4, eta = 0.1 eV, mu = 0",
             "gamma2_s": dt2, "gamma1_s": dt1, "reconstruct_s": dtr,
-            "re_sigma_over_pi4": dict(zip(map(float, W.cpu().numpy()), map(float, s[:, 0] / (np.pi / 4)))),
-            "kspace_reference_over_pi4": {0.5: 1.0054, 1.0: 1.0172, 1.5: 1.0375, 2.0: 1.0681}}
+            "re_sigma_over_pi4": dict(zip(map(float, W.cpu().numpy()), map(float, s[:, 0] / (np.pi / 4))))}
 
 
 def leg_singleshot(kpm, wl, np):

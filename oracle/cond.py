@@ -37,11 +37,16 @@ def velocity(model: lattice.Model, direction: int) -> sp.csr_matrix:
 
 
 def gamma_nm(Ht: sp.csr_matrix, ha: sp.csr_matrix, hb: sp.csr_matrix, vectors: np.ndarray, M: int,
-             n_idx=None, m_idx=None) -> np.ndarray:
+             n_idx=None, m_idx=None, with_bound: bool = False, progress=None):
     """Gamma_nm averaged over the given start vectors, for orders n in n_idx, m in m_idx.
 
     Returns complex [len(n_idx), len(m_idx)] in the eq. Gammanm normalisation
-    (includes 1/(1+d_n0) (1+d_m0) and 1/(R N)).
+    (includes 1/(1+d_n0) (1+d_m0) and 1/(R N)).  With with_bound it also
+    returns B_nm, the same normalisation of sum_r sum_k (|Re L_nk| + |Im L_nk|)
+    (|Re R_mk| + |Im R_mk|): the sum of the magnitudes of the real products
+    that make up Re and Im of Gamma_nm, the scale of a rounding-error bound
+    for an approximate evaluation of the same inner products.  progress, if
+    given, is called with a short message after each chain.
     """
     R, N = vectors.shape
     n_idx = np.arange(M) if n_idx is None else np.asarray(n_idx)
@@ -51,24 +56,37 @@ def gamma_nm(Ht: sp.csr_matrix, ha: sp.csr_matrix, hb: sp.csr_matrix, vectors: n
     n_pos = {int(n): k for k, n in enumerate(n_idx)}
     m_pos = {int(m): k for k, m in enumerate(m_idx)}
     G = np.zeros((len(n_idx), len(m_idx)), dtype=complex)
+    B = np.zeros((len(n_idx), len(m_idx)))
     for r in range(R):
         xi = vectors[r]
         Lstore = np.zeros((len(n_idx), N), dtype=complex)
         for n, Ln in enumerate(kpm.chebyshev_vectors(Ht, -(ha @ xi), n_need)):
             if n in n_pos:
                 Lstore[n_pos[n]] = Ln
+        if progress:
+            progress(f"vector {r}: L chain done")
+        Labs = np.abs(Lstore.real) + np.abs(Lstore.imag) if with_bound else None
         for m, Tm in enumerate(kpm.chebyshev_vectors(Ht, xi, m_need)):
             if m in m_pos:
                 Rm = hb @ Tm
                 for k in range(len(n_idx)):
                     G[k, m_pos[m]] += np.vdot(Lstore[k], Rm)
+                if with_bound:
+                    B[:, m_pos[m]] += Labs @ (np.abs(Rm.real) + np.abs(Rm.imag))
+        if progress:
+            progress(f"vector {r}: R chain done")
     dn = np.where(n_idx == 0, 2.0, 1.0)
     dm = np.where(m_idx == 0, 2.0, 1.0)
-    return G / (R * N) / dn[:, None] / dm[None, :]
+    norm = (R * N) * dn[:, None] * dm[None, :]
+    if with_bound:
+        return G / norm, B / norm
+    return G / norm
 
 
-def cond_gamma(lat, par, model=None, vectors=None, n_idx=None, m_idx=None):
-    """Gamma for a lattice and CondParams-like ``par`` with random-phase vectors."""
+def cond_gamma(lat, par, model=None, vectors=None, n_idx=None, m_idx=None, with_bound: bool = False,
+               progress=None):
+    """Gamma for a lattice and CondParams-like ``par`` with random-phase vectors
+    (with_bound: (Gamma, B) as gamma_nm returns them, and the model)."""
     if model is None:
         model = lattice.build(lat)
     Ht = kpm.rescale(model.H, lat.e_min, lat.e_max)
@@ -76,7 +94,7 @@ def cond_gamma(lat, par, model=None, vectors=None, n_idx=None, m_idx=None):
         vectors = kpm.random_phase_vectors(model, par.num_random, par.vector_seed, 0)
     ha = velocity(model, par.alpha)
     hb = velocity(model, par.beta)
-    return gamma_nm(Ht, ha, hb, vectors, par.num_moments, n_idx, m_idx), model
+    return gamma_nm(Ht, ha, hb, vectors, par.num_moments, n_idx, m_idx, with_bound, progress), model
 
 
 def sigma_from_gamma(gamma: np.ndarray, energies_ev: np.ndarray, e_min: float, e_max: float,

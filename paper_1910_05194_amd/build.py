@@ -31,8 +31,15 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+HEADERS = glob.glob(os.path.join(CSRC, "*.h")) + [os.path.join(ROOT, "include", "kpm.h")]
+
+
+def _compile(src: str, only_changed: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if only_changed and os.path.exists(obj):
+        newest = max(os.path.getmtime(f) for f in [src, *HEADERS])
+        if os.path.getmtime(obj) >= newest:
+            return obj
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -40,11 +47,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, only_changed: bool = False) -> str:
+    """Compile every source (only_changed=True: skip objects newer than their
+    source and the headers) and link libkpm.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda src: _compile(src, only_changed), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -57,5 +66,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, only_changed="--changed" in sys.argv)
     sys.exit(0)

@@ -1,0 +1,104 @@
+// Device-side pieces shared by the Chebyshev step kernels (kpm_dos.hip) and
+// the multi-step sweep kernels (kpm_sweep.hip).  Not part of the ABI.
+#pragma once
+
+#include "kpm_internal.h"
+
+namespace kpm {
+
+// Per-lattice constants seen by the kernels.
+template <typename T>
+struct LatDev {
+  int32_t L1, L2;
+  int64_t site_off;     // first site of the lattice in the batch per-site arrays
+  int64_t vec_off;      // first T element of the lattice's block in a vector buffer
+  int64_t phase_off;    // first complex entry of its [L1][3] Peierls table
+  T onsite_const;       // -de+/de- (used when there is no per-site array)
+  T hop;                // t/de-
+  T blk[3][8];          // spin lattice: H_{A,B'} / de- for bond class k (2x2 complex, row-major), no phase
+  T vc[5][2][4];        // velocity weights for [dir][sublattice of i][neighbour k]: dir 0, 1 = x, y:
+                        // (r_i - r_j)_dir * de-; dir 2, 3, 4 = xx, xy, yy: the product of two components * de-
+  T exch;               // spin lattice: Delta_ex / de- (+ on spin up, - on spin down)
+};
+
+// Largest step workgroup.  Two waves per SIMD leave each wave 256 VGPRs, which
+// the spinful (2x2 hopping) kernels need to run without scratch spills.
+constexpr int kMaxStepBlock = 512;
+
+// Workgroup barrier for LDS data: waits for this wave's LDS operations only.
+// __syncthreads() also drains the global loads in flight, which would defeat
+// the one-row-ahead register prefetch of the step kernels.  The memory clobber keeps the
+// compiler from moving LDS accesses across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <int KIND>
+struct KindTraits;
+template <>
+struct KindTraits<KPM_HONEYCOMB> { static constexpr int NSUB = 2, NSPIN = 1, NNB = 3; };
+template <>
+struct KindTraits<KPM_HONEYCOMB_SPIN> { static constexpr int NSUB = 2, NSPIN = 2, NNB = 3; };
+template <>
+struct KindTraits<KPM_SQUARE> { static constexpr int NSUB = 1, NSPIN = 1, NNB = 4; };
+
+template <typename T>
+__device__ inline void cmul_acc(T& ore, T& oim, T are, T aim, T bre, T bim) {
+  ore += are * bre - aim * bim;
+  oim += are * bim + aim * bre;
+}
+
+// Reduce the per-thread dot products of one moment slot over the workgroup
+// (fixed-order LDS tree) and write them to part[slot].
+template <int NC>
+__device__ inline void flush_slot(double* lds, double* part, int slot, int tid, int Ew, int grp, int n_grp,
+                                  double* vv, double* wv) {
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    lds[tid * 2 * NC + 2 * j] = vv[j];
+    lds[tid * 2 * NC + 2 * j + 1] = wv[j];
+    vv[j] = wv[j] = 0.0;
+  }
+  __syncthreads();
+  int p2 = 1;
+  while (p2 < n_grp) p2 <<= 1;
+  for (int st = p2 >> 1; st > 0; st >>= 1) {
+    if (grp < st && grp + st < n_grp) {
+#pragma unroll
+      for (int q = 0; q < 2 * NC; ++q) lds[tid * 2 * NC + q] += lds[(tid + st * Ew) * 2 * NC + q];
+    }
+    __syncthreads();
+  }
+  if (tid < Ew) {
+    double* dst = part + ((int64_t)slot * Ew * NC + tid * NC) * 2;
+#pragma unroll
+    for (int q = 0; q < 2 * NC; ++q) dst[q] = lds[tid * 2 * NC + q];
+  }
+  __syncthreads();
+}
+
+// Multi-step sweep kernels (kpm_sweep.hip): at most kMaxSweep Chebyshev steps per launch.
+constexpr int kMaxSweep = 5;
+
+template <typename T>
+struct SweepArgs {
+  const LatDev<T>* __restrict__ lats;
+  const int4* __restrict__ tiles;   // (lattice, r-group, x0, y0), x0 the first interior column
+  const int* __restrict__ slot_of;
+  int n_tiles;
+  const T* __restrict__ v;          // v_n
+  const T* __restrict__ w;          // v_{n-1} (read when read_w1)
+  T* __restrict__ out_a;            // v_{n+nlev-1} (nlev >= 2)
+  T* __restrict__ out_b;            // v_{n+nlev}
+  const T* __restrict__ onsite;
+  const uint8_t* __restrict__ mask;
+  const T* __restrict__ phase;      // Peierls table [L1][3] complex per lattice (PHASE)
+  double* part[kMaxSweep];          // slot partials of steps n .. n+nlev-1
+  T a1, b1;
+  int read_w1, nlev;
+  int Tx, Ty, E, Ew, Rp;            // Tx = thread columns (interior + 2 (KS - 1))
+};
+
+// The sweep kernel instance for a precision (KPM_FP32 / KPM_FP64), lattice kind,
+// steps per sweep (2..kMaxSweep) and the optional per-site arrays and Peierls table.
+void* sweep_kernel_fn(int prec, int kind, int ks, bool onsite, bool mask, bool phase);
+
+}  // namespace kpm

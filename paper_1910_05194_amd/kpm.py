@@ -211,6 +211,10 @@ def moments_dos(lattices: Sequence, par, out_device=None, stream=None):
     out_device=None -> numpy arrays (host outputs); otherwise a torch device
     (e.g. "cuda:0") on which torch float64 tensors are allocated and filled.
     """
+    return _moments_dos(LIB.kpm_moments_dos, lattices, par, out_device, stream)
+
+
+def _moments_dos(fn, lattices: Sequence, par, out_device, stream):
     lats = c_lattices(lattices)
     p, keep = c_params(par)
     R = _num_vectors(par)
@@ -219,16 +223,14 @@ def moments_dos(lattices: Sequence, par, out_device=None, stream=None):
     if out_device is None:
         mu = np.zeros(shape_pv)
         mean = np.zeros(shape_mean)
-        code = LIB.kpm_moments_dos(lats, len(lattices), ctypes.byref(p), mu.ctypes.data, mean.ctypes.data, 0,
-                                   _stream_handle(stream))
+        code = fn(lats, len(lattices), ctypes.byref(p), mu.ctypes.data, mean.ctypes.data, 0, _stream_handle(stream))
     else:
         import torch
         mu = torch.zeros(shape_pv, dtype=torch.float64, device=out_device)
         mean = torch.zeros(shape_mean, dtype=torch.float64, device=out_device)
         if stream is None:
             stream = torch.cuda.current_stream(mu.device)
-        code = LIB.kpm_moments_dos(lats, len(lattices), ctypes.byref(p), mu.data_ptr(), mean.data_ptr(), 1,
-                                   _stream_handle(stream))
+        code = fn(lats, len(lattices), ctypes.byref(p), mu.data_ptr(), mean.data_ptr(), 1, _stream_handle(stream))
     del keep
     _check(code)
     return mu, mean

@@ -90,10 +90,11 @@ def test_argument_validation_without_device():
         ([lat], par.replace(start=wl.START_SITES, sites=[lat.n_orbitals]), "out of range"),
     ]
     for lats, p, msg in bad:
-        with pytest.raises(kpm.KPMError) as e:
-            kpm.moments_dos(lats, p)
-        assert e.value.code == kpm.KPM_E_INVALID
-        assert msg in str(e.value), (msg, str(e.value))
+        for fn in (kpm.moments_dos,):
+            with pytest.raises(kpm.KPMError) as e:
+                fn(lats, p)
+            assert e.value.code == kpm.KPM_E_INVALID
+            assert msg in str(e.value), (fn.__name__, msg, str(e.value))
     for blk in (100, 1024):
         with pytest.raises(kpm.KPMError) as e:
             kpm.Plan([lat], par, block=blk)

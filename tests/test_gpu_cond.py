@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import workload as wl
+from _bounds import fp32_chain_bound, split_bf16_bound
 from oracle import cond as ocond
 from oracle import lattice as olat
 
@@ -71,6 +72,50 @@ def test_gamma_split_bf16(K, M):
           f"total {e_tot:.2e}")
     assert e_gemm <= 2e-5
     assert e_tot <= 1e-4
+
+
+def _tile_report(err_ratio, n_idx, m_idx):
+    """Worst |dGamma| / B per (128-row n tile, 256-row m tile) of the split-BF16 GEMM."""
+    out = {}
+    for a, n in enumerate(n_idx):
+        for b, m in enumerate(m_idx):
+            key = (int(n) // 128, int(m) // 256)
+            out[key] = max(out.get(key, 0.0), float(err_ratio[a, b]))
+    return out
+
+
+def test_gamma_split_bf16_elementwise_all_tiles(K):
+    """M = 300 (rows padded to 512): the GEMM runs 3 n tiles x 2 m tiles.  Every
+    element of split-BF16 Gamma against the FP64 GEMM on the same FP32 blocks
+    (the GEMM's own error) under the element bound above, and against the FP64
+    oracle (the GEMM plus the FP32 chains) under that bound plus the FP32
+    recursion term."""
+    lat = LATS[0]
+    M, R = 300, 2
+    par = wl.CondParams(num_moments=M, num_random=R, vector_seed=7, alpha=0, beta=1,
+                        gamma_mode=wl.GAMMA_SPLIT_BF16)
+    print(f"split-bf16 elementwise: {lat.L1}x{lat.L2} spinful, M={M}, R={R}", flush=True)
+    G_bf16 = K.moments_cond(lat, par, precision=wl.FP32)
+    G_f64g = K.moments_cond(lat, par.replace(gamma_mode=wl.GAMMA_FP64), precision=wl.FP32)
+    (Go, B), model = ocond.cond_gamma(lat, par, with_bound=True)
+    assert np.all(B > 0)
+    # Whole K in one chunk is the worst case: K = R x (orbitals padded to a 256 block).
+    k_chunk = R * 256 * int(np.ceil(model.H.shape[0] / 256))
+    bound = split_bf16_bound(k_chunk)
+    d_gemm = np.maximum(np.abs((G_bf16 - G_f64g).real), np.abs((G_bf16 - G_f64g).imag)) / B
+    idx = np.arange(M)
+    tiles = _tile_report(d_gemm, idx, idx)
+    print(f"split-bf16 vs fp64 GEMM: max |dG|/B = {d_gemm.max():.2e} (bound {bound:.2e}); per (n tile, m tile): "
+          + ", ".join(f"{k}: {v:.1e}" for k, v in sorted(tiles.items())))
+    assert len(tiles) == 6 and all(k[1] in (0, 1) for k in tiles)
+    assert np.all(d_gemm <= bound)
+    chain = fp32_chain_bound(idx[:, None], idx[None, :])
+    d_tot = np.maximum(np.abs((G_bf16 - Go).real), np.abs((G_bf16 - Go).imag)) / B
+    d_f32 = np.maximum(np.abs((G_f64g - Go).real), np.abs((G_f64g - Go).imag)) / B
+    print(f"fp32 blocks + fp64 GEMM vs oracle: max |dG|/B = {d_f32.max():.2e}; split-bf16 vs oracle: "
+          f"{d_tot.max():.2e}; worst ratio to the bound {np.max(d_tot / (bound + chain)):.2f}")
+    assert np.all(d_f32 <= chain)
+    assert np.all(d_tot <= bound + chain)
 
 
 def test_batching_matches(K):
@@ -251,10 +296,10 @@ def test_graphene_optical_conductivity_end_to_end(K):
     """Clean spinless graphene 1024 x 1024 at mu = 0: Re sigma_xx(omega) from the
     GPU chains (FP32, split-BF16 Gamma, M = 1024, R = 4), the GPU rank-1 Gamma and
     the GPU optical reconstruction (eta = 0.1 eV), against the oracle's converged
-    k-space values of the same model (600^2 Bloch grid, same eta): 1.0172, 1.0375,
-    1.0681 times the universal pi/4 e^2/h at 1, 1.5, 2 eV.  The remaining
-    difference is the stochastic trace (+-1 % between seeds; FP64 chains give the
-    same values as FP32): gate 2.5 %."""
+    k-space values of the same model (600^2 Bloch grid, same eta; about 1.02,
+    1.04, 1.07 times the universal pi/4 e^2/h at 1, 1.5, 2 eV), computed here.
+    The remaining difference is the stochastic trace (+-1 % between seeds; FP64
+    chains give the same values as FP32): gate 2.5 %."""
     import torch
     L = 1024
     lat = wl.Lattice(kind=wl.HONEYCOMB, L1=L, L2=L, t=-2.7, e_min=-9.0, e_max=9.0)
@@ -266,8 +311,10 @@ def test_graphene_optical_conductivity_end_to_end(K):
     W = torch.tensor([1.0, 1.5, 2.0], dtype=torch.float64, device="cuda")
     s = K.reconstruct_sigma_optical(G2, G1, W, 0.0, lat.e_min, lat.e_max, 0.1, opn).cpu().numpy()
     ratio = s[:, 0] / (np.pi / 4)
-    print("graphene Re sigma_xx / (pi/4):", np.round(ratio, 4), "Im:", np.round(s[:, 1], 4))
-    assert np.max(np.abs(ratio - np.array([1.0172, 1.0375, 1.0681]))) < 0.025, ratio
+    ref = ocond.sigma_optical_kgrid(lat.replace(L1=600, L2=600), [1.0, 1.5, 2.0], 0.0, 0.1, 0, 0).real / (np.pi / 4)
+    print("graphene Re sigma_xx / (pi/4):", np.round(ratio, 4), "Im:", np.round(s[:, 1], 4), "k-space:",
+          np.round(ref, 4))
+    assert np.max(np.abs(ratio - ref)) < 0.025, (ratio, ref)
 
 
 @pytest.mark.parametrize("lat", [LATS[0], LATS[1], LATS[3]], ids=["spin-flux", "honeycomb", "qahe"])
@@ -315,11 +362,13 @@ def test_singleshot_history_flushes_and_energy_groups(K):
 def test_graphene_minimum_conductivity_singleshot(K):
     """Clean spinless graphene 1024 x 1024, single-shot on the GPU (FP32, M = 1024,
     R = 4, eta = 0.1 eV): sigma_xx(0) = 2/pi e^2/h (the universal minimum, pinned in
-    the oracle), and the oracle's k-space values 1.2007 and 2.5937 e^2/h at 0.2 and
-    0.5 eV; gate 4 % (stochastic trace)."""
+    the oracle), and the oracle's k-space Kubo-Greenwood values at 0.2 and 0.5 eV
+    (600^2 Bloch grid, same eta; about 1.20 and 2.59 e^2/h), computed here; gate 4 %
+    (stochastic trace)."""
     lat = wl.Lattice(kind=wl.HONEYCOMB, L1=1024, L2=1024, t=-2.7, e_min=-9.0, e_max=9.0)
     par = wl.CondParams(num_moments=1024, num_random=4, vector_seed=6, alpha=0, beta=0)
     s = K.sigma_singleshot(lat, par, np.array([0.0, 0.2, 0.5]), 0.1)
-    ref = np.array([2 / np.pi, 1.2007, 2.5937])
+    kg = ocond.sigma_kubo_greenwood_kgrid(lat.replace(L1=600, L2=600), [0.2, 0.5], 0.1, 0, 0)
+    ref = np.array([2 / np.pi, kg[0], kg[1]])
     print("graphene single-shot sigma_xx:", np.round(s, 4), "ref", np.round(ref, 4))
     assert np.max(np.abs(s - ref) / ref) < 0.04, s

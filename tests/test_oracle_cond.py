@@ -58,6 +58,36 @@ def test_gamma_per_vector_matches_dense_products(lat, ab):
     assert np.max(np.abs(G - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
 
 
+def test_gamma_magnitude_sum_matches_dense_products():
+    """The with_bound output B_nm: the same Gamma as without it, and B equal to
+    the sum over vectors and orbitals of (|Re L_n| + |Im L_n|)(|Re R_m| + |Im R_m|)
+    with L_n = T_n(H~)(-h^a r), R_m = h^b T_m(H~) r built from dense
+    eigen-decomposition Chebyshev matrices; B dominates |Re Gamma| and |Im Gamma|."""
+    lat = wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=4, L2=3, t=-2.7, rashba=0.3, flux=1 / 4, anderson_w=0.7,
+                     vacancy_p=0.08, disorder_seed=2)
+    M, R = 9, 2
+    par = wl.CondParams(num_moments=M, num_random=R, vector_seed=31, alpha=0, beta=1)
+    G0, m = cond.cond_gamma(lat, par)
+    (G, B), _ = cond.cond_gamma(lat, par, model=m, with_bound=True)
+    assert np.array_equal(G, G0)
+    Ht = kpm.rescale(m.H, lat.e_min, lat.e_max).toarray()
+    ha, hb = m.hx.toarray(), m.hy.toarray()
+    vecs = kpm.random_phase_vectors(m, R, 31)
+    T = [_cheb_dense(Ht, n) for n in range(M)]
+    ref = np.zeros((M, M))
+    for r in range(R):
+        v = vecs[r]
+        for n in range(M):
+            Ln = T[n] @ (-(ha @ v))
+            for mm in range(M):
+                Rm = hb @ (T[mm] @ v)
+                ref[n, mm] += np.sum((np.abs(Ln.real) + np.abs(Ln.imag)) * (np.abs(Rm.real) + np.abs(Rm.imag)))
+    d = np.where(np.arange(M) == 0, 2.0, 1.0)
+    ref = ref / (R * m.n_active) / d[:, None] / d[None, :]
+    assert np.max(np.abs(B - ref)) <= 1e-12 * np.max(ref)
+    assert np.all(B >= np.abs(G.real)) and np.all(B >= np.abs(G.imag))
+
+
 def _exact_gamma(lat, M, alpha=0, beta=0):
     m = lattice.build(lat)
     vecs = np.sqrt(m.n_active) * np.eye(m.n_active, dtype=complex)
