@@ -164,6 +164,32 @@ int kpm_moments_dos(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
                     double* mu_per_vector, double* mu_mean, int32_t out_on_device, void* hip_stream);
 
 /*
+ * Allocation-free form of kpm_moments_dos, for callers that cannot allocate
+ * device memory: code running under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, outputs, launch shape,
+ * results (bit for bit) and errors as kpm_moments_dos, except that:
+ * - the device workspace (vectors, disorder arrays, tile list, moment
+ *   partials) is carved from a static device array of
+ *   KPM_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on
+ *   holds until the process ends; the call makes no hipMalloc or hipFree and
+ *   creates no stream, event or graph (the loop runs eagerly on hip_stream);
+ * - it runs on the current HIP device (hip_stream must belong to it);
+ * - a workload whose workspace exceeds the array (roughly n_orbitals x
+ *   R_padded complex values x 4 vectors, or x 2 when four do not fit in three
+ *   quarters of it) is rejected with KPM_E_INVALID before any launch, and
+ *   kpm_last_error() states the bytes it needs.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (the kernels write everything they later read; counters and flags
+ * are cleared by kernels on hip_stream).  The call synchronises hip_stream
+ * before it returns, so calls made one after another are safe; calls that
+ * overlap on one GPU (two host threads, or a second call before the first has
+ * returned) race on the array and give wrong results.
+ */
+#define KPM_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int kpm_moments_dos_noalloc(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
+                            double* mu_per_vector, double* mu_mean, int32_t out_on_device, void* hip_stream);
+
+/*
  * Launch-shape autotuner (the analogue of the paper's user-tuned TILE size,
  * Sec. 3(b) and Table 1).  Runs the recursion for probe_steps steps with each
  * candidate (kernel variant 1..6 x block x rows x grid x chunks) on the given

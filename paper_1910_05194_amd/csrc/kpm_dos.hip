@@ -36,6 +36,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -919,6 +920,17 @@ static void fill_latdev(kpm_plan* P, std::vector<LatDev<T>>& out) {
 
 static int plan_alloc(kpm_plan* P, void** ptr, size_t bytes) {
   if (bytes == 0) bytes = 16;
+  if (P->use_arena) {
+    // Caller-provided arena: 256-byte aligned pieces, no device allocation.
+    const size_t off = (P->arena_used + 255) & ~(size_t)255;
+    if (off > P->arena_cap || bytes > P->arena_cap - off) {
+      set_error("workspace of %zu bytes or more exceeds the %zu-byte scratch array", off + bytes, P->arena_cap);
+      return KPM_E_INVALID;
+    }
+    *ptr = P->arena_base + off;
+    P->arena_used = off + bytes;
+    return KPM_OK;
+  }
   hipError_t e = hipMalloc(ptr, bytes);
   if (e != hipSuccess) {
     set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
@@ -932,8 +944,9 @@ void plan_free(kpm_plan* P) {
   void* bufs[] = {P->X, P->Y, P->Z, P->W, P->onsite, P->mask, P->phase, P->latdev, P->tiles, P->slot_of, P->ranges,
                   P->part, P->dots, P->keys, P->d_sites, P->active, P->mlat, P->plat, P->flag,
                   P->mu_dev, P->mean_dev};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
+  if (!P->use_arena)
+    for (void* b : bufs)
+      if (b) (void)hipFree(b);
   if (P->graph_loop) (void)hipGraphExecDestroy(P->graph_loop);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   for (auto& e : P->ev)
@@ -941,7 +954,7 @@ void plan_free(kpm_plan* P) {
 }
 
 int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
-                       const kpm_tune_t* tune, kpm_plan** out) {
+                       const kpm_tune_t* tune, kpm_plan** out, int (*arena_get)(char**), size_t arena_cap) {
   KPM_CHECK_ARG(out != nullptr, "plan output pointer is NULL");
   *out = nullptr;
   // No launch shape given: use the autotune cache (KPM_TUNE_CACHE) if it has one.
@@ -969,6 +982,8 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     R = p->num_random;
   }
   kpm_plan* P = new kpm_plan();
+  P->use_arena = arena_get != nullptr;
+  P->arena_cap = P->use_arena ? arena_cap : 0;
   P->lats.assign(lat, lat + n_lat);
   P->p = *p;
   if (p->start == KPM_START_SITES) P->sites.assign(p->sites, p->sites + p->num_sites);
@@ -1038,7 +1053,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   const bool block_given = tune && tune->block > 0;
   P->block = block_given ? tune->block : 256;
   P->Ty = (tune && tune->rows > 0) ? tune->rows : 64;
-  P->use_graph = tune ? (tune->use_graph != 0) : true;
+  P->use_graph = (tune ? (tune->use_graph != 0) : true) && !P->use_arena;
   if (P->block < 64 || P->block > kMaxStepBlock || (P->block % 64) != 0) {
     set_error("block must be a multiple of 64 in [64, %d]", kMaxStepBlock);
     delete P;
@@ -1064,7 +1079,9 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   if (P->variant >= 3) {
     const double vec_b = (double)P->n_orb * P->Rp * 2 * P->tsize;
     size_t free_b = 0, total_b = 0;
-    const bool room = hipMemGetInfo(&free_b, &total_b) == hipSuccess && (double)free_b > 4.0 * vec_b + 2.0e9;
+    // Four vectors with 2 GB to spare, or (arena) with a quarter of the arena left for the rest.
+    const bool room = P->use_arena ? 4.0 * vec_b <= 0.75 * (double)P->arena_cap
+                                    : hipMemGetInfo(&free_b, &total_b) == hipSuccess && (double)free_b > 4.0 * vec_b + 2.0e9;
     // The sweep kernels address a lattice row with 32-bit offsets.
     bool rows_fit = true;
     for (int l = 0; l < n_lat; ++l)
@@ -1179,7 +1196,8 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   }
   const int Rw = P->Ew * P->NC;
   const double part_step_bytes = (double)P->n_slots * Rw * 2 * 8;
-  const double budget = 2.0e9;
+  // Moment partials: at most 2 GB, or an eighth of a caller-provided arena.
+  const double budget = P->use_arena ? (double)P->arena_cap / 8.0 : 2.0e9;
   P->steps_per_chunk = (int)std::max<double>(1.0, std::min<double>(P->n_steps, std::floor(budget / part_step_bytes)));
   // A sweep kernel writes the partials of its KS steps into one chunk.
   if (P->sweep > 1)
@@ -1197,8 +1215,11 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   // Device allocations.
   const size_t vec_bytes = (size_t)P->n_orb * P->Rp * 2 * P->tsize;
   int st = KPM_OK;
+  size_t need = 0;
+  bool measure = P->use_arena;
   auto A = [&](void** ptr, size_t bytes) {
-    if (st == KPM_OK) st = plan_alloc(P, ptr, bytes);
+    if (measure) need = ((need + 255) & ~(size_t)255) + std::max<size_t>(bytes, 16);
+    else if (st == KPM_OK) st = plan_alloc(P, ptr, bytes);
   };
   auto alloc_all = [&]() {
     A(&P->X, vec_bytes);
@@ -1225,6 +1246,22 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     A((void**)&P->mu_dev, (size_t)n_lat * R * P->M * sizeof(double));
     A((void**)&P->mean_dev, (size_t)n_lat * P->M * sizeof(double));
   };
+  if (measure) {
+    // Arena: the whole workspace must fit, checked before anything is carved.
+    alloc_all();
+    if (need > P->arena_cap) {
+      set_error("this workload needs %zu bytes of device workspace; the scratch array holds %zu", need,
+                P->arena_cap);
+      delete P;
+      return KPM_E_INVALID;
+    }
+    measure = false;
+    const int ast = arena_get(&P->arena_base);
+    if (ast != KPM_OK) {
+      delete P;
+      return ast;
+    }
+  }
   alloc_all();
   if (st != KPM_OK) {
     plan_free(P);
@@ -1278,9 +1315,12 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   if (!P->sites.empty()) H2D(P->d_sites, P->sites.data(), P->sites.size() * sizeof(int64_t));
   H2D(P->mlat, ml.data(), ml.size() * sizeof(ModelLat));
   H2D(P->plat, pl.data(), pl.size() * sizeof(PhaseLat));
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
-  for (auto& ev : P->ev)
-    if (e == hipSuccess) e = hipEventCreate(&ev);
+  if (!P->use_arena) {
+    // The graph-capture stream and the timing events (not in the allocation-free form).
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+    for (auto& ev : P->ev)
+      if (e == hipSuccess) e = hipEventCreate(&ev);
+  }
   if (e != hipSuccess) {
     set_error("plan setup failed: %s", hipGetErrorString(e));
     plan_free(P);
@@ -1502,9 +1542,10 @@ static hipError_t launch_finish(kpm_plan* P, hipStream_t s) {
 static int plan_run(kpm_plan* P, double* mu_pv, double* mu_mean, int32_t on_dev, void* stream) {
   KPM_CHECK_ARG(P != nullptr, "plan is NULL");
   hipStream_t s = (hipStream_t)stream;
-  KPM_TRY_HIP(hipEventRecord(P->ev[0], s));
+  const bool timed = P->ev[0] != nullptr;
+  if (timed) KPM_TRY_HIP(hipEventRecord(P->ev[0], s));
   KPM_TRY_HIP(plan_launch_prep(P, s));
-  KPM_TRY_HIP(hipEventRecord(P->ev[1], s));
+  if (timed) KPM_TRY_HIP(hipEventRecord(P->ev[1], s));
   if (P->use_graph) {
     if (!P->graph_loop) {
       // Capture the step loop once on the plan's private stream.
@@ -1529,15 +1570,15 @@ static int plan_run(kpm_plan* P, double* mu_pv, double* mu_mean, int32_t on_dev,
   } else {
     KPM_TRY_HIP(launch_loop(P, s));
   }
-  KPM_TRY_HIP(hipEventRecord(P->ev[2], s));
+  if (timed) KPM_TRY_HIP(hipEventRecord(P->ev[2], s));
   KPM_TRY_HIP(launch_finish(P, s));
   const size_t mu_bytes = (size_t)P->n_lat * P->R * P->M * sizeof(double);
   const size_t mean_bytes = (size_t)P->n_lat * P->M * sizeof(double);
   const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (mu_pv) KPM_TRY_HIP(hipMemcpyAsync(mu_pv, P->mu_dev, mu_bytes, kind, s));
   if (mu_mean) KPM_TRY_HIP(hipMemcpyAsync(mu_mean, P->mean_dev, mean_bytes, kind, s));
-  KPM_TRY_HIP(hipEventRecord(P->ev[3], s));
-  P->timed = true;
+  if (timed) KPM_TRY_HIP(hipEventRecord(P->ev[3], s));
+  P->timed = timed;
   // The spectrum check needs the flag on the host: synchronise on the run's end.
   int flag = 0;
   std::vector<unsigned long long> act(P->n_lat);
@@ -1551,6 +1592,33 @@ static int plan_run(kpm_plan* P, double* mu_pv, double* mu_mean, int32_t on_dev,
               flag - 1);
     return KPM_E_SPECTRUM;
   }
+  return KPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of the allocation-free entry point: a file-scope device array
+// (one copy per GPU, held until the process ends).  In host code its name is
+// only a stand-in; its device address comes from hipGetSymbolAddress, once
+// per device with that device current, and only that address is passed on.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)KPM_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_address(char** out) {
+  int dev = 0;
+  KPM_TRY_HIP(hipGetDevice(&dev));
+  KPM_CHECK_ARG(dev >= 0 && dev < kMaxDevices, "device %d is beyond the %d devices supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    KPM_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    KPM_CHECK_ARG(ptr != nullptr, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
   return KPM_OK;
 }
 
@@ -1629,6 +1697,27 @@ int kpm_moments_dos(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_param
   kpm_plan_destroy(plan);
   kpm::g_err = keep;
   return st;
+}
+
+int kpm_moments_dos_noalloc(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
+                            double* mu_per_vector, double* mu_mean, int32_t out_on_device, void* hip_stream) {
+  try {
+    kpm::clear_error();
+    kpm_tune_t tune;
+    std::memset(&tune, 0, sizeof(tune));
+    kpm_plan_t* plan = nullptr;
+    int st = kpm::plan_create(lat, n_lat, p, &tune, &plan, kpm::scratch_address, kpm::kNoAllocScratchBytes);
+    if (st != KPM_OK) return st;
+    st = kpm::plan_run(plan, mu_per_vector, mu_mean, out_on_device, hip_stream);
+    const std::string keep = kpm::g_err;
+    kpm::plan_free(plan);
+    delete plan;
+    kpm::g_err = keep;
+    return st;
+  } catch (...) {
+    kpm::set_error("internal error (exception) in kpm_moments_dos_noalloc");
+    return KPM_E_DEVICE;
+  }
 }
 
 }  // extern "C"

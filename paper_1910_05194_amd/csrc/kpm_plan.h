@@ -30,8 +30,11 @@ struct StepLaunch {
 hipError_t plan_launch_step(kpm_plan* P, hipStream_t s, const StepLaunch& L);
 hipError_t plan_launch_prep(kpm_plan* P, hipStream_t s);
 int plan_set_vector_base(kpm_plan* P, int64_t r0);
+// arena_get != nullptr: after the arguments are validated, arena_get supplies a device arena of
+// arena_cap bytes; every device buffer is carved from it instead of hipMalloc, and no stream, event
+// or graph is created (the allocation-free entry point).
 int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, const kpm_tune_t* tune,
-                kpm_plan** out);
+                kpm_plan** out, int (*arena_get)(char**) = nullptr, size_t arena_cap = 0);
 void plan_free(kpm_plan* P);
 bool tune_cache_lookup(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, kpm_tune_t* t);
 double cell_area_nm2(int kind);
@@ -83,6 +86,10 @@ struct kpm_plan {
   bool timed = false;
   double bytes_per_step = 0.0;
   int64_t n_active_total = 0;
+  // Caller-provided device memory that the buffers above are carved from (nullptr: hipMalloc).
+  bool use_arena = false;
+  char* arena_base = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
 };
 
 

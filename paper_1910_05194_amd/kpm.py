@@ -27,6 +27,7 @@ HONEYCOMB, HONEYCOMB_SPIN, SQUARE = 0, 1, 2
 FP32, FP64 = 0, 1
 START_RANDOM_PHASE, START_SITES = 0, 1
 GAMMA_FP64, GAMMA_FP32, GAMMA_SPLIT_BF16 = 0, 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20   # KPM_NOALLOC_SCRATCH_BYTES
 
 
 class KPMError(RuntimeError):
@@ -98,6 +99,8 @@ def _load():
         "kpm_last_error": (ctypes.c_char_p, []),
         "kpm_moments_dos": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, ctypes.POINTER(c_dos_params),
                                            _P, _P, ctypes.c_int32, _P]),
+        "kpm_moments_dos_noalloc": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32,
+                                                   ctypes.POINTER(c_dos_params), _P, _P, ctypes.c_int32, _P]),
         "kpm_plan_create": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.c_int32, ctypes.POINTER(c_dos_params),
                                            ctypes.POINTER(c_tune), ctypes.POINTER(_P)]),
         "kpm_plan_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P]),
@@ -212,6 +215,14 @@ def moments_dos(lattices: Sequence, par, out_device=None, stream=None):
     (e.g. "cuda:0") on which torch float64 tensors are allocated and filled.
     """
     return _moments_dos(LIB.kpm_moments_dos, lattices, par, out_device, stream)
+
+
+def moments_dos_noalloc(lattices: Sequence, par, out_device=None, stream=None):
+    """kpm_moments_dos_noalloc: kpm_moments_dos with its workspace in the
+    library's static device array (no device allocation inside the call).
+    Arguments and results as moments_dos; the caller's output tensors are
+    allocated here, outside the library call."""
+    return _moments_dos(LIB.kpm_moments_dos_noalloc, lattices, par, out_device, stream)
 
 
 def _moments_dos(fn, lattices: Sequence, par, out_device, stream):

@@ -90,11 +90,17 @@ def test_argument_validation_without_device():
         ([lat], par.replace(start=wl.START_SITES, sites=[lat.n_orbitals]), "out of range"),
     ]
     for lats, p, msg in bad:
-        for fn in (kpm.moments_dos,):
+        for fn in (kpm.moments_dos, kpm.moments_dos_noalloc):
             with pytest.raises(kpm.KPMError) as e:
                 fn(lats, p)
             assert e.value.code == kpm.KPM_E_INVALID
             assert msg in str(e.value), (fn.__name__, msg, str(e.value))
+    # The allocation-free form rejects a workspace beyond its static array
+    # before touching a device: 2M orbitals x 4 complex128 vectors x 2 buffers.
+    with pytest.raises(kpm.KPMError) as e:
+        kpm.moments_dos_noalloc([lat.replace(L1=1024, L2=1024)], par)
+    assert e.value.code == kpm.KPM_E_INVALID and "scratch array" in str(e.value), str(e.value)
+    assert str(kpm.NOALLOC_SCRATCH_BYTES) in str(e.value)
     for blk in (100, 1024):
         with pytest.raises(kpm.KPMError) as e:
             kpm.Plan([lat], par, block=blk)
