@@ -1336,7 +1336,8 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
     // v_n ring and one ring per inner level; the moment flush reuses the same LDS between tiles.
     const size_t rings = (4 * (size_t)P->sweep * (P->Tx + 2) + 1) * P->n_sub * P->Ew * 16;
     P->lds_bytes = std::max(rings, (size_t)P->block * 2 * P->NC * sizeof(double));
-    P->sweep_fn = sweep_kernel_fn(P->prec, P->kind, P->sweep, P->has_onsite, P->has_mask, P->has_phase);
+    P->sweep_fn = sweep_kernel_fn(P->prec, P->kind, P->sweep, P->has_onsite, P->has_mask, P->has_phase, P->block,
+                                  P->Tx, P->Ew);
   } else {
     P->lds_bytes = (P->variant == 2) ? ring_bytes : (size_t)P->block * 2 * P->NC * sizeof(double);
   }

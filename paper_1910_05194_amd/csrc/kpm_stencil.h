@@ -98,7 +98,8 @@ struct SweepArgs {
 };
 
 // The sweep kernel instance for a precision (KPM_FP32 / KPM_FP64), lattice kind,
-// steps per sweep (2..kMaxSweep) and the optional per-site arrays and Peierls table.
-void* sweep_kernel_fn(int prec, int kind, int ks, bool onsite, bool mask, bool phase);
+// steps per sweep (2..kMaxSweep), the optional per-site arrays and Peierls
+// table, and the launch's workgroup size, thread columns and chunks per site.
+void* sweep_kernel_fn(int prec, int kind, int ks, bool onsite, bool mask, bool phase, int block, int tx, int ew);
 
 }  // namespace kpm

@@ -10,12 +10,6 @@
 
 #include <type_traits>
 
-// Streaming (non-temporal) hints in the sweep kernels: bit 0 the two
-// output vectors, bit 1 the v_{n-1} loads.  Off by default (measured).
-#ifndef KPM_SWEEP_NT
-#define KPM_SWEEP_NT 0
-#endif
-
 namespace kpm {
 
 // ---------------------------------------------------------------------------
@@ -41,13 +35,14 @@ namespace kpm {
 // first nlev levels only (the last, short sweep of a recursion).
 // ---------------------------------------------------------------------------
 
-// out = a (H~ v)_i - b w_i at one site (one spin), and the doubling dot
-// products <v|v>, <out|v> added to the FP64 sums pv, pw when acc (a select of
-// the factors, not a branch: the values of threads outside their level's
-// columns may be anything).  The products are formed in FP64 from the
-// vectors' values (exact for FP32 vectors).  With PHASE the neighbour k
-// enters with the complex coefficient (hre[k], him[k]) = hop exp(i theta_k) of
-// the site's column, else with hop.
+// out = a (H~ v)_i - b w_i at one site (one spin), and, when acc (a uniform
+// condition: the row belongs to the tile), the doubling dot products <v|v>,
+// <out|v> added to the FP64 sums pv, pw.  The products are formed in FP64
+// from the vectors' values (exact for FP32 vectors).  Threads outside the
+// tile's interior add values that may be anything (NaN included); their sums
+// are discarded once per tile.  With PHASE the neighbour k enters with the
+// complex coefficient (hre[k], him[k]) = hop exp(i theta_k) of the site's
+// column, else with hop.
 template <typename T, int KIND, bool PHASE>
 __device__ inline void sweep_site(T a, T b, bool read_w, T hop, const T* hre, const T* him, T ons, bool alive,
                                   const Pack<T>& vo, const Pack<T>& wo, const Pack<T> (&vn)[KindTraits<KIND>::NNB],
@@ -77,15 +72,51 @@ __device__ inline void sweep_site(T a, T b, bool read_w, T hop, const T* hre, co
     }
     out.v[2 * j] = orr;
     out.v[2 * j + 1] = oi;
-    // All four factors are selected: a discarded column's values may be NaN or Inf (NaN * 0 is NaN).
-    const double xr = acc ? (double)vo.v[2 * j] : 0.0, xi = acc ? (double)vo.v[2 * j + 1] : 0.0;
-    const double yr = acc ? (double)orr : 0.0, yi = acc ? (double)oi : 0.0;
-    pv[j] = fma(xr, xr, fma(xi, xi, pv[j]));
-    pw[j] = fma(yr, xr, fma(yi, xi, pw[j]));
+    if (acc) {
+      const double xr = vo.v[2 * j], xi = vo.v[2 * j + 1];
+      pv[j] = fma(xr, xr, fma(xi, xi, pv[j]));
+      pw[j] = fma((double)orr, xr, fma((double)oi, xi, pw[j]));
+    }
   }
 }
 
-template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE, int KS>
+// Memory access through buffer resources.  A resource covers one lattice row
+// (its base is uniform; num_records = the row's bytes, < 2^31); an access at
+// an offset >= num_records is dropped by the hardware's range check (a store
+// writes nothing, a load returns zeros).  Threads without data for an access
+// pass kOOB instead of branching around it, so every wave issues the same
+// memory instructions in every row: the in-order vector-memory counter then
+// lets a row wait for its own loads without also waiting for the previous
+// row's stores (a branch around a store would make the compiler assume none
+// was issued and drain the counter).
+constexpr uint32_t kOOB = 0x80000000u;
+constexpr int kRsrcFlags = 0x00020000;   // dword 3 of a gfx9 raw buffer resource
+
+__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcFlags);
+}
+template <typename T>
+__device__ inline Pack<T> buf_ld_pack(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(Pack<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <typename T>
+__device__ inline void buf_st_pack(__amdgpu_buffer_rsrc_t r, uint32_t off, const Pack<T>& v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+}
+template <typename T>
+__device__ inline T buf_ld_scalar(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+}
+
+// SHAPE 0: the tile shape (chunks per site Ew, thread columns Tx) comes from
+// the arguments.  SHAPE 1: 512 threads, 8 chunks per site (the shape the
+// benchmarked workloads run): compile-time constants, so every LDS ring
+// offset is an instruction immediate instead of an address register.
+template <typename T, int KIND, bool ONSITE, bool MASK, bool PHASE, int KS, int SHAPE = 0>
 __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   using P = Pack<T>;
   constexpr int NC = P::NC;
@@ -95,17 +126,28 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   static_assert(!PHASE || KIND == KPM_HONEYCOMB, "Peierls phases on the honeycomb lattice only");
   static_assert(KS >= 2 && KS <= kMaxSweep, "2..kMaxSweep steps per sweep");
   constexpr int NH = 2 * KS - 1;   // site-data history: level l uses the entry 2 (l - 1) iterations old
+  // Rows of loads in flight, register sets (a divisor of the 4-row unroll),
+  // and the vector-memory count a row waits for: after a row's loads come
+  // its two stores and then, for each later row in flight, its loads and two
+  // stores.  Two rows ahead measured no faster than one (the kernel is not
+  // waiting on load latency) and costs 14 registers: one row ahead.
+  constexpr int kPrefetch = 1;
+  constexpr int kSets = 2;
+  constexpr int kLoads = 3 + (ONSITE ? 1 : 0) + (MASK ? 1 : 0);
+  constexpr int kWaitVm = 2 + (kPrefetch - 1) * (kLoads + 2);
+  static_assert(kPrefetch < kSets && 4 % kSets == 0 && kWaitVm < 16, "register sets and wait count");
   extern __shared__ double lds[];
 
   const int tid = threadIdx.x;
-  const int Ew = A.Ew;
+  constexpr int kShapeEw = 8, kShapeBlock = 512;
+  const int Ew = SHAPE ? kShapeEw : A.Ew;
   const int cl = tid % Ew;
   const int grp = tid / Ew;
-  const int n_grp = blockDim.x / Ew;
+  const int n_grp = (SHAPE ? kShapeBlock : (int)blockDim.x) / Ew;
   const int s = grp % NSUB;
   const int xl = grp / NSUB;
   const int Rp = A.Rp;
-  const int Tx = A.Tx;
+  const int Tx = SHAPE ? kShapeBlock / (NSUB * kShapeEw) : A.Tx;
   const int nlev = A.nlev;
   // v_n ring: [4 slots][Tx + 2 cells][sub][chunk] (cell = thread column + 1,
   // halos in cells 0 and wcols + 1); level l (1..KS-1) ring: the same shape;
@@ -132,12 +174,18 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   const int t_begin = (int)(((int64_t)xcd * A.n_tiles) >> 3);
   const int t_end = (int)(((int64_t)(xcd + 1) * A.n_tiles) >> 3);
 
-  // The doubling dot products of each level, summed in FP64 over the thread's sites.
-  double vv[KS][NC], wv[KS][NC];
+  // The doubling dot products of each level, summed in FP64 over the thread's
+  // sites: tv, tw over the current tile (every thread, garbage outside the
+  // interior), vv, wv over the tiles of the current moment slot (interior
+  // threads' tile sums only).
+  double vv[KS][NC], wv[KS][NC], tv[KS][NC], tw[KS][NC];
 #pragma unroll
   for (int l = 0; l < KS; ++l)
 #pragma unroll
-    for (int j = 0; j < NC; ++j) vv[l][j] = wv[l][j] = 0.0;
+    for (int j = 0; j < NC; ++j) vv[l][j] = wv[l][j] = tv[l][j] = tw[l][j] = 0.0;
+  // The two levels that go to HBM (levels nlev - 1 and nlev), kept from the
+  // level loop until the row's two stores.
+  P o_a = {}, o_b = {};
 
   for (int ti = t_begin + jx; ti < t_end; ti += gx) {
     const int4 tl = A.tiles[ti];
@@ -179,66 +227,73 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     const int hr = (xe + wcols) % L1;
     const bool load_left = lane_ok && (xl == 0) && (KIND == KPM_SQUARE || s == 0);
     const bool load_right = lane_ok && (xl == wcols - 1) && (KIND == KPM_SQUARE || s == 1);
-    // Row index modulo L2 (uniform, and within a few periods of the range:
-    // no division).
+    // Row index modulo L2 (used once per tile; rows then advance by one per
+    // iteration and wrap with one comparison).
     auto wrap = [&](int y) {
       while (y < 0) y += L2;
       while (y >= L2) y -= L2;
       return y;
     };
+    auto next_row = [&](int y) { return (y + 1 == L2) ? 0 : y + 1; };
     // Everything a row needs from HBM (v_n with halos, v_{n-1}, on-site
     // potential and vacancy flag of level 1's row) is loaded into registers
-    // one iteration ahead, as one group: the levels themselves only touch LDS
-    // and store, so the in-order load counter never makes them wait for the
-    // next row's loads.  Two register sets alternate.  A thread loads at most
-    // one halo cell (a sweep tile has at least three thread columns, and on
-    // the honeycomb lattice only sublattice 0 needs the left halo and only
+    // kPrefetch iterations ahead, as one group: the levels themselves only
+    // touch LDS and store.  The register sets rotate with the row phase
+    // (kPrefetch + 1 of them live at a time).  A thread loads at most one
+    // halo cell (a sweep tile has at least three thread columns, and on the
+    // honeycomb lattice only sublattice 0 needs the left halo and only
     // sublattice 1 the right one).
     struct RowSet {
       P own, halo, w;
       T ons;
       bool alive;
     };
-    RowSet set[2];
+    RowSet set[kSets];
     const bool load_halo = load_left || load_right;
     const int halo_col = load_left ? hl : hr;
     const int halo_cell = load_left ? 0 : wcols + 1;
-    // Offsets within a lattice row (bytes for the vectors, sites for the site
-    // arrays): a row's base is the same for the whole workgroup, so an access
-    // adds one 32-bit per-thread offset to it (a row holds < 2^31 bytes).
+    // Byte offsets within a lattice row (a row holds < 2^31 bytes), kOOB for
+    // threads without data.
     const int64_t row_elems = (int64_t)L1 * NSUB * Rp * 2;
     const int64_t row_sites = (int64_t)L1 * NSUB;
+    const uint32_t row_bytes = (uint32_t)(row_elems * (int64_t)sizeof(T));
     const uint32_t lane_b = (uint32_t)((((int64_t)n1 * NSUB + s) * Rp * 2 + coff) * (int64_t)sizeof(T));
     const uint32_t halo_b = (uint32_t)((((int64_t)halo_col * NSUB + s) * Rp * 2 + coff) * (int64_t)sizeof(T));
-    const int lane_site = n1 * NSUB + s;
-    auto vrow = [&](const T* base, int yy, uint32_t off) {
-      return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base + (int64_t)yy * row_elems) + off);
+    const uint32_t lane_site = (uint32_t)(n1 * NSUB + s);
+    const uint32_t off_own = act ? lane_b : kOOB;
+    const uint32_t off_halo = load_halo ? halo_b : kOOB;
+    const uint32_t off_ons = act ? lane_site * (uint32_t)sizeof(T) : kOOB;
+    const uint32_t off_mask = act ? lane_site : kOOB;
+    // Loads of one row of v_n (when in range) and of the site data and v_{n-1}
+    // of the row below it; out of range, the same instructions with kOOB.
+    auto fetch = [&](RowSet& S, int yv, int ys, bool in_range) {
+      const __amdgpu_buffer_rsrc_t rv = row_rsrc(vb + (int64_t)yv * row_elems, row_bytes);
+      const __amdgpu_buffer_rsrc_t rw = row_rsrc(wb + (int64_t)ys * row_elems, row_bytes);
+      S.own = buf_ld_pack<T>(rv, in_range ? off_own : kOOB);
+      S.halo = buf_ld_pack<T>(rv, in_range ? off_halo : kOOB);
+      S.w = buf_ld_pack<T>(rw, in_range ? off_own : kOOB);
+      const int64_t row_site = site_off + (int64_t)ys * row_sites;
+      if constexpr (ONSITE) {
+        S.ons = buf_ld_scalar<T>(row_rsrc(A.onsite + row_site, (uint32_t)(row_sites * (int64_t)sizeof(T))),
+                                 in_range ? off_ons : kOOB);
+      } else {
+        S.ons = ons_c;
+      }
+      if constexpr (MASK) {
+        S.alive = __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(A.mask + row_site, (uint32_t)row_sites),
+                                                      in_range ? off_mask : kOOB, 0, 0) != 0;
+      } else {
+        S.alive = true;
+      }
     };
-    auto fetch_row = [&](RowSet& S, int yy) {
-      if (act) S.own = ld_pack(vrow(vb, yy, lane_b));
-      if (load_halo) S.halo = ld_pack(vrow(vb, yy, halo_b));
+    auto fetch_v = [&](RowSet& S, int yv) {
+      const __amdgpu_buffer_rsrc_t rv = row_rsrc(vb + (int64_t)yv * row_elems, row_bytes);
+      S.own = buf_ld_pack<T>(rv, off_own);
+      S.halo = buf_ld_pack<T>(rv, off_halo);
     };
     auto store_row = [&](const RowSet& S, int slot) {
       if (act) r0(slot, xl + 1, s) = S.own;
       if (load_halo) r0(slot, halo_cell, s) = S.halo;
-    };
-    auto fetch_site = [&](RowSet& S, int yy) {
-      S.ons = ons_c;
-      S.alive = true;
-      if (act) {
-        if (A.read_w1) {
-          if constexpr ((KPM_SWEEP_NT & 2) != 0) S.w = ld_pack_nt(vrow(wb, yy, lane_b));
-          else S.w = ld_pack(vrow(wb, yy, lane_b));
-        }
-        const int64_t row_site = site_off + (int64_t)yy * row_sites;
-        if constexpr (ONSITE) S.ons = A.onsite[row_site + lane_site];
-        if constexpr (MASK) S.alive = A.mask[row_site + lane_site] != 0;
-      }
-    };
-    auto put = [&](T* base, int yy, const P& o) {
-      T* q = const_cast<T*>(vrow(base, yy, lane_b));
-      if constexpr ((KPM_SWEEP_NT & 1) != 0) st_pack_nt(q, o);
-      else st_pack(q, o);
     };
     const int ty = min(A.Ty, L2 - y0);
     // Level l forms row y0 + j - (2 l - 1) at iteration j: it reads rows of
@@ -257,16 +312,27 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       ons_h[k] = ons_c;
       alive_h[k] = true;
     }
-    // One iteration with phase p = (j - j0) mod 4: set[p & 1] holds v_n row
-    // y0 + j and the site data of row y0 + j - 1.  v_n row y0 + j sits in LDS
-    // slot (p + 2) & 3, the rows level l forms at iteration j in slot p.
-    auto row = [&](auto ph, int j) {
+    // Wrapped rows of the current iteration j: yf = y0 + j + kPrefetch (the
+    // v_n row fetched), ys = yf - 1 (its site data and v_{n-1}), yb = the row
+    // level nlev forms (stored to out_b) and ya = yb + 2 (level nlev - 1,
+    // stored to out_a).
+    int yf = wrap(y0 + j0 + kPrefetch), ys = wrap(y0 + j0 + kPrefetch - 1), yb = wrap(y0 + j0 - (2 * nlev - 1)),
+        ya = wrap(y0 + j0 - (2 * nlev - 3));
+    // One iteration with phase p = (j - j0) mod 4: set[p % kSets] holds v_n
+    // row y0 + j and the site data of row y0 + j - 1.  v_n row y0 + j sits in
+    // LDS slot (p + 2) & 3, the rows level l forms at iteration j in slot p.
+    // FULL (a group of rows in the middle of a full sweep's tile): every
+    // level is active, every row formed lies inside the tile and the next
+    // rows' loads are in range, so the row runs without those tests.
+    auto row = [&](auto ph, int j, auto full) {
       constexpr int p = decltype(ph)::value;
-      RowSet& cur = set[p & 1];
-      RowSet& nxt = set[(p + 1) & 1];
-      // All of cur has arrived (vmcnt(0); expcnt and lgkmcnt left at their
-      // maxima), so no later use of it waits for the loads issued below.
-      __builtin_amdgcn_s_waitcnt(0x0F70);
+      constexpr bool FULL = decltype(full)::value;
+      RowSet& cur = set[p % kSets];
+      RowSet& nxt = set[(p + kPrefetch) % kSets];
+      // cur has arrived: everything issued before the last kPrefetch rows'
+      // stores and the loads between them is complete (expcnt and lgkmcnt
+      // left at their maxima).
+      __builtin_amdgcn_s_waitcnt(0x0F70 | kWaitVm);
       store_row(cur, (p + 2) & 3);
 #pragma unroll
       for (int k = NH - 1; k > 0; --k) {
@@ -276,18 +342,14 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       ons_h[0] = cur.ons;
       alive_h[0] = cur.alive;
       __builtin_amdgcn_sched_barrier(0);
-      if (j + 1 <= ty + KS - 1) {
-        fetch_row(nxt, wrap(y0 + j + 1));
-        fetch_site(nxt, wrap(y0 + j));
-      }
+      fetch(nxt, yf, ys, FULL || j + kPrefetch <= ty + KS - 1);
       lds_barrier();
       // Levels from the deepest down: level l reads w from level l - 2's ring
       // slot of four iterations back, the slot that level l - 2 refills now.
 #pragma unroll
       for (int lev = KS; lev >= 2; --lev) {
         const int y = y0 + j - (2 * lev - 1);
-        const int yw = wrap(y);
-        if (lev <= nlev && j >= 3 * lev - 1 - KS && j <= ty + KS + lev - 2) {
+        if (FULL || (lev <= nlev && j >= 3 * lev - 1 - KS && j <= ty + KS + lev - 2)) {
           constexpr int sp1 = (p + 3) & 3, s0 = (p + 2) & 3, sm1 = (p + 1) & 3;   // rows y + 1, y, y - 1
           const int x = xlc + 1;   // this thread's cell
           P vn[NNB];
@@ -310,19 +372,33 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
           // the next iteration's row, from this same thread for its own cell),
           // or level lev-2's output of four iterations back.
           const P wo = (lev == 2) ? r0((p + 3) & 3, x, s) : rl(lev >= 3 ? lev - 2 : 1, p, x, s);
-          const bool own = inner && (y >= y0) && (y < y0 + ty);
           P o;
           sweep_site<T, KIND, PHASE>((T)2, (T)1, true, hop, hre, him, ons_h[2 * lev - 2], alive_h[2 * lev - 2], vo, wo,
-                                     vn, o, own, vv[lev - 1], wv[lev - 1]);
+                                     vn, o, FULL || ((y >= y0) && (y < y0 + ty)), tv[lev - 1], tw[lev - 1]);
           if (lev < KS) rl(lev, p, x, s) = o;
-          if (own && lev >= nlev - 1) put(lev == nlev ? ob : oa, yw, o);
+          // The stored levels: KS and KS - 1 in a full sweep, else nlev and
+          // nlev - 1 of the recursion's last, short sweep (element-wise
+          // selects: a conditional copy of the whole pack would be kept in
+          // scratch memory).
+          if (lev == KS) o_b = o;
+          if (lev == KS - 1) o_a = o;
+          if (!FULL && nlev < KS) {
+            const bool cb = lev == nlev, ca = lev == nlev - 1;
+#pragma unroll
+            for (int q = 0; q < 2 * NC; ++q) {
+              o_b.v[q] = cb ? o.v[q] : o_b.v[q];
+              o_a.v[q] = ca ? o.v[q] : o_a.v[q];
+            }
+          }
         }
+        // One level at a time: without branches between them the scheduler
+        // would start every level's LDS reads at once and run out of registers.
+        if constexpr (FULL) __builtin_amdgcn_sched_barrier(0);
       }
       // Level 1 (row y0 + j - 1) from v_n rows y0 + j - 2 .. y0 + j.
       {
         const int y = y0 + j - 1;
-        const int yw = wrap(y);
-        if (j <= ty + KS - 1) {
+        if (FULL || j <= ty + KS - 1) {
           constexpr int sp1 = (p + 2) & 3, s0 = (p + 1) & 3, sm1 = p;   // v_n rows y + 1, y, y - 1
           const int x = xlc + 1;
           P vn[NNB];
@@ -341,29 +417,80 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
             vn[2] = r0(sp1, x, 0);
           }
           const P vo = r0(s0, x, s);   // v_n row y
-          const bool own = inner && (y >= y0) && (y < y0 + ty);
           P o;
           sweep_site<T, KIND, PHASE>(A.a1, A.b1, A.read_w1 != 0, hop, hre, him, ons_h[0], alive_h[0], vo, cur.w, vn, o,
-                                     own, vv[0], wv[0]);
+                                     FULL || ((y >= y0) && (y < y0 + ty)), tv[0], tw[0]);
           rl(1, p, x, s) = o;
-          if (own && nlev <= 2) put(nlev == 1 ? ob : oa, yw, o);
+          if constexpr (KS == 2) o_a = o;   // a full two-step sweep stores levels 1 and 2
+          if (!FULL && nlev <= 2) {
+            const bool cb = nlev == 1;
+#pragma unroll
+            for (int q = 0; q < 2 * NC; ++q) {
+              o_b.v[q] = cb ? o.v[q] : o_b.v[q];
+              o_a.v[q] = cb ? o_a.v[q] : o.v[q];
+            }
+          }
         }
       }
+      // The row's two stores: level nlev at row y0 + j - (2 nlev - 1), level
+      // nlev - 1 two rows higher (a thread stores its interior cells of the
+      // tile's own rows; every other store is dropped).
+      {
+        const int yb_u = y0 + j - (2 * nlev - 1);
+        const bool own_b = inner && (FULL || ((yb_u >= y0) && (yb_u < y0 + ty)));
+        const bool own_a = inner && (FULL || ((nlev >= 2) && (yb_u + 2 >= y0) && (yb_u + 2 < y0 + ty)));
+        buf_st_pack<T>(row_rsrc(ob + (int64_t)yb * row_elems, row_bytes), own_b ? lane_b : kOOB, o_b);
+        buf_st_pack<T>(row_rsrc(oa + (int64_t)ya * row_elems, row_bytes), own_a ? lane_b : kOOB, o_a);
+      }
+      yf = next_row(yf);
+      ys = next_row(ys);
+      yb = next_row(yb);
+      ya = next_row(ya);
     };
     // Prologue: v_n rows y0 - KS and y0 - KS + 1 into slots 0 and 1, the
     // first iteration's row and site data into registers.
-    fetch_row(set[0], wrap(y0 - KS));
+    fetch_v(set[0], wrap(y0 - KS));
     store_row(set[0], 0);
-    fetch_row(set[0], wrap(y0 - KS + 1));
+    fetch_v(set[0], wrap(y0 - KS + 1));
     store_row(set[0], 1);
-    fetch_row(set[0], wrap(y0 + j0));
-    fetch_site(set[0], wrap(y0 + j0 - 1));
-    for (int j = j0; j <= j_last; j += 4) {
-      row(std::integral_constant<int, 0>{}, j);
-      row(std::integral_constant<int, 1>{}, j + 1);
-      row(std::integral_constant<int, 2>{}, j + 2);
-      row(std::integral_constant<int, 3>{}, j + 3);
+    // The first kPrefetch rows' loads, each followed by two dropped stores:
+    // the loop is entered with the same pattern of memory instructions as
+    // every later row sees (a row's loads, then that row's two stores), so
+    // its waits stay the same.
+#pragma unroll
+    for (int k = 0; k < kPrefetch; ++k) {
+      fetch(set[k], wrap(y0 + j0 + k), wrap(y0 + j0 + k - 1), true);
+      const __amdgpu_buffer_rsrc_t rz = row_rsrc(ob, row_bytes);
+      buf_st_pack<T>(rz, kOOB, o_b);
+      buf_st_pack<T>(rz, kOOB, o_a);
     }
+    // Rows j .. j + 3 are FULL when nlev = KS, j >= 2 KS - 1 (every level's
+    // first row formed) and j + 3 <= ty (the first level still inside the
+    // tile; the loads of rows up to j + 3 + kPrefetch <= ty + KS - 1 then stay
+    // in range since kPrefetch < KS).
+    const int j_full_end = ty - 3;
+    for (int j = j0; j <= j_last; j += 4) {
+      if (nlev == KS && j >= 2 * KS - 1 && j <= j_full_end) {
+        row(std::integral_constant<int, 0>{}, j, std::true_type{});
+        row(std::integral_constant<int, 1>{}, j + 1, std::true_type{});
+        row(std::integral_constant<int, 2>{}, j + 2, std::true_type{});
+        row(std::integral_constant<int, 3>{}, j + 3, std::true_type{});
+      } else {
+        row(std::integral_constant<int, 0>{}, j, std::false_type{});
+        row(std::integral_constant<int, 1>{}, j + 1, std::false_type{});
+        row(std::integral_constant<int, 2>{}, j + 2, std::false_type{});
+        row(std::integral_constant<int, 3>{}, j + 3, std::false_type{});
+      }
+    }
+    // The tile's sums count for interior threads only (a select: the others' may be NaN).
+#pragma unroll
+    for (int l = 0; l < KS; ++l)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        vv[l][q] += inner ? tv[l][q] : 0.0;
+        wv[l][q] += inner ? tw[l][q] : 0.0;
+        tv[l][q] = tw[l][q] = 0.0;
+      }
     __syncthreads();   // the next tile (or the moment flush) reuses the LDS
     const int tn = ti + gx;
     const int slot = A.slot_of[ti];
@@ -375,32 +502,37 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
   }
 }
 
-template <typename T, int KIND, bool PHASE, int KS>
+template <typename T, int KIND, bool PHASE, int KS, int SHAPE = 0>
 static void* pick_sweep_ks(bool onsite, bool mask) {
   if (onsite)
-    return mask ? (void*)sweep_kernel<T, KIND, true, true, PHASE, KS> : (void*)sweep_kernel<T, KIND, true, false, PHASE, KS>;
-  return mask ? (void*)sweep_kernel<T, KIND, false, true, PHASE, KS> : (void*)sweep_kernel<T, KIND, false, false, PHASE, KS>;
+    return mask ? (void*)sweep_kernel<T, KIND, true, true, PHASE, KS, SHAPE>
+                : (void*)sweep_kernel<T, KIND, true, false, PHASE, KS, SHAPE>;
+  return mask ? (void*)sweep_kernel<T, KIND, false, true, PHASE, KS, SHAPE>
+              : (void*)sweep_kernel<T, KIND, false, false, PHASE, KS, SHAPE>;
 }
 
 template <typename T, int KIND, bool PHASE>
-static void* pick_sweep(int ks, bool onsite, bool mask) {
+static void* pick_sweep(int ks, bool onsite, bool mask, bool shape1) {
   if (ks == 2) return pick_sweep_ks<T, KIND, PHASE, 2>(onsite, mask);
   if (ks == 3) return pick_sweep_ks<T, KIND, PHASE, 3>(onsite, mask);
-  if (ks == 4) return pick_sweep_ks<T, KIND, PHASE, 4>(onsite, mask);
+  if (ks == 4)
+    return shape1 ? pick_sweep_ks<T, KIND, PHASE, 4, 1>(onsite, mask) : pick_sweep_ks<T, KIND, PHASE, 4>(onsite, mask);
   return pick_sweep_ks<T, KIND, PHASE, 5>(onsite, mask);
 }
 
 // The square lattice has no Peierls table.
 template <typename T>
-static void* pick_sweep_kind(int kind, int ks, bool onsite, bool mask, bool phase) {
-  if (kind == KPM_SQUARE) return pick_sweep<T, KPM_SQUARE, false>(ks, onsite, mask);
-  return phase ? pick_sweep<T, KPM_HONEYCOMB, true>(ks, onsite, mask)
-               : pick_sweep<T, KPM_HONEYCOMB, false>(ks, onsite, mask);
+static void* pick_sweep_kind(int kind, int ks, bool onsite, bool mask, bool phase, bool shape1) {
+  if (kind == KPM_SQUARE) return pick_sweep<T, KPM_SQUARE, false>(ks, onsite, mask, shape1);
+  return phase ? pick_sweep<T, KPM_HONEYCOMB, true>(ks, onsite, mask, shape1)
+               : pick_sweep<T, KPM_HONEYCOMB, false>(ks, onsite, mask, shape1);
 }
 
-void* sweep_kernel_fn(int prec, int kind, int ks, bool onsite, bool mask, bool phase) {
-  return prec == KPM_FP32 ? pick_sweep_kind<float>(kind, ks, onsite, mask, phase)
-                          : pick_sweep_kind<double>(kind, ks, onsite, mask, phase);
+void* sweep_kernel_fn(int prec, int kind, int ks, bool onsite, bool mask, bool phase, int block, int tx, int ew) {
+  const int nsub = kind == KPM_SQUARE ? 1 : 2;
+  const bool shape1 = block == 512 && ew == 8 && tx == 512 / (nsub * 8);
+  return prec == KPM_FP32 ? pick_sweep_kind<float>(kind, ks, onsite, mask, phase, shape1)
+                          : pick_sweep_kind<double>(kind, ks, onsite, mask, phase, shape1);
 }
 
 }  // namespace kpm
