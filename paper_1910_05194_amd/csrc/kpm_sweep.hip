@@ -321,12 +321,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     // One iteration with phase p = (j - j0) mod 4: set[p % kSets] holds v_n
     // row y0 + j and the site data of row y0 + j - 1.  v_n row y0 + j sits in
     // LDS slot (p + 2) & 3, the rows level l forms at iteration j in slot p.
-    // FULL (a group of rows in the middle of a full sweep's tile): every
-    // level is active, every row formed lies inside the tile and the next
-    // rows' loads are in range, so the row runs without those tests.
-    auto row = [&](auto ph, int j, auto full) {
+    auto row = [&](auto ph, int j) {
       constexpr int p = decltype(ph)::value;
-      constexpr bool FULL = decltype(full)::value;
       RowSet& cur = set[p % kSets];
       RowSet& nxt = set[(p + kPrefetch) % kSets];
       // cur has arrived: everything issued before the last kPrefetch rows'
@@ -342,14 +338,14 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       ons_h[0] = cur.ons;
       alive_h[0] = cur.alive;
       __builtin_amdgcn_sched_barrier(0);
-      fetch(nxt, yf, ys, FULL || j + kPrefetch <= ty + KS - 1);
+      fetch(nxt, yf, ys, j + kPrefetch <= ty + KS - 1);
       lds_barrier();
       // Levels from the deepest down: level l reads w from level l - 2's ring
       // slot of four iterations back, the slot that level l - 2 refills now.
 #pragma unroll
       for (int lev = KS; lev >= 2; --lev) {
         const int y = y0 + j - (2 * lev - 1);
-        if (FULL || (lev <= nlev && j >= 3 * lev - 1 - KS && j <= ty + KS + lev - 2)) {
+        if (lev <= nlev && j >= 3 * lev - 1 - KS && j <= ty + KS + lev - 2) {
           constexpr int sp1 = (p + 3) & 3, s0 = (p + 2) & 3, sm1 = (p + 1) & 3;   // rows y + 1, y, y - 1
           const int x = xlc + 1;   // this thread's cell
           P vn[NNB];
@@ -374,7 +370,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
           const P wo = (lev == 2) ? r0((p + 3) & 3, x, s) : rl(lev >= 3 ? lev - 2 : 1, p, x, s);
           P o;
           sweep_site<T, KIND, PHASE>((T)2, (T)1, true, hop, hre, him, ons_h[2 * lev - 2], alive_h[2 * lev - 2], vo, wo,
-                                     vn, o, FULL || ((y >= y0) && (y < y0 + ty)), tv[lev - 1], tw[lev - 1]);
+                                     vn, o, (y >= y0) && (y < y0 + ty), tv[lev - 1], tw[lev - 1]);
           if (lev < KS) rl(lev, p, x, s) = o;
           // The stored levels: KS and KS - 1 in a full sweep, else nlev and
           // nlev - 1 of the recursion's last, short sweep (element-wise
@@ -382,7 +378,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
           // scratch memory).
           if (lev == KS) o_b = o;
           if (lev == KS - 1) o_a = o;
-          if (!FULL && nlev < KS) {
+          if (nlev < KS) {
             const bool cb = lev == nlev, ca = lev == nlev - 1;
 #pragma unroll
             for (int q = 0; q < 2 * NC; ++q) {
@@ -391,14 +387,11 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
             }
           }
         }
-        // One level at a time: without branches between them the scheduler
-        // would start every level's LDS reads at once and run out of registers.
-        if constexpr (FULL) __builtin_amdgcn_sched_barrier(0);
       }
       // Level 1 (row y0 + j - 1) from v_n rows y0 + j - 2 .. y0 + j.
       {
         const int y = y0 + j - 1;
-        if (FULL || j <= ty + KS - 1) {
+        if (j <= ty + KS - 1) {
           constexpr int sp1 = (p + 2) & 3, s0 = (p + 1) & 3, sm1 = p;   // v_n rows y + 1, y, y - 1
           const int x = xlc + 1;
           P vn[NNB];
@@ -419,10 +412,10 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
           const P vo = r0(s0, x, s);   // v_n row y
           P o;
           sweep_site<T, KIND, PHASE>(A.a1, A.b1, A.read_w1 != 0, hop, hre, him, ons_h[0], alive_h[0], vo, cur.w, vn, o,
-                                     FULL || ((y >= y0) && (y < y0 + ty)), tv[0], tw[0]);
+                                     (y >= y0) && (y < y0 + ty), tv[0], tw[0]);
           rl(1, p, x, s) = o;
           if constexpr (KS == 2) o_a = o;   // a full two-step sweep stores levels 1 and 2
-          if (!FULL && nlev <= 2) {
+          if (nlev <= 2) {
             const bool cb = nlev == 1;
 #pragma unroll
             for (int q = 0; q < 2 * NC; ++q) {
@@ -437,8 +430,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       // tile's own rows; every other store is dropped).
       {
         const int yb_u = y0 + j - (2 * nlev - 1);
-        const bool own_b = inner && (FULL || ((yb_u >= y0) && (yb_u < y0 + ty)));
-        const bool own_a = inner && (FULL || ((nlev >= 2) && (yb_u + 2 >= y0) && (yb_u + 2 < y0 + ty)));
+        const bool own_b = inner && (yb_u >= y0) && (yb_u < y0 + ty);
+        const bool own_a = inner && (nlev >= 2) && (yb_u + 2 >= y0) && (yb_u + 2 < y0 + ty);
         buf_st_pack<T>(row_rsrc(ob + (int64_t)yb * row_elems, row_bytes), own_b ? lane_b : kOOB, o_b);
         buf_st_pack<T>(row_rsrc(oa + (int64_t)ya * row_elems, row_bytes), own_a ? lane_b : kOOB, o_a);
       }
@@ -464,23 +457,11 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       buf_st_pack<T>(rz, kOOB, o_b);
       buf_st_pack<T>(rz, kOOB, o_a);
     }
-    // Rows j .. j + 3 are FULL when nlev = KS, j >= 2 KS - 1 (every level's
-    // first row formed) and j + 3 <= ty (the first level still inside the
-    // tile; the loads of rows up to j + 3 + kPrefetch <= ty + KS - 1 then stay
-    // in range since kPrefetch < KS).
-    const int j_full_end = ty - 3;
     for (int j = j0; j <= j_last; j += 4) {
-      if (nlev == KS && j >= 2 * KS - 1 && j <= j_full_end) {
-        row(std::integral_constant<int, 0>{}, j, std::true_type{});
-        row(std::integral_constant<int, 1>{}, j + 1, std::true_type{});
-        row(std::integral_constant<int, 2>{}, j + 2, std::true_type{});
-        row(std::integral_constant<int, 3>{}, j + 3, std::true_type{});
-      } else {
-        row(std::integral_constant<int, 0>{}, j, std::false_type{});
-        row(std::integral_constant<int, 1>{}, j + 1, std::false_type{});
-        row(std::integral_constant<int, 2>{}, j + 2, std::false_type{});
-        row(std::integral_constant<int, 3>{}, j + 3, std::false_type{});
-      }
+      row(std::integral_constant<int, 0>{}, j);
+      row(std::integral_constant<int, 1>{}, j + 1);
+      row(std::integral_constant<int, 2>{}, j + 2);
+      row(std::integral_constant<int, 3>{}, j + 3);
     }
     // The tile's sums count for interior threads only (a select: the others' may be NaN).
 #pragma unroll
