@@ -48,30 +48,52 @@ def log(*a):
     print(f"[{time.perf_counter() - _T0:7.1f} s]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(lat_full, par_full):
-    """The oracle on a bounded sample of the headline model: the same t, W,
-    bounds and seeds at 1024 x 1024 cells (2.1M orbitals), R = 1, M = 192, one
-    thread, model build included."""
+def _oracle_sample(args):
+    """One oracle run (model build + moments of one random vector): a worker of cpu_baseline."""
+    lat, par, seed = args
     from threadpoolctl import threadpool_limits
     from oracle import kpm as okpm
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        okpm.dos_moments(lat, par.replace(vector_seed=seed))
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(lat_full, par_full, workers: int):
+    """The oracle on a bounded sample of the headline model: the same t, W,
+    bounds and seeds at 1024 x 1024 cells (2.1M orbitals), R = 1, M = 192,
+    model build included; once on one thread, then one independent random
+    vector per worker process on `workers` cores at once (the oracle's work
+    splits over vectors with no communication).  Runs before the GPU is
+    touched (the workers are forked)."""
+    import multiprocessing as mp
     L, M, R = 1024, 192, 1
     lat = lat_full.replace(L1=L, L2=L)
     par = par_full.replace(num_moments=M, num_random=R, precision=1)
-    with threadpool_limits(1):
-        t0 = time.perf_counter()
-        okpm.dos_moments(lat, par)
-        dt = time.perf_counter() - t0
     n = lat.n_orbitals
-    model = ""
+    dt1 = _oracle_sample((lat, par, par.vector_seed))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        per = pool.map(_oracle_sample, [(lat, par, par.vector_seed + k) for k in range(workers)])
+    dt_all = time.perf_counter() - t0
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+            for line in f:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                    info[k] = v.strip()
     except OSError:
         pass
-    return {"value": n * M * R / dt, "unit": "orbital*moment*vector updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle (scipy CSR, FP64, one thread) on the headline model at 1024x1024 cells, R=1, "
-                      f"M={M}, model build included: {dt:.2f} s",
-            "host_cpu": model, "host_threads": os.cpu_count()}
+    return {"value": workers * n * M * R / dt_all, "unit": "orbital*moment*vector updates/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"oracle (scipy CSR, FP64) on the headline model at 1024x1024 cells, M={M}, model build "
+                      f"included: {workers} worker processes x one random vector each in {dt_all:.2f} s "
+                      f"(per worker {min(per):.2f}..{max(per):.2f} s); one thread alone: {dt1:.2f} s",
+            "single_thread_value": n * M * R / dt1,
+            "host_cpu": info, "host_threads": os.cpu_count()}
 
 
 def leg_small(kpm, wl, np):
@@ -231,7 +253,7 @@ def leg_batch(kpm, wl, np):
             "kernel": i["kernel"], "tiles": i["n_tiles"]}
 
 
-def leg_mlp(kpm, wl, np, n_train=4000, L_train=1024, R_train=2, epochs=200, n_eval=8):
+def leg_mlp(kpm, wl, np, n_train=20000, L_train=1024, R_train=2, epochs=200, n_eval=8):
     """Learned extrapolation 256 -> 2048 moments: data from the recursion, training with the
     library's kernels, BF16 inference, acceptance checks with fallback to the full recursion,
     DOS error against the full recursion."""
@@ -259,26 +281,35 @@ def leg_mlp(kpm, wl, np, n_train=4000, L_train=1024, R_train=2, epochs=200, n_ev
     ext = ex.splice(net, head)
     torch.cuda.synchronize()
     t_fast = time.perf_counter() - t0
-    e256, e320, e_ml, acc = [], [], [], []
+    e256, e320, e_ml = [], [], []
     for i, L in enumerate(evl):
         E = wl.energy_grid(L.e_min, L.e_max, 1024)
         rf = kpm.reconstruct_jackson(full[i], E, L.e_min, L.e_max)
         e256.append(ex.dos_error(kpm.reconstruct_jackson(head[i, :n_in], E, L.e_min, L.e_max), rf))
         e320.append(ex.dos_error(kpm.reconstruct_jackson(head[i], E, L.e_min, L.e_max), rf))
         e_ml.append(ex.dos_error(kpm.reconstruct_jackson(ext[i], E, L.e_min, L.e_max), rf))
-        acc.append(ex.accept(ext[i:i + 1], L.e_min, L.e_max, E, overlap=ov[i:i + 1], overlap_tol=1.0,
-                             neg_tol=0.05)[0])
+    # The learned path as a user runs it: the truncated recursion, the network,
+    # the acceptance checks and the full recursion for the rejected tables
+    # (fresh random vectors for those: their error against the reference is
+    # the stochastic-trace noise of two independent full runs).
+    t0 = time.perf_counter()
+    tables, ok_lp, _ = ex.learned_moments(net, evl, 16, 777, n_check=n_chk, overlap_tol=1.0, neg_tol=0.05, batch=4)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    e_lp = []
+    for i, L in enumerate(evl):
+        E = wl.energy_grid(L.e_min, L.e_max, 1024)
+        rf = kpm.reconstruct_jackson(full[i], E, L.e_min, L.e_max)
+        e_lp.append(ex.dos_error(kpm.reconstruct_jackson(tables[i], E, L.e_min, L.e_max), rf))
     # Lattices outside the training distribution (strong disorder, many vacancies).
     ood = [wl.Lattice(kind=wl.HONEYCOMB, L1=1024, L2=1024, t=-2.7, anderson_w=W, vacancy_p=p, disorder_seed=99 + j,
                       e_min=-1.01 * (8.1 + W / 2), e_max=1.01 * (8.1 + W / 2))
            for j, (W, p) in enumerate([(6.0, 0.0), (10.0, 0.0), (1.0, 0.10), (2.0, 0.25)])]
     ov_ood = ex.overlap_error(net, ex.generate_moments(ood, n_in + n_chk, 16, 555, batch=4), n_chk)
     net.close()
-    n_acc = int(sum(acc))
-    # Cost of the learned path: the truncated recursion for all lattices plus the
-    # full recursion for the rejected ones.
-    t_learned = t_fast + (n_eval - n_acc) / n_eval * t_full
-    e_final = [e_ml[i] if acc[i] else 0.0 for i in range(n_eval)]
+    n_acc = int(sum(ok_lp))
+    acc_i = [i for i in range(n_eval) if ok_lp[i]]
+    fb_i = [i for i in range(n_eval) if not ok_lp[i]]
     return {"workload": f"MLP 256->1024->1024->1792; train {n_train} lattices {L_train}^2 R={R_train}, {epochs} epochs; "
                         f"eval {n_eval} honeycomb 2048^2 R=16 (Anderson W~U[0,3] eV, vacancies ~U[0,2%])",
             "data_s": t_data, "train_s": t_train, "final_val_loss": hist["val"][-1],
@@ -288,7 +319,11 @@ def leg_mlp(kpm, wl, np, n_train=4000, L_train=1024, R_train=2, epochs=200, n_ev
             "gain_vs_truncated_320": float(np.mean(e320) / np.mean(e_ml)),
             "gain_vs_truncated_256": float(np.mean(e256) / np.mean(e_ml)),
             "accepted": n_acc, "fallbacks": n_eval - n_acc,
-            "dos_error_learned_path": float(np.mean(e_final)),
+            "dos_error_learned_path": float(np.mean(e_lp)),
+            "dos_error_learned_path_accepted": float(np.mean([e_lp[i] for i in acc_i])) if acc_i else None,
+            "dos_error_learned_path_fallbacks": float(np.mean([e_lp[i] for i in fb_i])) if fb_i else None,
+            "recursion_steps_full": M // 2, "recursion_steps_truncated": (n_in + n_chk) // 2,
+            "step_saving": (M // 2) / ((n_in + n_chk) // 2),
             "overlap_error_eval": [round(float(x), 4) for x in ov],
             "ood_overlap_error": [round(float(x), 4) for x in ov_ood],
             "ood_rejected": int(np.sum(ov_ood > 1.0)), "ood_total": len(ood)}
@@ -299,7 +334,7 @@ def step_kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1910_05194_amd", "csrc")
-    for f in ("kpm_dos.hip", "kpm_plan.h", "kpm_internal.h", "kpm_geometry.h"):
+    for f in ("kpm_dos.hip", "kpm_sweep.hip", "kpm_stencil.h", "kpm_plan.h", "kpm_internal.h", "kpm_geometry.h"):
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -338,9 +373,9 @@ def main():
                     help="launch the recursion steps one by one instead of replaying a hipGraph (for profilers)")
     ap.add_argument("--launch", default="",
                     help="pin the FP32 launch shape: kernel,block,rows,grid[,chunks] (skips the autotuner)")
-    ap.add_argument("--legs", default="c1,c3,c4,c5,hall,optical,singleshot,wavepacket",
-                    help="extra legs: c1,c3,c4,c5,hall,optical,singleshot (empty for none)")
-    ap.add_argument("--mlp-train", type=int, default=4000,
+    ap.add_argument("--legs", default="c1,c3,c4,c5,hall,optical,singleshot",
+                    help="extra legs: c1,c3,c4,c5,hall,optical,singleshot,wavepacket (empty for none)")
+    ap.add_argument("--mlp-train", type=int, default=20000,
                     help="training lattices (1024^2 cells each) of the learned-extrapolation leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time the plain 4 GiB device copy (the default; kept for the recorded profiling commands)")
@@ -352,8 +387,17 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     import workload as wl
+
+    cpu = None
+    if not args.no_cpu:
+        # First, before anything touches the GPU: the oracle's workers are forked.
+        log("[bench] cpu baseline (oracle)")
+        lat0, par0 = wl.graphene_large(precision=wl.FP32, L=args.L, M=args.M, R=args.R)
+        cpu = cpu_baseline(lat0, par0, min(16, os.cpu_count() or 1))
+        log(f"[bench] cpu baseline: {cpu['value']:.3e} updates/s on {cpu['cores']} cores")
+
+    import torch
     from paper_1910_05194_amd import kpm
 
     dev = torch.device("cuda:0")
@@ -480,11 +524,6 @@ def main():
                    "hall": "qahe_hall", "optical": "graphene_optical", "singleshot": "graphene_singleshot",
                    "wavepacket": "spin_wavepacket"}[name]] = \
                 fn(kpm, wl, np, **kw)
-
-    cpu = None
-    if not args.no_cpu:
-        log("[bench] cpu baseline (oracle)")
-        cpu = cpu_baseline(lat, par)
 
     traffic = measured_traffic(info, args)
     out = {

@@ -236,6 +236,16 @@ int kpm_reconstruct_jackson(const double* mu, int32_t M, const double* energies_
                             void* hip_stream);
 
 /*
+ * The damping factors of the KPM reconstructions (Sec. 2(a)): g[i] = g_{n0 + i}
+ * of an M-moment expansion, i < count, for kernel 0 = Jackson (Weisse et al.
+ * 2006, as in kpm_reconstruct_jackson) or 1 = Lorentz with lambda (as in
+ * kpm_reconstruct_lorentz).  g [count] FP64, host (on_device = 0) or device.
+ * KPM_E_INVALID unless 0 <= n0 < n0 + count <= M and (Lorentz) lambda > 0.
+ */
+int kpm_kernel_factors(int32_t kernel, int32_t M, double lambda, int32_t n0, int32_t count, double* g,
+                       int32_t on_device, void* hip_stream);
+
+/*
  * The same KPM reconstruction with the Lorentz kernel the paper prints for
  * damping Gibbs oscillations (Sec. 2(a)): g_n = sinh(lambda (1 - n/M)) /
  * sinh(lambda), n = 0..M-1; a delta peak becomes a Lorentzian of half width
@@ -511,6 +521,18 @@ int kpm_mlp_gradients(kpm_mlp_t* mlp, const float* x, const float* target, const
  * and training uses the standardised targets with weights w * sd_out (the same
  * loss in original units).  Gradients then refer to the standardised network. */
 int kpm_mlp_fit_scaling(kpm_mlp_t* mlp, const float* x, const float* target, int64_t n_rows, void* hip_stream);
+/* Acceptance measure of predicted moment tables: the network's output y for
+ * x [batch][n_in] (original units, use_bf16 as in forward) against reference
+ * moments ref [batch][n_cmp] (FP64) on its first n_cmp orders, weighted by
+ * weights [n_cmp] (FP32):
+ *   err[b] = ||w (y_b - ref_b)|| / ||w ref_b||   (FP64, [batch]).
+ * Validation loss: the training loss L of the network's output (original
+ * units) against target with weights, no update, into the device double
+ * loss_dev_out.  All pointers device; work enqueued on hip_stream. */
+int kpm_mlp_rel_error(kpm_mlp_t* mlp, const float* x, const double* ref, const float* weights, int32_t batch,
+                      int32_t n_cmp, int32_t use_bf16, double* err, void* hip_stream);
+int kpm_mlp_eval_loss(kpm_mlp_t* mlp, const float* x, const float* target, const float* weights, int32_t batch,
+                      int32_t use_bf16, double* loss_dev_out, void* hip_stream);
 
 /*
  * HBM bandwidth probe (measurement support for the roofline; not part of the

@@ -32,11 +32,14 @@ constexpr int kGTileM = 256;
 constexpr int kGWave = 64;
 static_assert(kGammaRowAlign % kGTileM == 0 && kGammaRowAlign % kGTileN == 0, "tiles must divide the row padding");
 // K values (complex) per LDS stage, and the LDS row pitch in bf16: 32 reals
-// plus 16 bytes, so that the rows read by one ds_read_b128 fall on distinct
-// banks.
+// (64 bytes, four 16-byte units), no padding.  The units of a row are
+// permuted by an XOR with (row / 2) % 4, so that both the staging stores
+// (8 lanes: 2 rows x 4 units) and the MFMA operand reads (8 lanes: 8 rows,
+// one unit) touch 8 distinct 16-byte bank groups of a 128-byte line.
 constexpr int kGStage = 16;
-constexpr int kGPitch = 2 * kGStage + 8;
+constexpr int kGPitch = 2 * kGStage;
 static_assert(kBlkK % kGStage == 0, "an LDS stage must not straddle a K block");
+__device__ inline int gslab_unit(int row, int unit) { return unit ^ ((row >> 1) & 3); }
 
 // (x0, x1, x2, ...) -> (x1, -x0, x3, -x2, ...): the imaginary-part operand.
 __device__ inline bf16x8 swap_neg(const bf16x8& b) {
@@ -50,7 +53,7 @@ __device__ inline bf16x8 swap_neg(const bf16x8& b) {
 }
 
 // One stage of the four planes: L hi/lo for the 128 n rows, R hi/lo for the
-// 256 m rows (61440 bytes).
+// 256 m rows (49152 bytes).
 struct GammaSlab {
   __bf16 l[2][kGTileN][kGPitch];
   __bf16 r[2][kGTileM][kGPitch];
@@ -116,13 +119,15 @@ __global__ void __launch_bounds__(512) gamma_bf16_kernel(const __bf16* __restric
     stg[4] = *reinterpret_cast<const bf16x8*>(rl + voff[1]);
     stg[5] = *reinterpret_cast<const bf16x8*>(rl + voff[2]);
   };
+  // Rows srow and 128 + srow share (row / 2) % 4, so one permuted column serves both.
+  const int lcol = 8 * gslab_unit(srow, t & 3);
   auto stash = [&](const Staging& stg, GammaSlab& dst) {
-    *reinterpret_cast<bf16x8*>(&dst.l[0][srow][scol]) = stg[0];
-    *reinterpret_cast<bf16x8*>(&dst.l[1][srow][scol]) = stg[1];
-    *reinterpret_cast<bf16x8*>(&dst.r[0][srow][scol]) = stg[2];
-    *reinterpret_cast<bf16x8*>(&dst.r[0][128 + srow][scol]) = stg[3];
-    *reinterpret_cast<bf16x8*>(&dst.r[1][srow][scol]) = stg[4];
-    *reinterpret_cast<bf16x8*>(&dst.r[1][128 + srow][scol]) = stg[5];
+    *reinterpret_cast<bf16x8*>(&dst.l[0][srow][lcol]) = stg[0];
+    *reinterpret_cast<bf16x8*>(&dst.l[1][srow][lcol]) = stg[1];
+    *reinterpret_cast<bf16x8*>(&dst.r[0][srow][lcol]) = stg[2];
+    *reinterpret_cast<bf16x8*>(&dst.r[0][128 + srow][lcol]) = stg[3];
+    *reinterpret_cast<bf16x8*>(&dst.r[1][srow][lcol]) = stg[4];
+    *reinterpret_cast<bf16x8*>(&dst.r[1][128 + srow][lcol]) = stg[5];
   };
 
   f32x16 re[2][2], im[2][2];
@@ -139,14 +144,16 @@ __global__ void __launch_bounds__(512) gamma_bf16_kernel(const __bf16* __restric
   struct Ops {
     bf16x8 ah[2], al[2], bh[2], bl[2];
   };
+  // Rows an + 32 i and bm + 32 j share (row / 2) % 4 with an and bm.
+  const int ca[2] = {8 * gslab_unit(an, kg), 8 * gslab_unit(an, 2 + kg)};
+  const int cb[2] = {8 * gslab_unit(bm, kg), 8 * gslab_unit(bm, 2 + kg)};
   auto read_ops = [&](const GammaSlab& src, int kk, Ops& o) {
-    const int c = 16 * kk + 8 * kg;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      o.ah[i] = *reinterpret_cast<const bf16x8*>(&src.l[0][an + 32 * i][c]);
-      o.al[i] = *reinterpret_cast<const bf16x8*>(&src.l[1][an + 32 * i][c]);
-      o.bh[i] = *reinterpret_cast<const bf16x8*>(&src.r[0][bm + 32 * i][c]);
-      o.bl[i] = *reinterpret_cast<const bf16x8*>(&src.r[1][bm + 32 * i][c]);
+      o.ah[i] = *reinterpret_cast<const bf16x8*>(&src.l[0][an + 32 * i][ca[kk]]);
+      o.al[i] = *reinterpret_cast<const bf16x8*>(&src.l[1][an + 32 * i][ca[kk]]);
+      o.bh[i] = *reinterpret_cast<const bf16x8*>(&src.r[0][bm + 32 * i][cb[kk]]);
+      o.bl[i] = *reinterpret_cast<const bf16x8*>(&src.r[1][bm + 32 * i][cb[kk]]);
     }
   };
   auto mfma = [&](const Ops& o) {

@@ -127,6 +127,32 @@ __global__ void mlp_loss_kernel(const float* Y, const float* T, const float* w, 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0] * inv;
 }
 
+// err[b] = sqrt(sum_j (w_j (Y_bj - R_bj))^2) / sqrt(sum_j (w_j R_bj)^2) over the
+// first n_cmp of the n_out columns of Y; one workgroup per row, FP64 sums in a
+// fixed-order tree.
+__global__ void rel_error_kernel(const float* Y, int n_out, const double* R, int n_cmp, const float* w, double* err) {
+  __shared__ double num[256], den[256];
+  const int b = blockIdx.x;
+  double a = 0.0, d = 0.0;
+  for (int j = threadIdx.x; j < n_cmp; j += blockDim.x) {
+    const double r = R[(int64_t)b * n_cmp + j], wj = w[j];
+    const double e = wj * ((double)Y[(int64_t)b * n_out + j] - r);
+    a += e * e;
+    d += (wj * r) * (wj * r);
+  }
+  num[threadIdx.x] = a;
+  den[threadIdx.x] = d;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      num[threadIdx.x] += num[threadIdx.x + st];
+      den[threadIdx.x] += den[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) err[b] = sqrt(num[0]) / fmax(sqrt(den[0]), 1e-300);
+}
+
 __global__ void sum_partials_kernel(const double* partial, int n, double* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double s = 0.0;
@@ -451,6 +477,52 @@ int kpm_mlp_forward(kpm_mlp_t* N, const float* x, int32_t batch, float* y, int32
   } else {
     forward(N, x, batch, use_bf16 != 0, y, s);
   }
+  KPM_TRY_HIP(hipGetLastError());
+  return KPM_OK;
+}
+
+// The network's output in original units (the fitted standardisation applied
+// around it) into N->Y.
+static void forward_scaled(kpm_mlp* N, const float* x, int batch, bool bf16, hipStream_t s) {
+  using namespace kpm;
+  if (N->scaled) {
+    const int64_t nx = (int64_t)batch * N->n_in, ny = (int64_t)batch * N->n_out;
+    hipLaunchKernelGGL(affine_kernel, dim3((unsigned)ceil_div(nx, 256)), dim3(256), 0, s, x, N->Xn, (int64_t)batch,
+                       N->n_in, N->x_shift, N->x_scale, 1);
+    forward(N, N->Xn, batch, bf16, N->Y, s);
+    hipLaunchKernelGGL(affine_kernel, dim3((unsigned)ceil_div(ny, 256)), dim3(256), 0, s, N->Y, N->Y, (int64_t)batch,
+                       N->n_out, N->y_shift, N->y_scale, 0);
+  } else {
+    forward(N, x, batch, bf16, N->Y, s);
+  }
+}
+
+int kpm_mlp_rel_error(kpm_mlp_t* N, const float* x, const double* ref, const float* weights, int32_t batch,
+                      int32_t n_cmp, int32_t use_bf16, double* err, void* hip_stream) {
+  using namespace kpm;
+  clear_error();
+  KPM_CHECK_ARG(N && x && ref && weights && err && batch >= 1, "bad arguments");
+  KPM_CHECK_ARG(n_cmp >= 1 && n_cmp <= N->n_out, "n_cmp must be in [1, n_out]");
+  KPM_TRY(mlp_reserve(N, batch));
+  hipStream_t s = (hipStream_t)hip_stream;
+  forward_scaled(N, x, batch, use_bf16 != 0, s);
+  hipLaunchKernelGGL(rel_error_kernel, dim3(batch), dim3(256), 0, s, N->Y, N->n_out, ref, n_cmp, weights, err);
+  KPM_TRY_HIP(hipGetLastError());
+  return KPM_OK;
+}
+
+int kpm_mlp_eval_loss(kpm_mlp_t* N, const float* x, const float* target, const float* weights, int32_t batch,
+                      int32_t use_bf16, double* loss_dev_out, void* hip_stream) {
+  using namespace kpm;
+  clear_error();
+  KPM_CHECK_ARG(N && x && target && weights && loss_dev_out && batch >= 1, "bad arguments");
+  KPM_TRY(mlp_reserve(N, batch));
+  hipStream_t s = (hipStream_t)hip_stream;
+  forward_scaled(N, x, batch, use_bf16 != 0, s);
+  const int lb = 256;
+  hipLaunchKernelGGL(mlp_loss_kernel, dim3(lb), dim3(256), 0, s, N->Y, target, weights, batch, N->n_out, N->dY,
+                     N->partial);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, N->partial, lb, loss_dev_out);
   KPM_TRY_HIP(hipGetLastError());
   return KPM_OK;
 }

@@ -245,6 +245,38 @@ static int reconstruct(const char* name, int which, const double* mu, int32_t M,
 }
 }  // namespace kpm
 
+namespace kpm {
+__global__ void kernel_factors_kernel(int kernel, int M, double lam, int n0, int count, double* g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) g[i] = damping(kernel, n0 + i, M, lam);
+}
+}  // namespace kpm
+
+extern "C" int kpm_kernel_factors(int32_t kernel, int32_t M, double lambda, int32_t n0, int32_t count, double* g,
+                                  int32_t on_device, void* hip_stream) {
+  kpm::clear_error();
+  KPM_CHECK_ARG(kernel == kpm::kKernelJackson || kernel == kpm::kKernelLorentz, "kernel must be 0 (Jackson) or 1 (Lorentz)");
+  KPM_CHECK_ARG(M >= 1 && n0 >= 0 && count >= 1 && (int64_t)n0 + count <= M, "need 0 <= n0 < n0 + count <= M");
+  KPM_CHECK_ARG(kernel == kpm::kKernelJackson || (std::isfinite(lambda) && lambda > 0.0), "lambda must be > 0");
+  KPM_CHECK_ARG(g != nullptr, "NULL argument");
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* dg = g;
+  if (!on_device) KPM_TRY_HIP(hipMalloc(&dg, sizeof(double) * (size_t)count));
+  hipLaunchKernelGGL(kpm::kernel_factors_kernel, dim3((unsigned)kpm::ceil_div(count, 256)), dim3(256), 0, s, kernel, M,
+                     lambda, n0, count, dg);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && !on_device) {
+    e = hipMemcpyAsync(g, dg, sizeof(double) * (size_t)count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (!on_device) (void)hipFree(dg);
+  if (e != hipSuccess) {
+    kpm::set_error("kpm_kernel_factors: %s", hipGetErrorString(e));
+    return KPM_E_DEVICE;
+  }
+  return KPM_OK;
+}
+
 extern "C" int kpm_reconstruct_jackson(const double* mu, int32_t M, const double* energies_ev, int32_t K,
                                        double e_min, double e_max, double* rho, int32_t on_device,
                                        void* hip_stream) {

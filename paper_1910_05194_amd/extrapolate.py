@@ -48,12 +48,10 @@ def generate_moments(lattices: Sequence, num_moments: int, num_random: int, vect
     return out
 
 
-def loss_weights(n_in: int, n_out: int) -> np.ndarray:
-    """Jackson factors g_n of an (n_in + n_out)-moment expansion for n = n_in .. n_in+n_out-1."""
-    M = n_in + n_out
-    n = np.arange(n_in, M, dtype=np.float64)
-    q = math.pi / (M + 1)
-    return ((M - n + 1) * np.cos(q * n) + np.sin(q * n) / math.tan(q)) / (M + 1)
+def loss_weights(n_in: int, n_out: int, device=None):
+    """Jackson factors g_n of an (n_in + n_out)-moment expansion for n = n_in .. n_in+n_out-1
+    (kpm_kernel_factors; numpy, or a float64 tensor on device)."""
+    return kpm.kernel_factors(n_in + n_out, n0=n_in, count=n_out, kernel=0, out_device=device)
 
 
 def train(net: "kpm.MLP", mu: np.ndarray, epochs: int, batch: int = 256, lr: float = 1e-3,
@@ -73,7 +71,7 @@ def train(net: "kpm.MLP", mu: np.ndarray, epochs: int, batch: int = 256, lr: flo
     val, tr = perm[:n_val], perm[n_val:]
     X = torch.tensor(mu[:, :n_in], dtype=torch.float32, device=device)
     T = torch.tensor(mu[:, n_in:n_in + n_out], dtype=torch.float32, device=device)
-    w = torch.tensor(loss_weights(n_in, n_out), dtype=torch.float32, device=device)
+    w = loss_weights(n_in, n_out, device=device).to(torch.float32)
     loss = torch.zeros(1, dtype=torch.float64, device=device)
     if standardise:
         ti = torch.tensor(tr, device=device)
@@ -92,8 +90,7 @@ def train(net: "kpm.MLP", mu: np.ndarray, epochs: int, batch: int = 256, lr: flo
             acc += float(loss.item()) if s == steps_per_epoch - 1 else 0.0
             step += 1
         vi = torch.tensor(val, device=device)
-        yv = net.forward(X[vi].contiguous()).cpu().numpy().astype(np.float64)
-        vloss = float(np.mean(((yv - mu[val, n_in:n_in + n_out]) * loss_weights(n_in, n_out)[None, :]) ** 2))
+        vloss = float(net.eval_loss(X[vi], T[vi], w).item())
         hist["train"].append(acc)
         hist["val"].append(vloss)
         if log:
@@ -123,11 +120,9 @@ def overlap_error(net: "kpm.MLP", mu_head, n_check: int = 64, bf16: bool = True)
     n_in = net.n_in
     assert mu_head.shape[1] >= n_in + n_check and n_check <= net.n_out
     x = torch.as_tensor(mu_head[:, :n_in], dtype=torch.float32, device="cuda").contiguous()
-    y = net.forward(x, bf16=bf16).to(torch.float64).cpu().numpy()[:, :n_check]
-    g = loss_weights(n_in, net.n_out)[:n_check]
-    ref = mu_head[:, n_in:n_in + n_check]
-    den = np.sqrt(np.sum((g * ref) ** 2, axis=1))
-    return np.sqrt(np.sum((g * (y - ref)) ** 2, axis=1)) / np.maximum(den, 1e-300)
+    ref = torch.as_tensor(mu_head[:, n_in:n_in + n_check], dtype=torch.float64, device="cuda").contiguous()
+    g = loss_weights(n_in, net.n_out, device="cuda")[:n_check].to(torch.float32)
+    return net.rel_error(x, ref, g, bf16=bf16).cpu().numpy()
 
 
 def fit_acceptance(net: "kpm.MLP", mu_val, n_check: int = 64, factor: float = 2.0) -> float:

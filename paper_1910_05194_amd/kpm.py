@@ -133,6 +133,10 @@ def _load():
         "kpm_mlp_train_step": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P]),
         "kpm_mlp_gradients": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P, _D, _P]),
         "kpm_mlp_fit_scaling": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P]),
+        "kpm_mlp_rel_error": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+        "kpm_mlp_eval_loss": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+        "kpm_kernel_factors": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                              ctypes.c_int32, _P, ctypes.c_int32, _P]),
         "kpm_cond_last_stats": (ctypes.c_int, [ctypes.POINTER(c_cond_stats)]),
         "kpm_moments_gamma1": (ctypes.c_int, [ctypes.POINTER(c_lattice), ctypes.POINTER(c_cond_params), _P,
                                               ctypes.c_int32, _P]),
@@ -323,6 +327,25 @@ def reconstruct_jackson(mu, energies, e_min: float, e_max: float, stream=None):
     _check(LIB.kpm_reconstruct_jackson(mu.data_ptr(), mu.numel(), en.data_ptr(), en.numel(), float(e_min),
                                        float(e_max), rho.data_ptr(), 1, _stream_handle(stream)))
     return rho
+
+
+def kernel_factors(M: int, n0: int = 0, count: Optional[int] = None, kernel: int = 0, lam: float = 0.0,
+                   out_device=None, stream=None):
+    """kpm_kernel_factors: damping factors g_n0 .. g_(n0+count-1) of an M-moment expansion
+    (kernel 0 = Jackson, 1 = Lorentz with lam); numpy array, or a float64 tensor on out_device."""
+    count = M - n0 if count is None else count
+    if out_device is None:
+        g = np.zeros(count)
+        _check(LIB.kpm_kernel_factors(int(kernel), int(M), float(lam), int(n0), int(count), g.ctypes.data, 0,
+                                      _stream_handle(stream)))
+        return g
+    import torch
+    g = torch.zeros(count, dtype=torch.float64, device=out_device)
+    if stream is None:
+        stream = torch.cuda.current_stream(g.device)
+    _check(LIB.kpm_kernel_factors(int(kernel), int(M), float(lam), int(n0), int(count), g.data_ptr(), 1,
+                                  _stream_handle(stream)))
+    return g
 
 
 def reconstruct_lorentz(mu, energies, e_min: float, e_max: float, lam: float, stream=None):
@@ -655,6 +678,30 @@ class MLP:
         target = target.contiguous()
         _check(LIB.kpm_mlp_fit_scaling(self._h, x.data_ptr(), target.data_ptr(), x.shape[0],
                                        _stream_handle(stream)))
+
+    def rel_error(self, x, ref, weights, bf16: bool = True, stream=None):
+        """kpm_mlp_rel_error: ||w (y - ref)|| / ||w ref|| per row on the first ref.shape[1] outputs.
+        x [B, n_in] float32, ref [B, n_cmp] float64, weights [n_cmp] float32 (device tensors)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        x, ref, weights = x.contiguous(), ref.contiguous(), weights.contiguous()
+        assert x.dtype == torch.float32 and ref.dtype == torch.float64 and weights.dtype == torch.float32
+        err = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+        _check(LIB.kpm_mlp_rel_error(self._h, x.data_ptr(), ref.data_ptr(), weights.data_ptr(), x.shape[0],
+                                     ref.shape[1], 1 if bf16 else 0, err.data_ptr(), _stream_handle(stream)))
+        return err
+
+    def eval_loss(self, x, target, weights, bf16: bool = False, stream=None):
+        """kpm_mlp_eval_loss: the weighted training loss of the network's output (no update), a device double."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        x, target, weights = x.contiguous(), target.contiguous(), weights.contiguous()
+        loss = torch.zeros(1, dtype=torch.float64, device=x.device)
+        _check(LIB.kpm_mlp_eval_loss(self._h, x.data_ptr(), target.data_ptr(), weights.data_ptr(), x.shape[0],
+                                     1 if bf16 else 0, loss.data_ptr(), _stream_handle(stream)))
+        return loss
 
     def close(self):
         if getattr(self, "_h", None):

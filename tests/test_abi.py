@@ -128,6 +128,10 @@ def test_argument_validation_without_device():
             kpm.reconstruct_lorentz(np.ones(4), np.zeros(4), -1.0, 1.0, bad)
     with pytest.raises(kpm.KPMError):
         kpm.bandwidth_probe(7, 1 << 20)
+    for kw in (dict(n0=7, count=4), dict(n0=-1, count=2), dict(kernel=1, lam=-1.0), dict(kernel=2)):
+        with pytest.raises(kpm.KPMError) as e:
+            kpm.kernel_factors(8, **kw)
+        assert e.value.code == kpm.KPM_E_INVALID
     with pytest.raises(kpm.KPMError):
         kpm.MLP(0, 16, 16)
     psi = np.zeros((1, lat.n_orbitals), dtype=np.complex128)

@@ -203,3 +203,53 @@ def test_learned_extrapolation_gains_over_truncation_and_falls_back(K):
     assert not any(ok0)
     assert np.array_equal(fb, full)
     net.close()
+
+
+def test_kernel_factors_match_oracle(K):
+    """kpm_kernel_factors against the oracle's Jackson and Lorentz kernels:
+    whole expansions and slices (the learned path's loss weights are the slice
+    n_in .. M-1 of a 2048-moment Jackson kernel), host and device outputs."""
+    import torch
+    for M in (1, 7, 256, 2048):
+        assert np.max(np.abs(K.kernel_factors(M) - okpm.jackson(M))) <= 1e-14
+        assert np.max(np.abs(K.kernel_factors(M, kernel=1, lam=4.0) - okpm.lorentz(M, 4.0))) <= 1e-14
+    g = K.kernel_factors(2048, n0=256, count=1792)
+    assert np.max(np.abs(g - okpm.jackson(2048)[256:])) <= 1e-14
+    gd = K.kernel_factors(2048, n0=256, count=1792, out_device="cuda").cpu().numpy()
+    assert np.array_equal(gd, g)
+    assert np.array_equal(omlp.loss_weights(256, 1792), okpm.jackson(2048)[256:])
+    for bad in (dict(n0=2040, count=16), dict(n0=-1, count=4), dict(kernel=1, lam=0.0), dict(kernel=3)):
+        with pytest.raises(K.KPMError):
+            K.kernel_factors(2048, **bad)
+
+
+def test_rel_error_and_eval_loss_match_oracle(K):
+    """kpm_mlp_rel_error (the overlap error of the acceptance check) and
+    kpm_mlp_eval_loss (the validation loss) against the same quantities
+    computed from the FP64 oracle's forward pass on the same weights: the
+    FP32 forward's relative error is <= 1e-5 (see above), so both agree to
+    ~1e-5 relative; with the fitted standardisation as well."""
+    import torch
+    net = K.MLP(256, 1024, 1792, seed=5)
+    params = net.get_params()
+    X, T, w = _data(48, 256, 1792, seed=9)
+    xd, td, wd = (torch.tensor(a, device="cuda") for a in (X, T, w))
+    p64 = [p.astype(np.float64) for p in params]
+    Y, _ = omlp.forward(p64, X.astype(np.float64))
+    n_cmp = 64
+    ref = (Y[:, :n_cmp] + np.random.default_rng(2).normal(size=(48, n_cmp)) * 1e-2)
+    wc = w[:n_cmp].astype(np.float64)
+    want = np.sqrt(np.sum((wc * (Y[:, :n_cmp] - ref)) ** 2, 1)) / np.sqrt(np.sum((wc * ref) ** 2, 1))
+    got = net.rel_error(xd, torch.tensor(ref, device="cuda"), wd[:n_cmp], bf16=False).cpu().numpy()
+    print("rel_error max rel dev", np.max(np.abs(got - want) / want))
+    assert np.max(np.abs(got - want) / want) <= 1e-3
+    L = omlp.loss(Y, T.astype(np.float64), w.astype(np.float64))
+    got_l = float(net.eval_loss(xd, td, wd).item())
+    print("eval_loss", got_l, "oracle", L)
+    assert abs(got_l - L) <= 1e-4 * L
+    # With standardisation: eval_loss equals the loss of forward() in original units.
+    net.fit_scaling(xd, td)
+    y = net.forward(xd).cpu().numpy().astype(np.float64)
+    L2 = omlp.loss(y, T.astype(np.float64), w.astype(np.float64))
+    assert abs(float(net.eval_loss(xd, td, wd).item()) - L2) <= 1e-6 * L2
+    net.close()
