@@ -33,13 +33,14 @@ constexpr int kGWave = 64;
 static_assert(kGammaRowAlign % kGTileM == 0 && kGammaRowAlign % kGTileN == 0, "tiles must divide the row padding");
 // K values (complex) per LDS stage, and the LDS row pitch in bf16: 32 reals
 // (64 bytes, four 16-byte units), no padding.  The units of a row are
-// permuted by an XOR with (row / 2) % 4, so that both the staging stores
-// (8 lanes: 2 rows x 4 units) and the MFMA operand reads (8 lanes: 8 rows,
-// one unit) touch 8 distinct 16-byte bank groups of a 128-byte line.
+// permuted by an XOR with (row / 4) % 4, so that both the staging stores
+// (16 lanes: 4 rows x 4 units) and the MFMA operand reads (16 lanes: 16
+// rows, one unit) touch 16 distinct 16-byte bank groups of a 256-byte span
+// of the 64 LDS banks.
 constexpr int kGStage = 16;
 constexpr int kGPitch = 2 * kGStage;
 static_assert(kBlkK % kGStage == 0, "an LDS stage must not straddle a K block");
-__device__ inline int gslab_unit(int row, int unit) { return unit ^ ((row >> 1) & 3); }
+__device__ inline int gslab_unit(int row, int unit) { return unit ^ ((row >> 2) & 3); }
 
 // (x0, x1, x2, ...) -> (x1, -x0, x3, -x2, ...): the imaginary-part operand.
 __device__ inline bf16x8 swap_neg(const bf16x8& b) {
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(512) gamma_bf16_kernel(const __bf16* __restric
     stg[4] = *reinterpret_cast<const bf16x8*>(rl + voff[1]);
     stg[5] = *reinterpret_cast<const bf16x8*>(rl + voff[2]);
   };
-  // Rows srow and 128 + srow share (row / 2) % 4, so one permuted column serves both.
+  // Rows srow and 128 + srow share (row / 4) % 4, so one permuted column serves both.
   const int lcol = 8 * gslab_unit(srow, t & 3);
   auto stash = [&](const Staging& stg, GammaSlab& dst) {
     *reinterpret_cast<bf16x8*>(&dst.l[0][srow][lcol]) = stg[0];
@@ -144,7 +145,7 @@ __global__ void __launch_bounds__(512) gamma_bf16_kernel(const __bf16* __restric
   struct Ops {
     bf16x8 ah[2], al[2], bh[2], bl[2];
   };
-  // Rows an + 32 i and bm + 32 j share (row / 2) % 4 with an and bm.
+  // Rows an + 32 i and bm + 32 j share (row / 4) % 4 with an and bm.
   const int ca[2] = {8 * gslab_unit(an, kg), 8 * gslab_unit(an, 2 + kg)};
   const int cb[2] = {8 * gslab_unit(bm, kg), 8 * gslab_unit(bm, 2 + kg)};
   auto read_ops = [&](const GammaSlab& src, int kk, Ops& o) {
