@@ -211,7 +211,11 @@ int kpm_autotune(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t
  * arrays, the tile work list, moment partials); run builds the disorder, the
  * start vectors and runs the whole recursion (replayed as a hipGraph after the
  * first run when tune->use_graph != 0); destroy frees everything.  A plan may
- * be run on different streams but not concurrently with itself. */
+ * be run on different streams but not concurrently with itself.  With the
+ * environment variable KPM_LOG set (and not "0"), plan creation (also inside
+ * kpm_moments_dos and kpm_moments_dos_noalloc) writes a one-line summary of the
+ * chosen plan to stderr: workload, kernel variant, tile shape, grid, LDS and
+ * device bytes, algorithmic bytes per step. */
 int kpm_plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p,
                     const kpm_tune_t* tune, kpm_plan_t** plan);
 int kpm_plan_run(kpm_plan_t* plan, double* mu_per_vector, double* mu_mean, int32_t out_on_device,
@@ -546,6 +550,27 @@ int kpm_mlp_eval_loss(kpm_mlp_t* mlp, const float* x, const float* target, const
  */
 int kpm_bandwidth_probe(int32_t pattern, int64_t bytes_per_array, int32_t iters, int32_t grid, int32_t block,
                         int32_t nontemporal, void* hip_stream, double* ms_per_iter, double* bytes_moved_per_iter);
+
+/*
+ * Error-path testing (test support; not part of the method).
+ *
+ * kpm_debug_inject_failure arms a countdown over the library's checked HIP
+ * operations in this process: device allocations, host/device copies, stream
+ * and event calls, and the status checks after kernel launches.  The nth of
+ * them from now on fails with the injected error and the countdown disarms:
+ * kind 0 = out of memory (the call returns KPM_E_NOMEM), kind 1 = launch
+ * failure (KPM_E_DEVICE).  An allocation or an enqueue so failed is not
+ * performed; a synchronising call or a kernel launch is performed and only
+ * its status is replaced.  nth = 0 disarms.  Returns how many failures were
+ * injected since the previous call (0 or 1), or KPM_E_INVALID for nth < 0 or
+ * an unknown kind.  Calls from every thread take part in the countdown.
+ *
+ * kpm_debug_live_allocations returns the number of device buffers the
+ * library holds at the moment (plans, networks, per-call workspaces), so a
+ * test can check that a failed call released everything it allocated.
+ */
+int32_t kpm_debug_inject_failure(int32_t nth, int32_t kind);
+int64_t kpm_debug_live_allocations(void);
 
 #ifdef __cplusplus
 }

@@ -114,17 +114,17 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
     st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
   };
   const size_t plane_bytes = split ? (size_t)Mp * row_elems * 2 : (size_t)Mp * row_elems * tsize;
-  hipError_t e = hipMalloc(&Lb, plane_bytes);
-  if (e == hipSuccess) e = hipMalloc(&Rblk, plane_bytes);
-  if (e == hipSuccess && split) e = hipMalloc(&Llo, plane_bytes);
-  if (e == hipSuccess && split) e = hipMalloc(&Rlo, plane_bytes);
+  hipError_t e = ::kpm::dev_malloc(&Lb, plane_bytes);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&Rblk, plane_bytes);
+  if (e == hipSuccess && split) e = ::kpm::dev_malloc(&Llo, plane_bytes);
+  if (e == hipSuccess && split) e = ::kpm::dev_malloc(&Rlo, plane_bytes);
   if (e == hipSuccess && (kpad != n_orb * P->Rp || Mp != M)) {   // padding rows / K block stay zero
     for (void* b : {Lb, Rblk, Llo, Rlo})
       if (b && e == hipSuccess) e = hipMemsetAsync(b, 0, plane_bytes, s);
   }
-  if (e == hipSuccess) e = hipMalloc(&acc, (size_t)M * M * 2 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&part, (size_t)KS * M * M * 2 * sizeof(double));
-  if (e == hipSuccess && !on_dev) e = hipMalloc(&gdev, (size_t)M * M * 2 * sizeof(double));
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&acc, (size_t)M * M * 2 * sizeof(double));
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&part, (size_t)KS * M * M * 2 * sizeof(double));
+  if (e == hipSuccess && !on_dev) e = ::kpm::dev_malloc(&gdev, (size_t)M * M * 2 * sizeof(double));
   if (e != hipSuccess) fail(e, "allocating Gamma blocks");
   double* gout = on_dev ? gamma : gdev;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -228,7 +228,7 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   if (st == KPM_OK) {
     hipLaunchKernelGGL(gamma_scale_kernel, dim3((unsigned)ceil_div((int64_t)M * M * 2, 256)), dim3(256), 0, s, acc, M,
                        Rtot, P->active, gout);
-    e = hipGetLastError();
+    e = ::kpm::launch_status();
     if (e == hipSuccess && !on_dev)
       e = hipMemcpyAsync(gamma, gdev, (size_t)M * M * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -245,7 +245,7 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   for (auto& x : ev)
     if (x) (void)hipEventDestroy(x);
   for (void* ptr : {Lb, Rblk, Llo, Rlo, (void*)acc, (void*)part, (void*)gdev})
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) (void)::kpm::dev_free(ptr);
   plan_free(P);
   delete P;
   return st;
@@ -325,9 +325,9 @@ static int gamma1_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, doub
   void* U = nullptr;
   double *part = nullptr, *gdev = nullptr;
   int st = KPM_OK;
-  hipError_t e = hipMalloc(&U, (size_t)n_cplx * 2 * P->tsize);
-  if (e == hipSuccess) e = hipMalloc(&part, (size_t)M * kDotBlocks * 2 * sizeof(double));
-  if (e == hipSuccess && !on_dev) e = hipMalloc(&gdev, (size_t)M * 2 * sizeof(double));
+  hipError_t e = ::kpm::dev_malloc(&U, (size_t)n_cplx * 2 * P->tsize);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&part, (size_t)M * kDotBlocks * 2 * sizeof(double));
+  if (e == hipSuccess && !on_dev) e = ::kpm::dev_malloc(&gdev, (size_t)M * 2 * sizeof(double));
   if (e == hipSuccess) st = plan_set_vector_base(P, 0);
   if (e == hipSuccess && st == KPM_OK) e = plan_launch_prep(P, s);
   auto dot = [&](const void* v, int n) {
@@ -337,7 +337,7 @@ static int gamma1_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, doub
     else
       hipLaunchKernelGGL(dot_partial_kernel<double>, dim3(kDotBlocks), dim3(256), 0, s, (const double*)v,
                          (const double*)U, n_cplx, part + (int64_t)n * kDotBlocks * 2);
-    return hipGetLastError();
+    return ::kpm::launch_status();
   };
   if (e == hipSuccess && st == KPM_OK) {
     // u = h~^{ab} xi (velocity-only launch: no output vector, no dots).
@@ -367,7 +367,7 @@ static int gamma1_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, doub
     double* out = on_dev ? g1 : gdev;
     hipLaunchKernelGGL(gamma1_finish_kernel, dim3((unsigned)ceil_div(M, 256)), dim3(256), 0, s, part, M, R, P->active,
                        out);
-    e = hipGetLastError();
+    e = ::kpm::launch_status();
     if (e == hipSuccess && !on_dev) e = hipMemcpyAsync(g1, gdev, (size_t)M * 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   } else {
@@ -378,7 +378,7 @@ static int gamma1_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, doub
     st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
   }
   for (void* ptr : {U, (void*)part, (void*)gdev})
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) (void)::kpm::dev_free(ptr);
   plan_free(P);
   delete P;
   return st;
@@ -458,7 +458,7 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
   std::vector<double> en((size_t)K);
   if (on_dev) {
     KPM_TRY_HIP(hipMemcpyAsync(en.data(), energies_ev, sizeof(double) * K, hipMemcpyDeviceToHost, s));
-    KPM_TRY_HIP(hipStreamSynchronize(s));
+    KPM_TRY_SYNC(hipStreamSynchronize(s));
   } else {
     std::memcpy(en.data(), energies_ev, sizeof(double) * K);
   }
@@ -516,13 +516,13 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
   }
   void *V0 = nullptr, *Sc = nullptr, *acc = nullptr, *hist = nullptr;
   double *dcoef = nullptr, *part = nullptr, *dsig = nullptr;
-  if (e == hipSuccess) e = hipMalloc(&V0, vec_b);
-  if (e == hipSuccess) e = hipMalloc(&Sc, vec_b);
-  if (e == hipSuccess) e = hipMalloc(&acc, 2 * vec_b * (size_t)kb);
-  if (e == hipSuccess) e = hipMalloc(&hist, vec_b * (size_t)B);
-  if (e == hipSuccess) e = hipMalloc(&dcoef, sizeof(double) * coef.size());
-  if (e == hipSuccess) e = hipMalloc(&part, sizeof(double) * 2 * kDotBlocks * (size_t)K);
-  if (e == hipSuccess) e = hipMalloc(&dsig, sizeof(double) * K);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&V0, vec_b);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&Sc, vec_b);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&acc, 2 * vec_b * (size_t)kb);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&hist, vec_b * (size_t)B);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&dcoef, sizeof(double) * coef.size());
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&part, sizeof(double) * 2 * kDotBlocks * (size_t)K);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&dsig, sizeof(double) * K);
   if (e == hipSuccess) e = hipMemcpyAsync(dcoef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) st = plan_set_vector_base(P, 0);
   const bool f32 = P->prec == KPM_FP32;
@@ -547,7 +547,7 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
         hipLaunchKernelGGL(accumulate_block_kernel<double>, eg, eb, 0, s, H, nb, n_elems, (double*)Ag, n_elems, c,
                            Kp, kg);
       }
-      er = hipGetLastError();
+      er = ::kpm::launch_status();
     }
     return er;
   };
@@ -607,7 +607,7 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
       else
         hipLaunchKernelGGL(dot_partial_kernel<double>, dim3(kDotBlocks), dim3(256), 0, s,
                            (const double*)(Ab + vec_b * (size_t)k), (const double*)Sc, n_elems / 2, pk);
-      e = hipGetLastError();
+      e = ::kpm::launch_status();
     }
   }
   if (e == hipSuccess && st == KPM_OK) {
@@ -615,7 +615,7 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
     double* out = on_dev ? sigma : dsig;
     hipLaunchKernelGGL(singleshot_finish_kernel, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, part, K,
                        2.0 * M_PI * M_PI / (omega * R), out);
-    e = hipGetLastError();
+    e = ::kpm::launch_status();
     if (e == hipSuccess && !on_dev) e = hipMemcpyAsync(sigma, dsig, sizeof(double) * K, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   } else {
@@ -626,7 +626,7 @@ static int singleshot_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, 
     st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
   }
   for (void* ptr : {V0, Sc, acc, hist, (void*)dcoef, (void*)part, (void*)dsig})
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) (void)::kpm::dev_free(ptr);
   plan_free(P);
   delete P;
   return st;

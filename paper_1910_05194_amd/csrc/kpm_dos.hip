@@ -33,6 +33,8 @@
 #endif
 
 #include <algorithm>
+#include <atomic>
+#include <cstdlib>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -43,6 +45,32 @@
 namespace kpm {
 
 static thread_local std::string g_err;
+
+// Fault injection state (kpm_debug_inject_failure) and the live-allocation count.
+static std::atomic<int64_t> g_fault_countdown{0};
+static std::atomic<int32_t> g_fault_kind{0};
+static std::atomic<int32_t> g_fault_fired{0};
+static std::atomic<int64_t> g_live_allocs{0};
+
+bool fault_due() {
+  int64_t c = g_fault_countdown.load(std::memory_order_relaxed);
+  while (c > 0) {
+    if (g_fault_countdown.compare_exchange_weak(c, c - 1, std::memory_order_relaxed)) {
+      if (c == 1) {
+        g_fault_fired.fetch_add(1, std::memory_order_relaxed);
+        return true;
+      }
+      return false;
+    }
+  }
+  return false;
+}
+
+hipError_t fault_error() {
+  return g_fault_kind.load(std::memory_order_relaxed) == 0 ? hipErrorOutOfMemory : hipErrorLaunchFailure;
+}
+
+void live_add(int64_t d) { g_live_allocs.fetch_add(d, std::memory_order_relaxed); }
 
 void set_error(const char* fmt, ...) {
   char buf[1024];
@@ -929,14 +957,16 @@ static int plan_alloc(kpm_plan* P, void** ptr, size_t bytes) {
     }
     *ptr = P->arena_base + off;
     P->arena_used = off + bytes;
+    P->dev_bytes += bytes;
     return KPM_OK;
   }
-  hipError_t e = hipMalloc(ptr, bytes);
+  hipError_t e = ::kpm::dev_malloc(ptr, bytes);
   if (e != hipSuccess) {
-    set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
     (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? KPM_E_NOMEM : KPM_E_DEVICE;
   }
+  P->dev_bytes += bytes;
   return KPM_OK;
 }
 
@@ -946,7 +976,7 @@ void plan_free(kpm_plan* P) {
                   P->mu_dev, P->mean_dev};
   if (!P->use_arena)
     for (void* b : bufs)
-      if (b) (void)hipFree(b);
+      if (b) (void)::kpm::dev_free(b);
   if (P->graph_loop) (void)hipGraphExecDestroy(P->graph_loop);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   for (auto& e : P->ev)
@@ -1297,7 +1327,7 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   }
   hipError_t e = hipSuccess;
   auto H2D = [&](void* dst, const void* src, size_t bytes) {
-    if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && bytes) e = KPM_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
   };
   if (P->prec == KPM_FP32) {
     std::vector<LatDev<float>> ld;
@@ -1317,15 +1347,15 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   H2D(P->plat, pl.data(), pl.size() * sizeof(PhaseLat));
   if (!P->use_arena) {
     // The graph-capture stream and the timing events (not in the allocation-free form).
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = KPM_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
     for (auto& ev : P->ev)
-      if (e == hipSuccess) e = hipEventCreate(&ev);
+      if (e == hipSuccess) e = KPM_HIP(hipEventCreate(&ev));
   }
   if (e != hipSuccess) {
     set_error("plan setup failed: %s", hipGetErrorString(e));
     plan_free(P);
     delete P;
-    return KPM_E_DEVICE;
+    return ::kpm::hip_status(e);
   }
   // LDS: the ring variant needs 4 rows of (Tx + 2) cells (fall back to direct
   // loads when that exceeds 64 KiB); a sweep kernel its row rings.
@@ -1347,6 +1377,18 @@ int plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t*
   P->step_fn_vel = (P->prec == KPM_FP32)
                        ? pick_step_kind<float, true>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase)
                        : pick_step_kind<double, true>(P->kind, P->variant, P->has_onsite, P->has_mask, P->has_phase);
+  if (const char* lg = std::getenv("KPM_LOG"); lg && *lg && std::strcmp(lg, "0") != 0) {
+    static const char* kKind[] = {"honeycomb", "honeycomb+spin", "square"};
+    std::fprintf(stderr,
+                 "[kpm] plan: %d lattice(s) %s, %lld orbitals, R=%d (padded %d), M=%d, %s; kernel %d (%d step%s "
+                 "per launch), block %d, tile %d cells x %d rows x %d chunks, grid %d, %d tiles, LDS %zu B, "
+                 "device %.1f MB%s, %.1f MB per step\n",
+                 n_lat, (P->kind >= 0 && P->kind <= 2) ? kKind[P->kind] : "?", (long long)P->n_orb, P->R, P->Rp,
+                 P->M, P->prec == KPM_FP32 ? "fp32" : "fp64", P->variant, P->sweep, P->sweep > 1 ? "s" : "",
+                 P->block, P->Tx, P->Ty, P->Ew, P->grid, P->n_tiles, P->lds_bytes,
+                 (double)P->dev_bytes / 1e6,
+                 P->use_arena ? " (scratch array)" : (P->use_graph ? ", graph" : ""), P->bytes_per_step / 1e6);
+  }
   *out = P;
   return KPM_OK;
 }
@@ -1375,7 +1417,7 @@ static hipError_t launch_prep(kpm_plan* P, hipStream_t s) {
                          P->d_sites, P->R, P->Rp);
     }
   }
-  return hipGetLastError();
+  return ::kpm::launch_status();
 }
 
 template <typename T>
@@ -1411,8 +1453,8 @@ static hipError_t launch_step_t(kpm_plan* P, hipStream_t s, const StepLaunch& L)
   a.vdir = L.vdir;
   a.part = L.part;
   void* args[] = {&a};
-  return hipLaunchKernel(L.velocity ? P->step_fn_vel : P->step_fn, dim3(P->grid), dim3(P->block), args,
-                         P->lds_bytes, s);
+  return ::kpm::after_call(hipLaunchKernel(L.velocity ? P->step_fn_vel : P->step_fn, dim3(P->grid),
+                                           dim3(P->block), args, P->lds_bytes, s));
 }
 
 hipError_t plan_launch_step(kpm_plan* P, hipStream_t s, const StepLaunch& L) {
@@ -1463,7 +1505,7 @@ static hipError_t launch_sweep_t(kpm_plan* P, hipStream_t s, const void* v, cons
   a.Ew = P->Ew;
   a.Rp = P->Rp;
   void* args[] = {&a};
-  return hipLaunchKernel(P->sweep_fn, dim3(P->grid), dim3(P->block), args, P->lds_bytes, s);
+  return ::kpm::after_call(hipLaunchKernel(P->sweep_fn, dim3(P->grid), dim3(P->block), args, P->lds_bytes, s));
 }
 
 // The DOS recursion with KS steps per launch: v_0 = start, v_1 = H~ v_0,
@@ -1499,7 +1541,7 @@ static hipError_t launch_loop_sweep(kpm_plan* P, hipStream_t s) {
       chunk0 = last + 1;
     }
   }
-  return hipGetLastError();
+  return ::kpm::launch_status();
 }
 
 static hipError_t launch_loop(kpm_plan* P, hipStream_t s) {
@@ -1527,7 +1569,7 @@ static hipError_t launch_loop(kpm_plan* P, hipStream_t s) {
       chunk0 = k + 1;
     }
   }
-  return hipGetLastError();
+  return ::kpm::launch_status();
 }
 
 static hipError_t launch_finish(kpm_plan* P, hipStream_t s) {
@@ -1537,7 +1579,7 @@ static hipError_t launch_finish(kpm_plan* P, hipStream_t s) {
                      P->n_steps, P->M, P->active, P->p.start == KPM_START_SITES ? 1 : 0, P->mu_dev, P->flag);
   hipLaunchKernelGGL(mean_kernel, dim3(ceil_div((int64_t)P->n_lat * P->M, 256)), dim3(256), 0, s, P->mu_dev,
                      P->n_lat, P->R, P->M, P->mean_dev);
-  return hipGetLastError();
+  return ::kpm::launch_status();
 }
 
 static int plan_run(kpm_plan* P, double* mu_pv, double* mu_mean, int32_t on_dev, void* stream) {
@@ -1557,14 +1599,15 @@ static int plan_run(kpm_plan* P, double* mu_pv, double* mu_mean, int32_t on_dev,
       if (le != hipSuccess || ce != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         set_error("graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));
-        return KPM_E_DEVICE;
+        (void)hipGetLastError();
+        return ::kpm::hip_status(le != hipSuccess ? le : ce);
       }
       hipError_t ie = hipGraphInstantiate(&P->graph_loop, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (ie != hipSuccess) {
         P->graph_loop = nullptr;
         set_error("graph instantiate failed: %s", hipGetErrorString(ie));
-        return KPM_E_DEVICE;
+        return ::kpm::hip_status(ie);
       }
     }
     KPM_TRY_HIP(hipGraphLaunch(P->graph_loop, s));
@@ -1583,9 +1626,18 @@ static int plan_run(kpm_plan* P, double* mu_pv, double* mu_mean, int32_t on_dev,
   // The spectrum check needs the flag on the host: synchronise on the run's end.
   int flag = 0;
   std::vector<unsigned long long> act(P->n_lat);
-  KPM_TRY_HIP(hipMemcpyAsync(&flag, P->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  KPM_TRY_HIP(hipMemcpyAsync(act.data(), P->active, act.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  KPM_TRY_HIP(hipStreamSynchronize(s));
+  hipError_t e = KPM_HIP(hipMemcpyAsync(&flag, P->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (e == hipSuccess)
+    e = KPM_HIP(hipMemcpyAsync(act.data(), P->active, act.size() * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s));
+  // Wait also after a failure: the copies write this frame's host memory.
+  const hipError_t se = ::kpm::after_call(hipStreamSynchronize(s));
+  if (e == hipSuccess) e = se;
+  if (e != hipSuccess) {
+    set_error("reading the run's status flags: %s", hipGetErrorString(e));
+    (void)hipGetLastError();
+    return ::kpm::hip_status(e);
+  }
   P->n_active_total = 0;
   for (auto a : act) P->n_active_total += (int64_t)a;
   if (flag != 0) {
@@ -1629,6 +1681,20 @@ extern "C" {
 
 int kpm_version(void) { return 1; }
 
+int32_t kpm_debug_inject_failure(int32_t nth, int32_t kind) {
+  if (nth < 0 || (kind != 0 && kind != 1)) {
+    kpm::set_error("kpm_debug_inject_failure: need nth >= 0 and kind 0 or 1");
+    return KPM_E_INVALID;
+  }
+  kpm::g_fault_countdown.store(0, std::memory_order_relaxed);
+  const int32_t fired = kpm::g_fault_fired.exchange(0, std::memory_order_relaxed);
+  kpm::g_fault_kind.store(kind, std::memory_order_relaxed);
+  kpm::g_fault_countdown.store(nth, std::memory_order_relaxed);
+  return fired;
+}
+
+int64_t kpm_debug_live_allocations(void) { return kpm::g_live_allocs.load(std::memory_order_relaxed); }
+
 const char* kpm_last_error(void) { return kpm::g_err.c_str(); }
 
 int kpm_plan_create(const kpm_lattice_t* lat, int32_t n_lat, const kpm_dos_params_t* p, const kpm_tune_t* tune,
@@ -1669,7 +1735,7 @@ int kpm_plan_info(kpm_plan_t* P, kpm_plan_info_t* info) {
   info->n_active_total = P->n_active_total;
   if (P->timed) {
     float ms = 0.f;
-    KPM_TRY_HIP(hipEventSynchronize(P->ev[3]));
+    KPM_TRY_SYNC(hipEventSynchronize(P->ev[3]));
     KPM_TRY_HIP(hipEventElapsedTime(&ms, P->ev[1], P->ev[2]));
     info->last_loop_ms = ms;
     KPM_TRY_HIP(hipEventElapsedTime(&ms, P->ev[0], P->ev[3]));

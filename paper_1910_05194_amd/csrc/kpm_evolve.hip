@@ -272,7 +272,7 @@ static int evolve_plan(const kpm_lattice_t* lat, int R, int precision, hipStream
     plan_free(P);
     delete P;
     set_error("model build: %s", hipGetErrorString(e));
-    return KPM_E_DEVICE;
+    return ::kpm::hip_status(e);
   }
   *out = P;
   return KPM_OK;
@@ -292,10 +292,10 @@ static int wavepacket_run(const kpm_lattice_t* lat, int32_t n_k, const double* k
   KPM_TRY(evolve_plan(lat, 1, KPM_FP64, s, &P));
   const int64_t n = P->n_orb;
   double *dk = nullptr, *dsp = nullptr, *part = nullptr, *dpsi = nullptr;
-  hipError_t e = hipMalloc(&dk, sizeof(double) * 2 * n_k);
-  if (e == hipSuccess) e = hipMalloc(&dsp, sizeof(double) * 2 * (size_t)n_k * per);
-  if (e == hipSuccess) e = hipMalloc(&part, sizeof(double) * 1025);
-  if (e == hipSuccess && !on_dev) e = hipMalloc(&dpsi, sizeof(double) * 2 * (size_t)n);
+  hipError_t e = ::kpm::dev_malloc(&dk, sizeof(double) * 2 * n_k);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&dsp, sizeof(double) * 2 * (size_t)n_k * per);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&part, sizeof(double) * 1025);
+  if (e == hipSuccess && !on_dev) e = ::kpm::dev_malloc(&dpsi, sizeof(double) * 2 * (size_t)n);
   if (e == hipSuccess) e = hipMemcpyAsync(dk, k_vectors, sizeof(double) * 2 * n_k, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(dsp, spinors, sizeof(double) * 2 * (size_t)n_k * per, hipMemcpyHostToDevice, s);
@@ -308,7 +308,7 @@ static int wavepacket_run(const kpm_lattice_t* lat, int32_t n_k, const double* k
                        0.5 / (width_nm * width_nm), xc, yc, (const uint8_t*)P->mask, out);
     hipLaunchKernelGGL(evo_sumsq_kernel, dim3(1024), dim3(256), 0, s, out, n, part);
     hipLaunchKernelGGL(evo_sum_kernel, dim3(1), dim3(64), 0, s, part, 1024, part + 1024);
-    e = hipGetLastError();
+    e = ::kpm::launch_status();
     if (e == hipSuccess) e = hipMemcpyAsync(&norm, part + 1024, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
@@ -320,7 +320,7 @@ static int wavepacket_run(const kpm_lattice_t* lat, int32_t n_k, const double* k
   if (e == hipSuccess && st == KPM_OK) {
     hipLaunchKernelGGL(evo_scale_kernel, dim3((unsigned)ceil_div(2 * n, 256)), dim3(256), 0, s, out, 2 * n,
                        1.0 / std::sqrt(norm));
-    e = hipGetLastError();
+    e = ::kpm::launch_status();
     if (e == hipSuccess && !on_dev) e = hipMemcpyAsync(psi, dpsi, sizeof(double) * 2 * (size_t)n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   } else {
@@ -328,10 +328,10 @@ static int wavepacket_run(const kpm_lattice_t* lat, int32_t n_k, const double* k
   }
   if (e != hipSuccess) {
     set_error("kpm_wavepacket_gaussian: %s", hipGetErrorString(e));
-    st = KPM_E_DEVICE;
+    st = ::kpm::hip_status(e);
   }
   for (void* ptr : {(void*)dk, (void*)dsp, (void*)part, (void*)dpsi})
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) (void)::kpm::dev_free(ptr);
   plan_free(P);
   delete P;
   return st;
@@ -352,7 +352,7 @@ static hipError_t evolve_loop(kpm_plan* P, const kpm_evolve_params_t* p, const C
                        P->Rp, part);
     hipLaunchKernelGGL(observables_finish_kernel, dim3((unsigned)ceil_div(R, 64)), dim3(64), 0, s, part, R, kObsBlocks,
                        obs + (size_t)k * R * 8);
-    return hipGetLastError();
+    return ::kpm::launch_status();
   };
   // T_n psi: psi itself for n = 0, history slot n mod B otherwise.
   auto hvec = [&](int n) -> void* { return n == 0 ? psi : (char*)hist + vec_b * (size_t)(n % B); };
@@ -360,7 +360,7 @@ static hipError_t evolve_loop(kpm_plan* P, const kpm_evolve_params_t* p, const C
     EvoHist<T> H;
     for (int b = 0; b < nb; ++b) H.v[b] = (const T*)hvec(n0 + b);
     hipLaunchKernelGGL(evolve_flush_kernel<T>, fg, fb, 0, s, H, nb, n_cplx, dcoef + n0, first, (T*)nxt);
-    return hipGetLastError();
+    return ::kpm::launch_status();
   };
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipError_t e = hipEventCreate(&ev0);
@@ -456,11 +456,11 @@ static int evolve_run(const kpm_lattice_t* lat, const kpm_evolve_params_t* p, do
   void* hist = nullptr;
   double2* dcoef = nullptr;
   double *part = nullptr, *dpsi = nullptr, *dobs = nullptr;
-  if (e == hipSuccess) e = hipMalloc(&hist, vec_b * (size_t)B);
-  if (e == hipSuccess) e = hipMalloc(&dcoef, sizeof(double2) * M);
-  if (e == hipSuccess) e = hipMalloc(&part, sizeof(double) * 8 * (size_t)kObsBlocks * R);
-  if (e == hipSuccess && !on_dev) e = hipMalloc(&dpsi, sizeof(double) * n_psi);
-  if (e == hipSuccess && !on_dev) e = hipMalloc(&dobs, sizeof(double) * n_obs);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&hist, vec_b * (size_t)B);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&dcoef, sizeof(double2) * M);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&part, sizeof(double) * 8 * (size_t)kObsBlocks * R);
+  if (e == hipSuccess && !on_dev) e = ::kpm::dev_malloc(&dpsi, sizeof(double) * n_psi);
+  if (e == hipSuccess && !on_dev) e = ::kpm::dev_malloc(&dobs, sizeof(double) * n_obs);
   if (e == hipSuccess) e = hipMemcpyAsync(dcoef, coef.data(), sizeof(double2) * M, hipMemcpyHostToDevice, s);
   double* sp = on_dev ? psi : dpsi;
   double* so = on_dev ? observables : dobs;
@@ -471,7 +471,7 @@ static int evolve_run(const kpm_lattice_t* lat, const kpm_evolve_params_t* p, do
     if (f32) {
       hipLaunchKernelGGL(evolve_copy_in_kernel<float>, dim3(gi), dim3(256), 0, s, sp, n_orb, R, P->Rp, g.n_spin,
                          (const uint8_t*)P->mask, (float*)P->X);
-      e = hipGetLastError();
+      e = ::kpm::launch_status();
       if (e == hipSuccess) e = evolve_loop<float>(P, p, g, dcoef, B, hist, part, so, s);
       if (e == hipSuccess)
         hipLaunchKernelGGL(evolve_copy_out_kernel<float>, dim3(go), dim3(256), 0, s, (const float*)P->X, n_orb, R,
@@ -479,13 +479,13 @@ static int evolve_run(const kpm_lattice_t* lat, const kpm_evolve_params_t* p, do
     } else {
       hipLaunchKernelGGL(evolve_copy_in_kernel<double>, dim3(gi), dim3(256), 0, s, sp, n_orb, R, P->Rp, g.n_spin,
                          (const uint8_t*)P->mask, (double*)P->X);
-      e = hipGetLastError();
+      e = ::kpm::launch_status();
       if (e == hipSuccess) e = evolve_loop<double>(P, p, g, dcoef, B, hist, part, so, s);
       if (e == hipSuccess)
         hipLaunchKernelGGL(evolve_copy_out_kernel<double>, dim3(go), dim3(256), 0, s, (const double*)P->X, n_orb, R,
                            P->Rp, sp);
     }
-    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = ::kpm::launch_status();
   }
   if (e == hipSuccess && !on_dev) e = hipMemcpyAsync(psi, dpsi, sizeof(double) * n_psi, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess && !on_dev) e = hipMemcpyAsync(observables, dobs, sizeof(double) * n_obs, hipMemcpyDeviceToHost, s);
@@ -497,7 +497,7 @@ static int evolve_run(const kpm_lattice_t* lat, const kpm_evolve_params_t* p, do
     st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
   }
   for (void* ptr : {hist, (void*)dcoef, (void*)part, (void*)dpsi, (void*)dobs})
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) (void)::kpm::dev_free(ptr);
   plan_free(P);
   delete P;
   return st;

@@ -304,7 +304,7 @@ hipError_t gamma_accumulate_bf16(const __bf16* Lh, const __bf16* Ll, const __bf1
                      n_logical, part);
   const int64_t n = (int64_t)M * M * 2;
   hipLaunchKernelGGL(gamma_reduce_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part, ks_used, n, acc);
-  return hipGetLastError();
+  return ::kpm::launch_status();
 }
 
 template <typename T>
@@ -316,7 +316,7 @@ hipError_t gamma_accumulate_fp64(const T* L, const T* R, int M, int Mp, int64_t 
   hipLaunchKernelGGL(gamma_fp64_kernel<T>, grid, dim3(256), 0, s, L, R, M, Mp, Kc, kchunk, part);
   const int64_t n = (int64_t)M * M * 2;
   hipLaunchKernelGGL(gamma_reduce_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, part, ks_used, n, acc);
-  return hipGetLastError();
+  return ::kpm::launch_status();
 }
 
 template hipError_t gamma_accumulate_fp64<float>(const float*, const float*, int, int, int64_t, int, double*,

@@ -16,15 +16,57 @@ namespace kpm {
 void set_error(const char* fmt, ...);
 void clear_error();
 
-#define KPM_TRY_HIP(call)                                                                   \
+// Fault injection for the error-path tests (kpm_debug_inject_failure).  While
+// it is armed, a countdown runs over the library's checked HIP operations;
+// the operation that takes it to zero reports the injected error.  An
+// allocation or a call wrapped in KPM_TRY_HIP is then skipped; a
+// synchronising call (KPM_TRY_SYNC) and a kernel launch (launch_status) run
+// and only their status is replaced, as when a real failure is reported by
+// a later call.
+bool fault_due();
+hipError_t fault_error();
+
+// Library status of a failed HIP call.
+inline int hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? KPM_E_NOMEM : KPM_E_DEVICE; }
+inline hipError_t after_call(hipError_t e) { return (e == hipSuccess && fault_due()) ? fault_error() : e; }
+// Status of the kernel launches issued since the last check.
+inline hipError_t launch_status() { return after_call(hipGetLastError()); }
+
+// Device allocations of the library: hipMalloc behind the fault countdown,
+// with a count of live allocations (kpm_debug_live_allocations) so that the
+// error-path tests can see every buffer released.
+void live_add(int64_t d);
+template <typename T>
+inline hipError_t dev_malloc(T** p, size_t bytes) {
+  if (fault_due()) {
+    *p = nullptr;
+    return fault_error();
+  }
+  const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e == hipSuccess) live_add(1);
+  else *p = nullptr;
+  return e;
+}
+inline hipError_t dev_free(void* p) {
+  if (!p) return hipSuccess;
+  live_add(-1);
+  return hipFree(p);
+}
+
+#define KPM_TRY_HIP_STATUS_(expr, text)                                                    \
   do {                                                                                      \
-    hipError_t e_ = (call);                                                                 \
+    hipError_t e_ = (expr);                                                                 \
     if (e_ != hipSuccess) {                                                                 \
-      ::kpm::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__,   \
+      ::kpm::set_error("%s failed: %s (%s:%d)", text, hipGetErrorString(e_), __FILE__,     \
                        __LINE__);                                                           \
+      (void)hipGetLastError();                                                              \
       return (e_ == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;                      \
     }                                                                                       \
   } while (0)
+// A HIP call behind the fault countdown (skipped when the injected failure falls on it).
+#define KPM_HIP(call) (::kpm::fault_due() ? ::kpm::fault_error() : (call))
+#define KPM_TRY_HIP(call) KPM_TRY_HIP_STATUS_(KPM_HIP(call), #call)
+#define KPM_TRY_SYNC(call) KPM_TRY_HIP_STATUS_(::kpm::after_call(call), #call)
 
 #define KPM_TRY(call)          \
   do {                         \

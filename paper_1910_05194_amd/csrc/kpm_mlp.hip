@@ -260,26 +260,26 @@ namespace kpm {
 
 static int mlp_reserve(kpm_mlp* N, int B) {
   if (B <= N->cap_b) return KPM_OK;
-  float** bufs[] = {&N->Z1, &N->A1, &N->Z2, &N->A2, &N->Y, &N->dY, &N->dA, &N->dZ};
-  for (float** b : bufs)
-    if (*b) {
-      (void)hipFree(*b);
-      *b = nullptr;
-    }
+  // Drop the old workspace first: after a failed allocation the network holds
+  // no workspace (cap_b = 0), and the next call allocates it again.
+  N->cap_b = 0;
+  float** bufs[] = {&N->Z1, &N->A1, &N->Z2, &N->A2, &N->Y, &N->dY, &N->dA, &N->dZ, &N->Xn, &N->Tn};
+  for (float** b : bufs) {
+    (void)::kpm::dev_free(*b);
+    *b = nullptr;
+  }
   const int64_t h = (int64_t)B * N->n_hid, o = (int64_t)B * N->n_out;
   const int64_t wmax = std::max<int64_t>(h, o);
-  KPM_TRY_HIP(hipMalloc(&N->Z1, h * 4));
-  KPM_TRY_HIP(hipMalloc(&N->A1, h * 4));
-  KPM_TRY_HIP(hipMalloc(&N->Z2, h * 4));
-  KPM_TRY_HIP(hipMalloc(&N->A2, h * 4));
-  KPM_TRY_HIP(hipMalloc(&N->Y, o * 4));
-  KPM_TRY_HIP(hipMalloc(&N->dY, o * 4));
-  KPM_TRY_HIP(hipMalloc(&N->dA, wmax * 4));
-  KPM_TRY_HIP(hipMalloc(&N->dZ, wmax * 4));
-  if (N->Xn) (void)hipFree(N->Xn);
-  if (N->Tn) (void)hipFree(N->Tn);
-  KPM_TRY_HIP(hipMalloc(&N->Xn, (int64_t)B * N->n_in * 4));
-  KPM_TRY_HIP(hipMalloc(&N->Tn, o * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->Z1, h * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->A1, h * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->Z2, h * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->A2, h * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->Y, o * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->dY, o * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->dA, wmax * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->dZ, wmax * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->Xn, (int64_t)B * N->n_in * 4));
+  KPM_TRY_HIP(::kpm::dev_malloc(&N->Tn, o * 4));
   N->cap_b = B;
   return KPM_OK;
 }
@@ -378,12 +378,12 @@ int kpm_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, uint64_t seed,
     o += (sz[i] + 63) / 64 * 64;
   }
   N->n_par = o;
-  hipError_t e = hipMalloc(&N->par, o * 4);
-  if (e == hipSuccess) e = hipMalloc(&N->grad, o * 4);
-  if (e == hipSuccess) e = hipMalloc(&N->m, o * 4);
-  if (e == hipSuccess) e = hipMalloc(&N->v, o * 4);
-  if (e == hipSuccess) e = hipMalloc(&N->partial, 256 * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&N->loss_dev, sizeof(double));
+  hipError_t e = ::kpm::dev_malloc(&N->par, o * 4);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&N->grad, o * 4);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&N->m, o * 4);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&N->v, o * 4);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&N->partial, 256 * sizeof(double));
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&N->loss_dev, sizeof(double));
   if (e == hipSuccess) {
     const unsigned gb = (unsigned)ceil_div(o, 256);
     hipLaunchKernelGGL(fill_f32, dim3(gb), dim3(256), 0, 0, N->par, o, 0.f);
@@ -396,7 +396,7 @@ int kpm_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, uint64_t seed,
       hipLaunchKernelGGL(init_uniform_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, 0, N->par + N->off[2 * l],
                          n, sm_key(5, seed, (uint64_t)l, 0), (float)std::sqrt(3.0 / fan[l]));
     }
-    e = hipGetLastError();
+    e = ::kpm::launch_status();
     if (e == hipSuccess) e = hipDeviceSynchronize();
   }
   if (e != hipSuccess) {
@@ -413,7 +413,7 @@ int kpm_mlp_destroy(kpm_mlp_t* N) {
   void* bufs[] = {N->par, N->grad, N->m, N->v, N->Z1, N->A1, N->Z2, N->A2, N->Y, N->dY, N->dA, N->dZ, N->partial,
                   N->loss_dev, N->x_shift, N->x_scale, N->y_shift, N->y_scale, N->Xn, N->Tn, N->wn};
   for (void* b : bufs)
-    if (b) (void)hipFree(b);
+    if (b) (void)::kpm::dev_free(b);
   delete N;
   return KPM_OK;
 }
@@ -444,7 +444,7 @@ int kpm_mlp_get_params(kpm_mlp_t* N, float* params) {
   using namespace kpm;
   clear_error();
   KPM_CHECK_ARG(N && params, "NULL argument");
-  KPM_TRY_HIP(hipDeviceSynchronize());
+  KPM_TRY_SYNC(hipDeviceSynchronize());
   return mlp_copy(N, N->par, params, true);
 }
 
@@ -452,12 +452,12 @@ int kpm_mlp_set_params(kpm_mlp_t* N, const float* params) {
   using namespace kpm;
   clear_error();
   KPM_CHECK_ARG(N && params, "NULL argument");
-  KPM_TRY_HIP(hipDeviceSynchronize());
+  KPM_TRY_SYNC(hipDeviceSynchronize());
   N->t = 0;
   const unsigned gb = (unsigned)ceil_div(N->n_par, 256);
   hipLaunchKernelGGL(fill_f32, dim3(gb), dim3(256), 0, 0, N->m, N->n_par, 0.f);
   hipLaunchKernelGGL(fill_f32, dim3(gb), dim3(256), 0, 0, N->v, N->n_par, 0.f);
-  KPM_TRY_HIP(hipDeviceSynchronize());
+  KPM_TRY_SYNC(hipDeviceSynchronize());
   return mlp_copy(N, N->par, const_cast<float*>(params), false);
 }
 
@@ -532,19 +532,18 @@ int kpm_mlp_fit_scaling(kpm_mlp_t* N, const float* x, const float* target, int64
   clear_error();
   KPM_CHECK_ARG(N && x && target && n_rows >= 1, "bad arguments");
   hipStream_t s = (hipStream_t)hip_stream;
-  if (!N->x_shift) {
-    KPM_TRY_HIP(hipMalloc(&N->x_shift, N->n_in * 4));
-    KPM_TRY_HIP(hipMalloc(&N->x_scale, N->n_in * 4));
-    KPM_TRY_HIP(hipMalloc(&N->y_shift, N->n_out * 4));
-    KPM_TRY_HIP(hipMalloc(&N->y_scale, N->n_out * 4));
-    KPM_TRY_HIP(hipMalloc(&N->wn, N->n_out * 4));
-  }
+  // Each buffer on its own, so that a call after a failed allocation completes the set.
+  if (!N->x_shift) KPM_TRY_HIP(::kpm::dev_malloc(&N->x_shift, N->n_in * 4));
+  if (!N->x_scale) KPM_TRY_HIP(::kpm::dev_malloc(&N->x_scale, N->n_in * 4));
+  if (!N->y_shift) KPM_TRY_HIP(::kpm::dev_malloc(&N->y_shift, N->n_out * 4));
+  if (!N->y_scale) KPM_TRY_HIP(::kpm::dev_malloc(&N->y_scale, N->n_out * 4));
+  if (!N->wn) KPM_TRY_HIP(::kpm::dev_malloc(&N->wn, N->n_out * 4));
   hipLaunchKernelGGL(column_stats_kernel, dim3((unsigned)ceil_div(N->n_in, 64)), dim3(64), 0, s, x, n_rows, N->n_in,
                      N->x_shift, N->x_scale);
   hipLaunchKernelGGL(column_stats_kernel, dim3((unsigned)ceil_div(N->n_out, 64)), dim3(64), 0, s, target, n_rows,
                      N->n_out, N->y_shift, N->y_scale);
   KPM_TRY_HIP(hipGetLastError());
-  KPM_TRY_HIP(hipStreamSynchronize(s));
+  KPM_TRY_SYNC(hipStreamSynchronize(s));
   N->scaled = true;
   return KPM_OK;
 }
@@ -558,7 +557,7 @@ int kpm_mlp_gradients(kpm_mlp_t* N, const float* x, const float* target, const f
   hipStream_t s = (hipStream_t)hip_stream;
   normalised_forward_backward(N, x, target, weights, batch, s);
   KPM_TRY_HIP(hipGetLastError());
-  KPM_TRY_HIP(hipStreamSynchronize(s));
+  KPM_TRY_SYNC(hipStreamSynchronize(s));
   if (loss) KPM_TRY_HIP(hipMemcpy(loss, N->loss_dev, sizeof(double), hipMemcpyDeviceToHost));
   if (grads_host) KPM_TRY(mlp_copy(N, N->grad, grads_host, true));
   return KPM_OK;

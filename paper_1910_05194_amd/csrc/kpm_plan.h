@@ -90,6 +90,7 @@ struct kpm_plan {
   bool use_arena = false;
   char* arena_base = nullptr;
   size_t arena_cap = 0, arena_used = 0;
+  size_t dev_bytes = 0;   // device bytes of the plan's buffers
 };
 
 

@@ -72,15 +72,15 @@ extern "C" int kpm_bandwidth_probe(int32_t pattern, int64_t bytes_per_array, int
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int st = KPM_OK;
   auto cleanup = [&]() {
-    if (a) (void)hipFree(a);
-    if (b) (void)hipFree(b);
-    if (red) (void)hipFree(red);
+    if (a) (void)::kpm::dev_free(a);
+    if (b) (void)::kpm::dev_free(b);
+    if (red) (void)::kpm::dev_free(red);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
   };
-  hipError_t e = hipMalloc(&a, n * 16);
-  if (e == hipSuccess) e = hipMalloc(&b, n * 16);
-  if (e == hipSuccess) e = hipMalloc(&red, (size_t)grid * block * sizeof(float));
+  hipError_t e = ::kpm::dev_malloc(&a, n * 16);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&b, n * 16);
+  if (e == hipSuccess) e = ::kpm::dev_malloc(&red, (size_t)grid * block * sizeof(float));
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e == hipSuccess) e = hipMemsetAsync(a, 0, n * 16, s);
@@ -103,7 +103,7 @@ extern "C" int kpm_bandwidth_probe(int32_t pattern, int64_t bytes_per_array, int
     e = hipEventRecord(e0, s);
   }
   for (int i = 0; e == hipSuccess && i < iters; ++i) launch();
-  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = ::kpm::launch_status();
   if (e == hipSuccess) e = hipEventRecord(e1, s);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;

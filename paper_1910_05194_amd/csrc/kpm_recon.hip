@@ -178,25 +178,29 @@ extern "C" int kpm_reconstruct_sigma(const double* gamma, int32_t M, const doubl
   double* dsig = sigma;
   double* tmp = nullptr;
   const size_t gn = (size_t)M * M * 2;
+  hipError_t e = hipSuccess;
   if (!on_device) {
-    KPM_TRY_HIP(hipMalloc(&tmp, sizeof(double) * (gn + 2 * (size_t)K)));
-    KPM_TRY_HIP(hipMemcpyAsync(tmp, gamma, sizeof(double) * gn, hipMemcpyHostToDevice, s));
-    KPM_TRY_HIP(hipMemcpyAsync(tmp + gn, energies_ev, sizeof(double) * K, hipMemcpyHostToDevice, s));
+    e = ::kpm::dev_malloc(&tmp, sizeof(double) * (gn + 2 * (size_t)K));
+    if (e == hipSuccess) e = KPM_HIP(hipMemcpyAsync(tmp, gamma, sizeof(double) * gn, hipMemcpyHostToDevice, s));
+    if (e == hipSuccess)
+      e = KPM_HIP(hipMemcpyAsync(tmp + gn, energies_ev, sizeof(double) * K, hipMemcpyHostToDevice, s));
     dg = tmp;
     den = tmp + gn;
     dsig = tmp + gn + K;
   }
-  hipLaunchKernelGGL(sigma_kernel, dim3(K), dim3(256), sizeof(double) * M, s, dg, M, den, K, e_min, e_max,
-                     orbitals_per_nm2, dsig);
-  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(sigma_kernel, dim3(K), dim3(256), sizeof(double) * M, s, dg, M, den, K, e_min, e_max,
+                       orbitals_per_nm2, dsig);
+    e = ::kpm::launch_status();
+  }
   if (e == hipSuccess && !on_device) {
     e = hipMemcpyAsync(sigma, dsig, sizeof(double) * K, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
-  if (tmp) (void)hipFree(tmp);
+  if (tmp) (void)::kpm::dev_free(tmp);
   if (e != hipSuccess) {
     set_error("kpm_reconstruct_sigma: %s", hipGetErrorString(e));
-    return KPM_E_DEVICE;
+    return ::kpm::hip_status(e);
   }
   return KPM_OK;
 }
@@ -216,30 +220,34 @@ static int reconstruct(const char* name, int which, const double* mu, int32_t M,
   double* drho = rho;
   double* dg = green;
   double* tmp = nullptr;
+  hipError_t e = hipSuccess;
   if (!on_device) {
-    KPM_TRY_HIP(hipMalloc(&tmp, sizeof(double) * ((size_t)M + 4 * (size_t)K)));
-    KPM_TRY_HIP(hipMemcpyAsync(tmp, mu, sizeof(double) * M, hipMemcpyHostToDevice, s));
-    KPM_TRY_HIP(hipMemcpyAsync(tmp + M, energies_ev, sizeof(double) * K, hipMemcpyHostToDevice, s));
+    e = ::kpm::dev_malloc(&tmp, sizeof(double) * ((size_t)M + 4 * (size_t)K));
+    if (e == hipSuccess) e = KPM_HIP(hipMemcpyAsync(tmp, mu, sizeof(double) * M, hipMemcpyHostToDevice, s));
+    if (e == hipSuccess)
+      e = KPM_HIP(hipMemcpyAsync(tmp + M, energies_ev, sizeof(double) * K, hipMemcpyHostToDevice, s));
     dmu = tmp;
     den = tmp + M;
     drho = tmp + M + K;
     dg = green ? tmp + M + 2 * (size_t)K : nullptr;
   }
-  const dim3 grid((unsigned)ceil_div(K, 256)), block(256);
-  if (which == 2)
-    hipLaunchKernelGGL(cpgf_kernel, grid, block, 0, s, dmu, M, den, K, e_min, e_max, param, drho, dg);
-  else
-    hipLaunchKernelGGL(kernel_dos_kernel, grid, block, 0, s, dmu, M, den, K, e_min, e_max, which, param, drho);
-  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    const dim3 grid((unsigned)ceil_div(K, 256)), block(256);
+    if (which == 2)
+      hipLaunchKernelGGL(cpgf_kernel, grid, block, 0, s, dmu, M, den, K, e_min, e_max, param, drho, dg);
+    else
+      hipLaunchKernelGGL(kernel_dos_kernel, grid, block, 0, s, dmu, M, den, K, e_min, e_max, which, param, drho);
+    e = ::kpm::launch_status();
+  }
   if (e == hipSuccess && !on_device) {
     e = hipMemcpyAsync(rho, drho, sizeof(double) * K, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && green) e = hipMemcpyAsync(green, dg, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
-  if (tmp) (void)hipFree(tmp);
+  if (tmp) (void)::kpm::dev_free(tmp);
   if (e != hipSuccess) {
     set_error("%s: %s", name, hipGetErrorString(e));
-    return KPM_E_DEVICE;
+    return ::kpm::hip_status(e);
   }
   return KPM_OK;
 }
@@ -261,18 +269,18 @@ extern "C" int kpm_kernel_factors(int32_t kernel, int32_t M, double lambda, int3
   KPM_CHECK_ARG(g != nullptr, "NULL argument");
   hipStream_t s = (hipStream_t)hip_stream;
   double* dg = g;
-  if (!on_device) KPM_TRY_HIP(hipMalloc(&dg, sizeof(double) * (size_t)count));
+  if (!on_device) KPM_TRY_HIP(::kpm::dev_malloc(&dg, sizeof(double) * (size_t)count));
   hipLaunchKernelGGL(kpm::kernel_factors_kernel, dim3((unsigned)kpm::ceil_div(count, 256)), dim3(256), 0, s, kernel, M,
                      lambda, n0, count, dg);
-  hipError_t e = hipGetLastError();
+  hipError_t e = ::kpm::launch_status();
   if (e == hipSuccess && !on_device) {
     e = hipMemcpyAsync(g, dg, sizeof(double) * (size_t)count, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
-  if (!on_device) (void)hipFree(dg);
+  if (!on_device) (void)::kpm::dev_free(dg);
   if (e != hipSuccess) {
     kpm::set_error("kpm_kernel_factors: %s", hipGetErrorString(e));
-    return KPM_E_DEVICE;
+    return ::kpm::hip_status(e);
   }
   return KPM_OK;
 }
@@ -544,7 +552,7 @@ extern "C" int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, cons
   const size_t gn = (size_t)M * M * 2;
   const size_t b_host = on_device ? 0 : sizeof(double) * (gn + 2 * (size_t)K);
   char* ws = nullptr;
-  KPM_TRY_HIP(hipMalloc(&ws, b_gam + b_tab + b_part + b_host));
+  KPM_TRY_HIP(::kpm::dev_malloc(&ws, b_gam + b_tab + b_part + b_host));
   double2* gam = (double2*)ws;
   double2* tab = (double2*)(ws + b_gam);
   double2* part = (double2*)(ws + b_gam + b_tab);
@@ -574,16 +582,16 @@ extern "C" int kpm_reconstruct_sigma_bastin(const double* gamma, int32_t M, cons
     // pref = -2 pi i (N/Omega)/de-^2 is imaginary: Re(pref F) = -Im(pref) Im(F).
     hipLaunchKernelGGL(bastin_sigma_kernel, dim3(K), dim3(256), 0, s, part, n_tiles, Q, den, K, e_min, e_max,
                        kT_ev / de_m, -2.0 * M_PI * orbitals_per_nm2 / (de_m * de_m), dsig);
-    e = hipGetLastError();
+    e = ::kpm::launch_status();
   }
   if (e == hipSuccess && !on_device) {
     e = hipMemcpyAsync(sigma, dsig, sizeof(double) * K, hipMemcpyDeviceToHost, s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(ws);
+  (void)::kpm::dev_free(ws);
   if (e != hipSuccess) {
     set_error("kpm_reconstruct_sigma_bastin: %s", hipGetErrorString(e));
-    return KPM_E_DEVICE;
+    return ::kpm::hip_status(e);
   }
   return KPM_OK;
 }
@@ -697,7 +705,7 @@ extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const doubl
   std::vector<double> om((size_t)K);
   if (on_device) {
     KPM_TRY_HIP(hipMemcpyAsync(om.data(), omegas_ev, sizeof(double) * K, hipMemcpyDeviceToHost, s));
-    KPM_TRY_HIP(hipStreamSynchronize(s));
+    KPM_TRY_SYNC(hipStreamSynchronize(s));
   } else {
     std::memcpy(om.data(), omegas_ev, sizeof(double) * K);
   }
@@ -716,7 +724,7 @@ extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const doubl
   const size_t gn = (size_t)M * M * 2;
   const size_t b_host = on_device ? 0 : sizeof(double) * (gn + 2 * (size_t)M + (size_t)K + 2 * (size_t)K);
   char* ws = nullptr;
-  KPM_TRY_HIP(hipMalloc(&ws, b_gam + b_tab + b_part + b_small + b_host));
+  KPM_TRY_HIP(::kpm::dev_malloc(&ws, b_gam + b_tab + b_part + b_small + b_host));
   double2* gam = (double2*)ws;
   double2* ta = (double2*)(ws + b_gam);
   double2* tb = ta + (size_t)Qp * Mp;
@@ -752,20 +760,20 @@ extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const doubl
       hipLaunchKernelGGL(bastin_contract_kernel, dim3(Qp / kBT, n_tiles), dim3(256), 0, s, ta, tb, gam, Q, Mp, part);
       hipLaunchKernelGGL(optical_para_kernel, dim3(1), dim3(256), 0, s, part, n_tiles, Q, mut, kTt,
                          para + 2 * k);
-      e = hipGetLastError();
+      e = ::kpm::launch_status();
     }
     if (e == hipSuccess) {
       hipLaunchKernelGGL(optical_final_kernel, dim3((unsigned)ceil_div(K, 256)), dim3(256), 0, s, para, lam, dom, K,
                          de_m, orbitals_per_nm2, dsig);
-      e = hipGetLastError();
+      e = ::kpm::launch_status();
     }
   }
   if (e == hipSuccess && !on_device) e = hipMemcpyAsync(sigma, dsig, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(ws);
+  (void)::kpm::dev_free(ws);
   if (e != hipSuccess) {
     set_error("kpm_reconstruct_sigma_optical: %s", hipGetErrorString(e));
-    return KPM_E_DEVICE;
+    return ::kpm::hip_status(e);
   }
   return KPM_OK;
 }

@@ -151,6 +151,8 @@ def _load():
                                         ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(c_tune), _D, _P]),
         "kpm_bandwidth_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                                ctypes.c_int32, ctypes.c_int32, _P, _D, _D]),
+        "kpm_debug_inject_failure": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32]),
+        "kpm_debug_live_allocations": (ctypes.c_int64, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -165,6 +167,21 @@ LIB = _load()
 def _check(code: int):
     if code != KPM_OK:
         raise KPMError(code, LIB.kpm_last_error().decode(errors="replace"))
+
+
+def debug_inject_failure(nth: int, kind: int = 0) -> int:
+    """Arm the library's fault countdown (kpm_debug_inject_failure): the nth checked
+    HIP operation from now on fails (kind 0: out of memory, 1: launch failure);
+    nth = 0 disarms.  Returns how many failures fired since the previous call."""
+    r = int(LIB.kpm_debug_inject_failure(int(nth), int(kind)))
+    if r < 0:
+        _check(r)
+    return r
+
+
+def debug_live_allocations() -> int:
+    """Device buffers the library holds right now (kpm_debug_live_allocations)."""
+    return int(LIB.kpm_debug_live_allocations())
 
 
 def last_error() -> str:

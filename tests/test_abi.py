@@ -18,7 +18,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libkpm.so not b
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(kpm_\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^(?:int|int32_t|int64_t|const char\*)\s+(kpm_\w+)\s*\(", text, flags=re.M)))
 
 
 def test_every_declared_function_is_exported():
@@ -150,3 +150,20 @@ def test_argument_validation_without_device():
         kpm.reconstruct_sigma_optical(G, np.zeros(8), np.array([0.5]), 0.0, -1.0, 1.0, 0.1, 1.0, kT=-0.01)
     assert "kT" in str(e.value)
     assert kpm.last_error() != ""
+
+
+def test_fault_injection_hook_without_device():
+    """kpm_debug_inject_failure: argument checks, arming and disarming; a call that
+    fails validation returns before any checked HIP operation, so nothing fires."""
+    from paper_1910_05194_amd import kpm
+    assert kpm.debug_live_allocations() >= 0
+    for nth, kind in ((-1, 0), (1, 2), (1, -1)):
+        with pytest.raises(kpm.KPMError) as e:
+            kpm.debug_inject_failure(nth, kind)
+        assert e.value.code == kpm.KPM_E_INVALID
+    assert kpm.debug_inject_failure(0, 0) == 0
+    assert kpm.debug_inject_failure(3, 1) == 0
+    with pytest.raises(kpm.KPMError) as e:
+        kpm.kernel_factors(8, n0=7, count=4)
+    assert e.value.code == kpm.KPM_E_INVALID
+    assert kpm.debug_inject_failure(0, 0) == 0
