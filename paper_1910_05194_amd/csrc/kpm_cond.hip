@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -131,6 +132,24 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
   for (auto& x : ev)
     if (e == hipSuccess) e = hipEventCreate(&x);
   if (e != hipSuccess && st == KPM_OK) fail(e, "creating events");
+  // Multi-step chain sweeps: KS = 4 steps per launch on the spinful lattice
+  // (3 in FP64), 2 on the spinless ones (the fastest measured on 1024^2
+  // lattices; the spinless kernels are bound by instruction issue at larger
+  // KS).  KPM_CHAIN_STEPS=1 keeps single steps, 2..4 sets KS; KPM_CHAIN_ROWS
+  // sets the rows per tile.  Without a tile shape that fits, single steps.
+  ChainPlan C;
+  bool sweep_chains = false;
+  if (st == KPM_OK) {
+    int ks = (P->n_spin == 2) ? 4 : 2, rows = 0;
+    if (const char* cs = std::getenv("KPM_CHAIN_STEPS"); cs && *cs) ks = std::atoi(cs);
+    if (const char* cr = std::getenv("KPM_CHAIN_ROWS"); cr && *cr) rows = std::max(0, std::atoi(cr));
+    if (ks >= 2) {
+      const int cst = chain_plan_create(P, std::min(ks, 4), rows, Mp, &C);
+      if (cst == KPM_OK) sweep_chains = true;
+      else if (cst == KPM_E_UNSUPPORTED) clear_error();   // single steps
+      else st = cst;
+    }
+  }
   if (st == KPM_OK) e = hipEventRecord(ev[3], s);
   g_stats.n_batches = n_batch;
   g_stats.vectors_per_batch = Rb;
@@ -152,10 +171,30 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
     e = plan_launch_prep(P, s);
     if (e != hipSuccess) { fail(e, "model/start kernels"); break; }
     e = hipEventRecord(ev[0], s);
+    if (sweep_chains) {
+      // L_0 = -h~^a xi by one velocity launch (into Y and block row 0), then L_1 .. L_{M-1}
+      // by sweeps, each level into its block row.
+      StepLaunch S0;
+      S0.dots = 0;
+      S0.blk = Lb;
+      S0.blk_lo = Llo;
+      S0.blk_row = 0;
+      S0.blk_rows = Mp;
+      S0.v = P->X; S0.out = P->Y; S0.write_out = 0; S0.read_w = 0; S0.a = 0.0; S0.b = 0.0;
+      S0.velocity = true; S0.vel = P->Y; S0.vdir = p->alpha; S0.vel_scale = -1.0; S0.blk_src = 1;
+      if (e == hipSuccess) e = plan_launch_step(P, s, S0);
+      g_stats.chain_bytes += step_bytes(S0);
+      if (e == hipSuccess && M > 1)
+        e = chain_run(P, C, s, 0, P->Y, P->X, M - 1, Lb, Llo, Mp, 0, 1.0, &g_stats.chain_bytes);
+      // R chain from xi again: R_m = h~^b T_m(H~) xi for m = 0 .. M-1 (M levels, each
+      // giving the velocity of the level below).
+      if (e == hipSuccess) e = plan_launch_prep(P, s);
+      if (e == hipSuccess) e = chain_run(P, C, s, 1, P->X, P->Y, M, Rblk, Rlo, Mp, p->beta, 1.0, &g_stats.chain_bytes);
+    }
     // L chain: L_0 = -h~^a xi, L_1 = H~ L_0, L_n = 2 H~ L_{n-1} - L_{n-2}, kept in the
     // plan's two vector buffers (L_n in X for odd n, in Y for even n >= 2) and
     // copied row by row into the K-blocked block Lb.
-    for (int n = 0; n < M && e == hipSuccess; ++n) {
+    for (int n = 0; n < M && e == hipSuccess && !sweep_chains; ++n) {
       StepLaunch S;
       S.dots = 0;
       S.blk = Lb;
@@ -178,8 +217,8 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
     }
     // R chain: start again from xi; v_0 = xi, v_1 = H~ v_0, v_{m+1} = 2 H~ v_m - v_{m-1}
     // (in place), with R_m = h~^b v_m from the same pass stored K-blocked in Rblk.
-    if (e == hipSuccess) e = plan_launch_prep(P, s);
-    for (int m = 0; m < M && e == hipSuccess; ++m) {
+    if (e == hipSuccess && !sweep_chains) e = plan_launch_prep(P, s);
+    for (int m = 0; m < M && e == hipSuccess && !sweep_chains; ++m) {
       StepLaunch S;
       S.dots = 0;
       S.velocity = true;
@@ -246,6 +285,7 @@ static int cond_run(const kpm_lattice_t* lat, const kpm_cond_params_t* p, double
     if (x) (void)hipEventDestroy(x);
   for (void* ptr : {Lb, Rblk, Llo, Rlo, (void*)acc, (void*)part, (void*)gdev})
     if (ptr) (void)::kpm::dev_free(ptr);
+  chain_plan_free(&C);
   plan_free(P);
   delete P;
   return st;

@@ -28,6 +28,32 @@ struct StepLaunch {
 };
 
 hipError_t plan_launch_step(kpm_plan* P, hipStream_t s, const StepLaunch& L);
+
+// Multi-step sweeps of the conductivity chains (kpm_chain.hip) over a plan's
+// lattice, site arrays and vector buffers X, Y: a tile list of their own, two
+// more vector buffers, and the launch shape.
+struct ChainPlan {
+  int ks = 0, block = 0, Tx = 0, Ty = 0, Ew = 0, grid = 0, n_tiles = 0;
+  size_t lds_bytes = 0;
+  int4* tiles = nullptr;
+  void* Z = nullptr;
+  void* W = nullptr;
+  void* fn[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [mode 0 levels / 1 velocities][split BF16]
+};
+// ks = steps per sweep (2..4), rows = rows per tile (0: chosen here),
+// blk_rows = rows of the Gamma store.  KPM_E_UNSUPPORTED when no tile shape
+// fits the LDS or a lattice row is too long for 32-bit offsets (the caller
+// then runs single steps).
+int chain_plan_create(const kpm_plan* P, int ks, int rows, int64_t blk_rows, ChainPlan* C);
+void chain_plan_free(ChainPlan* C);
+// n_levels recursion levels from level 0 in v0 (level 1 = H~ v0, then 2 H~ v - w),
+// with one Gamma block row per level: mode 0 stores levels 1..n_levels into rows
+// 1..n_levels; mode 1 stores the velocity vel_scale [r^vdir, H] of levels
+// 0..n_levels-1 into rows 0..n_levels-1.  w0 is a free vector buffer (X or Y).
+// *bytes receives the algorithmic HBM bytes moved.
+hipError_t chain_run(const kpm_plan* P, const ChainPlan& C, hipStream_t s, int mode, void* v0, void* w0,
+                     int n_levels, void* blk, void* blk_lo, int64_t blk_rows, int vdir, double vel_scale,
+                     double* bytes);
 hipError_t plan_launch_prep(kpm_plan* P, hipStream_t s);
 int plan_set_vector_base(kpm_plan* P, int64_t r0);
 // arena_get != nullptr: after the arguments are validated, arena_get supplies a device arena of

@@ -75,6 +75,38 @@ __device__ inline void flush_slot(double* lds, double* part, int slot, int tid, 
   __syncthreads();
 }
 
+// Memory access through buffer resources (the sweep kernels).  A resource covers one lattice row
+// (its base is uniform; num_records = the row's bytes, < 2^31); an access at
+// an offset >= num_records is dropped by the hardware's range check (a store
+// writes nothing, a load returns zeros).  Threads without data for an access
+// pass kOOB instead of branching around it, so every wave issues the same
+// memory instructions in every row: the in-order vector-memory counter then
+// lets a row wait for its own loads without also waiting for the previous
+// row's stores (a branch around a store would make the compiler assume none
+// was issued and drain the counter).
+constexpr uint32_t kOOB = 0x80000000u;
+constexpr int kRsrcFlags = 0x00020000;   // dword 3 of a gfx9 raw buffer resource
+
+__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcFlags);
+}
+template <typename T>
+__device__ inline Pack<T> buf_ld_pack(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(Pack<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <typename T>
+__device__ inline void buf_st_pack(__amdgpu_buffer_rsrc_t r, uint32_t off, const Pack<T>& v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+}
+template <typename T>
+__device__ inline T buf_ld_scalar(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+}
+
 // Multi-step sweep kernels (kpm_sweep.hip): at most kMaxSweep Chebyshev steps per launch.
 constexpr int kMaxSweep = 5;
 
