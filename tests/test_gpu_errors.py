@@ -113,17 +113,22 @@ def test_noalloc_every_failure(K):
         assert np.array_equal(mu, ref)
 
 
-def test_gamma_every_failure(K):
-    """Split-BF16 Gamma over two batches of vectors (max_batch = 1), and the FP64 GEMM."""
+@pytest.mark.parametrize("steps", ["1", "4"], ids=["single-steps", "sweeps"])
+def test_gamma_every_failure(K, monkeypatch, steps):
+    """Split-BF16 Gamma over two batches of vectors (max_batch = 1), and the FP64 GEMM,
+    with the chains as single steps and as four-step sweeps."""
+    monkeypatch.setenv("KPM_CHAIN_STEPS", steps)
     lat = wl.Lattice(kind=wl.HONEYCOMB_SPIN, L1=8, L2=6, t=-2.7, rashba=0.4, anderson_w=0.6, disorder_seed=3,
                      e_min=-9.0, e_max=9.0)
+    M = 24
     for mode in (wl.GAMMA_SPLIT_BF16, wl.GAMMA_FP64):
-        par = wl.CondParams(num_moments=24, num_random=2, vector_seed=9, alpha=0, beta=1, gamma_mode=mode)
+        par = wl.CondParams(num_moments=M, num_random=2, vector_seed=9, alpha=0, beta=1, gamma_mode=mode)
         ref = K.moments_cond(lat, par, precision=wl.FP32, max_batch=1)
-        res = _sweep(K, f"kpm_moments_cond (mode {mode})",
+        res = _sweep(K, f"kpm_moments_cond (mode {mode}, KPM_CHAIN_STEPS={steps})",
                      lambda: K.moments_cond(lat, par, precision=wl.FP32, max_batch=1))
         for kind, (G, n) in res.items():
-            assert n >= 2 * 2 * 24
+            # two batches, each with at least one checked launch per chain step or sweep
+            assert n >= 2 * 2 * (M // int(steps))
             assert np.array_equal(G, ref)
 
 
