@@ -122,6 +122,7 @@ def leg_small(kpm, wl, np):
 def leg_gamma(kpm, wl, np):
     """Gamma_nm 512x512 on the spinful Rashba + flux 1024^2 lattice, R = 8, split-BF16 MFMA."""
     lat, par = wl.rashba_flux()
+    kpm.moments_cond(lat, par.replace(num_random=4), precision=wl.FP32)   # warm-up: one batch, untimed
     t0 = time.perf_counter()
     G = kpm.moments_cond(lat, par, precision=wl.FP32)
     dt = time.perf_counter() - t0
