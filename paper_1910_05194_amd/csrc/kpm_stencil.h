@@ -4,6 +4,8 @@
 
 #include "kpm_internal.h"
 
+#include <type_traits>
+
 namespace kpm {
 
 // Per-lattice constants seen by the kernels.
@@ -89,6 +91,14 @@ constexpr int kRsrcFlags = 0x00020000;   // dword 3 of a gfx9 raw buffer resourc
 
 __device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcFlags);
+}
+// Start of row y of a row-major array whose rows hold row_bytes bytes: the
+// offset is formed as an unsigned 32 x 32 -> 64-bit product (y >= 0), two
+// scalar instructions instead of a signed 64-bit multiply.
+template <typename P>
+__device__ inline P* row_ptr(P* base, int y, uint32_t row_bytes) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<C*>(base) + (uint64_t)(uint32_t)y * (uint64_t)row_bytes);
 }
 template <typename T>
 __device__ inline Pack<T> buf_ld_pack(__amdgpu_buffer_rsrc_t r, uint32_t off) {

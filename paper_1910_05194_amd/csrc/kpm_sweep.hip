@@ -235,27 +235,28 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     // Loads of one row of v_n (when in range) and of the site data and v_{n-1}
     // of the row below it; out of range, the same instructions with kOOB.
     auto fetch = [&](RowSet& S, int yv, int ys, bool in_range) {
-      const __amdgpu_buffer_rsrc_t rv = row_rsrc(vb + (int64_t)yv * row_elems, row_bytes);
-      const __amdgpu_buffer_rsrc_t rw = row_rsrc(wb + (int64_t)ys * row_elems, row_bytes);
+      const __amdgpu_buffer_rsrc_t rv = row_rsrc(row_ptr(vb, yv, row_bytes), row_bytes);
+      const __amdgpu_buffer_rsrc_t rw = row_rsrc(row_ptr(wb, ys, row_bytes), row_bytes);
       S.own = buf_ld_pack<T>(rv, in_range ? off_own : kOOB);
       S.halo = buf_ld_pack<T>(rv, in_range ? off_halo : kOOB);
       S.w = buf_ld_pack<T>(rw, in_range ? off_own : kOOB);
-      const int64_t row_site = site_off + (int64_t)ys * row_sites;
+      const uint32_t ons_row_bytes = (uint32_t)(row_sites * (int64_t)sizeof(T));
       if constexpr (ONSITE) {
-        S.ons = buf_ld_scalar<T>(row_rsrc(A.onsite + row_site, (uint32_t)(row_sites * (int64_t)sizeof(T))),
+        S.ons = buf_ld_scalar<T>(row_rsrc(row_ptr(A.onsite + site_off, ys, ons_row_bytes), ons_row_bytes),
                                  in_range ? off_ons : kOOB);
       } else {
         S.ons = ons_c;
       }
       if constexpr (MASK) {
-        S.alive = __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(A.mask + row_site, (uint32_t)row_sites),
+        S.alive = __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(row_ptr(A.mask + site_off, ys, (uint32_t)row_sites),
+                                                                (uint32_t)row_sites),
                                                       in_range ? off_mask : kOOB, 0, 0) != 0;
       } else {
         S.alive = true;
       }
     };
     auto fetch_v = [&](RowSet& S, int yv) {
-      const __amdgpu_buffer_rsrc_t rv = row_rsrc(vb + (int64_t)yv * row_elems, row_bytes);
+      const __amdgpu_buffer_rsrc_t rv = row_rsrc(row_ptr(vb, yv, row_bytes), row_bytes);
       S.own = buf_ld_pack<T>(rv, off_own);
       S.halo = buf_ld_pack<T>(rv, off_halo);
     };
@@ -400,8 +401,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
         const int yb_u = y0 + j - (2 * nlev - 1);
         const bool own_b = inner && (yb_u >= y0) && (yb_u < y0 + ty);
         const bool own_a = inner && (nlev >= 2) && (yb_u + 2 >= y0) && (yb_u + 2 < y0 + ty);
-        buf_st_pack<T>(row_rsrc(ob + (int64_t)yb * row_elems, row_bytes), own_b ? lane_b : kOOB, o_b);
-        buf_st_pack<T>(row_rsrc(oa + (int64_t)ya * row_elems, row_bytes), own_a ? lane_b : kOOB, o_a);
+        buf_st_pack<T>(row_rsrc(row_ptr(ob, yb, row_bytes), row_bytes), own_b ? lane_b : kOOB, o_b);
+        buf_st_pack<T>(row_rsrc(row_ptr(oa, ya, row_bytes), row_bytes), own_a ? lane_b : kOOB, o_a);
       }
       yf = next_row(yf);
       ys = next_row(ys);
