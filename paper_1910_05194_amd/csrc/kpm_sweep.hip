@@ -72,10 +72,14 @@ __device__ inline void sweep_site(T a, T b, bool read_w, T hop, const T* hre, co
     }
     out.v[2 * j] = orr;
     out.v[2 * j + 1] = oi;
-    if (acc) {
+  }
+  // One uniform branch for all of the site's products.
+  if (acc) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
       const double xr = vo.v[2 * j], xi = vo.v[2 * j + 1];
       pv[j] = fma(xr, xr, fma(xi, xi, pv[j]));
-      pw[j] = fma((double)orr, xr, fma((double)oi, xi, pw[j]));
+      pw[j] = fma((double)out.v[2 * j], xr, fma((double)out.v[2 * j + 1], xi, pw[j]));
     }
   }
 }
@@ -271,6 +275,13 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     // Level l is active for j in [3 l - 1 - KS, ty + KS + l - 2].
     const int j0 = 2 - KS;
     const int j_last = ty + 2 * KS - 2;
+    // Iterations of level l (2..KS): l <= nlev and j - (3 l - 1 - KS) in
+    // [0, lev_cnt), one unsigned comparison per level and row (levels above
+    // nlev get a count of 0).  Level l forms row y0 + j - (2 l - 1), which
+    // belongs to the tile when j - (2 l - 1) is in [0, ty).
+    uint32_t lev_cnt[KS - 1];
+#pragma unroll
+    for (int lev = 2; lev <= KS; ++lev) lev_cnt[lev - 2] = (lev <= nlev) ? (uint32_t)(ty + 2 * KS - 2 * lev + 1) : 0u;
     // Site data of the rows the levels form, as a shift register.  The
     // centre value and w of a level come from this thread's own cell of the
     // LDS rings (no other thread writes that cell before the read).
@@ -313,8 +324,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       // slot of four iterations back, the slot that level l - 2 refills now.
 #pragma unroll
       for (int lev = KS; lev >= 2; --lev) {
-        const int y = y0 + j - (2 * lev - 1);
-        if (lev <= nlev && j >= 3 * lev - 1 - KS && j <= ty + KS + lev - 2) {
+        if ((uint32_t)(j - (3 * lev - 1 - KS)) < lev_cnt[lev - 2]) {
           constexpr int sp1 = (p + 3) & 3, s0 = (p + 2) & 3, sm1 = (p + 1) & 3;   // rows y + 1, y, y - 1
           const int x = xlc + 1;   // this thread's cell
           P vn[NNB];
@@ -339,7 +349,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
           const P wo = (lev == 2) ? r0((p + 3) & 3, x, s) : rl(lev >= 3 ? lev - 2 : 1, p, x, s);
           P o;
           sweep_site<T, KIND, PHASE>((T)2, (T)1, true, hop, hre, him, ons_h[2 * lev - 2], alive_h[2 * lev - 2], vo, wo,
-                                     vn, o, (y >= y0) && (y < y0 + ty), tv[lev - 1], tw[lev - 1]);
+                                     vn, o, (uint32_t)(j - (2 * lev - 1)) < (uint32_t)ty, tv[lev - 1], tw[lev - 1]);
           if (lev < KS) rl(lev, p, x, s) = o;
           // The stored levels: KS and KS - 1 in a full sweep, else nlev and
           // nlev - 1 of the recursion's last, short sweep (element-wise
@@ -359,7 +369,6 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       }
       // Level 1 (row y0 + j - 1) from v_n rows y0 + j - 2 .. y0 + j.
       {
-        const int y = y0 + j - 1;
         if (j <= ty + KS - 1) {
           constexpr int sp1 = (p + 2) & 3, s0 = (p + 1) & 3, sm1 = p;   // v_n rows y + 1, y, y - 1
           const int x = xlc + 1;
@@ -381,7 +390,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
           const P vo = r0(s0, x, s);   // v_n row y
           P o;
           sweep_site<T, KIND, PHASE>(A.a1, A.b1, A.read_w1 != 0, hop, hre, him, ons_h[0], alive_h[0], vo, cur.w, vn, o,
-                                     (y >= y0) && (y < y0 + ty), tv[0], tw[0]);
+                                     (uint32_t)(j - 1) < (uint32_t)ty, tv[0], tw[0]);
           rl(1, p, x, s) = o;
           if constexpr (KS == 2) o_a = o;   // a full two-step sweep stores levels 1 and 2
           if (nlev <= 2) {
