@@ -252,6 +252,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
     const uint32_t halo_b =
         (uint32_t)(((((int64_t)halo_col * NSUB + s) * NSPIN + sp_t) * Rp * 2 + (int64_t)c * NC * 2) * (int64_t)sizeof(T));
     const uint32_t lane_site = (uint32_t)(n1 * NSUB + s);
+    const uint32_t ons_row_bytes = (uint32_t)(row_sites * (int64_t)sizeof(T));
     const T* vb = A.v + Lg.vec_off;
     const T* wb = A.w + Lg.vec_off;
     T* oa = A.out_a + Lg.vec_off;
@@ -273,20 +274,21 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
     T onspre[2];
     bool alivepre[2];
     auto fetch = [&](int k, int yv, int ysd, bool in_range) {
-      const __amdgpu_buffer_rsrc_t rv = row_rsrc(vb + (int64_t)yv * row_elems, row_bytes);
+      const __amdgpu_buffer_rsrc_t rv = row_rsrc(row_ptr(vb, yv, row_bytes), row_bytes);
       own[k] = buf_ld_pack<T>(rv, (in_range && act) ? lane_b : kOOB);
       halo[k] = buf_ld_pack<T>(rv, (in_range && load_halo) ? halo_b : kOOB);
       const bool in1 = in_range && act;
-      if (A.read_w1) wpre[k] = buf_ld_pack<T>(row_rsrc(wb + (int64_t)ysd * row_elems, row_bytes), in1 ? lane_b : kOOB);
-      const int64_t row_site = site_off + (int64_t)ysd * row_sites;
+      if (A.read_w1)
+        wpre[k] = buf_ld_pack<T>(row_rsrc(row_ptr(wb, ysd, row_bytes), row_bytes), in1 ? lane_b : kOOB);
       onspre[k] = ons_c;
       if (A.has_onsite)
-        onspre[k] = buf_ld_scalar<T>(row_rsrc(A.onsite + row_site, (uint32_t)(row_sites * (int64_t)sizeof(T))),
+        onspre[k] = buf_ld_scalar<T>(row_rsrc(row_ptr(A.onsite + site_off, ysd, ons_row_bytes), ons_row_bytes),
                                      in1 ? lane_site * (uint32_t)sizeof(T) : kOOB) + ons_spin;
       alivepre[k] = true;
       if (A.has_mask)
-        alivepre[k] = __builtin_amdgcn_raw_buffer_load_b8(row_rsrc(A.mask + row_site, (uint32_t)row_sites),
-                                                          in1 ? lane_site : kOOB, 0, 0) != 0;
+        alivepre[k] = __builtin_amdgcn_raw_buffer_load_b8(
+                          row_rsrc(row_ptr(A.mask + site_off, ysd, (uint32_t)row_sites), (uint32_t)row_sites),
+                          in1 ? lane_site : kOOB, 0, 0) != 0;
     };
     // Threads without a cell to fill write to the spare cell after the last
     // ring instead (no branch): valid threads never read it.
@@ -310,7 +312,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
       const uint32_t kb0 = ey0 / kBlkK;
       const uint32_t ec = ey0 + lane_c32;
       const uint32_t off = ((ec / kBlkK) - kb0) * kstride + (ec % kBlkK) * (uint32_t)esize;
-      const int64_t base = ((int64_t)kb0 * A.blk_rows + brow) * kBlkK * esize;
+      const uint64_t base = (uint64_t)kb0 * kstride + (uint32_t)(brow * kBlkK * esize);
       const P& src = (MODE == 0) ? o : g;
       u32x2 h, l;
       if constexpr (split) {
@@ -337,7 +339,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
       __builtin_amdgcn_raw_buffer_store_b64(l, row_rsrc(p1, 0x7FFFFFFFu), own ? off : kOOB, 0, 0);
       T* dst = (lev == nlev) ? ob : oa;
       const bool to_vec = own && (lev == nlev || lev == nlev - 1);
-      buf_st_pack<T>(row_rsrc(dst + (int64_t)yw * row_elems, row_bytes), to_vec ? lane_b : kOOB, o);
+      buf_st_pack<T>(row_rsrc(row_ptr(dst, yw, row_bytes), row_bytes), to_vec ? lane_b : kOOB, o);
     };
     // The same three instructions, all dropped (a level without work in this row).
     auto emit_none = [&](const P& o) {
@@ -350,6 +352,12 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
     const int ty = min(A.Ty, L2 - y0);
     const int j0 = 2 - KS;
     const int j_last = ty + 2 * KS - 2;
+    // Level l (2..KS) works at iterations j with l <= nlev and j - (3 l - 1 - KS)
+    // in [0, lev_cnt), and forms row y0 + j - (2 l - 1), one of the tile's
+    // rows when j - (2 l - 1) is in [0, ty): one unsigned comparison each.
+    uint32_t lev_cnt[KS - 1];
+#pragma unroll
+    for (int lev = 2; lev <= KS; ++lev) lev_cnt[lev - 2] = (lev <= nlev) ? (uint32_t)(ty + 2 * KS - 2 * lev + 1) : 0u;
     T ons_h[NH];
     bool alive_h[NH];
 #pragma unroll
@@ -378,8 +386,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
       const int x = xlc + 1;
 #pragma unroll
       for (int lev = KS; lev >= 2; --lev) {
-        const int y = y0 + j - (2 * lev - 1);
-        if (lev <= nlev && j >= 3 * lev - 1 - KS && j <= ty + KS + lev - 2) {
+        if ((uint32_t)(j - (3 * lev - 1 - KS)) < lev_cnt[lev - 2]) {
           constexpr int sp1 = (p + 3) & 3, s0 = (p + 2) & 3, sm1 = (p + 1) & 3;   // rows y + 1, y, y - 1
           P vn[NNB][NSPIN];
 #pragma unroll
@@ -405,14 +412,13 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
           chain_site<T, KIND, MODE>((T)2, (T)1, true, C, ons_h[2 * lev - 3], A.vel_scale, alive_h[2 * lev - 3], vo,
                                     wo, vn, o, g);
           if (lev < KS) rl(lev, p, x, s, sp_t) = o;
-          emit(lev, yl[lev], inner && y >= y0 && y < y0 + ty, o, g);
+          emit(lev, yl[lev], inner && (uint32_t)(j - (2 * lev - 1)) < (uint32_t)ty, o, g);
         } else {
           emit_none(own[p & 1]);
         }
       }
       // Level 1 (row y0 + j - 1) from v_n rows y0 + j - 2 .. y0 + j.
       if (j <= ty + KS - 1) {
-        const int y = y0 + j - 1;
         constexpr int sp1 = (p + 2) & 3, s0 = (p + 1) & 3, sm1 = p;
         P vn[NNB][NSPIN];
 #pragma unroll
@@ -436,7 +442,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
         P o, g;
         chain_site<T, KIND, MODE>(A.a1, A.b1, A.read_w1 != 0, C, ons1, A.vel_scale, alive1, vo, w1, vn, o, g);
         rl(1, p, x, s, sp_t) = o;
-        emit(1, yl[1], inner && y >= y0 && y < y0 + ty, o, g);
+        emit(1, yl[1], inner && (uint32_t)(j - 1) < (uint32_t)ty, o, g);
       } else {
         emit_none(own[p & 1]);
       }
