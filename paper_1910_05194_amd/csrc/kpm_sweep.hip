@@ -282,6 +282,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     uint32_t lev_cnt[KS - 1];
 #pragma unroll
     for (int lev = 2; lev <= KS; ++lev) lev_cnt[lev - 2] = (lev <= nlev) ? (uint32_t)(ty + 2 * KS - 2 * lev + 1) : 0u;
+    // Level nlev - 1 (stored to out_a) exists when nlev >= 2.
+    const uint32_t a_cnt = (nlev >= 2) ? (uint32_t)ty : 0u;
     // Site data of the rows the levels form, as a shift register.  The
     // centre value and w of a level come from this thread's own cell of the
     // LDS rings (no other thread writes that cell before the read).
@@ -301,8 +303,12 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     // One iteration with phase p = (j - j0) mod 4: set[p % kSets] holds v_n
     // row y0 + j and the site data of row y0 + j - 1.  v_n row y0 + j sits in
     // LDS slot (p + 2) & 3, the rows level l forms at iteration j in slot p.
-    auto row = [&](auto ph, int j) {
+    auto row = [&](auto ph, auto full, int j) {
       constexpr int p = decltype(ph)::value;
+      // A full sweep (nlev == KS, every launch but the recursion's last) has
+      // no level selects: a compile-time level count.
+      constexpr bool FULL = decltype(full)::value;
+      const int nl = FULL ? KS : nlev;
       RowSet& cur = set[p % kSets];
       RowSet& nxt = set[(p + kPrefetch) % kSets];
       // cur has arrived: everything issued before the last kPrefetch rows'
@@ -357,8 +363,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
           // scratch memory).
           if (lev == KS) o_b = o;
           if (lev == KS - 1) o_a = o;
-          if (nlev < KS) {
-            const bool cb = lev == nlev, ca = lev == nlev - 1;
+          if (!FULL && nl < KS) {
+            const bool cb = lev == nl, ca = lev == nl - 1;
 #pragma unroll
             for (int q = 0; q < 2 * NC; ++q) {
               o_b.v[q] = cb ? o.v[q] : o_b.v[q];
@@ -393,8 +399,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
                                      (uint32_t)(j - 1) < (uint32_t)ty, tv[0], tw[0]);
           rl(1, p, x, s) = o;
           if constexpr (KS == 2) o_a = o;   // a full two-step sweep stores levels 1 and 2
-          if (nlev <= 2) {
-            const bool cb = nlev == 1;
+          if (!FULL && nl <= 2) {
+            const bool cb = nl == 1;
 #pragma unroll
             for (int q = 0; q < 2 * NC; ++q) {
               o_b.v[q] = cb ? o.v[q] : o_b.v[q];
@@ -407,9 +413,8 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       // nlev - 1 two rows higher (a thread stores its interior cells of the
       // tile's own rows; every other store is dropped).
       {
-        const int yb_u = y0 + j - (2 * nlev - 1);
-        const bool own_b = inner && (yb_u >= y0) && (yb_u < y0 + ty);
-        const bool own_a = inner && (nlev >= 2) && (yb_u + 2 >= y0) && (yb_u + 2 < y0 + ty);
+        const bool own_b = inner && (uint32_t)(j - (2 * nl - 1)) < (uint32_t)ty;
+        const bool own_a = inner && (uint32_t)(j - (2 * nl - 3)) < (FULL ? (uint32_t)ty : a_cnt);
         buf_st_pack<T>(row_rsrc(row_ptr(ob, yb, row_bytes), row_bytes), own_b ? lane_b : kOOB, o_b);
         buf_st_pack<T>(row_rsrc(row_ptr(oa, ya, row_bytes), row_bytes), own_a ? lane_b : kOOB, o_a);
       }
@@ -435,12 +440,18 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
       buf_st_pack<T>(rz, kOOB, o_b);
       buf_st_pack<T>(rz, kOOB, o_a);
     }
-    for (int j = j0; j <= j_last; j += 4) {
-      row(std::integral_constant<int, 0>{}, j);
-      row(std::integral_constant<int, 1>{}, j + 1);
-      row(std::integral_constant<int, 2>{}, j + 2);
-      row(std::integral_constant<int, 3>{}, j + 3);
-    }
+    auto march = [&](auto full) {
+      for (int j = j0; j <= j_last; j += 4) {
+        row(std::integral_constant<int, 0>{}, full, j);
+        row(std::integral_constant<int, 1>{}, full, j + 1);
+        row(std::integral_constant<int, 2>{}, full, j + 2);
+        row(std::integral_constant<int, 3>{}, full, j + 3);
+      }
+    };
+    if (nlev == KS)
+      march(std::true_type{});
+    else
+      march(std::false_type{});
     // The tile's sums count for interior threads only (a select: the others' may be NaN).
 #pragma unroll
     for (int l = 0; l < KS; ++l)
