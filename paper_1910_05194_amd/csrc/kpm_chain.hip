@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
     // rows when j - (2 l - 1) is in [0, ty): one unsigned comparison each.
     uint32_t lev_cnt[KS - 1];
 #pragma unroll
-    for (int lev = 2; lev <= KS; ++lev) lev_cnt[lev - 2] = (lev <= nlev) ? (uint32_t)(ty + 2 * KS - 2 * lev + 1) : 0u;
+    for (int lev = 2; lev <= KS; ++lev) lev_cnt[lev - 2] = (lev <= nlev) ? (uint32_t)(ty + 2 * KS - 2 * lev) : 0u;
     T ons_h[NH];
     bool alive_h[NH];
 #pragma unroll

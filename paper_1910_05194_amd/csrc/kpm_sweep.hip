@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
     // belongs to the tile when j - (2 l - 1) is in [0, ty).
     uint32_t lev_cnt[KS - 1];
 #pragma unroll
-    for (int lev = 2; lev <= KS; ++lev) lev_cnt[lev - 2] = (lev <= nlev) ? (uint32_t)(ty + 2 * KS - 2 * lev + 1) : 0u;
+    for (int lev = 2; lev <= KS; ++lev) lev_cnt[lev - 2] = (lev <= nlev) ? (uint32_t)(ty + 2 * KS - 2 * lev) : 0u;
     // Level nlev - 1 (stored to out_a) exists when nlev >= 2.
     const uint32_t a_cnt = (nlev >= 2) ? (uint32_t)ty : 0u;
     // Site data of the rows the levels form, as a shift register.  The

@@ -54,6 +54,23 @@ class Fail(AssertionError):
     pass
 
 
+def _ult(a, b):
+    """(uint32_t)a < (uint32_t)b: a negative a wraps to a large value."""
+    return (a & 0xFFFFFFFF) < (b & 0xFFFFFFFF)
+
+
+def kernel_branches(KS, nlev, ty, j):
+    """The kernel's own forms of a row's uniform conditions: level l (2..KS)
+    works while j - (3 l - 1 - KS), as a 32-bit unsigned value, is below a
+    per-tile count (0 for levels above nlev), level 1 while j <= ty + KS - 1;
+    the row a level forms is one of the tile's while j - (2 l - 1) is below ty."""
+    lev_cnt = {lev: (ty + 2 * KS - 2 * lev) if lev <= nlev else 0 for lev in range(2, KS + 1)}
+    active = {lev: _ult(j - (3 * lev - 1 - KS), lev_cnt[lev]) for lev in range(2, KS + 1)}
+    active[1] = j <= ty + KS - 1
+    in_tile = {lev: _ult(j - (2 * lev - 1), ty) for lev in range(1, KS + 1)}
+    return active, in_tile
+
+
 def simulate(kind, KS, nlev, mode, block, Ew, E, L1, L2, Ty, g, x0, y0, nb, blk, vec):
     ns, nsp = NSUB[kind], NSPIN[kind]
     Tx = block // (ns * nsp * Ew)
@@ -194,6 +211,12 @@ def simulate(kind, KS, nlev, mode, block, Ew, E, L1, L2, Ty, g, x0, y0, nb, blk,
             store_row(t, p & 1, (p + 2) & 3)
             t["w1"], t["s1"] = t["w"][p & 1], t["site"][p & 1]
             fetch(t, (p + 1) & 1, regs["yf"], regs["ys"], j + 1 <= ty + KS - 1)
+        # The kernel's unsigned forms of the conditions below agree with them.
+        k_active, k_in_tile = kernel_branches(KS, nlev, ty, j)
+        for lev in range(1, KS + 1):
+            lo = 3 * lev - 1 - KS if lev >= 2 else j0
+            check(k_active[lev] == (lev <= nlev and lo <= j <= ty + KS + lev - 2), f"level {lev} activity at j={j}")
+            check(k_in_tile[lev] == (y0 <= y0 + j - (2 * lev - 1) < y0 + ty), f"level {lev} row in tile at j={j}")
         barrier()
         for t in th:
             x = t["xlc"] + 1
@@ -330,3 +353,27 @@ def test_chain_model_detects_planted_mistakes():
             simulate = original
     finally:
         simulate = original
+
+
+def test_chain_model_detects_planted_branch_mistakes():
+    """A level count one too large or a tile-row check off by one in the
+    kernel's unsigned forms fails the model."""
+    global kernel_branches
+    import inspect
+    src = inspect.getsource(kernel_branches)
+    mutants = [
+        ("(ty + 2 * KS - 2 * lev) if", "(ty + 2 * KS - 2 * lev + 1) if"),
+        ("_ult(j - (2 * lev - 1), ty)", "_ult(j - (2 * lev - 2), ty)"),
+    ]
+    original = kernel_branches
+    try:
+        for a, b in mutants:
+            assert a in src, a
+            ns = {}
+            exec(compile(src.replace(a, b), "<mutant>", "exec"), globals(), ns)
+            kernel_branches = ns["kernel_branches"]
+            with pytest.raises(AssertionError):
+                run(SPIN, 3, 3, 1, 64, 1, 1, 6, 5, 3)
+            kernel_branches = original
+    finally:
+        kernel_branches = original

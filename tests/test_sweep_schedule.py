@@ -72,6 +72,29 @@ def tile_list(L1, L2, Tx, Ty, KS, n_rg):
     return [(g, x0, y0) for g in range(n_rg) for y0 in range(0, L2, Ty) for x0 in range(0, L1, xstep)]
 
 
+def _ult(a, b):
+    """(uint32_t)a < (uint32_t)b: a negative a wraps to a large value."""
+    return (a & 0xFFFFFFFF) < (b & 0xFFFFFFFF)
+
+
+def kernel_branches(KS, nlev, ty, j):
+    """The kernel's own forms of a row's uniform conditions: per-tile counts
+    and 32-bit unsigned comparisons, and in a full sweep (nlev == KS, its own
+    compile-time branch) the fixed stored levels.  Returns the activity of
+    levels 1..KS, whether the row each level forms lies in the tile, and the
+    row parts of the two store checks."""
+    full = nlev == KS
+    nl = KS if full else nlev
+    lev_cnt = {lev: (ty + 2 * KS - 2 * lev) if lev <= nlev else 0 for lev in range(2, KS + 1)}
+    a_cnt = ty if nlev >= 2 else 0
+    active = {lev: _ult(j - (3 * lev - 1 - KS), lev_cnt[lev]) for lev in range(2, KS + 1)}
+    active[1] = j <= ty + KS - 1
+    in_tile = {lev: _ult(j - (2 * lev - 1), ty) for lev in range(1, KS + 1)}
+    own_b = _ult(j - (2 * nl - 1), ty)
+    own_a = _ult(j - (2 * nl - 3), ty if full else a_cnt)
+    return active, in_tile, own_b, own_a
+
+
 def simulate_tile(kind, KS, nlev, block, Ew, E, L1, L2, Ty, g, x0, y0, nb, stores, dots):
     NSUB = NSUBS[kind]
     Tx = block // (NSUB * Ew)
@@ -202,6 +225,17 @@ def simulate_tile(kind, KS, nlev, block, Ew, E, L1, L2, Ty, g, x0, y0, nb, store
             t.ons_h = [cur[3]] + t.ons_h[:-1]
             t.sets[(p + 1) % 2] = fetch(t, yf, ys, j + 1 <= ty + KS - 1)
         check(yf == wrap(y0 + j + 1) and ys == wrap(y0 + j), f"row registers at j={j}")
+        # The kernel's unsigned forms of the conditions below agree with them.
+        k_active, k_in_tile, k_own_b, k_own_a = kernel_branches(KS, nlev, ty, j)
+        for lev in range(1, KS + 1):
+            lo = 3 * lev - 1 - KS if lev >= 2 else j0
+            hi = ty + KS + lev - 2
+            check(k_active[lev] == (lev <= nlev and lo <= j <= hi), f"level {lev} activity at j={j}")
+            yl = y0 + j - (2 * lev - 1)
+            check(k_in_tile[lev] == (y0 <= yl < y0 + ty), f"level {lev} row in tile at j={j}")
+        yb_u = y0 + j - (2 * nlev - 1)
+        check(k_own_b == (y0 <= yb_u < y0 + ty), f"store b at j={j}")
+        check(k_own_a == (nlev >= 2 and y0 <= yb_u + 2 < y0 + ty), f"store a at j={j}")
         barrier()
         for t in threads:
             x = t.xlc + 1
@@ -393,3 +427,30 @@ def test_model_detects_planted_mistakes():
             simulate_tile = original
     finally:
         simulate_tile = original
+
+
+def test_model_detects_planted_branch_mistakes():
+    """The kernel's unsigned forms of its row conditions are checked against
+    the level ranges: a level count one too large (a level running one
+    iteration past its range) or a store check that ignores a one-level
+    sweep fails the model."""
+    global kernel_branches
+    import inspect
+    src = inspect.getsource(kernel_branches)
+    mutants = [
+        ("(ty + 2 * KS - 2 * lev) if", "(ty + 2 * KS - 2 * lev + 1) if"),
+        ("_ult(j - (2 * nl - 3), ty if full else a_cnt)", "_ult(j - (2 * nl - 3), ty)"),
+    ]
+    original = kernel_branches
+    try:
+        for a, b in mutants:
+            assert a in src, a
+            ns = {}
+            exec(compile(src.replace(a, b), "<mutant>", "exec"), globals(), ns)
+            kernel_branches = ns["kernel_branches"]
+            with pytest.raises(AssertionError):
+                run_config(HONEYCOMB, 4, 4, 64, 1, 1, 7, 5, 3)
+                run_config(HONEYCOMB, 3, 1, 64, 2, 3, 9, 4, 8)
+            kernel_branches = original
+    finally:
+        kernel_branches = original
