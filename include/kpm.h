@@ -543,7 +543,8 @@ int kpm_mlp_eval_loss(kpm_mlp_t* mlp, const float* x, const float* target, const
  * method).  Streams float4 arrays of bytes_per_array bytes with a grid-stride
  * kernel of the given shape: pattern 0 = copy (dst = src), 1 = read-only
  * reduction, 2 = in-place w = 2 v - w (two reads and one write per element,
- * the memory pattern of a Chebyshev step).  nontemporal != 0 uses streaming
+ * the memory pattern of a Chebyshev step), 3 = copy with four elements per
+ * thread and iteration, loads before stores.  nontemporal != 0 uses streaming
  * loads/stores.  Allocates and frees its own arrays; synchronises the stream.
  * Outputs: average milliseconds per launch over iters launches (after one
  * warm-up launch) and the bytes moved per launch.

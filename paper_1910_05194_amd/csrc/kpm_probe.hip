@@ -6,6 +6,8 @@
 //   0 copy   dst = src                      (1 read, 1 write per element)
 //   1 read   acc += src                     (1 read)
 //   2 rmw    w = 2 v - w  (in place)        (2 reads, 1 write: the Chebyshev step's pattern)
+//   3 copy   dst = src, four elements per thread and iteration, all four
+//            loads issued before the stores (more bytes in flight per wave)
 
 #include "kpm_internal.h"
 
@@ -38,6 +40,23 @@ __global__ void probe_read(const f32x4* __restrict__ src, float* __restrict__ ou
 }
 
 template <bool NT>
+__global__ void probe_copy4(const f32x4* __restrict__ src, f32x4* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    f32x4 x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = NT ? __builtin_nontemporal_load(src + i + k * stride) : src[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if constexpr (NT) __builtin_nontemporal_store(x[k], dst + i + k * stride);
+      else dst[i + k * stride] = x[k];
+    }
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+template <bool NT>
 __global__ void probe_rmw(const f32x4* __restrict__ v, f32x4* __restrict__ w, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     f32x4 a, b;
@@ -61,7 +80,7 @@ extern "C" int kpm_bandwidth_probe(int32_t pattern, int64_t bytes_per_array, int
                                    double* bytes_moved_per_iter) {
   using namespace kpm;
   clear_error();
-  KPM_CHECK_ARG(pattern >= 0 && pattern <= 2, "pattern must be 0 (copy), 1 (read) or 2 (rmw)");
+  KPM_CHECK_ARG(pattern >= 0 && pattern <= 3, "pattern must be 0 (copy), 1 (read), 2 (rmw) or 3 (copy, 4 per thread)");
   KPM_CHECK_ARG(bytes_per_array >= 16 && iters >= 1, "need bytes_per_array >= 16 and iters >= 1");
   KPM_CHECK_ARG(grid >= 1 && block >= 64 && block <= 1024 && block % 64 == 0, "bad launch shape");
   KPM_CHECK_ARG(ms_per_iter && bytes_moved_per_iter, "NULL output");
@@ -90,6 +109,9 @@ extern "C" int kpm_bandwidth_probe(int32_t pattern, int64_t bytes_per_array, int
     if (pattern == 0) {
       if (nt) hipLaunchKernelGGL(probe_copy<true>, dim3(grid), dim3(block), 0, s, a, b, n);
       else hipLaunchKernelGGL(probe_copy<false>, dim3(grid), dim3(block), 0, s, a, b, n);
+    } else if (pattern == 3) {
+      if (nt) hipLaunchKernelGGL(probe_copy4<true>, dim3(grid), dim3(block), 0, s, a, b, n);
+      else hipLaunchKernelGGL(probe_copy4<false>, dim3(grid), dim3(block), 0, s, a, b, n);
     } else if (pattern == 1) {
       if (nt) hipLaunchKernelGGL(probe_read<true>, dim3(grid), dim3(block), 0, s, a, red, n);
       else hipLaunchKernelGGL(probe_read<false>, dim3(grid), dim3(block), 0, s, a, red, n);
@@ -113,7 +135,7 @@ extern "C" int kpm_bandwidth_probe(int32_t pattern, int64_t bytes_per_array, int
     st = (e == hipErrorOutOfMemory) ? KPM_E_NOMEM : KPM_E_DEVICE;
   } else {
     *ms_per_iter = ms / iters;
-    *bytes_moved_per_iter = (double)n * 16 * (pattern == 0 ? 2 : (pattern == 1 ? 1 : 3));
+    *bytes_moved_per_iter = (double)n * 16 * ((pattern == 0 || pattern == 3) ? 2 : (pattern == 1 ? 1 : 3));
   }
   cleanup();
   return st;

@@ -378,3 +378,14 @@ def test_lorentz_and_cpgf_reconstruction(K):
             K.reconstruct_cpgf(mean_o, E, lat.e_min, lat.e_max, bad)
         with pytest.raises(K.KPMError):
             K.reconstruct_lorentz(mean_o, E, lat.e_min, lat.e_max, bad)
+
+
+@pytest.mark.parametrize("pattern,per_elem", [(0, 2), (1, 1), (2, 3), (3, 2)], ids=["copy", "read", "rmw", "copy4"])
+def test_bandwidth_probe_patterns(K, pattern, per_elem):
+    """The HBM probe's patterns (measurement support for the roofline) on an
+    array whose element count leaves a tail past the unrolled loop: bytes per
+    launch as stated, a positive time."""
+    nbytes = (1 << 20) + 3 * 16
+    r = K.bandwidth_probe(pattern, nbytes, iters=2, grid=64, block=256, nontemporal=pattern == 3)
+    assert r["bytes"] == per_elem * nbytes
+    assert r["ms"] > 0 and np.isfinite(r["GBs"])
