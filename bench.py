@@ -294,7 +294,7 @@ def leg_mlp(kpm, wl, np, n_train=20000, L_train=1024, R_train=2, epochs=200, n_e
     # (fresh random vectors for those: their error against the reference is
     # the stochastic-trace noise of two independent full runs).
     t0 = time.perf_counter()
-    tables, ok_lp, _ = ex.learned_moments(net, evl, 16, 777, n_check=n_chk, overlap_tol=1.0, neg_tol=0.05, batch=4)
+    tables, ok_lp, z_lp = ex.learned_moments(net, evl, 16, 777, n_check=n_chk, z_tol=3.0, neg_tol=0.05, batch=4)
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     e_lp = []
@@ -307,6 +307,13 @@ def leg_mlp(kpm, wl, np, n_train=20000, L_train=1024, R_train=2, epochs=200, n_e
                       e_min=-1.01 * (8.1 + W / 2), e_max=1.01 * (8.1 + W / 2))
            for j, (W, p) in enumerate([(6.0, 0.0), (10.0, 0.0), (1.0, 0.10), (2.0, 0.25)])]
     ov_ood = ex.overlap_error(net, ex.generate_moments(ood, n_in + n_chk, 16, 555, batch=4), n_chk)
+    t_ood, ok_ood, z_ood = ex.learned_moments(net, ood, 16, 555, n_check=n_chk, z_tol=3.0, neg_tol=0.05, batch=4)
+    full_ood = ex.generate_moments(ood, M, 16, 555, batch=4)
+    e_ood = []
+    for i, L in enumerate(ood):
+        E = wl.energy_grid(L.e_min, L.e_max, 1024)
+        rf = kpm.reconstruct_jackson(full_ood[i], E, L.e_min, L.e_max)
+        e_ood.append(ex.dos_error(kpm.reconstruct_jackson(t_ood[i], E, L.e_min, L.e_max), rf))
     net.close()
     n_acc = int(sum(ok_lp))
     acc_i = [i for i in range(n_eval) if ok_lp[i]]
@@ -325,9 +332,14 @@ def leg_mlp(kpm, wl, np, n_train=20000, L_train=1024, R_train=2, epochs=200, n_e
             "dos_error_learned_path_fallbacks": float(np.mean([e_lp[i] for i in fb_i])) if fb_i else None,
             "recursion_steps_full": M // 2, "recursion_steps_truncated": (n_in + n_chk) // 2,
             "step_saving": (M // 2) / ((n_in + n_chk) // 2),
-            "overlap_error_eval": [round(float(x), 4) for x in ov],
-            "ood_overlap_error": [round(float(x), 4) for x in ov_ood],
-            "ood_rejected": int(np.sum(ov_ood > 1.0)), "ood_total": len(ood)}
+            "acceptance": "overlap z <= 3 (prediction vs the 64 computed orders past the input, in units of "
+                          "their statistical error 1/sqrt(N R)), Jackson DOS >= -5 % of its maximum, |mu| <= 1",
+            "overlap_z_eval": [round(float(x), 3) for x in z_lp],
+            "overlap_rel_error_eval": [round(float(x), 4) for x in ov],
+            "ood_overlap_z": [round(float(x), 3) for x in z_ood],
+            "ood_overlap_rel_error": [round(float(x), 4) for x in ov_ood],
+            "ood_rejected": int(len(ood) - sum(ok_ood)), "ood_total": len(ood),
+            "ood_dos_error_as_run": [round(float(x), 4) for x in e_ood]}
 
 
 def step_kernel_source_hash() -> str:

@@ -535,6 +535,19 @@ int kpm_mlp_fit_scaling(kpm_mlp_t* mlp, const float* x, const float* target, int
  * loss_dev_out.  All pointers device; work enqueued on hip_stream. */
 int kpm_mlp_rel_error(kpm_mlp_t* mlp, const float* x, const double* ref, const float* weights, int32_t batch,
                       int32_t n_cmp, int32_t use_bf16, double* err, void* hip_stream);
+/* Acceptance measure against the statistical error of the reference moments
+ * (Sec. 2(c), the stochastic trace: its error falls as 1/sqrt(R N)).  For
+ * random-phase vectors the variance of one vector's estimate of
+ * Tr T_n(H~)/N is sum_{i != j} |T_n,ij|^2 / N^2 <= Tr T_n(H~)^2 / N^2 <= 1/N,
+ * so the mean over R vectors has a standard error of at most 1/sqrt(N R);
+ * noise [batch] (FP64, device) holds that scale per row.  With the same x,
+ * ref, weights and use_bf16 as kpm_mlp_rel_error:
+ *   z[b] = ||w (y_b - ref_b)|| / (noise_b ||w||)   (FP64, [batch]),
+ * the weighted RMS deviation of the prediction in units of the reference's
+ * standard error (about 1 when the prediction is within the reference's
+ * noise).  All pointers device; work enqueued on hip_stream. */
+int kpm_mlp_noise_z(kpm_mlp_t* mlp, const float* x, const double* ref, const double* noise, const float* weights,
+                    int32_t batch, int32_t n_cmp, int32_t use_bf16, double* z, void* hip_stream);
 int kpm_mlp_eval_loss(kpm_mlp_t* mlp, const float* x, const float* target, const float* weights, int32_t batch,
                       int32_t use_bf16, double* loss_dev_out, void* hip_stream);
 

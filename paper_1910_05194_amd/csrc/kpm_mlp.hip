@@ -128,9 +128,11 @@ __global__ void mlp_loss_kernel(const float* Y, const float* T, const float* w, 
 }
 
 // err[b] = sqrt(sum_j (w_j (Y_bj - R_bj))^2) / sqrt(sum_j (w_j R_bj)^2) over the
-// first n_cmp of the n_out columns of Y; one workgroup per row, FP64 sums in a
-// fixed-order tree.
-__global__ void rel_error_kernel(const float* Y, int n_out, const double* R, int n_cmp, const float* w, double* err) {
+// first n_cmp of the n_out columns of Y, or with noise given,
+// sqrt(sum_j (w_j (Y_bj - R_bj))^2) / (noise_b sqrt(sum_j w_j^2)); one
+// workgroup per row, FP64 sums in a fixed-order tree.
+__global__ void rel_error_kernel(const float* Y, int n_out, const double* R, int n_cmp, const float* w,
+                                 const double* noise, double* err) {
   __shared__ double num[256], den[256];
   const int b = blockIdx.x;
   double a = 0.0, d = 0.0;
@@ -138,7 +140,7 @@ __global__ void rel_error_kernel(const float* Y, int n_out, const double* R, int
     const double r = R[(int64_t)b * n_cmp + j], wj = w[j];
     const double e = wj * ((double)Y[(int64_t)b * n_out + j] - r);
     a += e * e;
-    d += (wj * r) * (wj * r);
+    d += noise ? wj * wj : (wj * r) * (wj * r);
   }
   num[threadIdx.x] = a;
   den[threadIdx.x] = d;
@@ -150,7 +152,7 @@ __global__ void rel_error_kernel(const float* Y, int n_out, const double* R, int
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) err[b] = sqrt(num[0]) / fmax(sqrt(den[0]), 1e-300);
+  if (threadIdx.x == 0) err[b] = sqrt(num[0]) / fmax((noise ? noise[b] : 1.0) * sqrt(den[0]), 1e-300);
 }
 
 __global__ void sum_partials_kernel(const double* partial, int n, double* out) {
@@ -506,7 +508,22 @@ int kpm_mlp_rel_error(kpm_mlp_t* N, const float* x, const double* ref, const flo
   KPM_TRY(mlp_reserve(N, batch));
   hipStream_t s = (hipStream_t)hip_stream;
   forward_scaled(N, x, batch, use_bf16 != 0, s);
-  hipLaunchKernelGGL(rel_error_kernel, dim3(batch), dim3(256), 0, s, N->Y, N->n_out, ref, n_cmp, weights, err);
+  hipLaunchKernelGGL(rel_error_kernel, dim3(batch), dim3(256), 0, s, N->Y, N->n_out, ref, n_cmp, weights,
+                     (const double*)nullptr, err);
+  KPM_TRY_HIP(hipGetLastError());
+  return KPM_OK;
+}
+
+int kpm_mlp_noise_z(kpm_mlp_t* N, const float* x, const double* ref, const double* noise, const float* weights,
+                    int32_t batch, int32_t n_cmp, int32_t use_bf16, double* z, void* hip_stream) {
+  using namespace kpm;
+  clear_error();
+  KPM_CHECK_ARG(N && x && ref && noise && weights && z && batch >= 1, "bad arguments");
+  KPM_CHECK_ARG(n_cmp >= 1 && n_cmp <= N->n_out, "n_cmp must be in [1, n_out]");
+  KPM_TRY(mlp_reserve(N, batch));
+  hipStream_t s = (hipStream_t)hip_stream;
+  forward_scaled(N, x, batch, use_bf16 != 0, s);
+  hipLaunchKernelGGL(rel_error_kernel, dim3(batch), dim3(256), 0, s, N->Y, N->n_out, ref, n_cmp, weights, noise, z);
   KPM_TRY_HIP(hipGetLastError());
   return KPM_OK;
 }

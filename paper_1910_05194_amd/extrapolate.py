@@ -125,6 +125,31 @@ def overlap_error(net: "kpm.MLP", mu_head, n_check: int = 64, bf16: bool = True)
     return net.rel_error(x, ref, g, bf16=bf16).cpu().numpy()
 
 
+def stat_noise(lattices: Sequence, num_random: int) -> np.ndarray:
+    """Upper bound 1/sqrt(N R) of the standard error of mean moments from R
+    random-phase vectors on a lattice of N orbitals (the bound of
+    kpm_mlp_noise_z; vacancies leave fewer active orbitals, N (1 - p), which
+    raises it by 1/sqrt(1 - p))."""
+    return np.array([1.0 / math.sqrt(L.L1 * L.L2 * L.n_orb_cell * num_random) for L in lattices])
+
+
+def overlap_z(net: "kpm.MLP", mu_head, noise, n_check: int = 64, bf16: bool = True) -> np.ndarray:
+    """Kernel-weighted RMS deviation of the network's prediction on orders
+    n_in .. n_in+n_check-1 from the moments the recursion computed, in units of
+    those moments' statistical error (``stat_noise``): about 1 when the
+    prediction agrees with the recursion within its noise, larger when the
+    network is off by more than the recursion can resolve."""
+    import torch
+    mu_head = np.asarray(mu_head, dtype=np.float64)
+    n_in = net.n_in
+    assert mu_head.shape[1] >= n_in + n_check and n_check <= net.n_out
+    x = torch.as_tensor(mu_head[:, :n_in], dtype=torch.float32, device="cuda").contiguous()
+    ref = torch.as_tensor(mu_head[:, n_in:n_in + n_check], dtype=torch.float64, device="cuda").contiguous()
+    nz = torch.as_tensor(np.asarray(noise, dtype=np.float64), device="cuda").contiguous()
+    g = loss_weights(n_in, net.n_out, device="cuda")[:n_check].to(torch.float32)
+    return net.noise_z(x, ref, nz, g, bf16=bf16).cpu().numpy()
+
+
 def fit_acceptance(net: "kpm.MLP", mu_val, n_check: int = 64, factor: float = 2.0) -> float:
     """Acceptance threshold on the overlap error: factor x its 99th percentile on held-out tables."""
     e = overlap_error(net, mu_val, n_check)
@@ -172,28 +197,29 @@ def splice(net: "kpm.MLP", mu_head, bf16: bool = True) -> np.ndarray:
 
 
 def learned_moments(net: "kpm.MLP", lattices: Sequence, num_random: int, vector_seed: int, n_check: int = 64,
-                    overlap_tol: float = 1.0, neg_tol: float = 0.05, n_energies: int = 1024, batch: int = 64):
+                    z_tol: float = 3.0, neg_tol: float = 0.05, n_energies: int = 1024, batch: int = 64):
     """Moment tables [n, n_in + n_out] from the truncated recursion plus the network,
     with the full recursion as fallback.
 
     The recursion computes n_in + n_check moments per lattice; the network
-    extends each table; a table is kept when it passes ``accept`` (overlap
-    error on the n_check computed orders at most overlap_tol, a Jackson DOS on
-    n_energies midpoints that is non-negative within neg_tol, |mu_n| <= 1);
+    extends each table; a table is kept when it passes ``accept`` (the
+    network's deviation from the n_check computed orders, ``overlap_z`` in
+    units of their statistical error, at most z_tol; a Jackson DOS on
+    n_energies midpoints that is non-negative within neg_tol; |mu_n| <= 1);
     the lattices that fail are recomputed by the full recursion.  The random
     vectors are keyed by a lattice's place in its batch, so a fallback for
     every lattice reproduces the full run exactly, while a partial one draws
     fresh vectors for the rejected lattices.  Returns (tables, accepted flags,
-    overlap errors).
+    overlap z).
     """
     M = net.n_in + net.n_out
     head = generate_moments(lattices, net.n_in + n_check, num_random, vector_seed, batch=batch)
-    ov = overlap_error(net, head, n_check)
+    ov = overlap_z(net, head, stat_noise(lattices, num_random), n_check)
     out = splice(net, head)
     ok = []
     for i, L in enumerate(lattices):
         E = L.e_min + (np.arange(n_energies) + 0.5) * (L.e_max - L.e_min) / n_energies
-        ok.append(accept(out[i:i + 1], L.e_min, L.e_max, E, overlap=ov[i:i + 1], overlap_tol=overlap_tol,
+        ok.append(accept(out[i:i + 1], L.e_min, L.e_max, E, overlap=ov[i:i + 1], overlap_tol=z_tol,
                          neg_tol=neg_tol)[0])
     bad = [i for i, a in enumerate(ok) if not a]
     if bad:

@@ -134,6 +134,8 @@ def _load():
         "kpm_mlp_gradients": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P, _D, _P]),
         "kpm_mlp_fit_scaling": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, _P]),
         "kpm_mlp_rel_error": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P]),
+        "kpm_mlp_noise_z": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                           _P]),
         "kpm_mlp_eval_loss": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
         "kpm_kernel_factors": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                               ctypes.c_int32, _P, ctypes.c_int32, _P]),
@@ -708,6 +710,20 @@ class MLP:
         _check(LIB.kpm_mlp_rel_error(self._h, x.data_ptr(), ref.data_ptr(), weights.data_ptr(), x.shape[0],
                                      ref.shape[1], 1 if bf16 else 0, err.data_ptr(), _stream_handle(stream)))
         return err
+
+    def noise_z(self, x, ref, noise, weights, bf16: bool = True, stream=None):
+        """kpm_mlp_noise_z: ||w (y - ref)|| / (noise ||w||) per row on the first ref.shape[1] outputs.
+        x [B, n_in] float32, ref [B, n_cmp] float64, noise [B] float64, weights [n_cmp] float32 (device)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        x, ref, noise, weights = x.contiguous(), ref.contiguous(), noise.contiguous(), weights.contiguous()
+        assert x.dtype == torch.float32 and ref.dtype == torch.float64 and weights.dtype == torch.float32
+        assert noise.dtype == torch.float64 and noise.shape == (x.shape[0],)
+        z = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+        _check(LIB.kpm_mlp_noise_z(self._h, x.data_ptr(), ref.data_ptr(), noise.data_ptr(), weights.data_ptr(),
+                                   x.shape[0], ref.shape[1], 1 if bf16 else 0, z.data_ptr(), _stream_handle(stream)))
+        return z
 
     def eval_loss(self, x, target, weights, bf16: bool = False, stream=None):
         """kpm_mlp_eval_loss: the weighted training loss of the network's output (no update), a device double."""

@@ -134,6 +134,9 @@ def test_argument_validation_without_device():
         assert e.value.code == kpm.KPM_E_INVALID
     with pytest.raises(kpm.KPMError):
         kpm.MLP(0, 16, 16)
+    # The acceptance measures reject NULL handles and arrays before touching a device.
+    assert kpm.LIB.kpm_mlp_noise_z(None, None, None, None, None, 1, 1, 0, None, None) == kpm.KPM_E_INVALID
+    assert kpm.LIB.kpm_mlp_rel_error(None, None, None, None, 1, 1, 0, None, None) == kpm.KPM_E_INVALID
     psi = np.zeros((1, lat.n_orbitals), dtype=np.complex128)
     for args, msg in (((1.0, 1, 3), "num_moments"), ((0.0, 40, 3), "dt"), ((1.0, 40, 0), "num_points")):
         with pytest.raises(kpm.KPMError) as e:

@@ -185,7 +185,7 @@ def test_learned_extrapolation_gains_over_truncation_and_falls_back(K):
     ex.train(net, mu, epochs=120, batch=64, lr=1e-3)
     evl = [wl.mlp_training_lattice(i, L=256, seed=777) for i in range(8)]
     full = ex.generate_moments(evl, M, 32, 3, batch=64)
-    tables, ok, ov = ex.learned_moments(net, evl, 32, 3, n_check=n_chk, overlap_tol=np.inf, neg_tol=np.inf)
+    tables, ok, ov = ex.learned_moments(net, evl, 32, 3, n_check=n_chk, z_tol=np.inf, neg_tol=np.inf)
     assert all(ok)
     # Every computed order is kept; the network only fills the rest.
     assert np.array_equal(tables[:, :n_in + n_chk], full[:, :n_in + n_chk])
@@ -199,7 +199,7 @@ def test_learned_extrapolation_gains_over_truncation_and_falls_back(K):
     print(f"E_trunc({n_in + n_chk}) {np.mean(e_tr):.4f}  E_mlp {np.mean(e_ml):.4f}  gain {gain:.2f}  overlap {np.round(ov, 3)}")
     assert gain > 1.2
     # Rejecting everything hands every lattice to the full recursion (same vectors).
-    fb, ok0, _ = ex.learned_moments(net, evl, 32, 3, n_check=n_chk, overlap_tol=0.0)
+    fb, ok0, _ = ex.learned_moments(net, evl, 32, 3, n_check=n_chk, z_tol=0.0)
     assert not any(ok0)
     assert np.array_equal(fb, full)
     net.close()
@@ -224,8 +224,8 @@ def test_kernel_factors_match_oracle(K):
 
 
 def test_rel_error_and_eval_loss_match_oracle(K):
-    """kpm_mlp_rel_error (the overlap error of the acceptance check) and
-    kpm_mlp_eval_loss (the validation loss) against the same quantities
+    """kpm_mlp_rel_error and kpm_mlp_noise_z (the overlap measures of the
+    acceptance check) and kpm_mlp_eval_loss (the validation loss) against the same quantities
     computed from the FP64 oracle's forward pass on the same weights: the
     FP32 forward's relative error is <= 1e-5 (see above), so both agree to
     ~1e-5 relative; with the fitted standardisation as well."""
@@ -243,6 +243,13 @@ def test_rel_error_and_eval_loss_match_oracle(K):
     got = net.rel_error(xd, torch.tensor(ref, device="cuda"), wd[:n_cmp], bf16=False).cpu().numpy()
     print("rel_error max rel dev", np.max(np.abs(got - want) / want))
     assert np.max(np.abs(got - want) / want) <= 1e-3
+    # kpm_mlp_noise_z: the same deviation over the per-row noise times ||w||.
+    noise = np.random.default_rng(3).uniform(1e-4, 1e-2, 48)
+    want_z = np.sqrt(np.sum((wc * (Y[:, :n_cmp] - ref)) ** 2, 1)) / (noise * np.sqrt(np.sum(wc ** 2)))
+    got_z = net.noise_z(xd, torch.tensor(ref, device="cuda"), torch.tensor(noise, device="cuda"), wd[:n_cmp],
+                        bf16=False).cpu().numpy()
+    print("noise_z max rel dev", np.max(np.abs(got_z - want_z) / want_z))
+    assert np.max(np.abs(got_z - want_z) / want_z) <= 1e-3
     L = omlp.loss(Y, T.astype(np.float64), w.astype(np.float64))
     got_l = float(net.eval_loss(xd, td, wd).item())
     print("eval_loss", got_l, "oracle", L)
