@@ -57,7 +57,7 @@ extern "C" {
 #define KPM_E_NOMEM (-2)        /* device allocation failed */
 #define KPM_E_DEVICE (-3)       /* HIP runtime error */
 #define KPM_E_SPECTRUM (-4)     /* |mu_n| > 1 + 1e-6 or non-finite: the bounds do not enclose the spectrum */
-#define KPM_E_UNSUPPORTED (-5)  /* valid request outside what this build implements */
+#define KPM_E_UNSUPPORTED (-5)  /* valid request outside what the library implements */
 
 #define KPM_HONEYCOMB 0
 #define KPM_HONEYCOMB_SPIN 1
