@@ -114,7 +114,7 @@ def test_graphene_4096_with_field_full_size(K):
     mu32, mu64 = mu32.cpu().numpy()[0], mu64.cpu().numpy()[0]
     d = np.max(np.abs(mu32 - mu64))
     print(f"field, full size: max |mu_sweep_fp32 - mu_ring_fp64| = {d:.3e}")
-    assert d <= 4 * (M / 2) * 3e-7
+    assert d <= fp32_moment_bound(0, L * L * 2)
     nmax = 8
     ref = _oracle_prefix(lat, par64, [0], nmax)
     assert np.max(np.abs(mu64[0, :nmax] - ref[0])) <= 1e-10
