@@ -130,6 +130,37 @@ def test_stochastic_trace_within_error():
     assert np.all(np.abs(mu[1:] - mu_exact[1:]) <= 5 * sem[1:] + 1e-12)
 
 
+def test_random_phase_variance_bound():
+    """The statistical error behind the learned path's acceptance test: for
+    random-phase vectors one vector's estimate of mu_n = Tr T_n(H~)/N has
+    variance sum_{i != j} |T_n,ij|^2 / N^2 (the phases of different orbitals
+    are independent and uniform), at most Tr T_n(H~)^2 / N^2 = (1 + mu_2n) /
+    (2 N) <= 1/N.  Exact variances from dense T_n on a disordered lattice with
+    vacancies against the bound, and the sample variance of 1600 vectors'
+    moments against the exact variance (the spread of a sample variance of
+    1600 draws is about 3.5 %)."""
+    lat = wl.Lattice(kind=wl.HONEYCOMB, L1=6, L2=5, t=-2.7, anderson_w=1.5, vacancy_p=0.05, disorder_seed=3)
+    M, R = 12, 1600
+    par = wl.DosParams(num_moments=M, num_random=R, vector_seed=11)
+    mu_r, _, model = kpm.dos_moments(lat, par)
+    N = model.n_active
+    Ht = kpm.rescale(model.H, lat.e_min, lat.e_max).toarray()
+    T = [np.eye(N), Ht.copy()]
+    for _ in range(2, 2 * M):
+        T.append(2 * Ht @ T[-1] - T[-2])
+    mu_exact = np.array([np.trace(t).real / N for t in T])
+    for n in range(1, M):
+        off = np.sum(np.abs(T[n]) ** 2) - np.sum(np.abs(np.diag(T[n])) ** 2)
+        var = off / N ** 2
+        assert abs(np.sum(np.abs(T[n]) ** 2) / N ** 2 - (1 + mu_exact[2 * n]) / (2 * N)) < 1e-12
+        assert var <= (1 + mu_exact[2 * n]) / (2 * N) + 1e-15 <= 1.0 / N + 1e-15
+        assert abs(np.var(mu_r[:, n], ddof=1) / var - 1) < 0.2, (n, np.var(mu_r[:, n], ddof=1), var)
+    # A planted mistake, the diagonal counted in the variance, fails the sample
+    # comparison at n = 2 (where the diagonal holds 40 % of ||T_2||_F^2).
+    wrong = np.sum(np.abs(T[2]) ** 2) / N ** 2
+    assert abs(np.var(mu_r[:, 2], ddof=1) / wrong - 1) >= 0.2
+
+
 def test_jackson_kernel_properties():
     for M in [2, 16, 256, 2048]:
         g = kpm.jackson(M)
