@@ -83,7 +83,10 @@ typedef struct kpm_lattice_t {
   double anderson_w;       /* W >= 0, eV */
   double vacancy_p;        /* 0 <= p < 1 */
   uint64_t disorder_seed;
-  double e_min, e_max;     /* spectrum bounds used for the rescaling, eV, e_min < e_max */
+  double e_min, e_max;     /* spectrum bounds used for the rescaling, eV, e_min < e_max; rejected
+                              (KPM_E_INVALID) when they cut into the Gershgorin interval [-G, G],
+                              G = W/2 + |exchange| + Z|t| + 2|rashba| (Z = 3 honeycomb, 4 square),
+                              by more than (e_max - e_min)/8; tighter bounds give KPM_E_SPECTRUM */
   double exchange;         /* Delta_ex, eV: + Delta_ex on spin up, - on spin down (eq. HQAHE; KPM_HONEYCOMB_SPIN
                               only, else 0) */
 } kpm_lattice_t;

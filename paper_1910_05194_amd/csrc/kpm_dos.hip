@@ -872,8 +872,22 @@ static int validate_lattice(const kpm_lattice_t& L, int idx) {
     const double q = L.flux * L.L1;
     KPM_CHECK_ARG(std::fabs(q - std::round(q)) < 1e-9, "lattice %d: flux*L1 must be an integer (got %.12g)", idx, q);
   }
-  // Bounds that are too tight are detected from the moments themselves
-  // (|mu_n| <= 1 must hold when the rescaled spectrum lies in [-1, 1]).
+  // Gershgorin: every eigenvalue lies within G = max_i (|H_ii| + sum_j |H_ij|)
+  // = W/2 + |exchange| + Z |t| + 2 |rashba| of zero (Z = 3 bonds per site on
+  // the honeycomb lattices, 4 on the square one; a spinful bond's spin-flip
+  // entry has magnitude 2 |rashba| / 3; Peierls phases and vacancies do not
+  // raise a row sum).  The interval is rarely reached (disorder and spin-orbit
+  // terms do not add up at the band edge), so bounds may cut into it by a
+  // quarter of their half-width; tighter bounds are detected from the moments
+  // themselves (|mu_n| <= 1 must hold when the rescaled spectrum lies in
+  // [-1, 1]).
+  const double Z = (L.kind == KPM_SQUARE) ? 4.0 : 3.0;
+  const double G = 0.5 * L.anderson_w + std::fabs(L.exchange) + Z * std::fabs(L.t) + 2.0 * std::fabs(L.rashba);
+  const double slack = 0.125 * (L.e_max - L.e_min);
+  KPM_CHECK_ARG(-G >= L.e_min - slack && G <= L.e_max + slack,
+                "lattice %d: spectrum bounds [%g, %g] eV cut into the Gershgorin interval [%g, %g] eV by more "
+                "than a quarter of their half-width",
+                idx, L.e_min, L.e_max, -G, G);
   return KPM_OK;
 }
 

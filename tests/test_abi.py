@@ -82,8 +82,10 @@ def test_argument_validation_without_device():
         ([lat.replace(flux=0.1)], par, "flux*L1"),
         ([lat.replace(kind=wl.SQUARE, flux=1 / 64)], par, "square"),
         ([lat.replace(rashba=0.1)], par, "Rashba"),
+        ([lat.replace(e_min=-6.0, e_max=6.0)], par, "Gershgorin"),
+        ([lat.replace(e_min=-3.0, e_max=12.0)], par, "Gershgorin"),
         ([lat.replace(vacancy_p=1.0)], par, "vacancy_p"),
-        ([lat, lat.replace(kind=wl.SQUARE)], par, "same kind"),
+        ([lat, lat.replace(kind=wl.SQUARE, e_min=-11.5, e_max=11.5)], par, "same kind"),
         ([lat], par.replace(num_moments=1), "num_moments"),
         ([lat], par.replace(num_random=0), "num_random"),
         ([lat], par.replace(precision=7), "precision"),
@@ -95,6 +97,12 @@ def test_argument_validation_without_device():
                 fn(lats, p)
             assert e.value.code == kpm.KPM_E_INVALID
             assert msg in str(e.value), (fn.__name__, msg, str(e.value))
+    # Bounds within a quarter of their half-width of the Gershgorin radius
+    # (8.6 eV) pass validation (without a device the call then fails otherwise).
+    try:
+        kpm.moments_dos([lat.replace(e_min=-7.6, e_max=7.6)], par.replace(num_moments=8))
+    except kpm.KPMError as e:
+        assert e.code != kpm.KPM_E_INVALID, str(e)
     # The allocation-free form rejects a workspace beyond its static array
     # before touching a device: 2M orbitals x 4 complex128 vectors x 2 buffers.
     with pytest.raises(kpm.KPMError) as e:

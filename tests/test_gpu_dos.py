@@ -173,11 +173,16 @@ def test_large_r_groups(K):
 
 
 def test_spectrum_escape_detected(K):
+    """Bounds inside the band: a quarter of the half-width past the Gershgorin
+    radius (8.6 eV here) passes validation and the escape shows in the moments
+    (the band edge is near 8.1 eV); farther inside, validation rejects them."""
     lat, par = wl.graphene_small()
-    lat = lat.replace(e_min=-6.0, e_max=6.0)      # clean graphene band edge is 8.1 eV
     with pytest.raises(K.KPMError) as e:
-        K.moments_dos([lat], par.replace(num_moments=128))
+        K.moments_dos([lat.replace(e_min=-7.6, e_max=7.6)], par.replace(num_moments=128))
     assert e.value.code == K.KPM_E_SPECTRUM
+    with pytest.raises(K.KPMError) as e:
+        K.moments_dos([lat.replace(e_min=-6.0, e_max=6.0)], par.replace(num_moments=128))
+    assert e.value.code == K.KPM_E_INVALID and "Gershgorin" in str(e.value)
 
 
 def test_device_outputs_and_stream(K):
