@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <vector>
 
 namespace kpm {
@@ -368,7 +369,11 @@ int kpm_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out, uint64_t seed,
   *out = nullptr;
   KPM_CHECK_ARG(n_in >= 1 && n_hidden >= 1 && n_out >= 1 && n_in <= 65536 && n_hidden <= 65536 && n_out <= 65536,
                 "layer sizes must be in [1, 65536]");
-  kpm_mlp* N = new kpm_mlp();
+  kpm_mlp* N = new (std::nothrow) kpm_mlp();
+  if (!N) {
+    set_error("kpm_mlp_create: out of host memory");
+    return KPM_E_NOMEM;
+  }
   N->n_in = n_in;
   N->n_hid = n_hidden;
   N->n_out = n_out;

@@ -702,7 +702,13 @@ extern "C" int kpm_reconstruct_sigma_optical(const double* gamma_nm, const doubl
   KPM_CHECK_ARG(n_theta >= 0 && n_theta <= (1 << 20), "n_theta must be in [0, 2^20]");
   hipStream_t s = (hipStream_t)hip_stream;
   // The frequencies set the table shifts: they are needed on the host.
-  std::vector<double> om((size_t)K);
+  std::vector<double> om;
+  try {
+    om.resize((size_t)K);
+  } catch (...) {
+    set_error("kpm_reconstruct_sigma_optical: out of host memory");
+    return KPM_E_NOMEM;
+  }
   if (on_device) {
     KPM_TRY_HIP(hipMemcpyAsync(om.data(), omegas_ev, sizeof(double) * K, hipMemcpyDeviceToHost, s));
     KPM_TRY_SYNC(hipStreamSynchronize(s));
