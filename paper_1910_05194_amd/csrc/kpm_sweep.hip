@@ -448,7 +448,10 @@ __global__ void __launch_bounds__(kMaxStepBlock) sweep_kernel(SweepArgs<T> A) {
         row(std::integral_constant<int, 3>{}, full, j + 3);
       }
     };
-    if (nlev == KS)
+    // Five-step sweeps keep one copy of the loop: a second would push them
+    // further into scratch memory (their rings and levels already use most
+    // of the registers).
+    if (KS < 5 && nlev == KS)
       march(std::true_type{});
     else
       march(std::false_type{});
