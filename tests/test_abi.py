@@ -178,3 +178,25 @@ def test_fault_injection_hook_without_device():
         kpm.kernel_factors(8, n0=7, count=4)
     assert e.value.code == kpm.KPM_E_INVALID
     assert kpm.debug_inject_failure(0, 0) == 0
+
+
+def test_traffic_record_matches_kernel_sources():
+    """The HBM-traffic record that bench.py reports beside the step kernel's
+    roofline was taken on the committed kernel sources (a record counts only
+    for the sources whose SHA-256 it names), for the benchmarked workload and
+    both launch shapes the autotuner chooses between, with a calibration
+    factor from the plain copy."""
+    import importlib.util
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    with open(os.path.join(root, "profiles", "step_kernel_traffic.json")) as fh:
+        rec = json.load(fh)
+    sha = bench.step_kernel_source_hash()
+    launches = {tuple(r["launch"]) for r in rec["records"] if r["source_sha256"] == sha and r["workload"] == [4096, 32]}
+    assert {(5, 512, 256, 1024, 8), (5, 512, 128, 2048, 8)} <= launches
+    for r in rec["records"]:
+        assert 1.0 <= r["hbm_bytes_per_launch"] / r["algorithmic_bytes_per_launch"] < 1.2
+        assert abs(r["calibration"]["fetch_factor"] - 2.0) < 0.01 and abs(r["calibration"]["write_factor"] - 1.0) < 0.01
