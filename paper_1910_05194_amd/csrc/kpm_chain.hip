@@ -84,18 +84,36 @@ __device__ inline void chain_site(T a, T b, bool read_w, const Coef<T, KIND>& C,
   for (int j = 0; j < NC; ++j) {
     T hr = ons * vo.v[2 * j], hi = ons * vo.v[2 * j + 1];
     T gr = 0, gi = 0;
+    // Complex products as chains of FMAs (the compiler may not reassociate
+    // a sum of products into them): four per coefficient and value.  Mode 0
+    // adds every term straight into the result; mode 1 keeps each
+    // neighbour's term for the velocity sum.
 #pragma unroll
     for (int k = 0; k < NNB; ++k) {
-      T tr = C.re[k][0] * vn[k][0].v[2 * j] - C.im[k][0] * vn[k][0].v[2 * j + 1];
-      T ti = C.re[k][0] * vn[k][0].v[2 * j + 1] + C.im[k][0] * vn[k][0].v[2 * j];
-#pragma unroll
-      for (int s2 = 1; s2 < NSPIN; ++s2)
-        cmul_acc(tr, ti, C.re[k][s2], C.im[k][s2], vn[k][s2].v[2 * j], vn[k][s2].v[2 * j + 1]);
-      hr += tr;
-      hi += ti;
       if constexpr (MODE == 1) {
-        gr += C.vc[k] * tr;
-        gi += C.vc[k] * ti;
+        T tr = C.re[k][0] * vn[k][0].v[2 * j];
+        T ti = C.re[k][0] * vn[k][0].v[2 * j + 1];
+        tr = fma(-C.im[k][0], vn[k][0].v[2 * j + 1], tr);
+        ti = fma(C.im[k][0], vn[k][0].v[2 * j], ti);
+#pragma unroll
+        for (int s2 = 1; s2 < NSPIN; ++s2) {
+          tr = fma(C.re[k][s2], vn[k][s2].v[2 * j], tr);
+          tr = fma(-C.im[k][s2], vn[k][s2].v[2 * j + 1], tr);
+          ti = fma(C.re[k][s2], vn[k][s2].v[2 * j + 1], ti);
+          ti = fma(C.im[k][s2], vn[k][s2].v[2 * j], ti);
+        }
+        hr += tr;
+        hi += ti;
+        gr = fma(C.vc[k], tr, gr);
+        gi = fma(C.vc[k], ti, gi);
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < NSPIN; ++s2) {
+          hr = fma(C.re[k][s2], vn[k][s2].v[2 * j], hr);
+          hr = fma(-C.im[k][s2], vn[k][s2].v[2 * j + 1], hr);
+          hi = fma(C.re[k][s2], vn[k][s2].v[2 * j + 1], hi);
+          hi = fma(C.im[k][s2], vn[k][s2].v[2 * j], hi);
+        }
       }
     }
     T orr = a * hr, oi = a * hi;
@@ -317,15 +335,31 @@ __global__ void __launch_bounds__(kMaxStepBlock) chain_sweep_kernel(ChainArgs<T>
       u32x2 h, l;
       if constexpr (split) {
         if constexpr (sizeof(T) == 4) {
-          typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-          bf16x4 hi, lo;
+          if constexpr (MODE == 0) {
+            // Two values per conversion (v_cvt_pk_bf16_f32 rounds a pair;
+            // the velocity chain's code is already paired by the compiler).
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            hi[q] = (__bf16)src.v[q];
-            lo[q] = (__bf16)(src.v[q] - (float)hi[q]);
+            for (int q = 0; q < 2; ++q) {
+              const f32x2 x = {src.v[2 * q], src.v[2 * q + 1]};
+              const bf16x2 hv = __builtin_convertvector(x, bf16x2);
+              const f32x2 r = x - __builtin_convertvector(hv, f32x2);
+              const bf16x2 lv = __builtin_convertvector(r, bf16x2);
+              h[q] = __builtin_bit_cast(unsigned int, hv);
+              l[q] = __builtin_bit_cast(unsigned int, lv);
+            }
+          } else {
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16x4 hi, lo;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              hi[q] = (__bf16)src.v[q];
+              lo[q] = (__bf16)(src.v[q] - (float)hi[q]);
+            }
+            h = __builtin_bit_cast(u32x2, hi);
+            l = __builtin_bit_cast(u32x2, lo);
           }
-          h = __builtin_bit_cast(u32x2, hi);
-          l = __builtin_bit_cast(u32x2, lo);
         }
       } else {
         const u32x4 all = __builtin_bit_cast(u32x4, src);
