@@ -543,7 +543,8 @@ int kpm_mlp_rel_error(kpm_mlp_t* mlp, const float* x, const double* ref, const f
  * random-phase vectors the variance of one vector's estimate of
  * Tr T_n(H~)/N is sum_{i != j} |T_n,ij|^2 / N^2 <= Tr T_n(H~)^2 / N^2 <= 1/N,
  * so the mean over R vectors has a standard error of at most 1/sqrt(N R);
- * noise [batch] (FP64, device) holds that scale per row.  With the same x,
+ * noise [batch] (FP64, device, each > 0; not checked on the host, a zero
+ * gives an overflowing z) holds that scale per row.  With the same x,
  * ref, weights and use_bf16 as kpm_mlp_rel_error:
  *   z[b] = ||w (y_b - ref_b)|| / (noise_b ||w||)   (FP64, [batch]),
  * the weighted RMS deviation of the prediction in units of the reference's
