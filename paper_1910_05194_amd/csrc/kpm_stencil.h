@@ -44,8 +44,12 @@ struct KindTraits<KPM_SQUARE> { static constexpr int NSUB = 1, NSPIN = 1, NNB = 
 
 template <typename T>
 __device__ inline void cmul_acc(T& ore, T& oim, T are, T aim, T bre, T bim) {
-  ore += are * bre - aim * bim;
-  oim += are * bim + aim * bre;
+  // Four FMAs (a sum of products would compile to a multiply, an FMA and an
+  // add per real part: the compiler may not reassociate it).
+  ore = fma(are, bre, ore);
+  ore = fma(-aim, bim, ore);
+  oim = fma(are, bim, oim);
+  oim = fma(aim, bre, oim);
 }
 
 // Reduce the per-thread dot products of one moment slot over the workgroup
